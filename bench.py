@@ -1,0 +1,176 @@
+"""Benchmark of the PP-WCNS-IS hot path on one MI355X.
+
+Workload (default): 2D shock-bubble interaction on a 1024 x 1024 grid in
+FP64 (planar water shock at 1e9 Pa hitting an air bubble in water), SSP-RK3
+steps at CFL 0.5 with the time step computed on the device.  One timed "step"
+is one full SSP-RK3 step = 3 right-hand-side evaluations with their wave-speed
+reductions, limiters, flux differences and stage combinations.
+
+value = cell-updates per second per RHS (3 x cells x steps / time), in
+Mcell-updates/s, inputs resident in HBM before the timed region.
+
+Also reported:
+  roofline      the dominant kernel's algorithmic FP64 work per launch over
+                its average duration (HIP events around each launch on the
+                library's stream), against the FP64 VALU issue rate
+  cpu_baseline  the serial FP64 oracle timed on a bounded sample of the same
+                workload on this host (rank 0, N = 1 only)
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-updates/s per RHS, FP64 vs FP32/batched; solves/s and p99 latency"
+# FP64 VALU: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 issue slots/s
+# (78.6 TFLOP/s when every slot is an FMA counted as 2 flops)
+VALU_F64_SLOTS = 256 * 64 * 2.4e9
+W_DIV, W_SQRT = 11, 19   # VALU instructions of the IEEE FP64 divide / sqrt on gfx950
+
+
+def weighted(c):
+    return c["add"] + c["mul"] + c["cmp"] + W_DIV * c["div"] + W_SQRT * c["sqrt"]
+
+
+def kernel_ops(nx, ny, scheme="ppwcnsis"):
+    """Algorithmic (issue-weighted) FP64 ops per launch of each kernel."""
+    with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
+        oc = json.load(f)["counts"][scheme]
+    face = weighted(oc["face"])
+    node = weighted(oc["node"])
+    cells = nx * ny
+    diff = 6 * (1 + W_DIV)                 # -(G^- - G^+)/dx per component
+    rk = 6 * 5                             # ca*Un + cb*(W + dt*L)
+    return {
+        "node": cells * (node + 4),        # + |u|+c, |v|+c, two max
+        "sweep_x": (nx + 1) * ny * face + cells * diff,
+        "sweep_y": nx * (ny + 1) * face + cells * (diff + 6 + rk),
+    }
+
+
+def cpu_baseline(spec, target_s=12.0):
+    from oracle import oracle as orc
+    s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy, bc=spec.bc)
+    W = orc.prim_to_cons(s, spec.prim)
+    dt = orc.cfl_dt(s, W)
+    t0 = time.perf_counter()
+    orc.rhs(s, W, dt)
+    one = time.perf_counter() - t0
+    calls = max(1, int(target_s / max(one, 1e-3)) - 1)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        orc.rhs(s, W, dt)
+    el = time.perf_counter() - t0
+    return {"value": spec.nx * spec.ny * calls / el / 1e6, "unit": "Mcell-updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{calls} full-grid RHS evaluations of the {spec.nx}x{spec.ny} "
+                      f"shock-bubble initial state (serial FP64 C++ oracle, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import wcns
+
+    torch.cuda.set_device(0)
+    spec = pb.shock_bubble(args.n)
+    sol = wcns.Solver.from_spec(spec)
+    V = torch.from_numpy(spec.prim).cuda()
+    W0 = sol.prim_to_cons(V)
+    W = W0.clone()
+    print(f"# workload {spec.name} {spec.nx}x{spec.ny} fp64; warmup {args.warmup}", flush=True)
+    for _ in range(args.warmup):
+        sol.step(W, 0.0)
+    torch.cuda.synchronize()
+    W.copy_(W0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sol.step(W, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = spec.nx * spec.ny
+    value = 3 * cells * args.steps / el / 1e6
+    bad = sol.count_inadmissible(W)
+    print(f"# timed {args.steps} steps in {el:.3f}s; inadmissible cells after: {bad}", flush=True)
+
+    # per-kernel device time over the same number of steps (events on the
+    # library's stream); the dominant kernel gives the roofline
+    W.copy_(W0)
+    sol.profile(True)
+    for _ in range(args.steps):
+        sol.step(W, 0.0)
+    prof = sol.profile_read(reset=True)
+    sol.profile(False)
+    ops = kernel_ops(spec.nx, spec.ny)
+    dom = max((k for k in ops), key=lambda k: prof[k][0])
+    ms, n = prof[dom]
+    avg_s = ms / 1e3 / n
+    achieved = ops[dom] / avg_s / 1e12
+    peak = VALU_F64_SLOTS / 1e12
+    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "avg_launch_ms": avg_s * 1e3,
+                "ops_per_launch": ops[dom],
+                "op_model": "oracle op count, div=11 and sqrt=19 VALU slots; peak = FP64 "
+                            "VALU issue rate 256 CU x 64 lanes x 2.4 GHz"}
+    per_kernel = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
+
+    # pure RHS rate (no stage combination) for reference
+    dWdt = torch.empty_like(W)
+    dt = 1e-8
+    for _ in range(3):
+        sol.rhs(W0, dWdt, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nr = max(10, args.steps)
+    for _ in range(nr):
+        sol.rhs(W0, dWdt, dt)
+    torch.cuda.synchronize()
+    rhs_rate = cells * nr / (time.perf_counter() - t0) / 1e6
+
+    cpu = None
+    if not args.no_cpu:
+        print("# cpu baseline (oracle) ...", flush=True)
+        cpu = cpu_baseline(spec)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D shock-bubble interaction, {spec.nx}x{spec.ny}, FP64 "
+                               "PP-WCNS-IS, SSP-RK3 at CFL 0.5 (device dt)",
+                   "cells": cells, "rhs_per_step": 3, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rhs_only_mcells_per_s": rhs_rate,
+        "per_kernel": per_kernel,
+        "inadmissible_after": bad,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

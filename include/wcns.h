@@ -1,0 +1,158 @@
+/*
+ * wcns.h -- C ABI of the MI355X (gfx950) implementation of the right-hand
+ * side of the positivity- and boundedness-preserving incremental-stencil
+ * weighted compact nonlinear scheme (PP-WCNS-IS) for Allaire's five-equation
+ * gas-liquid model (Wong, Angel, Barad, Kiris, arXiv 2102.05287).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns a wcns_status; no exception crosses the ABI.
+ *  - State arrays are DEVICE pointers to float64, structure-of-arrays
+ *    [nvar][ny][nx] (x fastest), interior cells only (no ghost layers).
+ *      2D: nvar = 6, (a1*rho1, a2*rho2, rho*u, rho*v, E, a1)
+ *      1D: nvar = 5, (a1*rho1, a2*rho2, rho*u, E, a1)           (ny = 1)
+ *    This is the conservative vector W of the paper (Sec. 2, Sec. 3).
+ *  - The caller owns every state buffer; the context owns its scratch, which
+ *    is allocated once in wcns_create.  rhs/step/limit allocate nothing, so
+ *    a sequence of calls can be captured into a HIP graph.
+ *  - All kernels are enqueued on the context's stream (set at creation or
+ *    by wcns_set_stream); calls are asynchronous unless stated otherwise.
+ *    Calls on one context must not overlap (they share its scratch).
+ */
+#ifndef WCNS_H_
+#define WCNS_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  WCNS_OK = 0,
+  WCNS_ERR_ARG = -1,          /* bad argument (null pointer, size < 1, ...)    */
+  WCNS_ERR_EOS = -2,          /* fluids violate Lemma 1 / Theorem 1 (Sec. 2):  */
+                              /* one phase must have pinf = 0 and the other a  */
+                              /* ratio of specific heats >= the gas one        */
+  WCNS_ERR_NOMEM = -3,        /* device allocation failed                      */
+  WCNS_ERR_HIP = -4,          /* a HIP runtime call failed                     */
+  WCNS_ERR_INADMISSIBLE = -5, /* a state lies outside the admissible set G     */
+  WCNS_ERR_CFL = -6           /* non-finite or non-positive time step          */
+} wcns_status;
+
+typedef enum {
+  WCNS_BC_PERIODIC = 0,
+  WCNS_BC_EXTRAP = 1,         /* constant (zeroth-order) extrapolation         */
+  WCNS_BC_REFLECT = 2,        /* mirror state, negate wall-normal momentum     */
+  WCNS_BC_DIRICHLET = 3       /* fixed ghost state (grid.dirichlet)            */
+} wcns_bc;
+
+typedef enum { WCNS_FP64 = 0, WCNS_FP32_BULK = 1 } wcns_precision;
+typedef enum { WCNS_SCHEME_PPWCNSIS = 0, WCNS_SCHEME_HLLC1 = 1 } wcns_scheme;
+
+/* Fluids (Sec. 2 stiffened gas; Table 1): [0] liquid, [1] ideal gas. */
+typedef struct {
+  double gamma[2];
+  double pinf[2];
+} wcns_eos;
+
+/* Uniform Cartesian grid (Sec. 3: cells of size dx = (x1-x0)/nx). */
+typedef struct {
+  int32_t ndim;               /* 1 or 2                                        */
+  int32_t nx, ny;             /* ny = 1 when ndim = 1                          */
+  double x0, x1, y0, y1;
+  int32_t bc[4];              /* wcns_bc of x-lo, x-hi, y-lo, y-hi             */
+  double dirichlet[4][6];     /* host; conservative ghost state per side, in   */
+                              /* the nvar order above (used for DIRICHLET)     */
+} wcns_grid;
+
+/* Scheme options; wcns_params_default fills the paper's values. */
+typedef struct {
+  double eps_arho, eps_alpha, eps_rhoc2;  /* limiter tolerances, Sec. 5.1: 1e-10, 1e-10, 1e-8 */
+  double hs_arho, hs_alpha, hs_rhoc2;     /* hard-switch tolerances: 1e-11, 1e-11, 1e-9       */
+  double weno_eps;                        /* epsilon of the IS weights (Sec. 4.3); the paper  */
+                                          /* gives none; default 1e-40                        */
+  double cfl;                             /* CFL number, <= 0.5 (Sec. 3.3, 5.3); default 0.5  */
+  int32_t interp_limiter;                 /* 1: apply Algorithms 1-3 (Sec. 5.1)               */
+  int32_t flux_limiter;                   /* 1: apply Algorithms 4-6 (Sec. 5.2)               */
+  int32_t scheme;                         /* wcns_scheme                                      */
+  int32_t reserved;
+} wcns_params;
+
+typedef struct wcns_ctx wcns_ctx;
+
+/* Fill p with the paper's defaults. WCNS_ERR_ARG if p is NULL. */
+wcns_status wcns_params_default(wcns_params* p);
+
+/* Create a context for one grid.  Validates the fluids against Lemma 1
+ * (WCNS_ERR_EOS), the grid (nx, ny >= 1, ndim in {1,2}, bc kinds, reflective
+ * sides need >= 3 cells) and the parameters (WCNS_ERR_ARG), then allocates
+ * all device scratch once (WCNS_ERR_NOMEM).  stream: hipStream_t or NULL for
+ * the default stream.  On success *out owns the scratch until wcns_destroy. */
+wcns_status wcns_create(const wcns_grid* grid, const wcns_eos* eos, const wcns_params* params,
+                        int32_t precision, void* stream, wcns_ctx** out);
+
+/* Release the context and its scratch (synchronises its stream). */
+wcns_status wcns_destroy(wcns_ctx* ctx);
+
+/* Change the stream later calls enqueue on. */
+wcns_status wcns_set_stream(wcns_ctx* ctx, void* stream);
+
+/* Primitive -> conservative on the device (Sec. 2 mixture EOS):
+ * V = (a1r1, a2r2, u, [v], p, a1) SoA -> W, both device [nvar][ny][nx]. */
+wcns_status wcns_prim_to_cons(wcns_ctx* ctx, const double* V, double* W);
+
+/* Semi-discrete right-hand side L(W) (Sec. 4.1 flux-difference form with the
+ * split fluxes G^{+-} of Sec. 3.2, the WCNS steps of Sec. 4.2, the limiters
+ * of Sec. 5).  dt is the forward-Euler step the flux limiter protects: the
+ * limiter uses lambda = dt/(dx sigma) with sigma from W (Sec. 3.3).
+ * W, dWdt: device [nvar][ny][nx]; must not alias.  Asynchronous. */
+wcns_status wcns_rhs(wcns_ctx* ctx, const double* W, double* dWdt, double dt);
+
+/* Stand-alone flux limiter of one sweep direction (Algorithms 4-6 and the
+ * hard switch, Sec. 5.2).  dir 0: x-faces, layout [ny][nx+1]; dir 1:
+ * y-faces, layout [ny+1][nx]; face (k, line) lies between cells k-1 and k.
+ * G_ho, G_lo: device SoA [nvar+1][nfaces]: the high-order reconstructed flux
+ * Ghat (nvar components in the state order, alpha slot = fhat_alpha) and, in
+ * the last row, uhat; G_lo the same for the first-order HLLC flux.
+ * G_out: device SoA [2][nvar][nfaces]: limited G^- then G^+.
+ * theta: device [nfaces] (may be NULL): smallest theta applied, 0 if the hard
+ * switch fired.  lambda is computed from W and dt as in wcns_rhs. */
+wcns_status wcns_limit(wcns_ctx* ctx, int32_t dir, const double* W, const double* G_ho,
+                       const double* G_lo, double* G_out, double* theta, double dt);
+
+/* Maximum wave speeds max(|u|+c), max(|v|+c) over the cells (Sec. 3.3).
+ * d_amax: device double[2] (the second entry is 0 in 1D). */
+wcns_status wcns_max_wavespeed(wcns_ctx* ctx, const double* W, double* d_amax);
+
+/* One three-stage SSP Runge-Kutta step (TVD-RK3, Sec. 5.3, Sec. 6) in place
+ * on W.  dt > 0: that step; dt <= 0: CFL step dt = cfl/(tau_x + tau_y) from
+ * the state at the start of the step, computed on the device.  Every stage
+ * evaluates sigma/lambda from its own input state.  dt_used: device double*
+ * (may be NULL) receives the step taken.  Asynchronous; no host sync. */
+wcns_status wcns_ssprk3_step(wcns_ctx* ctx, double* W, double dt, double* dt_used);
+
+/* Count cells outside the admissible set G (Sec. 2): a1 < 0 or a1 > 1,
+ * a_k r_k < 0, or rho e - pbar_inf <= 0 (NaN counts as outside).
+ * Synchronises the stream; *n_bad is a host pointer. */
+wcns_status wcns_check_admissible(wcns_ctx* ctx, const double* W, long long* n_bad);
+
+/* Measurement aid (not needed for the method).  While enabled, every kernel
+ * the context launches is bracketed by a pair of HIP events recorded on the
+ * context's stream; wcns_profile_read synchronises the stream and returns,
+ * per kernel class, the summed device time in milliseconds and the number of
+ * launches since the last reset.  Classes (WCNS_NPROF = 6): 0 node
+ * primitives + wave-speed maxima, 1 dt/lambda finalize, 2 x-sweep, 3 y-sweep,
+ * 4 y-tile fixup, 5 other.  Enabling allocates the event pool (so it is not
+ * graph-capturable); disabling releases it. */
+#define WCNS_NPROF 6
+wcns_status wcns_profile(wcns_ctx* ctx, int32_t enable);
+wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
+
+/* Human-readable status. */
+const char* wcns_status_str(wcns_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCNS_H_ */

@@ -1,0 +1,474 @@
+// Host side of the C ABI declared in include/wcns.h: context creation and
+// validation, scratch allocation (once), and kernel launch sequences for the
+// RHS, the stand-alone flux limiter, the wave-speed reduction and the SSP-RK3
+// step.  No allocation happens after wcns_create.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "../../include/wcns.h"
+#include "wcns_kernels.hpp"
+
+using namespace wcns;
+
+struct wcns_ctx {
+  wcns_grid grid;
+  wcns_eos eos;
+  wcns_params params;
+  int32_t precision;
+  hipStream_t stream;
+  int nv;
+  long N;
+  double dx, dy;
+  KArgs base;
+  double *P, *L, *U1, *U2, *partial, *step, *dirW, *dirP, *edge;
+  unsigned long long* count;
+  int node_grid, tile_x, x_grid, nbr;
+  // measurement aid: event pairs around launches (wcns_profile)
+  int prof_on, prof_n, prof_cap;
+  hipEvent_t* ev;
+  int* ev_cls;
+  double prof_ms[WCNS_NPROF];
+  int64_t prof_cnt[WCNS_NPROF];
+};
+
+// Fold recorded event pairs into the per-class sums (synchronises).
+static wcns_status prof_fold(wcns_ctx* c) {
+  if (!c->prof_on || c->prof_n == 0) return WCNS_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return WCNS_ERR_HIP;
+  for (int k = 0; k < c->prof_n; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) != hipSuccess) return WCNS_ERR_HIP;
+    c->prof_ms[c->ev_cls[k]] += ms;
+    c->prof_cnt[c->ev_cls[k]] += 1;
+  }
+  c->prof_n = 0;
+  return WCNS_OK;
+}
+
+// RAII bracket of one launch when profiling is on
+struct ProfScope {
+  wcns_ctx* c;
+  int slot;
+  ProfScope(wcns_ctx* c_, int cls) : c(c_), slot(-1) {
+    if (!c->prof_on) return;
+    if (c->prof_n == c->prof_cap) (void)prof_fold(c);
+    slot = c->prof_n++;
+    c->ev_cls[slot] = cls;
+    (void)hipEventRecord(c->ev[2 * slot], c->stream);
+  }
+  ~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+  }
+};
+enum { PROF_NODE = 0, PROF_FIN = 1, PROF_X = 2, PROF_Y = 3, PROF_FIX = 4, PROF_OTHER = 5 };
+
+#define HIP_TRY(x)                                   \
+  do {                                               \
+    hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) return WCNS_ERR_HIP;       \
+  } while (0)
+#define LAUNCH_CHECK() HIP_TRY(hipGetLastError())
+
+extern "C" {
+
+const char* wcns_status_str(wcns_status s) {
+  switch (s) {
+    case WCNS_OK: return "ok";
+    case WCNS_ERR_ARG: return "invalid argument";
+    case WCNS_ERR_EOS: return "fluids violate Lemma 1 (need one ideal gas and gamma_liquid >= gamma_gas)";
+    case WCNS_ERR_NOMEM: return "device allocation failed";
+    case WCNS_ERR_HIP: return "HIP runtime error";
+    case WCNS_ERR_INADMISSIBLE: return "state outside the admissible set";
+    case WCNS_ERR_CFL: return "invalid time step";
+  }
+  return "unknown status";
+}
+
+wcns_status wcns_params_default(wcns_params* p) {
+  if (!p) return WCNS_ERR_ARG;
+  memset(p, 0, sizeof(*p));
+  p->eps_arho = 1e-10;
+  p->eps_alpha = 1e-10;
+  p->eps_rhoc2 = 1e-8;
+  p->hs_arho = 1e-11;
+  p->hs_alpha = 1e-11;
+  p->hs_rhoc2 = 1e-9;
+  p->weno_eps = 1e-40;
+  p->cfl = 0.5;
+  p->interp_limiter = 1;
+  p->flux_limiter = 1;
+  p->scheme = WCNS_SCHEME_PPWCNSIS;
+  return WCNS_OK;
+}
+
+// Lemma 1 / Theorem 1: the admissible set is convex when one phase is an
+// ideal gas (pinf = 0) and the other has a ratio of specific heats at least
+// as large; gamma > 1 and pinf >= 0 for both.
+static bool eos_ok(const wcns_eos* e) {
+  if (!(e->gamma[0] > 1.0) || !(e->gamma[1] > 1.0)) return false;
+  if (!(e->pinf[0] >= 0.0) || !(e->pinf[1] >= 0.0)) return false;
+  if (e->pinf[1] == 0.0) return e->gamma[0] >= e->gamma[1];
+  if (e->pinf[0] == 0.0) return e->gamma[1] >= e->gamma[0];
+  return false;
+}
+
+static int pick_tile_x(int nx) {
+  // largest T with T + (rows a run of T cells can touch) <= 64
+  for (int T = 62; T >= 1; --T) {
+    int rows = (T - 1 + nx - 1) / nx + 1;
+    if (T + rows <= 64) return T;
+  }
+  return 1;
+}
+
+static void prof_release(wcns_ctx* c) {
+  if (c->ev) {
+    for (int k = 0; k < 2 * c->prof_cap; ++k) (void)hipEventDestroy(c->ev[k]);
+    free(c->ev);
+    free(c->ev_cls);
+  }
+  c->ev = nullptr;
+  c->ev_cls = nullptr;
+  c->prof_cap = 0;
+  c->prof_n = 0;
+  c->prof_on = 0;
+}
+
+wcns_status wcns_destroy(wcns_ctx* c) {
+  if (!c) return WCNS_ERR_ARG;
+  prof_release(c);
+  (void)hipStreamSynchronize(c->stream);
+  double* bufs[] = {c->P, c->L, c->U1, c->U2, c->partial, c->step, c->dirW, c->dirP, c->edge};
+  for (double* b : bufs)
+    if (b) (void)hipFree(b);
+  if (c->count) (void)hipFree(c->count);
+  free(c);
+  return WCNS_OK;
+}
+
+wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
+                        int32_t precision, void* stream, wcns_ctx** out) {
+  if (!g || !eos || !prm || !out) return WCNS_ERR_ARG;
+  *out = nullptr;
+  if (g->ndim != 1 && g->ndim != 2) return WCNS_ERR_ARG;
+  if (g->nx < 1 || g->ny < 1 || (g->ndim == 1 && g->ny != 1)) return WCNS_ERR_ARG;
+  if ((long)g->nx * g->ny > (1L << 31)) return WCNS_ERR_ARG;
+  if (!(g->x1 > g->x0) || (g->ndim == 2 && !(g->y1 > g->y0))) return WCNS_ERR_ARG;
+  for (int d = 0; d < g->ndim; ++d) {
+    int lo = g->bc[2 * d], hi = g->bc[2 * d + 1];
+    int n = d == 0 ? g->nx : g->ny;
+    for (int b : {lo, hi})
+      if (b < WCNS_BC_PERIODIC || b > WCNS_BC_DIRICHLET) return WCNS_ERR_ARG;
+    if ((lo == WCNS_BC_PERIODIC) != (hi == WCNS_BC_PERIODIC)) return WCNS_ERR_ARG;
+    if ((lo == WCNS_BC_REFLECT || hi == WCNS_BC_REFLECT) && n < 3) return WCNS_ERR_ARG;
+  }
+  if (!eos_ok(eos)) return WCNS_ERR_EOS;
+  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5)) return WCNS_ERR_ARG;
+  if (!(prm->weno_eps > 0.0)) return WCNS_ERR_ARG;
+  if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
+  if (precision != WCNS_FP64) return WCNS_ERR_ARG;
+
+  wcns_ctx* c = (wcns_ctx*)calloc(1, sizeof(wcns_ctx));
+  if (!c) return WCNS_ERR_NOMEM;
+  c->grid = *g;
+  c->eos = *eos;
+  c->params = *prm;
+  c->precision = precision;
+  c->stream = (hipStream_t)stream;
+  c->nv = g->ndim == 1 ? 5 : 6;
+  c->N = (long)g->nx * g->ny;
+  c->dx = (g->x1 - g->x0) / g->nx;
+  c->dy = g->ndim == 2 ? (g->y1 - g->y0) / g->ny : 1.0;
+
+  KArgs& a = c->base;
+  memset(&a, 0, sizeof(a));
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nv = c->nv;
+  a.dx = c->dx;
+  a.dy = c->dy;
+  for (int k = 0; k < 4; ++k) a.bc[k] = g->bc[k];
+  if (g->ndim == 1) { a.bc[2] = WCNS_BC_PERIODIC; a.bc[3] = WCNS_BC_PERIODIC; }
+  a.interp_limiter = prm->interp_limiter ? 1 : 0;
+  a.flux_limiter = prm->flux_limiter ? 1 : 0;
+  a.scheme = prm->scheme;
+  a.eos.g1 = 1.0 / (eos->gamma[0] - 1.0);
+  a.eos.g2 = 1.0 / (eos->gamma[1] - 1.0);
+  a.eos.q1 = eos->gamma[0] * eos->pinf[0] / (eos->gamma[0] - 1.0);
+  a.eos.q2 = eos->gamma[1] * eos->pinf[1] / (eos->gamma[1] - 1.0);
+  a.tol.eps_arho = prm->eps_arho;
+  a.tol.eps_alpha = prm->eps_alpha;
+  a.tol.eps_rhoc2 = prm->eps_rhoc2;
+  a.tol.hs_arho = prm->hs_arho;
+  a.tol.hs_alpha = prm->hs_alpha;
+  a.tol.hs_rhoc2 = prm->hs_rhoc2;
+  a.tol.weno_eps = prm->weno_eps;
+
+  c->tile_x = pick_tile_x(g->nx);
+  a.tile_x = c->tile_x;
+  c->x_grid = (int)((c->N + c->tile_x - 1) / c->tile_x);
+  long ng = (c->N + 255) / 256;
+  c->node_grid = (int)(ng < 2048 ? ng : 2048);
+  c->nbr = (g->ny + 1 + Y_WAVES - 1) / Y_WAVES;
+
+  wcns_status st = WCNS_OK;
+  auto alloc = [&](double** p, size_t n) {
+    if (st != WCNS_OK) return;
+    if (hipMalloc((void**)p, n * sizeof(double)) != hipSuccess) { *p = nullptr; st = WCNS_ERR_NOMEM; }
+  };
+  alloc(&c->P, 5 * (size_t)c->N);
+  alloc(&c->U1, (size_t)c->nv * c->N);
+  alloc(&c->U2, (size_t)c->nv * c->N);
+  if (g->ndim == 2) {
+    alloc(&c->L, (size_t)c->nv * c->N);
+    alloc(&c->edge, (size_t)c->nbr * 12 * g->nx);
+  }
+  alloc(&c->partial, 2 * (size_t)c->node_grid);
+  alloc(&c->step, 8);
+  alloc(&c->dirW, 24);
+  alloc(&c->dirP, 20);
+  if (st == WCNS_OK && hipMalloc((void**)&c->count, sizeof(unsigned long long)) != hipSuccess)
+    st = WCNS_ERR_NOMEM;
+  if (st != WCNS_OK) { wcns_destroy(c); return st; }
+
+  // Dirichlet ghost states (unrotated 6-component form) and their primitives
+  double dw[24];
+  for (int s = 0; s < 4; ++s) {
+    const double* d = g->dirichlet[s];
+    bool used = g->bc[s] == WCNS_BC_DIRICHLET && (g->ndim == 2 || s < 2);
+    if (!used) {
+      // harmless admissible placeholder (never read)
+      double ph[6] = {1.0, 1.0, 0.0, 0.0, 1e6, 0.5};
+      memcpy(dw + 6 * s, ph, sizeof(ph));
+    } else if (g->ndim == 1) {
+      double x[6] = {d[0], d[1], d[2], 0.0, d[3], d[4]};
+      memcpy(dw + 6 * s, x, sizeof(x));
+    } else {
+      memcpy(dw + 6 * s, d, 6 * sizeof(double));
+    }
+  }
+  if (hipMemcpy(c->dirW, dw, sizeof(dw), hipMemcpyHostToDevice) != hipSuccess) {
+    wcns_destroy(c);
+    return WCNS_ERR_HIP;
+  }
+  double zero8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (hipMemcpy(c->step, zero8, sizeof(zero8), hipMemcpyHostToDevice) != hipSuccess) {
+    wcns_destroy(c);
+    return WCNS_ERR_HIP;
+  }
+  a.dirW = c->dirW;
+  a.dirP = c->dirP;
+  a.step = c->step;
+  a.edge = c->edge;
+  if (g->ndim == 2)
+    hipLaunchKernelGGL(k_dirichlet_prims<true>, dim3(1), dim3(64), 0, c->stream, a, c->dirP);
+  else
+    hipLaunchKernelGGL(k_dirichlet_prims<false>, dim3(1), dim3(64), 0, c->stream, a, c->dirP);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    wcns_destroy(c);
+    return WCNS_ERR_HIP;
+  }
+  *out = c;
+  return WCNS_OK;
+}
+
+wcns_status wcns_set_stream(wcns_ctx* c, void* stream) {
+  if (!c) return WCNS_ERR_ARG;
+  c->stream = (hipStream_t)stream;
+  return WCNS_OK;
+}
+
+// node primitives + wave-speed maxima + dt/lambda of state W
+static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mode, double dt,
+                                        double* dt_used) {
+  KArgs a = c->base;
+  a.W = W;
+  {
+  ProfScope ps(c, PROF_NODE);
+  if (c->grid.ndim == 2)
+    hipLaunchKernelGGL(k_node<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
+  else
+    hipLaunchKernelGGL(k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
+  }
+  LAUNCH_CHECK();
+  ProfScope ps(c, PROF_FIN);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
+                     c->node_grid, c->grid.ndim, c->dx, c->dy, c->params.cfl, dt_mode, dt, c->step,
+                     dt_used);
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+// x-sweep and (2D) y-sweep of state W into `out`; mode STORE (L) or RK.
+static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int mode,
+                                 const double* Un, double ca, double cb) {
+  KArgs a = c->base;
+  a.W = W;
+  a.P = c->P;
+  a.out = out;
+  a.Un = Un;
+  a.ca = ca;
+  a.cb = cb;
+  a.out_mode = mode;
+  if (c->grid.ndim == 1) {
+    a.Lout = nullptr;
+    ProfScope ps(c, PROF_X);
+    hipLaunchKernelGGL(k_sweep_x<false>, dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    LAUNCH_CHECK();
+    return WCNS_OK;
+  }
+  // 2D: L_x goes to `out` when storing L (summed in place by the y-sweep),
+  // to the context's L buffer for a Runge-Kutta stage
+  double* lx = mode == OUT_STORE ? out : c->L;
+  a.Lout = lx;
+  a.Lx = lx;
+  {
+    ProfScope ps(c, PROF_X);
+    hipLaunchKernelGGL(k_sweep_x<true>, dim3(c->x_grid), dim3(64), 0, c->stream, a);
+  }
+  LAUNCH_CHECK();
+  dim3 gy((c->grid.nx + 63) / 64, c->nbr);
+  {
+    ProfScope ps(c, PROF_Y);
+    hipLaunchKernelGGL(k_sweep_y, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+  }
+  LAUNCH_CHECK();
+  if (c->nbr > 1) {
+    long nt = (long)(c->nbr - 1) * c->grid.nx;
+    ProfScope ps(c, PROF_FIX);
+    hipLaunchKernelGGL(k_fixup_y, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, a,
+                       c->nbr);
+    LAUNCH_CHECK();
+  }
+  return WCNS_OK;
+}
+
+wcns_status wcns_prim_to_cons(wcns_ctx* c, const double* V, double* W) {
+  if (!c || !V || !W) return WCNS_ERR_ARG;
+  KArgs a = c->base;
+  unsigned g = (unsigned)((c->N + 255) / 256);
+  if (c->grid.ndim == 2)
+    hipLaunchKernelGGL(k_prim_to_cons<true>, dim3(g), dim3(256), 0, c->stream, a, V, W);
+  else
+    hipLaunchKernelGGL(k_prim_to_cons<false>, dim3(g), dim3(256), 0, c->stream, a, V, W);
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
+  if (!c || !W || !dWdt || W == dWdt) return WCNS_ERR_ARG;
+  if (!(dt >= 0.0) || !isfinite(dt)) return WCNS_ERR_CFL;
+  wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr);
+  if (s != WCNS_OK) return s;
+  return launch_sweeps(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
+}
+
+wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used) {
+  if (!c || !W) return WCNS_ERR_ARG;
+  if (!isfinite(dt)) return WCNS_ERR_CFL;
+  // stage inputs / outputs of the Shu-Osher form
+  const double* in[3] = {W, c->U1, c->U2};
+  double* outs[3] = {c->U1, c->U2, W};
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  for (int s = 0; s < 3; ++s) {
+    int mode = s == 0 ? (dt > 0.0 ? DT_GIVEN : DT_CFL) : DT_KEEP;
+    wcns_status st = launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr);
+    if (st != WCNS_OK) return st;
+    st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
+    if (st != WCNS_OK) return st;
+  }
+  return WCNS_OK;
+}
+
+wcns_status wcns_max_wavespeed(wcns_ctx* c, const double* W, double* d_amax) {
+  if (!c || !W || !d_amax) return WCNS_ERR_ARG;
+  wcns_status s = launch_node_finalize(c, W, DT_GIVEN, 0.0, nullptr);
+  if (s != WCNS_OK) return s;
+  hipLaunchKernelGGL(k_copy_amax, dim3(1), dim3(64), 0, c->stream, (const double*)c->step, d_amax,
+                     c->grid.ndim);
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+wcns_status wcns_limit(wcns_ctx* c, int32_t dir, const double* W, const double* G_ho,
+                       const double* G_lo, double* G_out, double* theta, double dt) {
+  if (!c || !W || !G_ho || !G_lo || !G_out) return WCNS_ERR_ARG;
+  if (dir != 0 && !(dir == 1 && c->grid.ndim == 2)) return WCNS_ERR_ARG;
+  if (!(dt >= 0.0) || !isfinite(dt)) return WCNS_ERR_CFL;
+  wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr);
+  if (s != WCNS_OK) return s;
+  KArgs a = c->base;
+  a.W = W;
+  a.P = c->P;
+  long nf = dir == 0 ? (long)(c->grid.nx + 1) * c->grid.ny : (long)c->grid.nx * (c->grid.ny + 1);
+  unsigned g = (unsigned)((nf + 255) / 256);
+  if (c->grid.ndim == 2)
+    hipLaunchKernelGGL(k_limit<true>, dim3(g), dim3(256), 0, c->stream, a, (int)dir, G_ho, G_lo,
+                       G_out, theta);
+  else
+    hipLaunchKernelGGL(k_limit<false>, dim3(g), dim3(256), 0, c->stream, a, (int)dir, G_ho, G_lo,
+                       G_out, theta);
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+wcns_status wcns_check_admissible(wcns_ctx* c, const double* W, long long* n_bad) {
+  if (!c || !W || !n_bad) return WCNS_ERR_ARG;
+  KArgs a = c->base;
+  a.W = W;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->count, 1);
+  LAUNCH_CHECK();
+  if (c->grid.ndim == 2)
+    hipLaunchKernelGGL(k_admissible<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->count);
+  else
+    hipLaunchKernelGGL(k_admissible<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->count);
+  LAUNCH_CHECK();
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, c->count, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *n_bad = (long long)h;
+  return WCNS_OK;
+}
+
+wcns_status wcns_profile(wcns_ctx* c, int32_t enable) {
+  if (!c) return WCNS_ERR_ARG;
+  if (enable && !c->prof_on) {
+    const int cap = 4096;
+    c->ev = (hipEvent_t*)calloc(2 * cap, sizeof(hipEvent_t));
+    c->ev_cls = (int*)calloc(cap, sizeof(int));
+    if (!c->ev || !c->ev_cls) { prof_release(c); return WCNS_ERR_NOMEM; }
+    for (int k = 0; k < 2 * cap; ++k) {
+      if (hipEventCreate(&c->ev[k]) != hipSuccess) {
+        c->prof_cap = k / 2;
+        prof_release(c);
+        return WCNS_ERR_HIP;
+      }
+    }
+    c->prof_cap = cap;
+    c->prof_n = 0;
+    c->prof_on = 1;
+    for (int k = 0; k < WCNS_NPROF; ++k) { c->prof_ms[k] = 0.0; c->prof_cnt[k] = 0; }
+  } else if (!enable && c->prof_on) {
+    wcns_status s = prof_fold(c);
+    prof_release(c);
+    return s;
+  }
+  return WCNS_OK;
+}
+
+wcns_status wcns_profile_read(wcns_ctx* c, double* ms, int64_t* launches, int32_t reset) {
+  if (!c || !ms || !launches) return WCNS_ERR_ARG;
+  wcns_status s = prof_fold(c);
+  if (s != WCNS_OK) return s;
+  for (int k = 0; k < WCNS_NPROF; ++k) {
+    ms[k] = c->prof_ms[k];
+    launches[k] = c->prof_cnt[k];
+    if (reset) { c->prof_ms[k] = 0.0; c->prof_cnt[k] = 0; }
+  }
+  return WCNS_OK;
+}
+
+}  // extern "C"

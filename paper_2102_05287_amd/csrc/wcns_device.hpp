@@ -1,0 +1,329 @@
+// Device-side arithmetic of the PP-WCNS-IS right-hand side on gfx950.
+//
+// Everything here is per-thread FP64 scalar code: the method is stencil and
+// Riemann-solver arithmetic with no dense contraction, so there is no MFMA
+// use.  Each routine cites the passage of the paper that defines it.
+//
+// Sweeps work on a 6-component state rotated into the sweep direction,
+//   X = (a1r1, a2r2, m_n, m_t, E, a1),
+// with m_n the normal and m_t the tangential momentum.  The 1D system (no
+// m_t) is the HAS_T = false instantiation: every tangential term is dropped
+// at compile time.
+//
+// Evaluation order of the primitive recovery, the mixture EOS and the
+// limiters follows the canonical order documented in the design doc so that FP64
+// results track the CPU reference to round-off; FMA contraction is switched
+// off in those routines (the liquid pressure recovery at low pressure
+// cancels ~4 decimal digits, so an extra rounding there is visible).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#pragma clang fp contract(off)
+
+namespace wcns {
+
+// Mixture EOS constants [Sec. 2]: g_k = 1/(gamma_k - 1),
+// q_k = gamma_k pinf_k/(gamma_k - 1).
+struct EosC {
+  double g1, g2, q1, q2;
+};
+
+struct Tol {
+  double eps_arho, eps_alpha, eps_rhoc2;   // Sec. 5.1 limiter tolerances
+  double hs_arho, hs_alpha, hs_rhoc2;      // hard-switch tolerances
+  double weno_eps;                         // IS-weight epsilon (Sec. 4.3)
+};
+
+// Node quantities in the rotated frame: the state and its primitive
+// recovery (u_n, u_t, p, c, rho*ctilde^2).
+struct NodeQ {
+  double w[6];
+  double un, ut, p, c, h;
+};
+
+// ---------------------------------------------------------------- EOS
+__device__ __forceinline__ double mix_gamma(const EosC& e, double a1) {
+#pragma clang fp contract(off)
+  double a2 = 1.0 - a1;
+  return a1 * e.g1 + a2 * e.g2;
+}
+__device__ __forceinline__ double mix_pi(const EosC& e, double a1) {
+#pragma clang fp contract(off)
+  double a2 = 1.0 - a1;
+  return a1 * e.q1 + a2 * e.q2;
+}
+
+// Primitive recovery and mixture sound speed of one state [Sec. 2]:
+// p = (rho e - Pi)/Gamma, pbar_inf = Pi/(1+Gamma), gbar = 1 + 1/Gamma,
+// c^2 = gbar (p + pbar_inf)/rho, h = rho e - pbar_inf.
+template <bool HAS_T>
+__device__ __forceinline__ void recover(const EosC& e, const double X[6], double& un, double& ut,
+                                        double& p, double& c, double& h) {
+#pragma clang fp contract(off)
+  double rho = X[0] + X[1];
+  double irho = 1.0 / rho;
+  un = X[2] * irho;
+  double ke;
+  if (HAS_T) {
+    ut = X[3] * irho;
+    ke = X[2] * un + X[3] * ut;
+  } else {
+    ut = 0.0;
+    ke = X[2] * un;
+  }
+  double rhoe = X[4] - 0.5 * ke;
+  double Gam = mix_gamma(e, X[5]);
+  double Pi = mix_pi(e, X[5]);
+  p = (rhoe - Pi) / Gam;
+  double pinf_bar = Pi / (1.0 + Gam);
+  double gbar = 1.0 + 1.0 / Gam;
+  double c2 = gbar * (p + pinf_bar) * irho;
+  c = sqrt(c2);
+  h = rhoe - pinf_bar;
+}
+
+// rho*ctilde^2 = rho e - pbar_inf of a state [Sec. 5.1]
+template <bool HAS_T>
+__device__ __forceinline__ double rhoc2_tilde(const EosC& e, const double X[6]) {
+#pragma clang fp contract(off)
+  double rho = X[0] + X[1];
+  double irho = 1.0 / rho;
+  double un = X[2] * irho;
+  double ke;
+  if (HAS_T) {
+    double ut = X[3] * irho;
+    ke = X[2] * un + X[3] * ut;
+  } else {
+    ke = X[2] * un;
+  }
+  double rhoe = X[4] - 0.5 * ke;
+  double Gam = mix_gamma(e, X[5]);
+  double Pi = mix_pi(e, X[5]);
+  return rhoe - Pi / (1.0 + Gam);
+}
+
+// Node flux G = F + (0,...,0, a1 u_n) [Sec. 3.2 flux-source form]
+template <bool HAS_T>
+__device__ __forceinline__ void node_flux(const NodeQ& n, double g[6]) {
+#pragma clang fp contract(off)
+  g[0] = n.w[0] * n.un;
+  g[1] = n.w[1] * n.un;
+  g[2] = n.w[2] * n.un + n.p;
+  g[3] = HAS_T ? n.w[3] * n.un : 0.0;
+  g[4] = (n.w[4] + n.p) * n.un;
+  g[5] = n.w[5] * n.un;
+}
+
+// ---------------------------------------------------------------- HLLC
+// [Sec. 3.1 star states with Einfeldt speeds and Batten's contact speed;
+// Sec. 3.2 conservative flux, f_alpha and u* = s*]
+struct HllcOut {
+  double F[5];
+  double fa, ss;
+};
+
+template <bool HAS_T>
+__device__ __forceinline__ void hllc(const NodeQ& L, const NodeQ& R, HllcOut& o) {
+#pragma clang fp contract(off)
+  double rhoL = L.w[0] + L.w[1], rhoR = R.w[0] + R.w[1];
+  double ubar = 0.5 * (L.un + R.un);
+  double cbar = 0.5 * (L.c + R.c);
+  double aL = ubar - cbar, bL = L.un - L.c;
+  double sL = (bL < aL) ? bL : aL;
+  double aR = ubar + cbar, bR = R.un + R.c;
+  double sR = (aR < bR) ? bR : aR;
+  double num = R.p - L.p + rhoL * L.un * (sL - L.un) - rhoR * R.un * (sR - R.un);
+  double den = rhoL * (sL - L.un) - rhoR * (sR - R.un);
+  double ss = num / den;
+  o.ss = ss;
+  double sm = (sL < 0.0) ? sL : 0.0;
+  double sp = (0.0 < sR) ? sR : 0.0;
+  // sgn(s*) with sgn(0) = 0: weights (1 +- sgn)/2
+  double sg = (ss > 0.0) ? 1.0 : ((ss < 0.0) ? -1.0 : 0.0);
+  double wl = (1.0 + sg) * 0.5;
+  double wr = (1.0 - sg) * 0.5;
+  double fl[5], fr[5];
+  {
+    double chi = (sL - L.un) / (sL - ss);
+    double g[6];
+    node_flux<HAS_T>(L, g);
+    double ws[5];
+    ws[0] = chi * L.w[0];
+    ws[1] = chi * L.w[1];
+    ws[2] = chi * rhoL * ss;
+    ws[3] = HAS_T ? chi * rhoL * L.ut : 0.0;
+    ws[4] = chi * (L.w[4] + (ss - L.un) * (rhoL * ss + L.p / (sL - L.un)));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) fl[v] = g[v] + sm * (ws[v] - L.w[v]);
+  }
+  {
+    double chi = (sR - R.un) / (sR - ss);
+    double g[6];
+    node_flux<HAS_T>(R, g);
+    double ws[5];
+    ws[0] = chi * R.w[0];
+    ws[1] = chi * R.w[1];
+    ws[2] = chi * rhoR * ss;
+    ws[3] = HAS_T ? chi * rhoR * R.ut : 0.0;
+    ws[4] = chi * (R.w[4] + (ss - R.un) * (rhoR * ss + R.p / (sR - R.un)));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) fr[v] = g[v] + sp * (ws[v] - R.w[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) o.F[v] = wl * fl[v] + wr * fr[v];
+  o.fa = wl * (L.w[5] * ss) + wr * (R.w[5] * ss);
+}
+
+// ---------------------------------------------------------------- WENO-IS
+// Incremental-stencil nonlinear interpolation [Sec. 4.3], left-biased on
+// (a,b,c,d,e) = (u_{i-2},...,u_{i+2}); right-biased = flipped stencil.
+__device__ __forceinline__ double weno_is(double a, double b, double c, double d, double e,
+                                          double eps) {
+#pragma clang fp contract(off)
+  double u0 = 0.5 * (c + d);
+  double u1 = 0.5 * (-b + 3.0 * c);
+  double u2 = 0.125 * (3.0 * c + 6.0 * d - e);
+  double u3 = 0.125 * (3.0 * a - 10.0 * b + 15.0 * c);
+  double b0 = (c - d) * (c - d);
+  double b1 = (b - c) * (b - c);
+  double t01a = b - 2.0 * c + d, t01b = b - d;
+  double b01 = (13.0 / 12.0) * t01a * t01a + 0.25 * t01b * t01b;
+  double t2a = c - 2.0 * d + e, t2b = 3.0 * c - 4.0 * d + e;
+  double b2 = (13.0 / 12.0) * t2a * t2a + 0.25 * t2b * t2b;
+  double t3a = a - 2.0 * b + c, t3b = a - 4.0 * b + 3.0 * c;
+  double b3 = (13.0 / 12.0) * t3a * t3a + 0.25 * t3b * t3b;
+  double t5a = e - 4.0 * d + 6.0 * c - 4.0 * b + a;
+  double t5b = e - 2.0 * d + 2.0 * b - a;
+  double tau5 = (13.0 / 12.0) * t5a * t5a + 0.25 * t5b * t5b;
+  double r01 = tau5 / (b01 + eps);
+  double eta0 = (15.0 / 32.0) * (1.0 + tau5 / (b0 + eps) * r01);
+  double eta1 = (5.0 / 32.0) * (1.0 + tau5 / (b1 + eps) * r01);
+  double eta2 = (5.0 / 16.0) * (1.0 + tau5 / (b2 + eps));
+  double eta3 = (1.0 / 16.0) * (1.0 + tau5 / (b3 + eps));
+  double sum = eta0 + eta1 + eta2 + eta3;
+  return (eta0 * u0 + eta1 * u1 + eta2 * u2 + eta3 * u3) / sum;
+}
+
+// ---------------------------------------------------------------- limiters
+// theta of the convex blend (1-theta) A + theta B for one test function
+// [Algorithms 1-6]: 0 if q(A) < eps, the root of the linear blend if
+// q(B) < eps, else 1.
+__device__ __forceinline__ double limiter_theta(double qA, double qB, double eps) {
+#pragma clang fp contract(off)
+  if (qA < eps) return 0.0;
+  if (qB < eps) return (qA - eps) / (qA - qB);
+  return 1.0;
+}
+
+// test function k: 0 a1r1, 1 a2r2, 2 a1, 3 1-a1, 4 rho*ctilde^2
+template <bool HAS_T>
+__device__ __forceinline__ double test_fn(const EosC& e, int k, const double X[6]) {
+#pragma clang fp contract(off)
+  switch (k) {
+    case 0: return X[0];
+    case 1: return X[1];
+    case 2: return X[5];
+    case 3: return 1.0 - X[5];
+    default: return rhoc2_tilde<HAS_T>(e, X);
+  }
+}
+
+__device__ __forceinline__ double tol_of(const Tol& t, int k) {
+  return k < 2 ? t.eps_arho : (k < 4 ? t.eps_alpha : t.eps_rhoc2);
+}
+
+template <bool HAS_T>
+__device__ __forceinline__ bool hard_switch_fails(const EosC& e, const Tol& t, const double X[6]) {
+#pragma clang fp contract(off)
+  if (X[0] < t.hs_arho) return true;
+  if (X[1] < t.hs_arho) return true;
+  if (X[5] < t.hs_alpha) return true;
+  if (1.0 - X[5] < t.hs_alpha) return true;
+  if (rhoc2_tilde<HAS_T>(e, X) < t.hs_rhoc2) return true;
+  return false;
+}
+
+// Interpolation limiter, Algorithms 1-3 and the hard switch [Sec. 5.1].
+// A: node state on the side of the interpolated value (W_i for the
+// left-biased value, W_{i+1} for the right-biased one), hA = its
+// rho*ctilde^2; B: interpolated state, limited in place.
+template <bool HAS_T>
+__device__ __forceinline__ void interp_limit(const EosC& e, const Tol& t, const double A[6],
+                                             double hA, double B[6]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double qA = (k == 4) ? hA : test_fn<HAS_T>(e, k, A);
+    double eps = tol_of(t, k);
+    if (qA < eps) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) B[v] = A[v];   // theta = 0
+    } else {
+      double qB = test_fn<HAS_T>(e, k, B);
+      if (qB < eps) {
+        double th = (qA - eps) / (qA - qB);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) B[v] = (1.0 - th) * A[v] + th * B[v];
+      }
+    }
+  }
+  if (hard_switch_fails<HAS_T>(e, t, B)) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) B[v] = A[v];
+  }
+}
+
+// Flux limiter, Algorithms 4-6 and the hard switch [Sec. 5.2].
+// Half-cell states P(G) = W_i - 2 lam (G^- - F_i), M(G) = W_{i+1} +
+// 2 lam (G^+ - F_{i+1}); theta = min(theta+, theta-) per test; both fluxes
+// blended toward the first-order HLLC ones (Hm, Hp).  Returns the smallest
+// theta applied (0 if the hard switch fired).
+template <bool HAS_T>
+__device__ __forceinline__ double flux_limit(const EosC& e, const Tol& t, const double Wl[6],
+                                             const double Wr[6], const double Fl[6],
+                                             const double Fr[6], double lam, const double Hm[6],
+                                             const double Hp[6], double Gm[6], double Gp[6]) {
+#pragma clang fp contract(off)
+  double PH[6], MH[6], PG[6], MG[6];
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    PH[v] = Wl[v] - 2.0 * lam * (Hm[v] - Fl[v]);
+    MH[v] = Wr[v] + 2.0 * lam * (Hp[v] - Fr[v]);
+    PG[v] = Wl[v] - 2.0 * lam * (Gm[v] - Fl[v]);
+    MG[v] = Wr[v] + 2.0 * lam * (Gp[v] - Fr[v]);
+  }
+  double thmin = 1.0;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double eps = tol_of(t, k);
+    double thp = limiter_theta(test_fn<HAS_T>(e, k, PH), test_fn<HAS_T>(e, k, PG), eps);
+    double thm = limiter_theta(test_fn<HAS_T>(e, k, MH), test_fn<HAS_T>(e, k, MG), eps);
+    double th = (thm < thp) ? thm : thp;
+    if (th != 1.0) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        Gp[v] = (1.0 - th) * Hp[v] + th * Gp[v];
+        Gm[v] = (1.0 - th) * Hm[v] + th * Gm[v];
+        PG[v] = Wl[v] - 2.0 * lam * (Gm[v] - Fl[v]);
+        MG[v] = Wr[v] + 2.0 * lam * (Gp[v] - Fr[v]);
+      }
+      thmin = (th < thmin) ? th : thmin;
+    }
+  }
+  if (hard_switch_fails<HAS_T>(e, t, PG) || hard_switch_fails<HAS_T>(e, t, MG)) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
+    thmin = 0.0;
+  }
+  return thmin;
+}
+
+// HCS implied reconstructed flux with psi = 256/175 [Sec. 4.1]:
+// [3072 gt - 505 (g_i + g_{i+1}) + 20 (g_{i-1} + g_{i+2}) - (g_{i-2} + g_{i+3})]/2100
+__device__ __forceinline__ double hcs(double gt, double s01, double s12, double s03) {
+#pragma clang fp contract(off)
+  return (3072.0 * gt - 505.0 * s01 + 20.0 * s12 - s03) / 2100.0;
+}
+
+}  // namespace wcns

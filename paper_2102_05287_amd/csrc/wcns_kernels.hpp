@@ -1,0 +1,610 @@
+// gfx950 kernels of the PP-WCNS-IS right-hand side and the SSP-RK3 step.
+//
+// Per RHS evaluation (2D):
+//   k_node      one thread per cell: primitive recovery (u, v, p, c, rho
+//               ctilde^2) written to scratch, plus per-block maxima of |u|+c
+//               and |v|+c (Sec. 3.3 wave speeds).
+//   k_finalize  one block: global maxima -> dt (CFL), sigma, lambda (Sec. 3.3)
+//               kept on the device so a whole step can be graph-captured.
+//   k_sweep_x   one wave per tile of flattened (row-major) cells; each lane
+//               computes one x-face with the full per-face pipeline and the
+//               flux difference uses a cross-lane shuffle (no LDS).
+//   k_sweep_y   one block = R waves over 64 columns x R y-face rows; every
+//               face is computed once; neighbours exchanged through LDS; the
+//               epilogue sums L_x + L_y and (for a step) applies the SSP-RK3
+//               stage combination.
+//   k_fixup_y   finishes the cell rows that straddle two y-tiles.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wcns_device.hpp"
+
+// No FMA contraction in this file: every operation is rounded as written
+// (see wcns_device.hpp).
+#pragma clang fp contract(off)
+
+namespace wcns {
+
+enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
+enum { OUT_STORE = 0, OUT_RK = 1 };
+constexpr int Y_WAVES = 8;   // y-face rows per y-sweep block
+
+struct KArgs {
+  int32_t nx, ny, nv, tile_x;     // tile_x: cells per x-sweep wave
+  double dx, dy;
+  int32_t bc[4];
+  int32_t interp_limiter, flux_limiter, scheme, pad;
+  EosC eos;
+  Tol tol;
+  const double* W;       // state differentiated
+  const double* P;       // node primitives of W: [5][ny][nx] (u, v, p, c, h)
+  const double* dirW;    // Dirichlet ghost states [4][6] (unrotated 6-comp)
+  const double* dirP;    // their primitives [4][5]
+  const double* step;    // [0] dt, [1] lam_x, [2] lam_y, [3] amax_x, [4] amax_y
+  const double* Lx;      // x-part of L (read by the y-sweep)
+  double* Lout;          // x-sweep output (L_x in 2D, full L in 1D)
+  double* out;           // final output (L or next stage state)
+  const double* Un;      // state at the start of the step (RK epilogue)
+  double* edge;          // y-tile boundary fluxes [nbr][2][6][nx]
+  double ca, cb;         // RK: out = ca*Un + cb*(W + dt*L)
+  int32_t out_mode, pad2;
+};
+
+// ------------------------------------------------------------------ nodes
+// Ghost mapping along a line of n cells [3 ghost layers; periodic, constant
+// extrapolation, reflective, Dirichlet].  Returns the source cell or -1 for
+// Dirichlet; flip = the wall-normal momentum changes sign.
+__device__ __forceinline__ int ghost_src(int g, int n, int bc_lo, int bc_hi, bool& flip) {
+  flip = false;
+  if (g >= 0 && g < n) return g;
+  int bc = g < 0 ? bc_lo : bc_hi;
+  if (bc == BC_PERIODIC) { int r = g % n; return r < 0 ? r + n : r; }
+  if (bc == BC_EXTRAP) return g < 0 ? 0 : n - 1;
+  if (bc == BC_REFLECT) { flip = true; return g < 0 ? -1 - g : 2 * n - 1 - g; }
+  return -1;
+}
+
+// Node (dir, line, g) in the frame rotated into direction dir.
+template <bool HAS_T>
+__device__ __forceinline__ void load_node(const KArgs& a, int dir, int line, int g, NodeQ& q) {
+  const int n = dir == 0 ? a.nx : a.ny;
+  bool flip;
+  int s = ghost_src(g, n, a.bc[2 * dir], a.bc[2 * dir + 1], flip);
+  double Y[6], u, v;
+  if (s < 0) {
+    const int side = 2 * dir + (g < 0 ? 0 : 1);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Y[k] = a.dirW[side * 6 + k];
+    u = a.dirP[side * 5 + 0]; v = a.dirP[side * 5 + 1];
+    q.p = a.dirP[side * 5 + 2]; q.c = a.dirP[side * 5 + 3]; q.h = a.dirP[side * 5 + 4];
+  } else {
+    const long N = (long)a.nx * a.ny;
+    const long o = dir == 0 ? (long)line * a.nx + s : (long)s * a.nx + line;
+    if (HAS_T) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) Y[k] = a.W[k * N + o];
+      v = a.P[1 * N + o];
+    } else {
+      Y[0] = a.W[o]; Y[1] = a.W[N + o]; Y[2] = a.W[2 * N + o]; Y[3] = 0.0;
+      Y[4] = a.W[3 * N + o]; Y[5] = a.W[4 * N + o];
+      v = 0.0;
+    }
+    u = a.P[o];
+    q.p = a.P[2 * N + o]; q.c = a.P[3 * N + o]; q.h = a.P[4 * N + o];
+  }
+  q.w[0] = Y[0]; q.w[1] = Y[1]; q.w[4] = Y[4]; q.w[5] = Y[5];
+  if (dir == 0) { q.w[2] = Y[2]; q.w[3] = Y[3]; q.un = u; q.ut = v; }
+  else { q.w[2] = Y[3]; q.w[3] = Y[2]; q.un = v; q.ut = u; }
+  if (flip) { q.w[2] = -q.w[2]; q.un = -q.un; }
+}
+
+// ------------------------------------------------------------------ face
+// One face i+1/2 of a sweep: WCNS steps 1-9 [Sec. 4.2] with the
+// interpolation limiter [Sec. 5.1] and the flux limiter [Sec. 5.2].
+// Stencil nodes i-2 .. i+3 are g0 .. g0+5 along the line.
+template <bool HAS_T>
+__device__ __forceinline__ double face_flux(const KArgs& a, int dir, int line, int g0, double lam,
+                                            double Gm[6], double Gp[6]) {
+  const EosC& e = a.eos;
+  NodeQ nl, nr;
+  load_node<HAS_T>(a, dir, line, g0 + 2, nl);
+  load_node<HAS_T>(a, dir, line, g0 + 3, nr);
+  // first-order HLLC flux from W_i, W_{i+1} and its split [Sec. 3.2]
+  HllcOut h1;
+  hllc<HAS_T>(nl, nr, h1);
+  double Hm[6], Hp[6];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) { Hm[v] = h1.F[v]; Hp[v] = h1.F[v]; }
+  {
+    Hm[5] = h1.fa - nl.w[5] * h1.ss;
+    Hp[5] = h1.fa - nr.w[5] * h1.ss;
+  }
+  if (a.scheme == 1) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
+    return 0.0;
+  }
+  // face averages and projection constants [Sec. 4.2; App. A]
+  double fa1, fa2, frho, fc, k1, k2;
+  {
+    fa1 = 0.5 * (nl.w[0] + nr.w[0]);
+    fa2 = 0.5 * (nl.w[1] + nr.w[1]);
+    frho = 0.5 * ((nl.w[0] + nl.w[1]) + (nr.w[0] + nr.w[1]));
+    fc = 0.5 * (nl.c + nr.c);
+    k1 = 1.0 / (frho * fc);
+    k2 = 1.0 / (frho * fc * fc);
+  }
+  // characteristic projection U = R^{-1} V and IS-WENO per field
+  double UL[6], UR[6];
+  {
+    double s0[6], s5[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      NodeQ q;
+      load_node<HAS_T>(a, dir, line, g0 + m, q);
+      s0[m] = q.un - q.p * k1;
+      s5[m] = q.un + q.p * k1;
+    }
+    UL[0] = weno_is(s0[0], s0[1], s0[2], s0[3], s0[4], a.tol.weno_eps);
+    UR[0] = weno_is(s0[5], s0[4], s0[3], s0[2], s0[1], a.tol.weno_eps);
+    UL[5] = weno_is(s5[0], s5[1], s5[2], s5[3], s5[4], a.tol.weno_eps);
+    UR[5] = weno_is(s5[5], s5[4], s5[3], s5[2], s5[1], a.tol.weno_eps);
+  }
+  {
+    double s1[6], s2[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      NodeQ q;
+      load_node<HAS_T>(a, dir, line, g0 + m, q);
+      s1[m] = q.w[0] - fa1 * q.p * k2;
+      s2[m] = q.w[1] - fa2 * q.p * k2;
+    }
+    UL[1] = weno_is(s1[0], s1[1], s1[2], s1[3], s1[4], a.tol.weno_eps);
+    UR[1] = weno_is(s1[5], s1[4], s1[3], s1[2], s1[1], a.tol.weno_eps);
+    UL[2] = weno_is(s2[0], s2[1], s2[2], s2[3], s2[4], a.tol.weno_eps);
+    UR[2] = weno_is(s2[5], s2[4], s2[3], s2[2], s2[1], a.tol.weno_eps);
+  }
+  {
+    double s3[6], s4[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      NodeQ q;
+      load_node<HAS_T>(a, dir, line, g0 + m, q);
+      s3[m] = HAS_T ? q.ut : 0.0;
+      s4[m] = q.w[5];
+    }
+    if (HAS_T) {
+      UL[3] = weno_is(s3[0], s3[1], s3[2], s3[3], s3[4], a.tol.weno_eps);
+      UR[3] = weno_is(s3[5], s3[4], s3[3], s3[2], s3[1], a.tol.weno_eps);
+    } else {
+      UL[3] = 0.0; UR[3] = 0.0;
+    }
+    UL[4] = weno_is(s4[0], s4[1], s4[2], s4[3], s4[4], a.tol.weno_eps);
+    UR[4] = weno_is(s4[5], s4[4], s4[3], s4[2], s4[1], a.tol.weno_eps);
+  }
+  // back-projection V = R U, then V -> W [App. A; Sec. 2]
+  double WL[6], WR[6];
+  {
+    double twoc = 2.0 * fc;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double* U = side == 0 ? UL : UR;
+      double* X = side == 0 ? WL : WR;
+      double d = U[5] - U[0];
+      double a1r1 = U[1] + fa1 * d / twoc;
+      double a2r2 = U[2] + fa2 * d / twoc;
+      double un = 0.5 * (U[0] + U[5]);
+      double ut = U[3];
+      double p = 0.5 * frho * fc * d;
+      double a1 = U[4];
+      double rho = a1r1 + a2r2;
+      X[0] = a1r1;
+      X[1] = a2r2;
+      X[2] = rho * un;
+      X[3] = HAS_T ? rho * ut : 0.0;
+      double ke = HAS_T ? (un * un + ut * ut) : un * un;
+      X[4] = mix_gamma(e, a1) * p + mix_pi(e, a1) + 0.5 * rho * ke;
+      X[5] = a1;
+    }
+  }
+  if (a.interp_limiter) {
+    interp_limit<HAS_T>(e, a.tol, nl.w, nl.h, WL);
+    interp_limit<HAS_T>(e, a.tol, nr.w, nr.h, WR);
+  }
+  // high-order midpoint flux from the limited states [WCNS step 6]
+  HllcOut h2;
+  {
+    NodeQ tl, tr;
+#pragma unroll
+    for (int v = 0; v < 6; ++v) { tl.w[v] = WL[v]; tr.w[v] = WR[v]; }
+    recover<HAS_T>(e, tl.w, tl.un, tl.ut, tl.p, tl.c, tl.h);
+    recover<HAS_T>(e, tr.w, tr.un, tr.ut, tr.p, tr.c, tr.h);
+    hllc<HAS_T>(tl, tr, h2);
+  }
+  // HCS reconstruction of flux and velocity [Sec. 4.1; WCNS steps 7-8]
+  double Gh[6], uh;
+  {
+    double gt[6] = {h2.F[0], h2.F[1], h2.F[2], h2.F[3], h2.F[4], h2.fa};
+    double s01[7], s12[7], s03[7];
+#pragma unroll
+    for (int pr = 0; pr < 3; ++pr) {
+      // pairs (i, i+1), (i-1, i+2), (i-2, i+3)
+      const int ma = 2 - pr, mb = 3 + pr;
+      NodeQ qa, qb;
+      load_node<HAS_T>(a, dir, line, g0 + ma, qa);
+      load_node<HAS_T>(a, dir, line, g0 + mb, qb);
+      double ga[6], gb[6];
+      node_flux<HAS_T>(qa, ga);
+      node_flux<HAS_T>(qb, gb);
+      double* s = pr == 0 ? s01 : (pr == 1 ? s12 : s03);
+#pragma unroll
+      for (int v = 0; v < 6; ++v) s[v] = ga[v] + gb[v];
+      s[6] = qa.un + qb.un;
+    }
+#pragma unroll
+    for (int v = 0; v < 6; ++v) Gh[v] = hcs(gt[v], s01[v], s12[v], s03[v]);
+    uh = hcs(h2.ss, s01[6], s12[6], s03[6]);
+  }
+  // split fluxes G^{-+} [Sec. 3.2, WCNS step 9]
+#pragma unroll
+  for (int v = 0; v < 5; ++v) { Gm[v] = Gh[v]; Gp[v] = Gh[v]; }
+  {
+    Gm[5] = Gh[5] - nl.w[5] * uh;
+    Gp[5] = Gh[5] - nr.w[5] * uh;
+  }
+  if (a.flux_limiter) {
+    double gl[6], gr[6];
+    node_flux<HAS_T>(nl, gl);
+    node_flux<HAS_T>(nr, gr);
+    gl[5] = 0.0;
+    gr[5] = 0.0;
+    return flux_limit<HAS_T>(e, a.tol, nl.w, nr.w, gl, gr, lam, Hm, Hp, Gm, Gp);
+  }
+  return 1.0;
+}
+
+// map rotated flux component v of direction dir to the state index
+__device__ __forceinline__ int state_index(int dir, int v, bool has_t) {
+  if (!has_t) return v < 3 ? v : v - 1;      // 1D: (0,1,2,-,3,4)
+  if (dir == 1 && (v == 2 || v == 3)) return 5 - v;
+  return v;
+}
+
+// final write of one cell: L (store) or the SSP-RK3 combination
+__device__ __forceinline__ void write_cell(const KArgs& a, double* dst, long idx, long N, int k,
+                                           double L) {
+  if (a.out_mode == OUT_STORE) {
+    dst[k * N + idx] = L;
+  } else {
+    double dt = a.step[0];
+    dst[k * N + idx] = a.ca * a.Un[k * N + idx] + a.cb * (a.W[k * N + idx] + dt * L);
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+template <bool HAS_T>
+__global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partial) {
+  const long N = (long)a.nx * a.ny;
+  double mx = 0.0, my = 0.0;
+  for (long o = (long)blockIdx.x * blockDim.x + threadIdx.x; o < N;
+       o += (long)gridDim.x * blockDim.x) {
+    double X[6];
+    if (HAS_T) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) X[k] = a.W[k * N + o];
+    } else {
+      X[0] = a.W[o]; X[1] = a.W[N + o]; X[2] = a.W[2 * N + o]; X[3] = 0.0;
+      X[4] = a.W[3 * N + o]; X[5] = a.W[4 * N + o];
+    }
+    double un, ut, p, c, h;
+    recover<HAS_T>(a.eos, X, un, ut, p, c, h);
+    P[o] = un; P[N + o] = ut; P[2 * N + o] = p; P[3 * N + o] = c; P[4 * N + o] = h;
+    double sx = fabs(un) + c, sy = fabs(ut) + c;
+    mx = fmax(mx, sx);
+    my = fmax(my, sy);
+  }
+  // wavefront max via cross-lane shuffles, then across the 4 waves in LDS
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    my = fmax(my, __shfl_xor(my, off, 64));
+  }
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = mx; red[1][w] = my; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = red[0][0], a1v = red[1][0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { a0 = fmax(a0, red[0][k]); a1v = fmax(a1v, red[1][k]); }
+    partial[2 * blockIdx.x] = a0;
+    partial[2 * blockIdx.x + 1] = a1v;
+  }
+}
+
+// primitives of the (up to 4) Dirichlet ghost states
+template <bool HAS_T>
+__global__ void k_dirichlet_prims(KArgs a, double* dirP) {
+  int s = threadIdx.x;
+  if (s >= 4) return;
+  double X[6];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) X[k] = a.dirW[s * 6 + k];
+  double un, ut, p, c, h;
+  recover<HAS_T>(a.eos, X, un, ut, p, c, h);
+  dirP[s * 5 + 0] = un; dirP[s * 5 + 1] = ut; dirP[s * 5 + 2] = p;
+  dirP[s * 5 + 3] = c; dirP[s * 5 + 4] = h;
+}
+
+enum { DT_GIVEN = 0, DT_CFL = 1, DT_KEEP = 2 };
+
+// Global maxima -> dt and lambda [Sec. 3.3]:
+//   dt = CFL/(tau_x + tau_y), tau = max(|u|+c)/dx (1D: CFL dx/max(|u|+c)),
+//   sigma_x = tau_x/(tau_x + tau_y), lambda_x = dt/(dx sigma_x)  (1D: dt/dx).
+__global__ __launch_bounds__(256) void k_finalize(const double* partial, int nblk, int ndim,
+                                                  double dx, double dy, double cfl, int dt_mode,
+                                                  double dt_in, double* step, double* dt_used) {
+  double mx = 0.0, my = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    mx = fmax(mx, partial[2 * b]);
+    my = fmax(my, partial[2 * b + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    my = fmax(my, __shfl_xor(my, off, 64));
+  }
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = mx; red[1][w] = my; }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 1; k < 4; ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
+  mx = fmax(mx, red[0][0]);
+  my = fmax(my, red[1][0]);
+  double dt;
+  if (dt_mode == DT_GIVEN) dt = dt_in;
+  else if (dt_mode == DT_KEEP) dt = step[0];
+  else dt = ndim == 1 ? cfl * dx / mx : cfl / (mx / dx + my / dy);
+  step[0] = dt;
+  if (ndim == 1) {
+    step[1] = dt / dx;
+    step[2] = 0.0;
+  } else {
+    double tx = mx / dx, ty = my / dy;
+    double sx = tx / (tx + ty), sy = ty / (tx + ty);
+    step[1] = dt / (dx * sx);
+    step[2] = dt / (dy * sy);
+  }
+  step[3] = mx;
+  step[4] = my;
+  if (dt_used) *dt_used = dt;
+}
+
+// x-sweep: one wave per tile of tile_x flattened cells.  Lane t < T owns the
+// left face of cell c0+t; lanes T.. own the right face of each row segment's
+// last cell.  Cell c0+t then takes G^+ of its own face and G^- of the lane
+// that owns its right face.
+template <bool HAS_T>
+__global__ __launch_bounds__(64) void k_sweep_x(KArgs a) {
+  const int lane = threadIdx.x;
+  const int nx = a.nx;
+  const long N = (long)nx * a.ny;
+  const int T = a.tile_x;
+  const long c0 = (long)blockIdx.x * T;
+  const long c1 = (c0 + T < N ? c0 + T : N) - 1;
+  const int j0 = (int)(c0 / nx), j1 = (int)(c1 / nx);
+  int fj = 0, fk = 0;
+  bool active = false;
+  if (lane < T) {
+    long c = c0 + lane;
+    if (c <= c1) { fj = (int)(c / nx); fk = (int)(c % nx); active = true; }
+  } else {
+    int r = lane - T;
+    if (j0 + r <= j1) {
+      fj = j0 + r;
+      long last = (fj == j1) ? c1 : (long)fj * nx + nx - 1;
+      fk = (int)(last % nx) + 1;
+      active = true;
+    }
+  }
+  double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
+  if (active) face_flux<HAS_T>(a, 0, fj, fk - 3, a.step[1], Gm, Gp);
+  // lane holding the right face of my cell
+  int src = lane;
+  const long c = c0 + lane;
+  const bool owns_cell = lane < T && c <= c1;
+  if (owns_cell) {
+    const int cj = (int)(c / nx);
+    src = (c == c1 || (c % nx) == nx - 1) ? T + (cj - j0) : lane + 1;
+  }
+  double Gr[6];
+#pragma unroll
+  for (int v = 0; v < 6; ++v) Gr[v] = __shfl(Gm[v], src, 64);
+  if (!owns_cell) return;
+  double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;
+  const int nvs = HAS_T ? 6 : 5;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    if (!HAS_T && v == 3) continue;
+    double L;
+    {
+      L = -(Gr[v] - Gp[v]) / a.dx;
+    }
+    const int k = state_index(0, v, HAS_T);
+    if (HAS_T) {
+      dst[k * N + c] = L;   // L_x; the y-sweep finishes the cell
+    } else {
+      write_cell(a, a.out, c, N, k, L);
+    }
+  }
+  (void)nvs;
+}
+
+// y-sweep: block = Y_WAVES waves; wave w computes y-face row k = kb + w for
+// 64 columns.  Cell row kb + w (w < Y_WAVES-1) uses G^+ of its own face and
+// G^- of face row kb + w + 1 (through LDS).  The last face row of the tile
+// leaves G^+ in the edge buffer and the first one G^-; k_fixup_y finishes the
+// cell row in between.
+__global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
+  __shared__ double sGm[Y_WAVES][6][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int kb = blockIdx.y * Y_WAVES;
+  const int k = kb + w;                   // my face row (between cells k-1 and k)
+  const int nx = a.nx, ny = a.ny;
+  const long N = (long)nx * ny;
+  const bool active = i < nx && k <= ny;
+  double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
+  if (active) face_flux<true>(a, 1, i, k - 3, a.step[2], Gm, Gp);
+#pragma unroll
+  for (int v = 0; v < 6; ++v) sGm[w][v][lane] = Gm[v];
+  // tile edges for the fixup of the straddling cell rows
+  if (active) {
+    double* e = a.edge + (long)blockIdx.y * 12 * nx;
+    if (w == 0) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
+    }
+    if (w == Y_WAVES - 1 || k == ny) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
+    }
+  }
+  __syncthreads();
+  const int j = k;   // cell row between face rows k and k+1
+  if (!active || w == Y_WAVES - 1 || j >= ny) return;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    double L;
+    {
+      double Ly = -(sGm[w + 1][v][lane] - Gp[v]) / a.dy;
+      const int s = state_index(1, v, true);
+      L = a.Lx[s * N + (long)j * nx + i] + Ly;
+    }
+    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
+  }
+}
+
+// cell rows j = (b+1)*Y_WAVES - 1 between y-tile b and b+1
+__global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
+  const int nx = a.nx, ny = a.ny;
+  const long N = (long)nx * ny;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = (int)(t / nx), i = (int)(t % nx);
+  if (b >= nbr - 1) return;
+  const int j = (b + 1) * Y_WAVES - 1;
+  if (j >= ny) return;
+  const double* lo = a.edge + (long)b * 12 * nx + 6 * nx;       // G^+ of face row j
+  const double* hi = a.edge + (long)(b + 1) * 12 * nx;          // G^- of face row j+1
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    double L;
+    {
+      double Ly = -(hi[v * nx + i] - lo[v * nx + i]) / a.dy;
+      const int s = state_index(1, v, true);
+      L = a.Lx[s * N + (long)j * nx + i] + Ly;
+    }
+    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
+  }
+}
+
+// Stand-alone flux limiter over the faces of one direction.
+template <bool HAS_T>
+__global__ __launch_bounds__(256) void k_limit(KArgs a, int dir, const double* Gho,
+                                               const double* Glo, double* Gout, double* theta) {
+  const int nx = a.nx, ny = a.ny;
+  const long nf = dir == 0 ? (long)(nx + 1) * ny : (long)nx * (ny + 1);
+  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int line, k;
+  if (dir == 0) { line = (int)(f / (nx + 1)); k = (int)(f % (nx + 1)); }
+  else { k = (int)(f / nx); line = (int)(f % nx); }
+  NodeQ nl, nr;
+  load_node<HAS_T>(a, dir, line, k - 1, nl);
+  load_node<HAS_T>(a, dir, line, k, nr);
+  const int nv = HAS_T ? 6 : 5;
+  double Gh[6], Hh[6];
+  double uh = Gho[(long)nv * nf + f], uhh = Glo[(long)nv * nf + f];
+  for (int v = 0; v < 6; ++v) {
+    if (!HAS_T && v == 3) { Gh[v] = 0.0; Hh[v] = 0.0; continue; }
+    const int s = state_index(dir, v, HAS_T);
+    Gh[v] = Gho[(long)s * nf + f];
+    Hh[v] = Glo[(long)s * nf + f];
+  }
+  double Gm[6], Gp[6], Hm[6], Hp[6];
+  for (int v = 0; v < 5; ++v) { Gm[v] = Gh[v]; Gp[v] = Gh[v]; Hm[v] = Hh[v]; Hp[v] = Hh[v]; }
+  {
+    Gm[5] = Gh[5] - nl.w[5] * uh;
+    Gp[5] = Gh[5] - nr.w[5] * uh;
+    Hm[5] = Hh[5] - nl.w[5] * uhh;
+    Hp[5] = Hh[5] - nr.w[5] * uhh;
+  }
+  double gl[6], gr[6];
+  node_flux<HAS_T>(nl, gl);
+  node_flux<HAS_T>(nr, gr);
+  gl[5] = 0.0;
+  gr[5] = 0.0;
+  double lam = a.step[1 + dir];
+  double th = flux_limit<HAS_T>(a.eos, a.tol, nl.w, nr.w, gl, gr, lam, Hm, Hp, Gm, Gp);
+  for (int v = 0; v < 6; ++v) {
+    if (!HAS_T && v == 3) continue;
+    const int s = state_index(dir, v, HAS_T);
+    Gout[(long)s * nf + f] = Gm[v];
+    Gout[(long)(nv + s) * nf + f] = Gp[v];
+  }
+  if (theta) theta[f] = th;
+}
+
+// V (a1r1, a2r2, u, [v], p, a1) -> W  [Sec. 2 mixture EOS]
+template <bool HAS_T>
+__global__ __launch_bounds__(256) void k_prim_to_cons(KArgs a, const double* V, double* W) {
+  const long N = (long)a.nx * a.ny;
+  const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= N) return;
+  const int nv = HAS_T ? 6 : 5;
+  double a1r1 = V[o], a2r2 = V[N + o], u = V[2 * N + o];
+  double v = HAS_T ? V[3 * N + o] : 0.0;
+  double p = V[(nv - 2) * N + o], a1 = V[(nv - 1) * N + o];
+  double rho = a1r1 + a2r2;
+  W[o] = a1r1;
+  W[N + o] = a2r2;
+  W[2 * N + o] = rho * u;
+  if (HAS_T) W[3 * N + o] = rho * v;
+  double ke = HAS_T ? (u * u + v * v) : u * u;
+  W[(nv - 2) * N + o] = mix_gamma(a.eos, a1) * p + mix_pi(a.eos, a1) + 0.5 * rho * ke;
+  W[(nv - 1) * N + o] = a1;
+}
+
+// Admissible set G [Sec. 2]; NaN fails every comparison and counts as bad.
+template <bool HAS_T>
+__global__ __launch_bounds__(256) void k_admissible(KArgs a, unsigned long long* count) {
+  const long N = (long)a.nx * a.ny;
+  unsigned long long bad = 0;
+  for (long o = (long)blockIdx.x * blockDim.x + threadIdx.x; o < N;
+       o += (long)gridDim.x * blockDim.x) {
+    double X[6];
+    if (HAS_T) {
+      for (int k = 0; k < 6; ++k) X[k] = a.W[k * N + o];
+    } else {
+      X[0] = a.W[o]; X[1] = a.W[N + o]; X[2] = a.W[2 * N + o]; X[3] = 0.0;
+      X[4] = a.W[3 * N + o]; X[5] = a.W[4 * N + o];
+    }
+    double h = rhoc2_tilde<HAS_T>(a.eos, X);
+    bool ok = X[5] >= 0.0 && X[5] <= 1.0 && X[0] >= 0.0 && X[1] >= 0.0 && h > 0.0;
+    bad += ok ? 0ull : 1ull;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
+  if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  int t = threadIdx.x;
+  if (t < n) p[t] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_copy_amax(const double* step, double* out, int ndim) {
+  if (threadIdx.x == 0) { out[0] = step[3]; if (ndim == 2) out[1] = step[4]; }
+}
+
+}  // namespace wcns

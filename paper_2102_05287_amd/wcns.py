@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libwcns.so (the C ABI in include/wcns.h).
+
+Argument marshalling only: every step of the right-hand side, the limiter
+and the Runge-Kutta step runs in the library's HIP kernels.  Device buffers
+are torch tensors on the ROCm device (torch's "cuda" device); their
+``data_ptr()`` is passed straight to the C ABI, and calls are enqueued on
+the current torch stream unless a stream is given.
+
+The library must have been built (``python -m paper_2102_05287_amd.build``
+or ``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwcns.so")
+
+WCNS_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "fluids violate Lemma 1", -3: "out of memory",
+          -4: "HIP error", -5: "inadmissible state", -6: "invalid time step"}
+BC_PERIODIC, BC_EXTRAP, BC_REFLECT, BC_DIRICHLET = 0, 1, 2, 3
+FP64, FP32_BULK = 0, 1
+SCHEME_PPWCNSIS, SCHEME_HLLC1 = 0, 1
+
+
+class WcnsError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class _Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("pad", C.c_int32),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("bc", C.c_int32 * 4),
+                ("dirichlet", (C.c_double * 6) * 4)]
+
+
+class _Eos(C.Structure):
+    _fields_ = [("gamma", C.c_double * 2), ("pinf", C.c_double * 2)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("eps_arho", C.c_double), ("eps_alpha", C.c_double), ("eps_rhoc2", C.c_double),
+                ("hs_arho", C.c_double), ("hs_alpha", C.c_double), ("hs_rhoc2", C.c_double),
+                ("weno_eps", C.c_double), ("cfl", C.c_double),
+                ("interp_limiter", C.c_int32), ("flux_limiter", C.c_int32),
+                ("scheme", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
+           "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
+           "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
+           "wcns_status_str"]
+PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other"]
+
+
+def lib():
+    """Load libwcns.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m "
+                              "paper_2102_05287_amd.build` (no CPU fallback exists)")
+        # load torch first so the library binds to the HIP runtime torch
+        # already uses (same soname) instead of a second copy
+        import torch  # noqa: F401
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.c_void_p
+        L.wcns_params_default.argtypes = [C.POINTER(_Params)]
+        L.wcns_create.argtypes = [C.POINTER(_Grid), C.POINTER(_Eos), C.POINTER(_Params), C.c_int32,
+                                  vp, C.POINTER(vp)]
+        L.wcns_destroy.argtypes = [vp]
+        L.wcns_set_stream.argtypes = [vp, vp]
+        L.wcns_prim_to_cons.argtypes = [vp, dp, dp]
+        L.wcns_rhs.argtypes = [vp, dp, dp, C.c_double]
+        L.wcns_limit.argtypes = [vp, C.c_int32, dp, dp, dp, dp, dp, C.c_double]
+        L.wcns_max_wavespeed.argtypes = [vp, dp, dp]
+        L.wcns_ssprk3_step.argtypes = [vp, dp, C.c_double, dp]
+        L.wcns_check_admissible.argtypes = [vp, dp, C.POINTER(C.c_longlong)]
+        L.wcns_profile.argtypes = [vp, C.c_int32]
+        L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+        L.wcns_status_str.argtypes = [C.c_int]
+        L.wcns_status_str.restype = C.c_char_p
+        for name in EXPORTS:
+            if name != "wcns_status_str":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code, where):
+    if code != WCNS_OK:
+        raise WcnsError(code, where)
+
+
+def default_params(**overrides) -> _Params:
+    p = _Params()
+    _check(lib().wcns_params_default(C.byref(p)), "wcns_params_default")
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One grid + fluids + options, bound to a device context.
+
+    grid: ndim, nx, ny, x0, x1, y0, y1, bc (4 kinds), dirichlet (4 host
+    conservative states, only for Dirichlet sides)."""
+
+    def __init__(self, ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4,
+                 gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), precision=FP64, stream=None,
+                 dirichlet=None, **params):
+        import torch
+        g = _Grid()
+        g.ndim, g.nx, g.ny = ndim, nx, ny
+        g.x0, g.x1, g.y0, g.y1 = x0, x1, y0, y1
+        for k in range(4):
+            g.bc[k] = int(bc[k])
+            if dirichlet is not None and dirichlet[k] is not None:
+                for v, val in enumerate(dirichlet[k]):
+                    g.dirichlet[k][v] = float(val)
+        e = _Eos()
+        e.gamma[0], e.gamma[1] = gamma
+        e.pinf[0], e.pinf[1] = pinf
+        p = default_params(**params)
+        self.ndim, self.nx, self.ny = ndim, nx, ny
+        self.nvar = 5 if ndim == 1 else 6
+        self.params = p
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self._stream = stream
+        ctx = C.c_void_p()
+        _check(lib().wcns_create(C.byref(g), C.byref(e), C.byref(p), int(precision),
+                                 C.c_void_p(stream), C.byref(ctx)), "wcns_create")
+        self._ctx = ctx
+
+    @classmethod
+    def from_spec(cls, spec, **kw):
+        """Build from a seeded ProblemSpec (paper_2102_05287_amd.problems)."""
+        return cls(spec.ndim, spec.nx, spec.ny, spec.x0, spec.x1, spec.y0, spec.y1,
+                   bc=spec.bc, gamma=spec.gamma, pinf=spec.pinf, cfl=spec.cfl, **kw)
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            lib().wcns_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        self._stream = stream
+        _check(lib().wcns_set_stream(self._ctx, C.c_void_p(stream)), "wcns_set_stream")
+
+    # ----------------------------------------------------------- buffers
+    def empty_state(self, dtype=None):
+        import torch
+        return torch.empty((self.nvar, self.ny, self.nx), dtype=torch.float64, device="cuda")
+
+    def _chk(self, t):
+        import torch
+        assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "device f64 contiguous"
+        assert t.numel() == self.nvar * self.nx * self.ny, "shape [nvar][ny][nx]"
+
+    # ----------------------------------------------------------- entry points
+    def prim_to_cons(self, V, W=None):
+        self._chk(V)
+        W = self.empty_state() if W is None else W
+        self._chk(W)
+        _check(lib().wcns_prim_to_cons(self._ctx, _ptr(V), _ptr(W)), "wcns_prim_to_cons")
+        return W
+
+    def rhs(self, W, dWdt=None, dt=0.0):
+        self._chk(W)
+        dWdt = self.empty_state() if dWdt is None else dWdt
+        self._chk(dWdt)
+        _check(lib().wcns_rhs(self._ctx, _ptr(W), _ptr(dWdt), float(dt)), "wcns_rhs")
+        return dWdt
+
+    def step(self, W, dt=0.0, dt_used=None):
+        """One SSP-RK3 step in place on W; dt <= 0 selects the CFL step.
+        dt_used: optional device float64 tensor of >= 1 element."""
+        self._chk(W)
+        _check(lib().wcns_ssprk3_step(self._ctx, _ptr(W), float(dt), _ptr(dt_used)),
+               "wcns_ssprk3_step")
+        return W
+
+    def max_wavespeed(self, W, out=None):
+        import torch
+        self._chk(W)
+        out = torch.zeros(2, dtype=torch.float64, device="cuda") if out is None else out
+        _check(lib().wcns_max_wavespeed(self._ctx, _ptr(W), _ptr(out)), "wcns_max_wavespeed")
+        return out
+
+    def limit(self, direction, W, G_ho, G_lo, dt, G_out=None, theta=None):
+        import torch
+        self._chk(W)
+        nf = (self.nx + 1) * self.ny if direction == 0 else self.nx * (self.ny + 1)
+        if G_out is None:
+            G_out = torch.empty((2, self.nvar, nf), dtype=torch.float64, device="cuda")
+        _check(lib().wcns_limit(self._ctx, int(direction), _ptr(W), _ptr(G_ho), _ptr(G_lo),
+                                _ptr(G_out), _ptr(theta), float(dt)), "wcns_limit")
+        return G_out
+
+    def count_inadmissible(self, W) -> int:
+        self._chk(W)
+        n = C.c_longlong(0)
+        _check(lib().wcns_check_admissible(self._ctx, _ptr(W), C.byref(n)), "wcns_check_admissible")
+        return int(n.value)
+
+    # ----------------------------------------------------------- measurement
+    def profile(self, enable: bool):
+        _check(lib().wcns_profile(self._ctx, int(bool(enable))), "wcns_profile")
+
+    def profile_read(self, reset: bool = True) -> dict:
+        ms = (C.c_double * len(PROF_CLASSES))()
+        n = (C.c_int64 * len(PROF_CLASSES))()
+        _check(lib().wcns_profile_read(self._ctx, ms, n, int(bool(reset))), "wcns_profile_read")
+        return {k: (ms[i], n[i]) for i, k in enumerate(PROF_CLASSES)}

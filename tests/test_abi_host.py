@@ -1,0 +1,87 @@
+"""CPU-side checks of the C ABI library: it loads, exports every entry point
+declared in include/wcns.h, and its host-side validation rejects bad
+arguments before touching a device.  No kernel is launched here."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from helpers import ROOT
+from paper_2102_05287_amd import wcns
+
+HEADER = os.path.join(ROOT, "include", "wcns.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wcns_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = wcns.lib()
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_params_default_matches_paper():
+    p = wcns.default_params()
+    assert (p.eps_arho, p.eps_alpha, p.eps_rhoc2) == (1e-10, 1e-10, 1e-8)
+    assert (p.hs_arho, p.hs_alpha, p.hs_rhoc2) == (1e-11, 1e-11, 1e-9)
+    assert p.cfl == 0.5 and p.interp_limiter == 1 and p.flux_limiter == 1 and p.scheme == 0
+    assert wcns.lib().wcns_params_default(None) == -1
+
+
+def test_status_strings():
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert wcns.lib().wcns_status_str(code)
+
+
+def _create(**kw):
+    g = wcns._Grid()
+    g.ndim, g.nx, g.ny = kw.get("ndim", 2), kw.get("nx", 8), kw.get("ny", 8)
+    g.x0, g.x1, g.y0, g.y1 = 0.0, 1.0, 0.0, 1.0
+    for k, b in enumerate(kw.get("bc", (1, 1, 1, 1))):
+        g.bc[k] = b
+    e = wcns._Eos()
+    e.gamma[0], e.gamma[1] = kw.get("gamma", (6.12, 1.4))
+    e.pinf[0], e.pinf[1] = kw.get("pinf", (3.43e8, 0.0))
+    p = wcns.default_params()
+    for k in ("cfl", "scheme", "weno_eps"):
+        if k in kw:
+            setattr(p, k, kw[k])
+    ctx = C.c_void_p()
+    return wcns.lib().wcns_create(C.byref(g), C.byref(e), C.byref(p), kw.get("precision", 0),
+                                  None, C.byref(ctx))
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(gamma=(1.2, 1.67)), -2),              # gamma_liquid < gamma_gas: Lemma 1 fails
+    (dict(pinf=(3.43e8, 1e5)), -2),             # no ideal-gas phase
+    (dict(gamma=(1.0, 1.4)), -2),
+    (dict(nx=0), -1),                           # empty grid
+    (dict(ndim=1, ny=2), -1),
+    (dict(ndim=3), -1),
+    (dict(bc=(0, 1, 1, 1)), -1),                # periodic on one side only
+    (dict(bc=(2, 2, 1, 1), nx=2), -1),          # reflective wall needs 3 cells
+    (dict(bc=(7, 1, 1, 1)), -1),
+    (dict(cfl=0.6), -1),                        # positivity needs CFL <= 0.5
+    (dict(cfl=0.0), -1),
+    (dict(scheme=5), -1),
+    (dict(weno_eps=0.0), -1),
+    (dict(precision=9), -1),
+])
+def test_create_rejects_bad_arguments(kw, code):
+    assert _create(**kw) == code
+
+
+def test_null_arguments():
+    L = wcns.lib()
+    assert L.wcns_rhs(None, None, None, 0.0) == -1
+    assert L.wcns_ssprk3_step(None, None, 0.0, None) == -1
+    assert L.wcns_destroy(None) == -1
