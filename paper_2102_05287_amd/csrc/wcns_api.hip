@@ -154,7 +154,8 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   *out = nullptr;
   if (g->ndim != 1 && g->ndim != 2) return WCNS_ERR_ARG;
   if (g->nx < 1 || g->ny < 1 || (g->ndim == 1 && g->ny != 1)) return WCNS_ERR_ARG;
-  if ((long)g->nx * g->ny > (1L << 31)) return WCNS_ERR_ARG;
+  // node loads use 32-bit byte offsets within one component array
+  if ((long)g->nx * g->ny >= (1L << 29)) return WCNS_ERR_ARG;
   if (!(g->x1 > g->x0) || (g->ndim == 2 && !(g->y1 > g->y0))) return WCNS_ERR_ARG;
   for (int d = 0; d < g->ndim; ++d) {
     int lo = g->bc[2 * d], hi = g->bc[2 * d + 1];
@@ -301,6 +302,22 @@ static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mod
   return WCNS_OK;
 }
 
+// per-component base pointers of a state and of the node primitives
+static void set_bases(wcns_ctx* c, KArgs& a, const double* W) {
+  const long N = c->N;
+  if (c->grid.ndim == 2) {
+    for (int k = 0; k < 6; ++k) a.Wc[k] = W + k * N;
+  } else {
+    a.Wc[0] = W; a.Wc[1] = W + N; a.Wc[2] = W + 2 * N; a.Wc[3] = W;
+    a.Wc[4] = W + 3 * N; a.Wc[5] = W + 4 * N;
+  }
+  for (int k = 0; k < 5; ++k) a.Pc[k] = c->P + k * N;
+}
+
+static bool diri(const wcns_ctx* c, int dir) {
+  return c->grid.bc[2 * dir] == WCNS_BC_DIRICHLET || c->grid.bc[2 * dir + 1] == WCNS_BC_DIRICHLET;
+}
+
 // x-sweep and (2D) y-sweep of state W into `out`; mode STORE (L) or RK.
 static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int mode,
                                  const double* Un, double ca, double cb) {
@@ -312,10 +329,14 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   a.ca = ca;
   a.cb = cb;
   a.out_mode = mode;
+  set_bases(c, a, W);
   if (c->grid.ndim == 1) {
     a.Lout = nullptr;
     ProfScope ps(c, PROF_X);
-    hipLaunchKernelGGL(k_sweep_x<false>, dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    if (diri(c, 0))
+      hipLaunchKernelGGL((k_sweep_x<false, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_sweep_x<false, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
     LAUNCH_CHECK();
     return WCNS_OK;
   }
@@ -326,13 +347,19 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   a.Lx = lx;
   {
     ProfScope ps(c, PROF_X);
-    hipLaunchKernelGGL(k_sweep_x<true>, dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    if (diri(c, 0))
+      hipLaunchKernelGGL((k_sweep_x<true, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_sweep_x<true, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
   }
   LAUNCH_CHECK();
   dim3 gy((c->grid.nx + 63) / 64, c->nbr);
   {
     ProfScope ps(c, PROF_Y);
-    hipLaunchKernelGGL(k_sweep_y, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+    if (diri(c, 1))
+      hipLaunchKernelGGL(k_sweep_y<true>, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL(k_sweep_y<false>, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
   }
   LAUNCH_CHECK();
   if (c->nbr > 1) {
@@ -403,6 +430,7 @@ wcns_status wcns_limit(wcns_ctx* c, int32_t dir, const double* W, const double* 
   KArgs a = c->base;
   a.W = W;
   a.P = c->P;
+  set_bases(c, a, W);
   long nf = dir == 0 ? (long)(c->grid.nx + 1) * c->grid.ny : (long)c->grid.nx * (c->grid.ny + 1);
   unsigned g = (unsigned)((nf + 255) / 256);
   if (c->grid.ndim == 2)

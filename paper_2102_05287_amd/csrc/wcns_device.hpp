@@ -42,6 +42,31 @@ struct NodeQ {
   double un, ut, p, c, h;
 };
 
+// ---------------------------------------------------------------- division
+// 1/b from the hardware reciprocal refined by two Newton steps (5 VALU
+// slots instead of the 11 of the IEEE divide; within ~1 ulp for the
+// normal-range operands used here).
+__device__ __forceinline__ double rcp_nr(double b) {
+#pragma clang fp contract(fast)
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  return r;
+}
+
+// a/b through the refined reciprocal (within ~2 ulp of the IEEE quotient).
+__device__ __forceinline__ double fdiv(double a, double b) { return a * rcp_nr(b); }
+
+// Division used by the face pipeline: IEEE when FAST is false (node kernel),
+// refined reciprocal otherwise.
+template <bool FAST>
+__device__ __forceinline__ double qdiv(double a, double b) {
+  if (FAST) return fdiv(a, b);
+  return a / b;
+}
+
 // ---------------------------------------------------------------- EOS
 __device__ __forceinline__ double mix_gamma(const EosC& e, double a1) {
 #pragma clang fp contract(off)
@@ -57,12 +82,12 @@ __device__ __forceinline__ double mix_pi(const EosC& e, double a1) {
 // Primitive recovery and mixture sound speed of one state [Sec. 2]:
 // p = (rho e - Pi)/Gamma, pbar_inf = Pi/(1+Gamma), gbar = 1 + 1/Gamma,
 // c^2 = gbar (p + pbar_inf)/rho, h = rho e - pbar_inf.
-template <bool HAS_T>
+template <bool HAS_T, bool FAST = false>
 __device__ __forceinline__ void recover(const EosC& e, const double X[6], double& un, double& ut,
                                         double& p, double& c, double& h) {
 #pragma clang fp contract(off)
   double rho = X[0] + X[1];
-  double irho = 1.0 / rho;
+  double irho = qdiv<FAST>(1.0, rho);
   un = X[2] * irho;
   double ke;
   if (HAS_T) {
@@ -75,9 +100,9 @@ __device__ __forceinline__ void recover(const EosC& e, const double X[6], double
   double rhoe = X[4] - 0.5 * ke;
   double Gam = mix_gamma(e, X[5]);
   double Pi = mix_pi(e, X[5]);
-  p = (rhoe - Pi) / Gam;
-  double pinf_bar = Pi / (1.0 + Gam);
-  double gbar = 1.0 + 1.0 / Gam;
+  p = qdiv<FAST>(rhoe - Pi, Gam);
+  double pinf_bar = qdiv<FAST>(Pi, 1.0 + Gam);
+  double gbar = 1.0 + qdiv<FAST>(1.0, Gam);
   double c2 = gbar * (p + pinf_bar) * irho;
   c = sqrt(c2);
   h = rhoe - pinf_bar;
@@ -178,6 +203,9 @@ __device__ __forceinline__ void hllc(const NodeQ& L, const NodeQ& R, HllcOut& o)
 // ---------------------------------------------------------------- WENO-IS
 // Incremental-stencil nonlinear interpolation [Sec. 4.3], left-biased on
 // (a,b,c,d,e) = (u_{i-2},...,u_{i+2}); right-biased = flipped stencil.
+// Sub-stencils S0..S3, indicators beta_0, beta_1, beta_01, beta_2, beta_3,
+// reference indicator tau_5 and the IS weights eta_k/sum(eta), every
+// operation rounded as written (IEEE divides, no contraction).
 __device__ __forceinline__ double weno_is(double a, double b, double c, double d, double e,
                                           double eps) {
 #pragma clang fp contract(off)
@@ -203,6 +231,15 @@ __device__ __forceinline__ double weno_is(double a, double b, double c, double d
   double eta3 = (1.0 / 16.0) * (1.0 + tau5 / (b3 + eps));
   double sum = eta0 + eta1 + eta2 + eta3;
   return (eta0 * u0 + eta1 * u1 + eta2 * u2 + eta3 * u3) / sum;
+}
+
+// Compiler-only barrier between phases of the face pipeline: node values
+// are re-read (from L1/L2) after it instead of being held in registers, and
+// the scheduler does not interleave the phases (which would multiply the
+// live registers).
+__device__ __forceinline__ void phase_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // ---------------------------------------------------------------- limiters
@@ -247,71 +284,129 @@ __device__ __forceinline__ bool hard_switch_fails(const EosC& e, const Tol& t, c
 // Interpolation limiter, Algorithms 1-3 and the hard switch [Sec. 5.1].
 // A: node state on the side of the interpolated value (W_i for the
 // left-biased value, W_{i+1} for the right-biased one), hA = its
-// rho*ctilde^2; B: interpolated state, limited in place.
+// rho*ctilde^2; B: interpolated state, limited in place.  A blend with
+// theta = 1 is the identity, so it is skipped; the hard switch reuses the
+// last rho*ctilde^2 of B when B has not changed since it was evaluated.
 template <bool HAS_T>
 __device__ __forceinline__ void interp_limit(const EosC& e, const Tol& t, const double A[6],
                                              double hA, double B[6]) {
-#pragma clang fp contract(off)
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double qA = (k == 4) ? hA : test_fn<HAS_T>(e, k, A);
+  for (int k = 0; k < 4; ++k) {
+    double qA = test_fn<HAS_T>(e, k, A);
     double eps = tol_of(t, k);
+    double qB = test_fn<HAS_T>(e, k, B);
     if (qA < eps) {
 #pragma unroll
       for (int v = 0; v < 6; ++v) B[v] = A[v];   // theta = 0
-    } else {
-      double qB = test_fn<HAS_T>(e, k, B);
-      if (qB < eps) {
-        double th = (qA - eps) / (qA - qB);
+    } else if (qB < eps) {
+      double th = (qA - eps) / (qA - qB);
 #pragma unroll
-        for (int v = 0; v < 6; ++v) B[v] = (1.0 - th) * A[v] + th * B[v];
-      }
+      for (int v = 0; v < 6; ++v) B[v] = (1.0 - th) * A[v] + th * B[v];
     }
   }
-  if (hard_switch_fails<HAS_T>(e, t, B)) {
+  double hB = rhoc2_tilde<HAS_T>(e, B);
+  if (hA < t.eps_rhoc2) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) B[v] = A[v];
+    hB = hA;
+  } else if (hB < t.eps_rhoc2) {
+    double th = (hA - t.eps_rhoc2) / (hA - hB);
+#pragma unroll
+    for (int v = 0; v < 6; ++v) B[v] = (1.0 - th) * A[v] + th * B[v];
+    hB = rhoc2_tilde<HAS_T>(e, B);
+  }
+  bool fail = B[0] < t.hs_arho || B[1] < t.hs_arho || B[5] < t.hs_alpha ||
+              1.0 - B[5] < t.hs_alpha || hB < t.hs_rhoc2;
+  if (fail) {
 #pragma unroll
     for (int v = 0; v < 6; ++v) B[v] = A[v];
   }
 }
 
+// Half-cell state component v of the flux limiter [Sec. 5.2]:
+//   side 0: W_i - 2 lam (G^- - F_i),  side 1: W_{i+1} + 2 lam (G^+ - F_{i+1})
+__device__ __forceinline__ double half_state(int side, double w, double lam, double g, double f) {
+  return side == 0 ? w - 2.0 * lam * (g - f) : w + 2.0 * lam * (g - f);
+}
+
 // Flux limiter, Algorithms 4-6 and the hard switch [Sec. 5.2].
 // Half-cell states P(G) = W_i - 2 lam (G^- - F_i), M(G) = W_{i+1} +
 // 2 lam (G^+ - F_{i+1}); theta = min(theta+, theta-) per test; both fluxes
-// blended toward the first-order HLLC ones (Hm, Hp).  Returns the smallest
+// blended toward the first-order HLLC ones (Hm, Hp).  The states are formed
+// on demand from (W, F, G) instead of being stored.  Returns the smallest
 // theta applied (0 if the hard switch fired).
 template <bool HAS_T>
 __device__ __forceinline__ double flux_limit(const EosC& e, const Tol& t, const double Wl[6],
                                              const double Wr[6], const double Fl[6],
                                              const double Fr[6], double lam, const double Hm[6],
                                              const double Hp[6], double Gm[6], double Gp[6]) {
-#pragma clang fp contract(off)
-  double PH[6], MH[6], PG[6], MG[6];
-#pragma unroll
-  for (int v = 0; v < 6; ++v) {
-    PH[v] = Wl[v] - 2.0 * lam * (Hm[v] - Fl[v]);
-    MH[v] = Wr[v] + 2.0 * lam * (Hp[v] - Fr[v]);
-    PG[v] = Wl[v] - 2.0 * lam * (Gm[v] - Fl[v]);
-    MG[v] = Wr[v] + 2.0 * lam * (Gp[v] - Fr[v]);
-  }
   double thmin = 1.0;
+  double hPG = 0.0, hMG = 0.0;
 #pragma unroll
   for (int k = 0; k < 5; ++k) {
-    double eps = tol_of(t, k);
-    double thp = limiter_theta(test_fn<HAS_T>(e, k, PH), test_fn<HAS_T>(e, k, PG), eps);
-    double thm = limiter_theta(test_fn<HAS_T>(e, k, MH), test_fn<HAS_T>(e, k, MG), eps);
+    const double eps = tol_of(t, k);
+    double qPH, qPG, qMH, qMG;
+    if (k < 4) {
+      // a1r1, a2r2, a1 or 1-a1 of the four half-cell states
+      const int v = k == 0 ? 0 : (k == 1 ? 1 : 5);
+      qPH = half_state(0, Wl[v], lam, Hm[v], Fl[v]);
+      qPG = half_state(0, Wl[v], lam, Gm[v], Fl[v]);
+      qMH = half_state(1, Wr[v], lam, Hp[v], Fr[v]);
+      qMG = half_state(1, Wr[v], lam, Gp[v], Fr[v]);
+      if (k == 3) { qPH = 1.0 - qPH; qPG = 1.0 - qPG; qMH = 1.0 - qMH; qMG = 1.0 - qMG; }
+    } else {
+      double X[6];
+#pragma unroll
+      for (int v = 0; v < 6; ++v) X[v] = half_state(0, Wl[v], lam, Hm[v], Fl[v]);
+      qPH = rhoc2_tilde<HAS_T>(e, X);
+#pragma unroll
+      for (int v = 0; v < 6; ++v) X[v] = half_state(0, Wl[v], lam, Gm[v], Fl[v]);
+      qPG = rhoc2_tilde<HAS_T>(e, X);
+#pragma unroll
+      for (int v = 0; v < 6; ++v) X[v] = half_state(1, Wr[v], lam, Hp[v], Fr[v]);
+      qMH = rhoc2_tilde<HAS_T>(e, X);
+#pragma unroll
+      for (int v = 0; v < 6; ++v) X[v] = half_state(1, Wr[v], lam, Gp[v], Fr[v]);
+      qMG = rhoc2_tilde<HAS_T>(e, X);
+      hPG = qPG;
+      hMG = qMG;
+    }
+    double thp = limiter_theta(qPH, qPG, eps);
+    double thm = limiter_theta(qMH, qMG, eps);
     double th = (thm < thp) ? thm : thp;
     if (th != 1.0) {
 #pragma unroll
       for (int v = 0; v < 6; ++v) {
         Gp[v] = (1.0 - th) * Hp[v] + th * Gp[v];
         Gm[v] = (1.0 - th) * Hm[v] + th * Gm[v];
-        PG[v] = Wl[v] - 2.0 * lam * (Gm[v] - Fl[v]);
-        MG[v] = Wr[v] + 2.0 * lam * (Gp[v] - Fr[v]);
       }
       thmin = (th < thmin) ? th : thmin;
+      if (k == 4) {
+        double X[6];
+#pragma unroll
+        for (int v = 0; v < 6; ++v) X[v] = half_state(0, Wl[v], lam, Gm[v], Fl[v]);
+        hPG = rhoc2_tilde<HAS_T>(e, X);
+#pragma unroll
+        for (int v = 0; v < 6; ++v) X[v] = half_state(1, Wr[v], lam, Gp[v], Fr[v]);
+        hMG = rhoc2_tilde<HAS_T>(e, X);
+      }
     }
   }
-  if (hard_switch_fails<HAS_T>(e, t, PG) || hard_switch_fails<HAS_T>(e, t, MG)) {
+  // hard switch on the final half-cell states
+  bool fail = false;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const double* Wx = side == 0 ? Wl : Wr;
+    const double* Fx = side == 0 ? Fl : Fr;
+    const double* Gx = side == 0 ? Gm : Gp;
+    double x0 = half_state(side, Wx[0], lam, Gx[0], Fx[0]);
+    double x1 = half_state(side, Wx[1], lam, Gx[1], Fx[1]);
+    double x5 = half_state(side, Wx[5], lam, Gx[5], Fx[5]);
+    double hx = side == 0 ? hPG : hMG;
+    fail = fail || x0 < t.hs_arho || x1 < t.hs_arho || x5 < t.hs_alpha || 1.0 - x5 < t.hs_alpha ||
+           hx < t.hs_rhoc2;
+  }
+  if (fail) {
 #pragma unroll
     for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
     thmin = 0.0;

@@ -19,8 +19,11 @@
 
 #include "wcns_device.hpp"
 
-// No FMA contraction in this file: every operation is rounded as written
-// (see wcns_device.hpp).
+// The FP64 path rounds every operation as written, in the same order as the
+// serial reference (no FMA contraction, IEEE divides and square roots): the
+// positivity limiters divide by differences of order 1e-8 near material
+// interfaces, so any change of rounding upstream would move their blends by
+// ~1e-8 relative ("bit-reproducible FP64").
 #pragma clang fp contract(off)
 
 namespace wcns {
@@ -38,6 +41,9 @@ struct KArgs {
   Tol tol;
   const double* W;       // state differentiated
   const double* P;       // node primitives of W: [5][ny][nx] (u, v, p, c, h)
+  const double* Wc[6];   // per-component bases of W in rotated-frame-free state
+                         // order (1D: a1r1, a2r2, m, -, E, a1 with slot 3 unused)
+  const double* Pc[5];   // per-component bases of P
   const double* dirW;    // Dirichlet ghost states [4][6] (unrotated 6-comp)
   const double* dirP;    // their primitives [4][5]
   const double* step;    // [0] dt, [1] lam_x, [2] lam_y, [3] amax_x, [4] amax_y
@@ -64,69 +70,119 @@ __device__ __forceinline__ int ghost_src(int g, int n, int bc_lo, int bc_hi, boo
   return -1;
 }
 
-// Node (dir, line, g) in the frame rotated into direction dir.
-template <bool HAS_T>
-__device__ __forceinline__ void load_node(const KArgs& a, int dir, int line, int g, NodeQ& q) {
-  const int n = dir == 0 ? a.nx : a.ny;
-  bool flip;
-  int s = ghost_src(g, n, a.bc[2 * dir], a.bc[2 * dir + 1], flip);
+// Stencil of one face: byte offsets (within one component array) of the 6
+// nodes i-2 .. i+3 after ghost mapping, a bit mask of reflective ghosts
+// (normal momentum and velocity change sign) and, with Dirichlet sides, a
+// mask of Dirichlet ghosts.  Computed once per face; every node load after
+// that is a branch-free 32-bit-offset load from a per-component base.
+struct Sten {
+  uint32_t off[6];
+  uint32_t flip, diri;
+};
+
+template <int DIR>
+__device__ __forceinline__ Sten make_sten(const KArgs& a, int line, int g0) {
+  const int n = DIR == 0 ? a.nx : a.ny;
+  Sten st;
+  st.flip = 0;
+  st.diri = 0;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const int g = g0 + m;
+    bool flip;
+    int s = ghost_src(g, n, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
+    if (s < 0) { st.diri |= 1u << m; s = 0; }
+    if (flip) st.flip |= 1u << m;
+    const uint32_t o = DIR == 0 ? (uint32_t)line * (uint32_t)a.nx + (uint32_t)s
+                                : (uint32_t)s * (uint32_t)a.nx + (uint32_t)line;
+    st.off[m] = o * 8u;
+  }
+  return st;
+}
+
+__device__ __forceinline__ double ldc(const double* base, uint32_t byte_off) {
+  return *(const double*)((const char*)base + byte_off);
+}
+
+// Node m of a stencil in the frame rotated into direction DIR.
+template <int DIR, bool HAS_T, bool DIRI>
+__device__ __forceinline__ void load_node(const KArgs& a, const Sten& st, int m, int g0, NodeQ& q) {
+  const uint32_t o = st.off[m];
   double Y[6], u, v;
-  if (s < 0) {
-    const int side = 2 * dir + (g < 0 ? 0 : 1);
+  Y[0] = ldc(a.Wc[0], o);
+  Y[1] = ldc(a.Wc[1], o);
+  Y[2] = ldc(a.Wc[2], o);
+  Y[3] = HAS_T ? ldc(a.Wc[3], o) : 0.0;
+  Y[4] = ldc(a.Wc[4], o);
+  Y[5] = ldc(a.Wc[5], o);
+  u = ldc(a.Pc[0], o);
+  v = HAS_T ? ldc(a.Pc[1], o) : 0.0;
+  q.p = ldc(a.Pc[2], o);
+  q.c = ldc(a.Pc[3], o);
+  q.h = ldc(a.Pc[4], o);
+  if (DIRI && ((st.diri >> m) & 1u)) {
+    const int side = 2 * DIR + (g0 + m < 0 ? 0 : 1);
 #pragma unroll
     for (int k = 0; k < 6; ++k) Y[k] = a.dirW[side * 6 + k];
-    u = a.dirP[side * 5 + 0]; v = a.dirP[side * 5 + 1];
-    q.p = a.dirP[side * 5 + 2]; q.c = a.dirP[side * 5 + 3]; q.h = a.dirP[side * 5 + 4];
-  } else {
-    const long N = (long)a.nx * a.ny;
-    const long o = dir == 0 ? (long)line * a.nx + s : (long)s * a.nx + line;
-    if (HAS_T) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) Y[k] = a.W[k * N + o];
-      v = a.P[1 * N + o];
-    } else {
-      Y[0] = a.W[o]; Y[1] = a.W[N + o]; Y[2] = a.W[2 * N + o]; Y[3] = 0.0;
-      Y[4] = a.W[3 * N + o]; Y[5] = a.W[4 * N + o];
-      v = 0.0;
-    }
-    u = a.P[o];
-    q.p = a.P[2 * N + o]; q.c = a.P[3 * N + o]; q.h = a.P[4 * N + o];
+    u = a.dirP[side * 5 + 0];
+    v = a.dirP[side * 5 + 1];
+    q.p = a.dirP[side * 5 + 2];
+    q.c = a.dirP[side * 5 + 3];
+    q.h = a.dirP[side * 5 + 4];
   }
   q.w[0] = Y[0]; q.w[1] = Y[1]; q.w[4] = Y[4]; q.w[5] = Y[5];
-  if (dir == 0) { q.w[2] = Y[2]; q.w[3] = Y[3]; q.un = u; q.ut = v; }
+  if (DIR == 0) { q.w[2] = Y[2]; q.w[3] = Y[3]; q.un = u; q.ut = v; }
   else { q.w[2] = Y[3]; q.w[3] = Y[2]; q.un = v; q.ut = u; }
-  if (flip) { q.w[2] = -q.w[2]; q.un = -q.un; }
+  const double sg = ((st.flip >> m) & 1u) ? -1.0 : 1.0;   // exact sign flip
+  q.w[2] *= sg;
+  q.un *= sg;
 }
 
 // ------------------------------------------------------------------ face
+// Characteristic field f of node q with the face's projection constants
+// [App. A, R^{-1}]: U1 = u - p/(rho c), U2 = a1r1 - a1 p/(rho c^2),
+// U3 = a2r2 - a2 p/(rho c^2), U4 = u_t, U5 = a1, U6 = u + p/(rho c).
+__device__ __forceinline__ double char_field(int f, const NodeQ& q, double fa1, double fa2,
+                                             double k1, double k2) {
+  switch (f) {
+    case 0: return q.un - q.p * k1;
+    case 1: return q.w[0] - fa1 * q.p * k2;
+    case 2: return q.w[1] - fa2 * q.p * k2;
+    case 3: return q.ut;
+    case 4: return q.w[5];
+    default: return q.un + q.p * k1;
+  }
+}
+
 // One face i+1/2 of a sweep: WCNS steps 1-9 [Sec. 4.2] with the
 // interpolation limiter [Sec. 5.1] and the flux limiter [Sec. 5.2].
-// Stencil nodes i-2 .. i+3 are g0 .. g0+5 along the line.
-template <bool HAS_T>
-__device__ __forceinline__ double face_flux(const KArgs& a, int dir, int line, int g0, double lam,
+// Stencil nodes i-2 .. i+3 are g0 .. g0+5 along the line.  Node data are
+// re-read from the cache in each phase (phase_barrier) to keep the live
+// register set small.
+template <int DIR, bool HAS_T, bool DIRI>
+__device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, double lam,
                                             double Gm[6], double Gp[6]) {
   const EosC& e = a.eos;
-  NodeQ nl, nr;
-  load_node<HAS_T>(a, dir, line, g0 + 2, nl);
-  load_node<HAS_T>(a, dir, line, g0 + 3, nr);
-  // first-order HLLC flux from W_i, W_{i+1} and its split [Sec. 3.2]
-  HllcOut h1;
-  hllc<HAS_T>(nl, nr, h1);
+  const Sten st = make_sten<DIR>(a, line, g0);
+  // first-order HLLC flux from W_i, W_{i+1} and its split [Sec. 3.2];
+  // face averages for the projection [Sec. 4.2; App. A]
   double Hm[6], Hp[6];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) { Hm[v] = h1.F[v]; Hp[v] = h1.F[v]; }
-  {
-    Hm[5] = h1.fa - nl.w[5] * h1.ss;
-    Hp[5] = h1.fa - nr.w[5] * h1.ss;
-  }
-  if (a.scheme == 1) {
-#pragma unroll
-    for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
-    return 0.0;
-  }
-  // face averages and projection constants [Sec. 4.2; App. A]
   double fa1, fa2, frho, fc, k1, k2;
   {
+    NodeQ nl, nr;
+    load_node<DIR, HAS_T, DIRI>(a, st, 2, g0, nl);
+    load_node<DIR, HAS_T, DIRI>(a, st, 3, g0, nr);
+    HllcOut h1;
+    hllc<HAS_T>(nl, nr, h1);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) { Hm[v] = h1.F[v]; Hp[v] = h1.F[v]; }
+    Hm[5] = h1.fa - nl.w[5] * h1.ss;
+    Hp[5] = h1.fa - nr.w[5] * h1.ss;
+    if (a.scheme == 1) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
+      return 0.0;
+    }
     fa1 = 0.5 * (nl.w[0] + nr.w[0]);
     fa2 = 0.5 * (nl.w[1] + nr.w[1]);
     frho = 0.5 * ((nl.w[0] + nl.w[1]) + (nr.w[0] + nr.w[1]));
@@ -134,54 +190,24 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int dir, int line, i
     k1 = 1.0 / (frho * fc);
     k2 = 1.0 / (frho * fc * fc);
   }
-  // characteristic projection U = R^{-1} V and IS-WENO per field
+  // characteristic projection U = R^{-1} V and IS-WENO, one field at a time
   double UL[6], UR[6];
-  {
-    double s0[6], s5[6];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    if (!HAS_T && f == 3) { UL[3] = 0.0; UR[3] = 0.0; continue; }
+    phase_barrier();
+    double u[6];
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       NodeQ q;
-      load_node<HAS_T>(a, dir, line, g0 + m, q);
-      s0[m] = q.un - q.p * k1;
-      s5[m] = q.un + q.p * k1;
+      load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+      u[m] = char_field(f, q, fa1, fa2, k1, k2);
     }
-    UL[0] = weno_is(s0[0], s0[1], s0[2], s0[3], s0[4], a.tol.weno_eps);
-    UR[0] = weno_is(s0[5], s0[4], s0[3], s0[2], s0[1], a.tol.weno_eps);
-    UL[5] = weno_is(s5[0], s5[1], s5[2], s5[3], s5[4], a.tol.weno_eps);
-    UR[5] = weno_is(s5[5], s5[4], s5[3], s5[2], s5[1], a.tol.weno_eps);
+    UL[f] = weno_is(u[0], u[1], u[2], u[3], u[4], a.tol.weno_eps);
+    phase_barrier();
+    UR[f] = weno_is(u[5], u[4], u[3], u[2], u[1], a.tol.weno_eps);
   }
-  {
-    double s1[6], s2[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      NodeQ q;
-      load_node<HAS_T>(a, dir, line, g0 + m, q);
-      s1[m] = q.w[0] - fa1 * q.p * k2;
-      s2[m] = q.w[1] - fa2 * q.p * k2;
-    }
-    UL[1] = weno_is(s1[0], s1[1], s1[2], s1[3], s1[4], a.tol.weno_eps);
-    UR[1] = weno_is(s1[5], s1[4], s1[3], s1[2], s1[1], a.tol.weno_eps);
-    UL[2] = weno_is(s2[0], s2[1], s2[2], s2[3], s2[4], a.tol.weno_eps);
-    UR[2] = weno_is(s2[5], s2[4], s2[3], s2[2], s2[1], a.tol.weno_eps);
-  }
-  {
-    double s3[6], s4[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      NodeQ q;
-      load_node<HAS_T>(a, dir, line, g0 + m, q);
-      s3[m] = HAS_T ? q.ut : 0.0;
-      s4[m] = q.w[5];
-    }
-    if (HAS_T) {
-      UL[3] = weno_is(s3[0], s3[1], s3[2], s3[3], s3[4], a.tol.weno_eps);
-      UR[3] = weno_is(s3[5], s3[4], s3[3], s3[2], s3[1], a.tol.weno_eps);
-    } else {
-      UL[3] = 0.0; UR[3] = 0.0;
-    }
-    UL[4] = weno_is(s4[0], s4[1], s4[2], s4[3], s4[4], a.tol.weno_eps);
-    UR[4] = weno_is(s4[5], s4[4], s4[3], s4[2], s4[1], a.tol.weno_eps);
-  }
+  phase_barrier();
   // back-projection V = R U, then V -> W [App. A; Sec. 2]
   double WL[6], WR[6];
   {
@@ -207,9 +233,15 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int dir, int line, i
       X[5] = a1;
     }
   }
+  // interpolation limiter toward W_i (left value) and W_{i+1} (right value)
   if (a.interp_limiter) {
-    interp_limit<HAS_T>(e, a.tol, nl.w, nl.h, WL);
-    interp_limit<HAS_T>(e, a.tol, nr.w, nr.h, WR);
+    NodeQ q;
+    load_node<DIR, HAS_T, DIRI>(a, st, 2, g0, q);
+    interp_limit<HAS_T>(e, a.tol, q.w, q.h, WL);
+    phase_barrier();
+    load_node<DIR, HAS_T, DIRI>(a, st, 3, g0, q);
+    interp_limit<HAS_T>(e, a.tol, q.w, q.h, WR);
+    phase_barrier();
   }
   // high-order midpoint flux from the limited states [WCNS step 6]
   HllcOut h2;
@@ -221,37 +253,38 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int dir, int line, i
     recover<HAS_T>(e, tr.w, tr.un, tr.ut, tr.p, tr.c, tr.h);
     hllc<HAS_T>(tl, tr, h2);
   }
-  // HCS reconstruction of flux and velocity [Sec. 4.1; WCNS steps 7-8]
-  double Gh[6], uh;
-  {
-    double gt[6] = {h2.F[0], h2.F[1], h2.F[2], h2.F[3], h2.F[4], h2.fa};
-    double s01[7], s12[7], s03[7];
+  // HCS reconstruction of flux and velocity [Sec. 4.1; WCNS steps 7-8]:
+  // ((3072 gt - 505 s01) + 20 s12 - s03)/2100, node pairs s01 = (i, i+1),
+  // s12 = (i-1, i+2), s03 = (i-2, i+3)
+  double acc[7] = {h2.F[0], h2.F[1], h2.F[2], h2.F[3], h2.F[4], h2.fa, h2.ss};
 #pragma unroll
-    for (int pr = 0; pr < 3; ++pr) {
-      // pairs (i, i+1), (i-1, i+2), (i-2, i+3)
-      const int ma = 2 - pr, mb = 3 + pr;
-      NodeQ qa, qb;
-      load_node<HAS_T>(a, dir, line, g0 + ma, qa);
-      load_node<HAS_T>(a, dir, line, g0 + mb, qb);
-      double ga[6], gb[6];
-      node_flux<HAS_T>(qa, ga);
-      node_flux<HAS_T>(qb, gb);
-      double* s = pr == 0 ? s01 : (pr == 1 ? s12 : s03);
+  for (int pr = 0; pr < 3; ++pr) {
+    phase_barrier();
+    const int ma = 2 - pr, mb = 3 + pr;
+    NodeQ qa, qb;
+    load_node<DIR, HAS_T, DIRI>(a, st, ma, g0, qa);
+    load_node<DIR, HAS_T, DIRI>(a, st, mb, g0, qb);
+    double ga[6], gb[6];
+    node_flux<HAS_T>(qa, ga);
+    node_flux<HAS_T>(qb, gb);
 #pragma unroll
-      for (int v = 0; v < 6; ++v) s[v] = ga[v] + gb[v];
-      s[6] = qa.un + qb.un;
+    for (int v = 0; v < 7; ++v) {
+      double sum = v < 6 ? ga[v] + gb[v] : qa.un + qb.un;
+      if (pr == 0) acc[v] = 3072.0 * acc[v] - 505.0 * sum;
+      else if (pr == 1) acc[v] = acc[v] + 20.0 * sum;
+      else acc[v] = (acc[v] - sum) / 2100.0;
     }
-#pragma unroll
-    for (int v = 0; v < 6; ++v) Gh[v] = hcs(gt[v], s01[v], s12[v], s03[v]);
-    uh = hcs(h2.ss, s01[6], s12[6], s03[6]);
   }
-  // split fluxes G^{-+} [Sec. 3.2, WCNS step 9]
+  const double uh = acc[6];
+  // split fluxes G^{-+} [Sec. 3.2, WCNS step 9] and the flux limiter
+  phase_barrier();
+  NodeQ nl, nr;
+  load_node<DIR, HAS_T, DIRI>(a, st, 2, g0, nl);
+  load_node<DIR, HAS_T, DIRI>(a, st, 3, g0, nr);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) { Gm[v] = Gh[v]; Gp[v] = Gh[v]; }
-  {
-    Gm[5] = Gh[5] - nl.w[5] * uh;
-    Gp[5] = Gh[5] - nr.w[5] * uh;
-  }
+  for (int v = 0; v < 5; ++v) { Gm[v] = acc[v]; Gp[v] = acc[v]; }
+  Gm[5] = acc[5] - nl.w[5] * uh;
+  Gp[5] = acc[5] - nr.w[5] * uh;
   if (a.flux_limiter) {
     double gl[6], gr[6];
     node_flux<HAS_T>(nl, gl);
@@ -384,7 +417,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int nbl
 // left face of cell c0+t; lanes T.. own the right face of each row segment's
 // last cell.  Cell c0+t then takes G^+ of its own face and G^- of the lane
 // that owns its right face.
-template <bool HAS_T>
+template <bool HAS_T, bool DIRI>
 __global__ __launch_bounds__(64) void k_sweep_x(KArgs a) {
   const int lane = threadIdx.x;
   const int nx = a.nx;
@@ -408,7 +441,7 @@ __global__ __launch_bounds__(64) void k_sweep_x(KArgs a) {
     }
   }
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
-  if (active) face_flux<HAS_T>(a, 0, fj, fk - 3, a.step[1], Gm, Gp);
+  if (active) face_flux<0, HAS_T, DIRI>(a, fj, fk - 3, a.step[1], Gm, Gp);
   // lane holding the right face of my cell
   int src = lane;
   const long c = c0 + lane;
@@ -445,6 +478,7 @@ __global__ __launch_bounds__(64) void k_sweep_x(KArgs a) {
 // G^- of face row kb + w + 1 (through LDS).  The last face row of the tile
 // leaves G^+ in the edge buffer and the first one G^-; k_fixup_y finishes the
 // cell row in between.
+template <bool DIRI>
 __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
   __shared__ double sGm[Y_WAVES][6][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -455,7 +489,7 @@ __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
   const long N = (long)nx * ny;
   const bool active = i < nx && k <= ny;
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
-  if (active) face_flux<true>(a, 1, i, k - 3, a.step[2], Gm, Gp);
+  if (active) face_flux<1, true, DIRI>(a, i, k - 3, a.step[2], Gm, Gp);
 #pragma unroll
   for (int v = 0; v < 6; ++v) sGm[w][v][lane] = Gm[v];
   // tile edges for the fixup of the straddling cell rows
@@ -520,8 +554,15 @@ __global__ __launch_bounds__(256) void k_limit(KArgs a, int dir, const double* G
   if (dir == 0) { line = (int)(f / (nx + 1)); k = (int)(f % (nx + 1)); }
   else { k = (int)(f / nx); line = (int)(f % nx); }
   NodeQ nl, nr;
-  load_node<HAS_T>(a, dir, line, k - 1, nl);
-  load_node<HAS_T>(a, dir, line, k, nr);
+  if (dir == 0) {
+    const Sten st = make_sten<0>(a, line, k - 3);
+    load_node<0, HAS_T, true>(a, st, 2, k - 3, nl);
+    load_node<0, HAS_T, true>(a, st, 3, k - 3, nr);
+  } else {
+    const Sten st = make_sten<1>(a, line, k - 3);
+    load_node<1, HAS_T, true>(a, st, 2, k - 3, nl);
+    load_node<1, HAS_T, true>(a, st, 3, k - 3, nr);
+  }
   const int nv = HAS_T ? 6 : 5;
   double Gh[6], Hh[6];
   double uh = Gho[(long)nv * nf + f], uhh = Glo[(long)nv * nf + f];

@@ -31,6 +31,9 @@ def host(t):
 def assert_parity(g, r, tol=RTOL, what=""):
     g = np.asarray(g).reshape(r.shape[0], -1)
     r = r.reshape(r.shape[0], -1)
+    worst = max(float((np.abs(g[v] - r[v]) / np.maximum(np.abs(r[v]), np.abs(r[v]).max() + 1e-300)).max())
+                for v in range(r.shape[0]))
+    print(f"  parity {what}: max scaled error {worst:.3e} (tol {tol:.0e})", flush=True)
     for v in range(r.shape[0]):
         M = np.abs(r[v]).max()
         bound = tol * np.maximum(np.abs(r[v]), M) + 1e-300
@@ -106,21 +109,52 @@ def test_rhs_schemes_and_limiter_switches():
     rhs_case(spec, flux_limiter=False, interp_limiter=False)
 
 
-def test_rhs_limiters_active_strong_shock():
-    """Sedov-like blast in 2D: liquid under tension next to a very strong gas
-    pressure, which activates both limiters and the hard switches."""
-    spec = pb.random_smooth_state(40, 36, 22)
+def _blast_2d(nx=40, ny=36):
+    """2D planar-Sedov-like blast (Sec. 6.4 style): a 4x4 block of air at
+    1.28e6/dx Pa inside water under tension (-3e7 Pa)."""
+    spec = pb.random_smooth_state(nx, ny, 22, with_bubble=False, with_shock=False)
     V = spec.prim
-    V[4][:] = -2.0e7
-    V[4][18, 20] = 1e12
-    V[0][18, 20] = 1e-8
-    V[1][18, 20] = 1.0
-    V[5][18, 20] = 1e-6
+    V[4][:] = -3.0e7
+    blk = (slice(16, 20), slice(18, 22))
+    V[0][blk] = 1e-8
+    V[1][blk] = 1.0
+    V[5][blk] = 1e-8
+    V[4][blk] = 1.28e6 / spec.dx
+    return spec
+
+
+def test_rhs_limiters_active_blast():
+    """States where the flux limiter (and its hard switch) is active on many
+    faces: the 2D blast initially and after 5 oracle steps, and the 1D
+    Sedov problem after 55 oracle steps."""
+    spec = _blast_2d()
     s = oracle_setup(spec)
     W = oracle_W(spec, s)
-    Gm, Gp, th = orc.faces(s, W, 0, orc.cfl_dt(s, W))
-    assert (th < 1).sum() > 0, "test must exercise the flux limiter"
-    rhs_case(spec)
+    for k in range(2):
+        dt = orc.cfl_dt(s, W)
+        _, _, thx = orc.faces(s, W, 0, dt)
+        _, _, thy = orc.faces(s, W, 1, dt)
+        assert (thx < 1).sum() > 10 and (thy < 1).sum() > 10
+        sol = solver_for(spec)
+        got = host(sol.rhs(dev(W), dt=dt))
+        assert_parity(got, orc.rhs(s, W, dt), what=f"blast{k}")
+        for _ in range(5):
+            W, _, bad = orc.ssprk3_step(s, W)
+            assert bad == 0
+    spec = pb.sedov_multimaterial(401)
+    s = oracle_setup(spec)
+    W, steps, t = orc.run(s, oracle_W(spec, s), 55 * spec.dt_fixed * (1 - 1e-12), spec.dt_fixed)
+    _, _, th = orc.faces(s, W, 0, spec.dt_fixed)
+    assert (th == 0).sum() > 0, "hard switch must fire"
+    sol = solver_for(spec)
+    got = host(sol.rhs(dev(W), dt=spec.dt_fixed))
+    assert_parity(got, orc.rhs(s, W, spec.dt_fixed), what="sedov")
+    # and a step from there (fixed dt) keeps every cell admissible
+    Wd = dev(W)
+    sol.step(Wd, spec.dt_fixed)
+    ref, _, bad = orc.ssprk3_step(s, W, spec.dt_fixed)
+    assert bad == 0 and sol.count_inadmissible(Wd) == 0
+    assert_parity(host(Wd), ref, what="sedov step")
 
 
 def test_rhs_full_size_shock_bubble():
