@@ -293,7 +293,9 @@ template <class T>
 inline void interp_limit(const Eos& e, const Problem& P, const T A[6], T B[6]) {
   for (int k = 0; k < 5; ++k) {
     T th = limiter_theta(test_fn(e, k, A), test_fn(e, k, B), tol_of(P, k));
-    for (int v = 0; v < 6; ++v) B[v] = (T(1.0) - th) * A[v] + th * B[v];
+    // the blend with theta = 1 is the identity: only a theta < 1 changes B
+    if (val(th) != 1.0)
+      for (int v = 0; v < 6; ++v) B[v] = (T(1.0) - th) * A[v] + th * B[v];
   }
   if (hard_switch_fails(e, P, B))
     for (int v = 0; v < 6; ++v) B[v] = A[v];
@@ -325,14 +327,16 @@ inline T flux_limit(const Eos& e, const Problem& P, const T Wl[6], const T Wr[6]
     T thp = limiter_theta(test_fn(e, k, PH), test_fn(e, k, PG), eps);
     T thm = limiter_theta(test_fn(e, k, MH), test_fn(e, k, MG), eps);
     T th = tmin(thp, thm);
-    for (int v = 0; v < 6; ++v) {
-      Gp[v] = (T(1.0) - th) * Hp[v] + th * Gp[v];
-      Gm[v] = (T(1.0) - th) * Hm[v] + th * Gm[v];
+    if (val(th) != 1.0) {   // theta = 1 leaves both fluxes unchanged
+      for (int v = 0; v < 6; ++v) {
+        Gp[v] = (T(1.0) - th) * Hp[v] + th * Gp[v];
+        Gm[v] = (T(1.0) - th) * Hm[v] + th * Gm[v];
+      }
+      // Reading: the half-cell states of the next test are recomputed from
+      // the blended fluxes (equal, in exact arithmetic, to blending states).
+      states(Gm, Gp, PG, MG);
+      thmin = tmin(thmin, th);
     }
-    // Reading: the half-cell states of the next test are recomputed from the
-    // blended fluxes (equal, in exact arithmetic, to blending the states).
-    states(Gm, Gp, PG, MG);
-    thmin = tmin(thmin, th);
   }
   if (hard_switch_fails(e, P, PG) || hard_switch_fails(e, P, MG)) {
     for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
