@@ -56,6 +56,30 @@ def kernel_ops(nx, ny, scheme="ppwcnsis"):
     }
 
 
+def source_hash():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2102_05287_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or
+    None when the kernel sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_hash") != source_hash() or kernel not in t["kernels"]:
+        return None
+    k, c = t["kernels"][kernel], t["calibration"]
+    return (k["fetch_kib"] * c["fetch_factor"] + k["write_kib"] * c["write_factor"]) * 1024.0
+
+
 def cpu_baseline(spec, target_s=12.0):
     from oracle import oracle as orc
     s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy, bc=spec.bc)
@@ -143,7 +167,7 @@ def main():
     achieved = ops[dom] / avg_s / 1e12
     peak = VALU_F64_SLOTS / 1e12
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
                 "avg_launch_ms": avg_s * 1e3,
                 "ops_per_launch": ops[dom],
                 "op_model": "oracle op count, div=11 and sqrt=19 VALU slots; peak = FP64 "
