@@ -142,12 +142,21 @@ wcns_status wcns_check_admissible(wcns_ctx* ctx, const double* W, long long* n_b
  * context's stream; wcns_profile_read synchronises the stream and returns,
  * per kernel class, the summed device time in milliseconds and the number of
  * launches since the last reset.  Classes (WCNS_NPROF = 6): 0 node
- * primitives + wave-speed maxima, 1 dt/lambda finalize, 2 x-sweep, 3 y-sweep,
- * 4 y-tile fixup, 5 other.  Enabling allocates the event pool (so it is not
+ * primitives + wave-speed maxima, 1 dt/lambda finalize, 2 x-sweep,
+ * 3 y-sweep, 4 y-tile fixup, 5 other.  Enabling allocates the event pool (so it is not
  * graph-capturable); disabling releases it. */
 #define WCNS_NPROF 6
 wcns_status wcns_profile(wcns_ctx* ctx, int32_t enable);
 wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
+
+/* Verification aid: the kernels divide with the core of gfx950's
+ * correctly rounded FP64 division sequence without its range-scaling steps
+ * (valid for normal-range operands).  This computes, on the device, both
+ * q_ieee[k] = a[k]/b[k] through the compiler's full IEEE sequence and
+ * q_core[k] through the kernels' core, for device arrays of n doubles, so a
+ * test can check they agree bit for bit over the operand ranges used. */
+wcns_status wcns_selftest_division(const double* a, const double* b, double* q_ieee,
+                                   double* q_core, int64_t n, void* stream);
 
 /* Human-readable status. */
 const char* wcns_status_str(wcns_status s);

@@ -281,23 +281,31 @@ wcns_status wcns_set_stream(wcns_ctx* c, void* stream) {
   return WCNS_OK;
 }
 
-// node primitives + wave-speed maxima + dt/lambda of state W
+// node primitives + wave-speed maxima, then dt/lambda of state W
 static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mode, double dt,
                                         double* dt_used) {
   KArgs a = c->base;
   a.W = W;
   {
-  ProfScope ps(c, PROF_NODE);
-  if (c->grid.ndim == 2)
-    hipLaunchKernelGGL(k_node<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
-  else
-    hipLaunchKernelGGL(k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
+    ProfScope ps(c, PROF_NODE);
+    if (c->grid.ndim == 2)
+      hipLaunchKernelGGL(k_node<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
+    else
+      hipLaunchKernelGGL(k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
   }
   LAUNCH_CHECK();
+  FinArgs f;
+  f.ndim = c->grid.ndim;
+  f.dt_mode = dt_mode;
+  f.dx = c->dx;
+  f.dy = c->dy;
+  f.cfl = c->params.cfl;
+  f.dt_in = dt;
+  f.step = c->step;
+  f.dt_used = dt_used;
   ProfScope ps(c, PROF_FIN);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
-                     c->node_grid, c->grid.ndim, c->dx, c->dy, c->params.cfl, dt_mode, dt, c->step,
-                     dt_used);
+                     c->node_grid, f);
   LAUNCH_CHECK();
   return WCNS_OK;
 }
@@ -356,10 +364,17 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   dim3 gy((c->grid.nx + 63) / 64, c->nbr);
   {
     ProfScope ps(c, PROF_Y);
+#if WCNS_YMARCH
+    if (diri(c, 1))
+      hipLaunchKernelGGL(k_sweep_y_march<true>, gy, dim3(64), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL(k_sweep_y_march<false>, gy, dim3(64), 0, c->stream, a);
+#else
     if (diri(c, 1))
       hipLaunchKernelGGL(k_sweep_y<true>, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
     else
       hipLaunchKernelGGL(k_sweep_y<false>, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+#endif
   }
   LAUNCH_CHECK();
   if (c->nbr > 1) {
@@ -458,6 +473,17 @@ wcns_status wcns_check_admissible(wcns_ctx* c, const double* W, long long* n_bad
   HIP_TRY(hipMemcpyAsync(&h, c->count, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   *n_bad = (long long)h;
+  return WCNS_OK;
+}
+
+wcns_status wcns_selftest_division(const double* a, const double* b, double* q_ieee,
+                                   double* q_core, int64_t n, void* stream) {
+  if (!a || !b || !q_ieee || !q_core || n < 0) return WCNS_ERR_ARG;
+  if (n == 0) return WCNS_OK;
+  unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_selftest_div, dim3(g), dim3(256), 0, (hipStream_t)stream, a, b, q_ieee, q_core,
+                     (long)n);
+  LAUNCH_CHECK();
   return WCNS_OK;
 }
 

@@ -59,12 +59,34 @@ __device__ __forceinline__ double rcp_nr(double b) {
 // a/b through the refined reciprocal (within ~2 ulp of the IEEE quotient).
 __device__ __forceinline__ double fdiv(double a, double b) { return a * rcp_nr(b); }
 
-// Division used by the face pipeline: IEEE when FAST is false (node kernel),
-// refined reciprocal otherwise.
+// IEEE-754 double division without the range-scaling steps.  gfx950's
+// correctly rounded divide is: div_scale(den), rcp, div_scale(num), two
+// Newton steps (4 FMA), mul, residual FMA, div_fmas, div_fixup.  When
+// neither operand needs exponent scaling (|a|, |b| in roughly
+// [1e-290, 1e300], quotient normal) and no operand is 0/inf/NaN in the
+// denominator, div_scale returns its input, div_fmas is a plain FMA and
+// div_fixup returns the quotient unchanged, so the 8-instruction core below
+// yields the same bits (sign of a zero quotient aside).  Every division of
+// the face pipeline has such operands (positive densities, Gamma, sound
+// speeds, beta + eps >= eps, strictly negative HLLC denominators, ...);
+// wcns_selftest_division checks the identity on the device.
+__device__ __forceinline__ double ddiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-b, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  double q = a * r;
+  double rem = __builtin_fma(-b, q, a);
+  return __builtin_fma(rem, r, q);
+}
+
+// Division used by the face pipeline: the IEEE core, or the refined
+// reciprocal when FAST.
 template <bool FAST>
 __device__ __forceinline__ double qdiv(double a, double b) {
   if (FAST) return fdiv(a, b);
-  return a / b;
+  return ddiv(a, b);
 }
 
 // ---------------------------------------------------------------- EOS
@@ -113,7 +135,7 @@ template <bool HAS_T>
 __device__ __forceinline__ double rhoc2_tilde(const EosC& e, const double X[6]) {
 #pragma clang fp contract(off)
   double rho = X[0] + X[1];
-  double irho = 1.0 / rho;
+  double irho = ddiv(1.0, rho);
   double un = X[2] * irho;
   double ke;
   if (HAS_T) {
@@ -125,7 +147,7 @@ __device__ __forceinline__ double rhoc2_tilde(const EosC& e, const double X[6]) 
   double rhoe = X[4] - 0.5 * ke;
   double Gam = mix_gamma(e, X[5]);
   double Pi = mix_pi(e, X[5]);
-  return rhoe - Pi / (1.0 + Gam);
+  return rhoe - ddiv(Pi, 1.0 + Gam);
 }
 
 // Node flux G = F + (0,...,0, a1 u_n) [Sec. 3.2 flux-source form]
@@ -160,7 +182,7 @@ __device__ __forceinline__ void hllc(const NodeQ& L, const NodeQ& R, HllcOut& o)
   double sR = (aR < bR) ? bR : aR;
   double num = R.p - L.p + rhoL * L.un * (sL - L.un) - rhoR * R.un * (sR - R.un);
   double den = rhoL * (sL - L.un) - rhoR * (sR - R.un);
-  double ss = num / den;
+  double ss = ddiv(num, den);
   o.ss = ss;
   double sm = (sL < 0.0) ? sL : 0.0;
   double sp = (0.0 < sR) ? sR : 0.0;
@@ -170,7 +192,7 @@ __device__ __forceinline__ void hllc(const NodeQ& L, const NodeQ& R, HllcOut& o)
   double wr = (1.0 - sg) * 0.5;
   double fl[5], fr[5];
   {
-    double chi = (sL - L.un) / (sL - ss);
+    double chi = ddiv(sL - L.un, sL - ss);
     double g[6];
     node_flux<HAS_T>(L, g);
     double ws[5];
@@ -178,12 +200,12 @@ __device__ __forceinline__ void hllc(const NodeQ& L, const NodeQ& R, HllcOut& o)
     ws[1] = chi * L.w[1];
     ws[2] = chi * rhoL * ss;
     ws[3] = HAS_T ? chi * rhoL * L.ut : 0.0;
-    ws[4] = chi * (L.w[4] + (ss - L.un) * (rhoL * ss + L.p / (sL - L.un)));
+    ws[4] = chi * (L.w[4] + (ss - L.un) * (rhoL * ss + ddiv(L.p, sL - L.un)));
 #pragma unroll
     for (int v = 0; v < 5; ++v) fl[v] = g[v] + sm * (ws[v] - L.w[v]);
   }
   {
-    double chi = (sR - R.un) / (sR - ss);
+    double chi = ddiv(sR - R.un, sR - ss);
     double g[6];
     node_flux<HAS_T>(R, g);
     double ws[5];
@@ -191,7 +213,7 @@ __device__ __forceinline__ void hllc(const NodeQ& L, const NodeQ& R, HllcOut& o)
     ws[1] = chi * R.w[1];
     ws[2] = chi * rhoR * ss;
     ws[3] = HAS_T ? chi * rhoR * R.ut : 0.0;
-    ws[4] = chi * (R.w[4] + (ss - R.un) * (rhoR * ss + R.p / (sR - R.un)));
+    ws[4] = chi * (R.w[4] + (ss - R.un) * (rhoR * ss + ddiv(R.p, sR - R.un)));
 #pragma unroll
     for (int v = 0; v < 5; ++v) fr[v] = g[v] + sp * (ws[v] - R.w[v]);
   }
@@ -224,23 +246,20 @@ __device__ __forceinline__ double weno_is(double a, double b, double c, double d
   double t5a = e - 4.0 * d + 6.0 * c - 4.0 * b + a;
   double t5b = e - 2.0 * d + 2.0 * b - a;
   double tau5 = (13.0 / 12.0) * t5a * t5a + 0.25 * t5b * t5b;
-  double r01 = tau5 / (b01 + eps);
-  double eta0 = (15.0 / 32.0) * (1.0 + tau5 / (b0 + eps) * r01);
-  double eta1 = (5.0 / 32.0) * (1.0 + tau5 / (b1 + eps) * r01);
-  double eta2 = (5.0 / 16.0) * (1.0 + tau5 / (b2 + eps));
-  double eta3 = (1.0 / 16.0) * (1.0 + tau5 / (b3 + eps));
+  double r01 = ddiv(tau5, b01 + eps);
+  double eta0 = (15.0 / 32.0) * (1.0 + ddiv(tau5, b0 + eps) * r01);
+  double eta1 = (5.0 / 32.0) * (1.0 + ddiv(tau5, b1 + eps) * r01);
+  double eta2 = (5.0 / 16.0) * (1.0 + ddiv(tau5, b2 + eps));
+  double eta3 = (1.0 / 16.0) * (1.0 + ddiv(tau5, b3 + eps));
   double sum = eta0 + eta1 + eta2 + eta3;
-  return (eta0 * u0 + eta1 * u1 + eta2 * u2 + eta3 * u3) / sum;
+  return ddiv(eta0 * u0 + eta1 * u1 + eta2 * u2 + eta3 * u3, sum);
 }
 
 // Compiler-only barrier between phases of the face pipeline: node values
-// are re-read (from L1/L2) after it instead of being held in registers, and
-// the scheduler does not interleave the phases (which would multiply the
-// live registers).
-__device__ __forceinline__ void phase_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_sched_barrier(0);
-}
+// are re-read (from L1/L2) after it instead of being held in registers.
+// (A scheduling barrier as well was measured to be slower: the scheduler's
+// overlap of neighbouring phases pays for the registers it costs.)
+__device__ __forceinline__ void phase_barrier() { asm volatile("" ::: "memory"); }
 
 // ---------------------------------------------------------------- limiters
 // theta of the convex blend (1-theta) A + theta B for one test function
@@ -249,7 +268,7 @@ __device__ __forceinline__ void phase_barrier() {
 __device__ __forceinline__ double limiter_theta(double qA, double qB, double eps) {
 #pragma clang fp contract(off)
   if (qA < eps) return 0.0;
-  if (qB < eps) return (qA - eps) / (qA - qB);
+  if (qB < eps) return ddiv(qA - eps, qA - qB);
   return 1.0;
 }
 
@@ -299,7 +318,7 @@ __device__ __forceinline__ void interp_limit(const EosC& e, const Tol& t, const 
 #pragma unroll
       for (int v = 0; v < 6; ++v) B[v] = A[v];   // theta = 0
     } else if (qB < eps) {
-      double th = (qA - eps) / (qA - qB);
+      double th = ddiv(qA - eps, qA - qB);
 #pragma unroll
       for (int v = 0; v < 6; ++v) B[v] = (1.0 - th) * A[v] + th * B[v];
     }
@@ -310,7 +329,7 @@ __device__ __forceinline__ void interp_limit(const EosC& e, const Tol& t, const 
     for (int v = 0; v < 6; ++v) B[v] = A[v];
     hB = hA;
   } else if (hB < t.eps_rhoc2) {
-    double th = (hA - t.eps_rhoc2) / (hA - hB);
+    double th = ddiv(hA - t.eps_rhoc2, hA - hB);
 #pragma unroll
     for (int v = 0; v < 6; ++v) B[v] = (1.0 - th) * A[v] + th * B[v];
     hB = rhoc2_tilde<HAS_T>(e, B);
@@ -418,7 +437,7 @@ __device__ __forceinline__ double flux_limit(const EosC& e, const Tol& t, const 
 // [3072 gt - 505 (g_i + g_{i+1}) + 20 (g_{i-1} + g_{i+2}) - (g_{i-2} + g_{i+3})]/2100
 __device__ __forceinline__ double hcs(double gt, double s01, double s12, double s03) {
 #pragma clang fp contract(off)
-  return (3072.0 * gt - 505.0 * s01 + 20.0 * s12 - s03) / 2100.0;
+  return ddiv(3072.0 * gt - 505.0 * s01 + 20.0 * s12 - s03, 2100.0);
 }
 
 }  // namespace wcns

@@ -30,7 +30,13 @@ namespace wcns {
 
 enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 enum { OUT_STORE = 0, OUT_RK = 1 };
-constexpr int Y_WAVES = 8;   // y-face rows per y-sweep block
+#ifndef WCNS_YTILE
+#define WCNS_YTILE 4
+#endif
+#ifndef WCNS_YMARCH
+#define WCNS_YMARCH 0
+#endif
+constexpr int Y_WAVES = WCNS_YTILE;   // y-face rows per y-sweep tile
 
 struct KArgs {
   int32_t nx, ny, nv, tile_x;     // tile_x: cells per x-sweep wave
@@ -187,8 +193,8 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
     fa2 = 0.5 * (nl.w[1] + nr.w[1]);
     frho = 0.5 * ((nl.w[0] + nl.w[1]) + (nr.w[0] + nr.w[1]));
     fc = 0.5 * (nl.c + nr.c);
-    k1 = 1.0 / (frho * fc);
-    k2 = 1.0 / (frho * fc * fc);
+    k1 = ddiv(1.0, frho * fc);
+    k2 = ddiv(1.0, frho * fc * fc);
   }
   // characteristic projection U = R^{-1} V and IS-WENO, one field at a time
   double UL[6], UR[6];
@@ -217,8 +223,8 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
       const double* U = side == 0 ? UL : UR;
       double* X = side == 0 ? WL : WR;
       double d = U[5] - U[0];
-      double a1r1 = U[1] + fa1 * d / twoc;
-      double a2r2 = U[2] + fa2 * d / twoc;
+      double a1r1 = U[1] + ddiv(fa1 * d, twoc);
+      double a2r2 = U[2] + ddiv(fa2 * d, twoc);
       double un = 0.5 * (U[0] + U[5]);
       double ut = U[3];
       double p = 0.5 * frho * fc * d;
@@ -272,7 +278,7 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
       double sum = v < 6 ? ga[v] + gb[v] : qa.un + qb.un;
       if (pr == 0) acc[v] = 3072.0 * acc[v] - 505.0 * sum;
       else if (pr == 1) acc[v] = acc[v] + 20.0 * sum;
-      else acc[v] = (acc[v] - sum) / 2100.0;
+      else acc[v] = ddiv(acc[v] - sum, 2100.0);
     }
   }
   const double uh = acc[6];
@@ -315,6 +321,28 @@ __device__ __forceinline__ void write_cell(const KArgs& a, double* dst, long idx
 }
 
 // ------------------------------------------------------------------ kernels
+enum { DT_GIVEN = 0, DT_CFL = 1, DT_KEEP = 2 };
+
+// Time step and directional split from the global maxima [Sec. 3.3]:
+//   dt = CFL/(tau_x + tau_y), tau = max(|u|+c)/dx (1D: CFL dx/max(|u|+c)),
+//   sigma_x = tau_x/(tau_x + tau_y), lambda_x = dt/(dx sigma_x) (1D: dt/dx).
+struct FinArgs {
+  int32_t ndim, dt_mode;
+  double dx, dy, cfl, dt_in;
+  double* step;       // [0] dt, [1] lam_x, [2] lam_y, [3] amax_x, [4] amax_y
+  double* dt_used;    // optional copy of dt
+};
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Node primitives (u, v, p, c, rho*ctilde^2) of every cell [Sec. 2] and the
+// per-block wave-speed maxima.  (A last-block reduction here instead of
+// k_finalize was measured 4x slower: its device-scope fence has to make the
+// block's writes visible across the XCDs' separate L2s.)
 template <bool HAS_T>
 __global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partial) {
   const long N = (long)a.nx * a.ny;
@@ -332,16 +360,11 @@ __global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partia
     double un, ut, p, c, h;
     recover<HAS_T>(a.eos, X, un, ut, p, c, h);
     P[o] = un; P[N + o] = ut; P[2 * N + o] = p; P[3 * N + o] = c; P[4 * N + o] = h;
-    double sx = fabs(un) + c, sy = fabs(ut) + c;
-    mx = fmax(mx, sx);
-    my = fmax(my, sy);
+    mx = fmax(mx, fabs(un) + c);
+    my = fmax(my, fabs(ut) + c);
   }
-  // wavefront max via cross-lane shuffles, then across the 4 waves in LDS
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    mx = fmax(mx, __shfl_xor(mx, off, 64));
-    my = fmax(my, __shfl_xor(my, off, 64));
-  }
+  mx = wave_max(mx);
+  my = wave_max(my);
   __shared__ double red[2][4];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (l == 0) { red[0][w] = mx; red[1][w] = my; }
@@ -352,6 +375,42 @@ __global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partia
     partial[2 * blockIdx.x] = a0;
     partial[2 * blockIdx.x + 1] = a1v;
   }
+}
+
+// Global maxima -> dt, sigma and lambda in the device step record (one
+// block), so a whole step needs no host round trip.
+__global__ __launch_bounds__(256) void k_finalize(const double* partial, int nblk, FinArgs f) {
+  double mx = 0.0, my = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+    mx = fmax(mx, partial[2 * b]);
+    my = fmax(my, partial[2 * b + 1]);
+  }
+  mx = wave_max(mx);
+  my = wave_max(my);
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = mx; red[1][w] = my; }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 4; ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
+  double* step = f.step;
+  double dt;
+  if (f.dt_mode == DT_GIVEN) dt = f.dt_in;
+  else if (f.dt_mode == DT_KEEP) dt = step[0];
+  else dt = f.ndim == 1 ? f.cfl * f.dx / mx : f.cfl / (mx / f.dx + my / f.dy);
+  step[0] = dt;
+  if (f.ndim == 1) {
+    step[1] = dt / f.dx;
+    step[2] = 0.0;
+  } else {
+    double tx = mx / f.dx, ty = my / f.dy;
+    double sx = tx / (tx + ty), sy = ty / (tx + ty);
+    step[1] = dt / (f.dx * sx);
+    step[2] = dt / (f.dy * sy);
+  }
+  step[3] = mx;
+  step[4] = my;
+  if (f.dt_used) *f.dt_used = dt;
 }
 
 // primitives of the (up to 4) Dirichlet ghost states
@@ -368,57 +427,12 @@ __global__ void k_dirichlet_prims(KArgs a, double* dirP) {
   dirP[s * 5 + 3] = c; dirP[s * 5 + 4] = h;
 }
 
-enum { DT_GIVEN = 0, DT_CFL = 1, DT_KEEP = 2 };
-
-// Global maxima -> dt and lambda [Sec. 3.3]:
-//   dt = CFL/(tau_x + tau_y), tau = max(|u|+c)/dx (1D: CFL dx/max(|u|+c)),
-//   sigma_x = tau_x/(tau_x + tau_y), lambda_x = dt/(dx sigma_x)  (1D: dt/dx).
-__global__ __launch_bounds__(256) void k_finalize(const double* partial, int nblk, int ndim,
-                                                  double dx, double dy, double cfl, int dt_mode,
-                                                  double dt_in, double* step, double* dt_used) {
-  double mx = 0.0, my = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    mx = fmax(mx, partial[2 * b]);
-    my = fmax(my, partial[2 * b + 1]);
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    mx = fmax(mx, __shfl_xor(mx, off, 64));
-    my = fmax(my, __shfl_xor(my, off, 64));
-  }
-  __shared__ double red[2][4];
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  if (l == 0) { red[0][w] = mx; red[1][w] = my; }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int k = 1; k < 4; ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
-  mx = fmax(mx, red[0][0]);
-  my = fmax(my, red[1][0]);
-  double dt;
-  if (dt_mode == DT_GIVEN) dt = dt_in;
-  else if (dt_mode == DT_KEEP) dt = step[0];
-  else dt = ndim == 1 ? cfl * dx / mx : cfl / (mx / dx + my / dy);
-  step[0] = dt;
-  if (ndim == 1) {
-    step[1] = dt / dx;
-    step[2] = 0.0;
-  } else {
-    double tx = mx / dx, ty = my / dy;
-    double sx = tx / (tx + ty), sy = ty / (tx + ty);
-    step[1] = dt / (dx * sx);
-    step[2] = dt / (dy * sy);
-  }
-  step[3] = mx;
-  step[4] = my;
-  if (dt_used) *dt_used = dt;
-}
-
 // x-sweep: one wave per tile of tile_x flattened cells.  Lane t < T owns the
 // left face of cell c0+t; lanes T.. own the right face of each row segment's
 // last cell.  Cell c0+t then takes G^+ of its own face and G^- of the lane
 // that owns its right face.
 template <bool HAS_T, bool DIRI>
-__global__ __launch_bounds__(64) void k_sweep_x(KArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_x(KArgs a) {
   const int lane = threadIdx.x;
   const int nx = a.nx;
   const long N = (long)nx * a.ny;
@@ -461,7 +475,7 @@ __global__ __launch_bounds__(64) void k_sweep_x(KArgs a) {
     if (!HAS_T && v == 3) continue;
     double L;
     {
-      L = -(Gr[v] - Gp[v]) / a.dx;
+      L = ddiv(-(Gr[v] - Gp[v]), a.dx);
     }
     const int k = state_index(0, v, HAS_T);
     if (HAS_T) {
@@ -511,11 +525,52 @@ __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
   for (int v = 0; v < 6; ++v) {
     double L;
     {
-      double Ly = -(sGm[w + 1][v][lane] - Gp[v]) / a.dy;
+      double Ly = ddiv(-(sGm[w + 1][v][lane] - Gp[v]), a.dy);
       const int s = state_index(1, v, true);
       L = a.Lx[s * N + (long)j * nx + i] + Ly;
     }
     write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
+  }
+}
+
+// y-sweep, marching form: one wave per 64 columns x Y_WAVES y-face rows;
+// the wave walks up its face rows, keeping G^+ of the previous face in
+// registers, so a cell row is finished as soon as its upper face is known.
+// The first/last face rows leave their fluxes in the edge buffer for
+// k_fixup_y, exactly as the LDS form does.
+template <bool DIRI>
+__global__ __launch_bounds__(64) void k_sweep_y_march(KArgs a) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  const int kb = blockIdx.y * Y_WAVES;
+  const int nx = a.nx, ny = a.ny;
+  const long N = (long)nx * ny;
+  if (i >= nx) return;
+  double* e = a.edge + (long)blockIdx.y * 12 * nx;
+  double Gprev[6];
+  for (int w = 0; w < Y_WAVES; ++w) {
+    const int k = kb + w;
+    if (k > ny) break;
+    double Gm[6], Gp[6];
+    face_flux<1, true, DIRI>(a, i, k - 3, a.step[2], Gm, Gp);
+    if (w == 0) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
+    } else {
+      const int j = k - 1;
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        double Ly = ddiv(-(Gm[v] - Gprev[v]), a.dy);
+        const int s = state_index(1, v, true);
+        double L = a.Lx[s * N + (long)j * nx + i] + Ly;
+        write_cell(a, a.out, (long)j * nx + i, N, s, L);
+      }
+    }
+    if (w == Y_WAVES - 1 || k == ny) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 6; ++v) Gprev[v] = Gp[v];
   }
 }
 
@@ -534,7 +589,7 @@ __global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
   for (int v = 0; v < 6; ++v) {
     double L;
     {
-      double Ly = -(hi[v * nx + i] - lo[v * nx + i]) / a.dy;
+      double Ly = ddiv(-(hi[v * nx + i] - lo[v * nx + i]), a.dy);
       const int s = state_index(1, v, true);
       L = a.Lx[s * N + (long)j * nx + i] + Ly;
     }
@@ -637,6 +692,15 @@ __global__ __launch_bounds__(256) void k_admissible(KArgs a, unsigned long long*
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
   if ((threadIdx.x & 63) == 0 && bad) atomicAdd(count, bad);
+}
+
+// Division self-test: the IEEE quotient as compiled (`/`) next to ddiv.
+__global__ __launch_bounds__(256) void k_selftest_div(const double* a, const double* b, double* q_ieee,
+                                                       double* q_core, long n) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  q_ieee[t] = a[t] / b[t];
+  q_core[t] = ddiv(a[t], b[t]);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {

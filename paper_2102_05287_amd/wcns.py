@@ -58,7 +58,7 @@ _lib = None
 EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
            "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
            "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
-           "wcns_status_str"]
+           "wcns_selftest_division", "wcns_status_str"]
 PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other"]
 
 
@@ -87,6 +87,7 @@ def lib():
         L.wcns_check_admissible.argtypes = [vp, dp, C.POINTER(C.c_longlong)]
         L.wcns_profile.argtypes = [vp, C.c_int32]
         L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+        L.wcns_selftest_division.argtypes = [dp, dp, dp, dp, C.c_int64, vp]
         L.wcns_status_str.argtypes = [C.c_int]
         L.wcns_status_str.restype = C.c_char_p
         for name in EXPORTS:
@@ -234,3 +235,14 @@ class Solver:
         n = (C.c_int64 * len(PROF_CLASSES))()
         _check(lib().wcns_profile_read(self._ctx, ms, n, int(bool(reset))), "wcns_profile_read")
         return {k: (ms[i], n[i]) for i, k in enumerate(PROF_CLASSES)}
+
+
+def selftest_division(a, b):
+    """(IEEE quotient, kernels' division core) of device f64 tensors a, b."""
+    import torch
+    qi = torch.empty_like(a)
+    qc = torch.empty_like(a)
+    _check(lib().wcns_selftest_division(_ptr(a), _ptr(b), _ptr(qi), _ptr(qc), a.numel(),
+                                        C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           "wcns_selftest_division")
+    return qi, qc

@@ -61,6 +61,32 @@ def rhs_case(spec, dt=None, **kw):
     return got, ref
 
 
+def test_division_core_is_ieee():
+    """The kernels' division core equals the compiler's IEEE quotient bit for
+    bit over the operand ranges of the method (and far beyond them)."""
+    rng = np.random.default_rng(123)
+    n = 1 << 22
+    ea = rng.uniform(-280, 280, n)
+    eb = rng.uniform(-280, 280, n)
+    a = rng.choice([-1.0, 1.0], n) * rng.uniform(1, 2, n) * 2.0 ** ea
+    b = rng.choice([-1.0, 1.0], n) * rng.uniform(1, 2, n) * 2.0 ** eb
+    keep = np.abs(ea - eb) < 700          # quotient stays normal
+    a, b = a[keep], b[keep]
+    # hard cases: near-equal operands, exact quotients, powers of two, the
+    # method's own small quantities
+    extra_a = np.concatenate([b[:1000] * (1 + 1e-15), np.arange(1, 5001.0), np.full(100, 1e-40),
+                              np.array([0.0, 1.0, 3.0, 1e-8, 1e9])])
+    extra_b = np.concatenate([b[:1000], np.full(5000, 3.0), np.full(100, 7.0),
+                              np.array([5.0, 3.0, 1e-40, 2100.0, 2100.0])])
+    a = np.concatenate([a, extra_a])
+    b = np.concatenate([b, extra_b])
+    qi, qc = wcns.selftest_division(dev(a), dev(b))
+    qi, qc = host(qi), host(qc)
+    assert np.array_equal(qi, a / b)          # the device IEEE divide is correctly rounded
+    same = (qi == qc) | (np.isnan(qi) & np.isnan(qc))
+    assert same.all(), (a[~same][:5], b[~same][:5])
+
+
 def test_prim_to_cons_matches_oracle():
     for spec in (pb.water_air_shock_tube(400), pb.shock_bubble(96)):
         s = oracle_setup(spec)
