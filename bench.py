@@ -80,6 +80,53 @@ def measured_traffic(kernel):
     return (k["fetch_kib"] * c["fetch_factor"] + k["write_kib"] * c["write_factor"]) * 1024.0
 
 
+def time_steps(sol, W0, steps, warmup):
+    """Seconds for `steps` device-CFL SSP-RK3 steps from W0 (after warmup)."""
+    import torch
+    W = W0.clone()
+    for _ in range(warmup):
+        sol.step(W, 0.0)
+    W.copy_(W0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sol.step(W, 0.0)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, W
+
+
+def precision_form(n, steps, warmup):
+    """Underwater explosion at n^2: FP32-bulk and FP64 paths on the same
+    device, Mcell-updates/s per RHS each, and the relative L1 per variable of
+    the FP32-bulk state against the FP64 one after the same steps (both with
+    the FP64 path's time steps, so the runs are step-aligned)."""
+    import torch
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import wcns
+    spec = pb.underwater_explosion(n)
+    s64 = wcns.Solver.from_spec(spec)
+    s32 = wcns.Solver.from_spec(spec, precision=wcns.FP32_BULK)
+    W0 = s64.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+    t64, W64 = time_steps(s64, W0, steps, warmup)
+    t32, W32 = time_steps(s32, W0, steps, warmup)
+    cells = spec.nx * spec.ny
+    # step-aligned accuracy: same dt sequence (from the FP64 state)
+    A, B = W0.clone(), W0.clone()
+    dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        s64.step(A, 0.0, dt_used=dtu)
+        s32.step(B, float(dtu.item()))
+    l1 = ((B - A).abs().sum(dim=(1, 2)) / A.abs().sum(dim=(1, 2)).clamp_min(1e-300)).tolist()
+    bad = s32.count_inadmissible(B)
+    return {"workload": f"2D underwater explosion near a wall, {n}x{n}",
+            "steps": steps,
+            "fp64_mcells_per_s": 3 * cells * steps / t64 / 1e6,
+            "fp32_bulk_mcells_per_s": 3 * cells * steps / t32 / 1e6,
+            "speedup_fp32_bulk": t64 / t32,
+            "rel_l1_fp32_vs_fp64_per_variable": l1,
+            "inadmissible_fp32": bad}
+
+
 def cpu_baseline(spec, target_s=12.0):
     from oracle import oracle as orc
     s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy, bc=spec.bc)
@@ -106,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision/batched/serving forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -187,6 +236,11 @@ def main():
     torch.cuda.synchronize()
     rhs_rate = cells * nr / (time.perf_counter() - t0) / 1e6
 
+    forms = {}
+    if not args.no_forms:
+        print("# precision form (2048^2 underwater explosion) ...", flush=True)
+        forms["precision_fp32_bulk"] = precision_form(2048, 20, 3)
+
     cpu = None
     if not args.no_cpu:
         print("# cpu baseline (oracle) ...", flush=True)
@@ -205,6 +259,7 @@ def main():
         "rhs_only_mcells_per_s": rhs_rate,
         "per_kernel": per_kernel,
         "inadmissible_after": bad,
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
 

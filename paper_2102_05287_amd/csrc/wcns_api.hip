@@ -169,7 +169,7 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   if (!(prm->cfl > 0.0 && prm->cfl <= 0.5)) return WCNS_ERR_ARG;
   if (!(prm->weno_eps > 0.0)) return WCNS_ERR_ARG;
   if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
-  if (precision != WCNS_FP64) return WCNS_ERR_ARG;
+  if (precision != WCNS_FP64 && precision != WCNS_FP32_BULK) return WCNS_ERR_ARG;
 
   wcns_ctx* c = (wcns_ctx*)calloc(1, sizeof(wcns_ctx));
   if (!c) return WCNS_ERR_NOMEM;
@@ -338,13 +338,18 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   a.cb = cb;
   a.out_mode = mode;
   set_bases(c, a, W);
+  const bool b32 = c->precision == WCNS_FP32_BULK;
   if (c->grid.ndim == 1) {
     a.Lout = nullptr;
     ProfScope ps(c, PROF_X);
-    if (diri(c, 0))
-      hipLaunchKernelGGL((k_sweep_x<false, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((k_sweep_x<false, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    const bool d = diri(c, 0);
+    if (b32) {
+      if (d) hipLaunchKernelGGL((k_sweep_x<false, true, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      else hipLaunchKernelGGL((k_sweep_x<false, false, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    } else {
+      if (d) hipLaunchKernelGGL((k_sweep_x<false, true, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      else hipLaunchKernelGGL((k_sweep_x<false, false, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    }
     LAUNCH_CHECK();
     return WCNS_OK;
   }
@@ -355,26 +360,27 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   a.Lx = lx;
   {
     ProfScope ps(c, PROF_X);
-    if (diri(c, 0))
-      hipLaunchKernelGGL((k_sweep_x<true, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL((k_sweep_x<true, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    const bool d = diri(c, 0);
+    if (b32) {
+      if (d) hipLaunchKernelGGL((k_sweep_x<true, true, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      else hipLaunchKernelGGL((k_sweep_x<true, false, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    } else {
+      if (d) hipLaunchKernelGGL((k_sweep_x<true, true, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      else hipLaunchKernelGGL((k_sweep_x<true, false, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    }
   }
   LAUNCH_CHECK();
   dim3 gy((c->grid.nx + 63) / 64, c->nbr);
   {
     ProfScope ps(c, PROF_Y);
-#if WCNS_YMARCH
-    if (diri(c, 1))
-      hipLaunchKernelGGL(k_sweep_y_march<true>, gy, dim3(64), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL(k_sweep_y_march<false>, gy, dim3(64), 0, c->stream, a);
-#else
-    if (diri(c, 1))
-      hipLaunchKernelGGL(k_sweep_y<true>, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
-    else
-      hipLaunchKernelGGL(k_sweep_y<false>, gy, dim3(64 * Y_WAVES), 0, c->stream, a);
-#endif
+    const bool d = diri(c, 1);
+    if (b32) {
+      if (d) hipLaunchKernelGGL((k_sweep_y<true, true>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+      else hipLaunchKernelGGL((k_sweep_y<false, true>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+    } else {
+      if (d) hipLaunchKernelGGL((k_sweep_y<true, false>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+      else hipLaunchKernelGGL((k_sweep_y<false, false>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
+    }
   }
   LAUNCH_CHECK();
   if (c->nbr > 1) {

@@ -255,6 +255,102 @@ __device__ __forceinline__ double weno_is(double a, double b, double c, double d
   return ddiv(eta0 * u0 + eta1 * u1 + eta2 * u2 + eta3 * u3, sum);
 }
 
+// ---------------------------------------------------------------- FP32 bulk
+// The precision form evaluates the characteristic interpolation, the
+// midpoint HLLC flux and the HCS reconstruction in FP32; the primitive
+// recovery (p, c^2), the limiters' states and theta solves and the
+// first-order HLLC fallback flux stay FP64 (their positivity argument needs
+// it).  FP32 quotients use the hardware reciprocal (~1 ulp).
+__device__ __forceinline__ float fdivf(float a, float b) {
+#pragma clang fp contract(fast)
+  return a * __builtin_amdgcn_rcpf(b);
+}
+
+struct NodeQf {
+  float w[6];
+  float un, ut, p, c;
+};
+
+struct HllcOutF {
+  float F[5];
+  float fa, ss;
+};
+
+// HLLC flux [Sec. 3.1-3.2] in FP32 (same formulas as hllc()).
+template <bool HAS_T>
+__device__ __forceinline__ void hllc_f(const NodeQf& L, const NodeQf& R, HllcOutF& o) {
+#pragma clang fp contract(fast)
+  float rhoL = L.w[0] + L.w[1], rhoR = R.w[0] + R.w[1];
+  float ubar = 0.5f * (L.un + R.un);
+  float cbar = 0.5f * (L.c + R.c);
+  float sL = fminf(ubar - cbar, L.un - L.c);
+  float sR = fmaxf(ubar + cbar, R.un + R.c);
+  float num = R.p - L.p + rhoL * L.un * (sL - L.un) - rhoR * R.un * (sR - R.un);
+  float den = rhoL * (sL - L.un) - rhoR * (sR - R.un);
+  float ss = fdivf(num, den);
+  o.ss = ss;
+  float sm = fminf(sL, 0.0f);
+  float sp = fmaxf(sR, 0.0f);
+  float sg = (ss > 0.0f) ? 1.0f : ((ss < 0.0f) ? -1.0f : 0.0f);
+  float wl = (1.0f + sg) * 0.5f;
+  float wr = (1.0f - sg) * 0.5f;
+  float fl[5], fr[5];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const NodeQf& K = side == 0 ? L : R;
+    float rho = side == 0 ? rhoL : rhoR;
+    float sK = side == 0 ? sL : sR;
+    float sE = side == 0 ? sm : sp;
+    float chi = fdivf(sK - K.un, sK - ss);
+    float g[5] = {K.w[0] * K.un, K.w[1] * K.un, K.w[2] * K.un + K.p, HAS_T ? K.w[3] * K.un : 0.0f,
+                  (K.w[4] + K.p) * K.un};
+    float ws[5];
+    ws[0] = chi * K.w[0];
+    ws[1] = chi * K.w[1];
+    ws[2] = chi * rho * ss;
+    ws[3] = HAS_T ? chi * rho * K.ut : 0.0f;
+    ws[4] = chi * (K.w[4] + (ss - K.un) * (rho * ss + fdivf(K.p, sK - K.un)));
+    float* f = side == 0 ? fl : fr;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) f[v] = g[v] + sE * (ws[v] - K.w[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) o.F[v] = wl * fl[v] + wr * fr[v];
+  o.fa = wl * (L.w[5] * ss) + wr * (R.w[5] * ss);
+}
+
+// IS-WENO interpolation [Sec. 4.3] in FP32.  Guard for the FP32 range:
+// eps is raised to 1e-30 (1e-40 is subnormal in FP32) and each ratio
+// tau_5/(beta + eps) is capped at 1e15 so the products of two ratios stay
+// finite; a capped weight still exceeds the others by ~1e15, far beyond FP32
+// resolution, so the selected stencils are unchanged.
+__device__ __forceinline__ float weno_is_f(float a, float b, float c, float d, float e, float eps) {
+#pragma clang fp contract(fast)
+  const float cap = 1e15f;
+  float u0 = 0.5f * (c + d);
+  float u1 = 0.5f * (-b + 3.0f * c);
+  float u2 = 0.125f * (3.0f * c + 6.0f * d - e);
+  float u3 = 0.125f * (3.0f * a - 10.0f * b + 15.0f * c);
+  float b0 = (c - d) * (c - d);
+  float b1 = (b - c) * (b - c);
+  float t01a = b - 2.0f * c + d, t01b = b - d;
+  float b01 = (13.0f / 12.0f) * t01a * t01a + 0.25f * t01b * t01b;
+  float t2a = c - 2.0f * d + e, t2b = 3.0f * c - 4.0f * d + e;
+  float b2 = (13.0f / 12.0f) * t2a * t2a + 0.25f * t2b * t2b;
+  float t3a = a - 2.0f * b + c, t3b = a - 4.0f * b + 3.0f * c;
+  float b3 = (13.0f / 12.0f) * t3a * t3a + 0.25f * t3b * t3b;
+  float t5a = e - 4.0f * d + 6.0f * c - 4.0f * b + a;
+  float t5b = e - 2.0f * d + 2.0f * b - a;
+  float tau5 = (13.0f / 12.0f) * t5a * t5a + 0.25f * t5b * t5b;
+  float r01 = fminf(fdivf(tau5, b01 + eps), cap);
+  float eta0 = (15.0f / 32.0f) * (1.0f + fminf(fdivf(tau5, b0 + eps), cap) * r01);
+  float eta1 = (5.0f / 32.0f) * (1.0f + fminf(fdivf(tau5, b1 + eps), cap) * r01);
+  float eta2 = (5.0f / 16.0f) * (1.0f + fminf(fdivf(tau5, b2 + eps), cap));
+  float eta3 = (1.0f / 16.0f) * (1.0f + fminf(fdivf(tau5, b3 + eps), cap));
+  float sum = eta0 + eta1 + eta2 + eta3;
+  return fdivf(eta0 * u0 + eta1 * u1 + eta2 * u2 + eta3 * u3, sum);
+}
+
 // Compiler-only barrier between phases of the face pipeline: node values
 // are re-read (from L1/L2) after it instead of being held in registers.
 // (A scheduling barrier as well was measured to be slower: the scheduler's

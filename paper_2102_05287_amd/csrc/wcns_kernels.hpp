@@ -30,13 +30,9 @@ namespace wcns {
 
 enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 enum { OUT_STORE = 0, OUT_RK = 1 };
-#ifndef WCNS_YTILE
-#define WCNS_YTILE 4
-#endif
-#ifndef WCNS_YMARCH
-#define WCNS_YMARCH 0
-#endif
-constexpr int Y_WAVES = WCNS_YTILE;   // y-face rows per y-sweep tile
+// y-face rows per y-sweep block (4 measured fastest against 2 and 8, and
+// against a one-wave form that marches up the rows)
+constexpr int Y_WAVES = 4;
 
 struct KArgs {
   int32_t nx, ny, nv, tile_x;     // tile_x: cells per x-sweep wave
@@ -165,7 +161,7 @@ __device__ __forceinline__ double char_field(int f, const NodeQ& q, double fa1, 
 // Stencil nodes i-2 .. i+3 are g0 .. g0+5 along the line.  Node data are
 // re-read from the cache in each phase (phase_barrier) to keep the live
 // register set small.
-template <int DIR, bool HAS_T, bool DIRI>
+template <int DIR, bool HAS_T, bool DIRI, bool B32 = false>
 __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, double lam,
                                             double Gm[6], double Gp[6]) {
   const EosC& e = a.eos;
@@ -197,10 +193,13 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
     k2 = ddiv(1.0, frho * fc * fc);
   }
   // characteristic projection U = R^{-1} V and IS-WENO, one field at a time
+  // (FP32 interpolation in the precision form)
   double UL[6], UR[6];
+  float ULf[6], URf[6];
+  const float eps32 = fmaxf((float)a.tol.weno_eps, 1e-30f);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
-    if (!HAS_T && f == 3) { UL[3] = 0.0; UR[3] = 0.0; continue; }
+    if (!HAS_T && f == 3) { UL[3] = 0.0; UR[3] = 0.0; ULf[3] = 0.0f; URf[3] = 0.0f; continue; }
     phase_barrier();
     double u[6];
 #pragma unroll
@@ -209,14 +208,54 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
       load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
       u[m] = char_field(f, q, fa1, fa2, k1, k2);
     }
-    UL[f] = weno_is(u[0], u[1], u[2], u[3], u[4], a.tol.weno_eps);
-    phase_barrier();
-    UR[f] = weno_is(u[5], u[4], u[3], u[2], u[1], a.tol.weno_eps);
+    if constexpr (B32) {
+      float v[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) v[m] = (float)u[m];
+      ULf[f] = weno_is_f(v[0], v[1], v[2], v[3], v[4], eps32);
+      URf[f] = weno_is_f(v[5], v[4], v[3], v[2], v[1], eps32);
+    } else {
+      UL[f] = weno_is(u[0], u[1], u[2], u[3], u[4], a.tol.weno_eps);
+      phase_barrier();
+      UR[f] = weno_is(u[5], u[4], u[3], u[2], u[1], a.tol.weno_eps);
+    }
   }
   phase_barrier();
+  if constexpr (B32) {
+    // back-projection V = R U in FP32 [App. A]
+    const float c2f = 2.0f * (float)fc, fa1f = (float)fa1, fa2f = (float)fa2;
+    const float half_rc = 0.5f * (float)frho * (float)fc;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const float* U = side == 0 ? ULf : URf;
+      double* V = side == 0 ? UL : UR;   // reused as primitive storage
+      float d = U[5] - U[0];
+      V[0] = (double)(U[1] + fdivf(fa1f * d, c2f));
+      V[1] = (double)(U[2] + fdivf(fa2f * d, c2f));
+      V[2] = (double)(0.5f * (U[0] + U[5]));
+      V[3] = (double)U[3];
+      V[4] = (double)(half_rc * d);
+      V[5] = (double)U[4];
+    }
+  }
   // back-projection V = R U, then V -> W [App. A; Sec. 2]
   double WL[6], WR[6];
-  {
+  if constexpr (B32) {
+    // FP64 conservative state (the energy needs FP64: Pi ~ 4e8 vs Gamma p)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const double* V = side == 0 ? UL : UR;
+      double* X = side == 0 ? WL : WR;
+      double rho = V[0] + V[1];
+      X[0] = V[0];
+      X[1] = V[1];
+      X[2] = rho * V[2];
+      X[3] = HAS_T ? rho * V[3] : 0.0;
+      double ke = HAS_T ? (V[2] * V[2] + V[3] * V[3]) : V[2] * V[2];
+      X[4] = mix_gamma(e, V[5]) * V[4] + mix_pi(e, V[5]) + 0.5 * rho * ke;
+      X[5] = V[5];
+    }
+  } else {
     double twoc = 2.0 * fc;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -250,19 +289,41 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
     phase_barrier();
   }
   // high-order midpoint flux from the limited states [WCNS step 6]
-  HllcOut h2;
+  // (p and c recovered in FP64; the flux itself in FP32 in the precision form)
+  double acc[7];
   {
     NodeQ tl, tr;
 #pragma unroll
     for (int v = 0; v < 6; ++v) { tl.w[v] = WL[v]; tr.w[v] = WR[v]; }
     recover<HAS_T>(e, tl.w, tl.un, tl.ut, tl.p, tl.c, tl.h);
     recover<HAS_T>(e, tr.w, tr.un, tr.ut, tr.p, tr.c, tr.h);
-    hllc<HAS_T>(tl, tr, h2);
+    if constexpr (B32) {
+      NodeQf fl, fr;
+#pragma unroll
+      for (int v = 0; v < 6; ++v) { fl.w[v] = (float)tl.w[v]; fr.w[v] = (float)tr.w[v]; }
+      fl.un = (float)tl.un; fl.ut = (float)tl.ut; fl.p = (float)tl.p; fl.c = (float)tl.c;
+      fr.un = (float)tr.un; fr.ut = (float)tr.ut; fr.p = (float)tr.p; fr.c = (float)tr.c;
+      HllcOutF h2;
+      hllc_f<HAS_T>(fl, fr, h2);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v] = h2.F[v];
+      acc[5] = h2.fa;
+      acc[6] = h2.ss;
+    } else {
+      HllcOut h2;
+      hllc<HAS_T>(tl, tr, h2);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) acc[v] = h2.F[v];
+      acc[5] = h2.fa;
+      acc[6] = h2.ss;
+    }
   }
   // HCS reconstruction of flux and velocity [Sec. 4.1; WCNS steps 7-8]:
   // ((3072 gt - 505 s01) + 20 s12 - s03)/2100, node pairs s01 = (i, i+1),
   // s12 = (i-1, i+2), s03 = (i-2, i+3)
-  double acc[7] = {h2.F[0], h2.F[1], h2.F[2], h2.F[3], h2.F[4], h2.fa, h2.ss};
+  float accf[7];
+#pragma unroll
+  for (int v = 0; v < 7; ++v) accf[v] = (float)acc[v];
 #pragma unroll
   for (int pr = 0; pr < 3; ++pr) {
     phase_barrier();
@@ -275,11 +336,22 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
     node_flux<HAS_T>(qb, gb);
 #pragma unroll
     for (int v = 0; v < 7; ++v) {
-      double sum = v < 6 ? ga[v] + gb[v] : qa.un + qb.un;
-      if (pr == 0) acc[v] = 3072.0 * acc[v] - 505.0 * sum;
-      else if (pr == 1) acc[v] = acc[v] + 20.0 * sum;
-      else acc[v] = ddiv(acc[v] - sum, 2100.0);
+      if constexpr (B32) {
+        float sum = v < 6 ? (float)ga[v] + (float)gb[v] : (float)qa.un + (float)qb.un;
+        if (pr == 0) accf[v] = 3072.0f * accf[v] - 505.0f * sum;
+        else if (pr == 1) accf[v] = accf[v] + 20.0f * sum;
+        else accf[v] = (accf[v] - sum) * (1.0f / 2100.0f);
+      } else {
+        double sum = v < 6 ? ga[v] + gb[v] : qa.un + qb.un;
+        if (pr == 0) acc[v] = 3072.0 * acc[v] - 505.0 * sum;
+        else if (pr == 1) acc[v] = acc[v] + 20.0 * sum;
+        else acc[v] = ddiv(acc[v] - sum, 2100.0);
+      }
     }
+  }
+  if constexpr (B32) {
+#pragma unroll
+    for (int v = 0; v < 7; ++v) acc[v] = (double)accf[v];
   }
   const double uh = acc[6];
   // split fluxes G^{-+} [Sec. 3.2, WCNS step 9] and the flux limiter
@@ -431,7 +503,7 @@ __global__ void k_dirichlet_prims(KArgs a, double* dirP) {
 // left face of cell c0+t; lanes T.. own the right face of each row segment's
 // last cell.  Cell c0+t then takes G^+ of its own face and G^- of the lane
 // that owns its right face.
-template <bool HAS_T, bool DIRI>
+template <bool HAS_T, bool DIRI, bool B32>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_x(KArgs a) {
   const int lane = threadIdx.x;
   const int nx = a.nx;
@@ -455,7 +527,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     }
   }
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
-  if (active) face_flux<0, HAS_T, DIRI>(a, fj, fk - 3, a.step[1], Gm, Gp);
+  if (active) face_flux<0, HAS_T, DIRI, B32>(a, fj, fk - 3, a.step[1], Gm, Gp);
   // lane holding the right face of my cell
   int src = lane;
   const long c = c0 + lane;
@@ -492,7 +564,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
 // G^- of face row kb + w + 1 (through LDS).  The last face row of the tile
 // leaves G^+ in the edge buffer and the first one G^-; k_fixup_y finishes the
 // cell row in between.
-template <bool DIRI>
+template <bool DIRI, bool B32>
 __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
   __shared__ double sGm[Y_WAVES][6][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -503,7 +575,7 @@ __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
   const long N = (long)nx * ny;
   const bool active = i < nx && k <= ny;
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
-  if (active) face_flux<1, true, DIRI>(a, i, k - 3, a.step[2], Gm, Gp);
+  if (active) face_flux<1, true, DIRI, B32>(a, i, k - 3, a.step[2], Gm, Gp);
 #pragma unroll
   for (int v = 0; v < 6; ++v) sGm[w][v][lane] = Gm[v];
   // tile edges for the fixup of the straddling cell rows
@@ -530,47 +602,6 @@ __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
       L = a.Lx[s * N + (long)j * nx + i] + Ly;
     }
     write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
-  }
-}
-
-// y-sweep, marching form: one wave per 64 columns x Y_WAVES y-face rows;
-// the wave walks up its face rows, keeping G^+ of the previous face in
-// registers, so a cell row is finished as soon as its upper face is known.
-// The first/last face rows leave their fluxes in the edge buffer for
-// k_fixup_y, exactly as the LDS form does.
-template <bool DIRI>
-__global__ __launch_bounds__(64) void k_sweep_y_march(KArgs a) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int kb = blockIdx.y * Y_WAVES;
-  const int nx = a.nx, ny = a.ny;
-  const long N = (long)nx * ny;
-  if (i >= nx) return;
-  double* e = a.edge + (long)blockIdx.y * 12 * nx;
-  double Gprev[6];
-  for (int w = 0; w < Y_WAVES; ++w) {
-    const int k = kb + w;
-    if (k > ny) break;
-    double Gm[6], Gp[6];
-    face_flux<1, true, DIRI>(a, i, k - 3, a.step[2], Gm, Gp);
-    if (w == 0) {
-#pragma unroll
-      for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
-    } else {
-      const int j = k - 1;
-#pragma unroll
-      for (int v = 0; v < 6; ++v) {
-        double Ly = ddiv(-(Gm[v] - Gprev[v]), a.dy);
-        const int s = state_index(1, v, true);
-        double L = a.Lx[s * N + (long)j * nx + i] + Ly;
-        write_cell(a, a.out, (long)j * nx + i, N, s, L);
-      }
-    }
-    if (w == Y_WAVES - 1 || k == ny) {
-#pragma unroll
-      for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
-    }
-#pragma unroll
-    for (int v = 0; v < 6; ++v) Gprev[v] = Gp[v];
   }
 }
 
