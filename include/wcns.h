@@ -158,6 +158,54 @@ wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int3
 wcns_status wcns_selftest_division(const double* a, const double* b, double* q_ieee,
                                    double* q_core, int64_t n, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent solves of uneven sizes advanced together.
+ * Every phase of a Runge-Kutta stage is one launch over all instances (a
+ * device list of (instance, tile) tasks); a whole step is a fixed sequence
+ * of launches captured once into a HIP graph and replayed, on the batch's
+ * own non-blocking stream.
+ * ---------------------------------------------------------------------- */
+typedef struct wcns_batch wcns_batch;
+
+/* Create a batch of n solves that share ndim, fluids, options and
+ * precision (no Dirichlet sides).  grids[b] is instance b's grid; W[b] its
+ * device state [nvar][ny_b][nx_b] (caller-owned, stepped in place).
+ * capacity_cells: scratch sized for at least this many cells in total (0:
+ * exactly the given instances), so wcns_batch_reset can later rebind other
+ * instance sets without allocating.  Errors as wcns_create, plus
+ * WCNS_ERR_ARG for n < 1, mixed ndim or a Dirichlet side. */
+wcns_status wcns_batch_create(int32_t n, const wcns_grid* grids, const wcns_eos* eos,
+                              const wcns_params* params, int32_t precision, double* const* W,
+                              int64_t capacity_cells, wcns_batch** out);
+
+/* Rebind the batch to another instance set (same ndim) inside its existing
+ * scratch; WCNS_ERR_NOMEM if it does not fit.  Synchronises the batch
+ * stream; the captured graph is rebuilt on the next step. */
+wcns_status wcns_batch_reset(wcns_batch* b, int32_t n, const wcns_grid* grids, double* const* W);
+
+/* Schedule: ytile in {2, 4, 8} y-face rows per y-sweep block; order 0 =
+ * instances in the given order, 1 = largest instance first, 2 = tiles of an
+ * instance kept on one XCD (blocks are dealt round-robin to the 8 XCDs).
+ * Takes effect at the next step (the graph is re-captured). */
+wcns_status wcns_batch_configure(wcns_batch* b, int32_t ytile, int32_t order);
+
+/* Enqueue nsteps SSP-RK3 steps of every instance, each with its own CFL
+ * time step computed on the device (Sec. 3.3, 5.3).  Asynchronous. */
+wcns_status wcns_batch_step(wcns_batch* b, int32_t nsteps);
+
+/* Enqueue one RHS evaluation of every instance into scratch (the states are
+ * not changed); used to time schedules.  Asynchronous. */
+wcns_status wcns_batch_rhs(wcns_batch* b);
+
+/* Wait for the batch stream; return its handle (hipStream_t) in *stream. */
+wcns_status wcns_batch_sync(wcns_batch* b);
+wcns_status wcns_batch_stream(wcns_batch* b, void** stream);
+
+/* Host copy of every instance's last time step, dt[n] (synchronises). */
+wcns_status wcns_batch_dt(wcns_batch* b, double* dt);
+
+wcns_status wcns_batch_destroy(wcns_batch* b);
+
 /* Human-readable status. */
 const char* wcns_status_str(wcns_status s);
 

@@ -8,7 +8,10 @@
 #include <string.h>
 
 #include "../../include/wcns.h"
-#include "wcns_kernels.hpp"
+#include "wcns_batch.hpp"
+
+#include <algorithm>
+#include <vector>
 
 using namespace wcns;
 
@@ -213,6 +216,7 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   long ng = (c->N + 255) / 256;
   c->node_grid = (int)(ng < 2048 ? ng : 2048);
   c->nbr = (g->ny + 1 + Y_WAVES - 1) / Y_WAVES;
+  a.nbr = c->nbr;
 
   wcns_status st = WCNS_OK;
   auto alloc = [&](double** p, size_t n) {
@@ -528,6 +532,421 @@ wcns_status wcns_profile_read(wcns_ctx* c, double* ms, int64_t* launches, int32_
     launches[k] = c->prof_cnt[k];
     if (reset) { c->prof_ms[k] = 0.0; c->prof_cnt[k] = 0; }
   }
+  return WCNS_OK;
+}
+
+
+}  // extern "C"
+
+// ============================================================================
+// Batched form
+// ============================================================================
+struct wcns_batch {
+  int n = 0, ndim = 0, nv = 0, precision = 0;
+  wcns_eos eos;
+  wcns_params params;
+  KArgs proto;
+  hipStream_t stream = nullptr;
+  double* arena = nullptr;
+  size_t arena_cap = 0;        // doubles
+  std::vector<wcns_grid> grids;
+  std::vector<double*> W;
+  std::vector<size_t> off;     // arena offset of each instance's scratch
+  KArgs* d_ka = nullptr;       // [4][n]: stages 1-3 and the RHS-only set
+  size_t ka_cap = 0;
+  Task* d_tasks = nullptr;
+  size_t tasks_cap = 0;
+  int n_node = 0, n_x = 0, n_y = 0, n_fix = 0;
+  size_t o_node = 0, o_x = 0, o_y = 0, o_fix = 0;
+  double* d_dt = nullptr;      // per-instance dt of the last step
+  int dt_cap = 0;
+  int ytile = 4, order = 2;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool dirty = true;
+};
+
+static size_t round32(size_t x) { return (x + 31) & ~(size_t)31; }
+
+// scratch doubles of one instance: P, U1, U2, (L), edge (for the smallest
+// y-tile), block maxima, step record
+static size_t inst_doubles(const wcns_grid& g, int nv) {
+  const size_t N = (size_t)g.nx * g.ny;
+  size_t nblk = (N + 255) / 256;
+  size_t nbr = (size_t)(g.ny + 1 + 1) / 2;
+  size_t d = round32(5 * N) + 2 * round32(nv * N) + round32(2 * nblk) + 32;
+  if (g.ndim == 2) d += round32(nv * N) + round32(nbr * 12 * g.nx);
+  return d;
+}
+
+static wcns_status batch_check_grids(int n, const wcns_grid* grids, int ndim) {
+  for (int b = 0; b < n; ++b) {
+    const wcns_grid& g = grids[b];
+    if (g.ndim != ndim) return WCNS_ERR_ARG;
+    if (g.nx < 1 || g.ny < 1 || (ndim == 1 && g.ny != 1)) return WCNS_ERR_ARG;
+    if ((long)g.nx * g.ny >= (1L << 29)) return WCNS_ERR_ARG;
+    if (!(g.x1 > g.x0) || (ndim == 2 && !(g.y1 > g.y0))) return WCNS_ERR_ARG;
+    for (int d = 0; d < ndim; ++d) {
+      int lo = g.bc[2 * d], hi = g.bc[2 * d + 1];
+      int m = d == 0 ? g.nx : g.ny;
+      for (int k : {lo, hi})
+        if (k < WCNS_BC_PERIODIC || k > WCNS_BC_REFLECT) return WCNS_ERR_ARG;   // no Dirichlet
+      if ((lo == WCNS_BC_PERIODIC) != (hi == WCNS_BC_PERIODIC)) return WCNS_ERR_ARG;
+      if ((lo == WCNS_BC_REFLECT || hi == WCNS_BC_REFLECT) && m < 3) return WCNS_ERR_ARG;
+    }
+  }
+  return WCNS_OK;
+}
+
+static void batch_drop_graph(wcns_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->dirty = true;
+}
+
+// deal a task list to the 8 XCDs in contiguous chunks: block i runs on XCD
+// i % 8, so position 8k + x takes the k-th task of chunk x
+static void xcd_chunk(std::vector<Task>& t) {
+  const size_t M = t.size();
+  if (M < 16) return;
+  std::vector<Task> out;
+  out.reserve(M);
+  const size_t per = (M + 7) / 8;
+  for (size_t k = 0; k < per; ++k)
+    for (size_t x = 0; x < 8; ++x) {
+      size_t src = x * per + k;
+      if (src < M) out.push_back(t[src]);
+    }
+  t.swap(out);
+}
+
+// (re)build the per-instance arguments and the task lists
+static wcns_status batch_build(wcns_batch* b) {
+  const int n = b->n;
+  std::vector<KArgs> ka(4 * (size_t)n);
+  std::vector<int> inst_order(n);
+  for (int k = 0; k < n; ++k) inst_order[k] = k;
+  if (b->order >= 1)
+    std::stable_sort(inst_order.begin(), inst_order.end(), [&](int p, int q) {
+      return (long)b->grids[p].nx * b->grids[p].ny > (long)b->grids[q].nx * b->grids[q].ny;
+    });
+  std::vector<Task> tn, tx, ty, tf;
+  const int yw = b->ytile;
+  for (int k = 0; k < n; ++k) {
+    const wcns_grid& g = b->grids[k];
+    const long N = (long)g.nx * g.ny;
+    double* base = b->arena + b->off[k];
+    double* P = base;
+    double* U1 = P + round32(5 * N);
+    double* U2 = U1 + round32((size_t)b->nv * N);
+    double* part = U2 + round32((size_t)b->nv * N);
+    const int nblk = (int)((N + 255) / 256);
+    double* step = part + round32(2 * (size_t)nblk);
+    double* L = step + 32;
+    double* edge = L + round32((size_t)b->nv * N);
+    const int nbr = (g.ny + 1 + yw - 1) / yw;
+    KArgs a = b->proto;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.dx = (g.x1 - g.x0) / g.nx;
+    a.dy = g.ndim == 2 ? (g.y1 - g.y0) / g.ny : 1.0;
+    for (int q = 0; q < 4; ++q) a.bc[q] = g.bc[q];
+    if (g.ndim == 1) { a.bc[2] = WCNS_BC_PERIODIC; a.bc[3] = WCNS_BC_PERIODIC; }
+    int T = 62;
+    for (T = 62; T >= 1; --T)
+      if (T + (T - 1 + g.nx - 1) / g.nx + 1 <= 64) break;
+    a.tile_x = T;
+    a.P = P;
+    a.Pw = P;
+    for (int q = 0; q < 5; ++q) a.Pc[q] = P + q * N;
+    a.step = step;
+    a.partial = part;
+    a.nblk = nblk;
+    a.edge = g.ndim == 2 ? edge : nullptr;
+    a.nbr = nbr;
+    a.ndim = g.ndim;
+    a.cfl = b->params.cfl;
+    a.dt_used = b->d_dt + k;
+    const double* in[3] = {b->W[k], U1, U2};
+    double* outs[3] = {U1, U2, b->W[k]};
+    const double cA[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double cB[3] = {1.0, 0.25, 2.0 / 3.0};
+    for (int s = 0; s < 4; ++s) {
+      KArgs x = a;
+      const double* Ws = s < 3 ? in[s] : b->W[k];
+      x.W = Ws;
+      if (g.ndim == 2) {
+        for (int q = 0; q < 6; ++q) x.Wc[q] = Ws + q * N;
+      } else {
+        x.Wc[0] = Ws; x.Wc[1] = Ws + N; x.Wc[2] = Ws + 2 * N; x.Wc[3] = Ws;
+        x.Wc[4] = Ws + 3 * N; x.Wc[5] = Ws + 4 * N;
+      }
+      if (s < 3) {
+        x.out = outs[s];
+        x.Un = b->W[k];
+        x.ca = cA[s];
+        x.cb = cB[s];
+        x.out_mode = OUT_RK;
+        x.dt_mode = s == 0 ? DT_CFL : DT_KEEP;
+        x.Lout = g.ndim == 2 ? L : nullptr;
+        x.Lx = L;
+      } else {
+        // RHS only: L into scratch U2 (summed in place in 2D), state untouched
+        x.out = U2;
+        x.Un = nullptr;
+        x.out_mode = OUT_STORE;
+        x.dt_mode = DT_CFL;
+        x.Lout = g.ndim == 2 ? U2 : nullptr;
+        x.Lx = U2;
+        x.dt_used = nullptr;
+      }
+      ka[(size_t)s * n + k] = x;
+    }
+  }
+  for (int k : inst_order) {
+    const wcns_grid& g = b->grids[k];
+    const long N = (long)g.nx * g.ny;
+    const int nblk = (int)((N + 255) / 256);
+    for (int q = 0; q < nblk; ++q) tn.push_back({k, q, 0, 0});
+    const int T = ka[k].tile_x;
+    const long nt = (N + T - 1) / T;
+    for (long q = 0; q < nt; ++q) tx.push_back({k, (int)q, 0, 0});
+    if (g.ndim == 2) {
+      const int nbr = ka[k].nbr;
+      const int nbx = (g.nx + 63) / 64;
+      for (int by = 0; by < nbr; ++by)
+        for (int bx = 0; bx < nbx; ++bx) ty.push_back({k, bx, by, 0});
+      const long nfc = (long)(nbr - 1) * g.nx;
+      for (long q = 0; q < (nfc + 255) / 256; ++q) tf.push_back({k, (int)q, 0, 0});
+    }
+  }
+  if (b->order == 2) {
+    xcd_chunk(tx);
+    xcd_chunk(ty);
+  }
+  b->n_node = (int)tn.size();
+  b->n_x = (int)tx.size();
+  b->n_y = (int)ty.size();
+  b->n_fix = (int)tf.size();
+  std::vector<Task> all;
+  b->o_node = all.size(); all.insert(all.end(), tn.begin(), tn.end());
+  b->o_x = all.size(); all.insert(all.end(), tx.begin(), tx.end());
+  b->o_y = all.size(); all.insert(all.end(), ty.begin(), ty.end());
+  b->o_fix = all.size(); all.insert(all.end(), tf.begin(), tf.end());
+  if (all.size() > b->tasks_cap) {
+    if (b->d_tasks) (void)hipFree(b->d_tasks);
+    b->d_tasks = nullptr;
+    if (hipMalloc((void**)&b->d_tasks, all.size() * sizeof(Task)) != hipSuccess) return WCNS_ERR_NOMEM;
+    b->tasks_cap = all.size();
+  }
+  if (ka.size() > b->ka_cap) {
+    if (b->d_ka) (void)hipFree(b->d_ka);
+    b->d_ka = nullptr;
+    if (hipMalloc((void**)&b->d_ka, ka.size() * sizeof(KArgs)) != hipSuccess) return WCNS_ERR_NOMEM;
+    b->ka_cap = ka.size();
+  }
+  HIP_TRY(hipMemcpyAsync(b->d_tasks, all.data(), all.size() * sizeof(Task), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->d_ka, ka.data(), ka.size() * sizeof(KArgs), hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  batch_drop_graph(b);
+  return WCNS_OK;
+}
+
+// launches of one stage (set s of the per-instance arguments)
+template <int YW>
+static void batch_stage_launches(wcns_batch* b, int s) {
+  const KArgs* ka = b->d_ka + (size_t)s * b->n;
+  const bool b32 = b->precision == WCNS_FP32_BULK;
+  if (b->ndim == 2)
+    hipLaunchKernelGGL(kb_node<true>, dim3(b->n_node), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_node);
+  else
+    hipLaunchKernelGGL(kb_node<false>, dim3(b->n_node), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_node);
+  hipLaunchKernelGGL(kb_finalize, dim3(b->n), dim3(256), 0, b->stream, ka);
+  if (b->ndim == 2) {
+    if (b32) hipLaunchKernelGGL((kb_sweep_x<true, true>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
+    else hipLaunchKernelGGL((kb_sweep_x<true, false>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
+    if (b32) hipLaunchKernelGGL((kb_sweep_y<YW, true>), dim3(b->n_y), dim3(64 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
+    else hipLaunchKernelGGL((kb_sweep_y<YW, false>), dim3(b->n_y), dim3(64 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
+    if (b->n_fix > 0)
+      hipLaunchKernelGGL(kb_fixup<YW>, dim3(b->n_fix), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_fix);
+  } else {
+    if (b32) hipLaunchKernelGGL((kb_sweep_x<false, true>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
+    else hipLaunchKernelGGL((kb_sweep_x<false, false>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
+  }
+}
+
+static void batch_stage(wcns_batch* b, int s) {
+  if (b->ytile == 2) batch_stage_launches<2>(b, s);
+  else if (b->ytile == 8) batch_stage_launches<8>(b, s);
+  else batch_stage_launches<4>(b, s);
+}
+
+static wcns_status batch_layout(wcns_batch* b, int n, const wcns_grid* grids, double* const* W) {
+  size_t need = 0;
+  std::vector<size_t> off(n);
+  for (int k = 0; k < n; ++k) {
+    off[k] = need;
+    need += inst_doubles(grids[k], b->nv);
+  }
+  if (need > b->arena_cap) return WCNS_ERR_NOMEM;
+  b->n = n;
+  b->grids.assign(grids, grids + n);
+  b->W.assign(W, W + n);
+  b->off = off;
+  if (n > b->dt_cap) {
+    if (b->d_dt) (void)hipFree(b->d_dt);
+    b->d_dt = nullptr;
+    if (hipMalloc((void**)&b->d_dt, sizeof(double) * n) != hipSuccess) return WCNS_ERR_NOMEM;
+    b->dt_cap = n;
+  }
+  return batch_build(b);
+}
+
+extern "C" {
+
+wcns_status wcns_batch_destroy(wcns_batch* b) {
+  if (!b) return WCNS_ERR_ARG;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  batch_drop_graph(b);
+  if (b->arena) (void)hipFree(b->arena);
+  if (b->d_ka) (void)hipFree(b->d_ka);
+  if (b->d_tasks) (void)hipFree(b->d_tasks);
+  if (b->d_dt) (void)hipFree(b->d_dt);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_create(int32_t n, const wcns_grid* grids, const wcns_eos* eos,
+                              const wcns_params* prm, int32_t precision, double* const* W,
+                              int64_t capacity_cells, wcns_batch** out) {
+  if (!out) return WCNS_ERR_ARG;
+  *out = nullptr;
+  if (n < 1 || !grids || !eos || !prm || !W) return WCNS_ERR_ARG;
+  for (int k = 0; k < n; ++k)
+    if (!W[k]) return WCNS_ERR_ARG;
+  const int ndim = grids[0].ndim;
+  if (ndim != 1 && ndim != 2) return WCNS_ERR_ARG;
+  wcns_status st = batch_check_grids(n, grids, ndim);
+  if (st != WCNS_OK) return st;
+  if (!eos_ok(eos)) return WCNS_ERR_EOS;
+  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5) || !(prm->weno_eps > 0.0)) return WCNS_ERR_ARG;
+  if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
+  if (precision != WCNS_FP64 && precision != WCNS_FP32_BULK) return WCNS_ERR_ARG;
+  if (capacity_cells < 0) return WCNS_ERR_ARG;
+  wcns_batch* b = new wcns_batch();
+  b->ndim = ndim;
+  b->nv = ndim == 1 ? 5 : 6;
+  b->precision = precision;
+  b->eos = *eos;
+  b->params = *prm;
+  KArgs& a = b->proto;
+  memset(&a, 0, sizeof(a));
+  a.nv = b->nv;
+  a.interp_limiter = prm->interp_limiter ? 1 : 0;
+  a.flux_limiter = prm->flux_limiter ? 1 : 0;
+  a.scheme = prm->scheme;
+  a.eos.g1 = 1.0 / (eos->gamma[0] - 1.0);
+  a.eos.g2 = 1.0 / (eos->gamma[1] - 1.0);
+  a.eos.q1 = eos->gamma[0] * eos->pinf[0] / (eos->gamma[0] - 1.0);
+  a.eos.q2 = eos->gamma[1] * eos->pinf[1] / (eos->gamma[1] - 1.0);
+  a.tol.eps_arho = prm->eps_arho;
+  a.tol.eps_alpha = prm->eps_alpha;
+  a.tol.eps_rhoc2 = prm->eps_rhoc2;
+  a.tol.hs_arho = prm->hs_arho;
+  a.tol.hs_alpha = prm->hs_alpha;
+  a.tol.hs_rhoc2 = prm->hs_rhoc2;
+  a.tol.weno_eps = prm->weno_eps;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return WCNS_ERR_HIP;
+  }
+  // the Dirichlet slots of the arguments must point at readable memory
+  size_t need = 32;
+  for (int k = 0; k < n; ++k) need += inst_doubles(grids[k], b->nv);
+  if (capacity_cells > 0) {
+    wcns_grid big = grids[0];
+    big.nx = (int32_t)std::min<int64_t>(capacity_cells, (1L << 29) - 1);
+    big.ny = 1;
+    size_t cap = inst_doubles(big, b->nv) + (size_t)n * 4096;
+    need = std::max(need, cap);
+  }
+  if (hipMalloc((void**)&b->arena, need * sizeof(double)) != hipSuccess) {
+    wcns_batch_destroy(b);
+    return WCNS_ERR_NOMEM;
+  }
+  b->arena_cap = need - 32;
+  double* dummy = b->arena + b->arena_cap;
+  a.dirW = dummy;
+  a.dirP = dummy;
+  st = batch_layout(b, n, grids, W);
+  if (st != WCNS_OK) {
+    wcns_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_reset(wcns_batch* b, int32_t n, const wcns_grid* grids, double* const* W) {
+  if (!b || n < 1 || !grids || !W) return WCNS_ERR_ARG;
+  for (int k = 0; k < n; ++k)
+    if (!W[k]) return WCNS_ERR_ARG;
+  wcns_status st = batch_check_grids(n, grids, b->ndim);
+  if (st != WCNS_OK) return st;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return batch_layout(b, n, grids, W);
+}
+
+wcns_status wcns_batch_configure(wcns_batch* b, int32_t ytile, int32_t order) {
+  if (!b || (ytile != 2 && ytile != 4 && ytile != 8) || order < 0 || order > 2) return WCNS_ERR_ARG;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->ytile = ytile;
+  b->order = order;
+  return batch_build(b);
+}
+
+wcns_status wcns_batch_step(wcns_batch* b, int32_t nsteps) {
+  if (!b || nsteps < 0) return WCNS_ERR_ARG;
+  if (b->dirty) {
+    batch_drop_graph(b);
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    for (int s = 0; s < 3; ++s) batch_stage(b, s);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamEndCapture(b->stream, &b->graph);
+    if (e1 != hipSuccess || e2 != hipSuccess) { batch_drop_graph(b); return WCNS_ERR_HIP; }
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->dirty = false;
+  }
+  for (int k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_rhs(wcns_batch* b) {
+  if (!b) return WCNS_ERR_ARG;
+  batch_stage(b, 3);
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_sync(wcns_batch* b) {
+  if (!b) return WCNS_ERR_ARG;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_stream(wcns_batch* b, void** stream) {
+  if (!b || !stream) return WCNS_ERR_ARG;
+  *stream = (void*)b->stream;
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_dt(wcns_batch* b, double* dt) {
+  if (!b || !dt) return WCNS_ERR_ARG;
+  HIP_TRY(hipMemcpyAsync(dt, b->d_dt, sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
   return WCNS_OK;
 }
 

@@ -55,7 +55,13 @@ struct KArgs {
   const double* Un;      // state at the start of the step (RK epilogue)
   double* edge;          // y-tile boundary fluxes [nbr][2][6][nx]
   double ca, cb;         // RK: out = ca*Un + cb*(W + dt*L)
-  int32_t out_mode, pad2;
+  int32_t out_mode, nbr; // nbr: y-tile rows (edge buffer rows)
+  double* partial;       // per-block wave-speed maxima of this instance
+  double* Pw;            // node-primitive output of k_node (= P)
+  int32_t nblk, ndim;    // node blocks of this instance; 1 or 2
+  int32_t dt_mode, pad3; // stage's time-step mode (DT_GIVEN/DT_CFL/DT_KEEP)
+  double cfl, dt_in;
+  double* dt_used;       // optional copy of dt
 };
 
 // ------------------------------------------------------------------ nodes
@@ -499,17 +505,89 @@ __global__ void k_dirichlet_prims(KArgs a, double* dirP) {
   dirP[s * 5 + 3] = c; dirP[s * 5 + 4] = h;
 }
 
+// One block of the node pass of one instance (batched form): cells
+// [blk*256, blk*256 + 256), primitives to a.Pw, block maxima to partial[blk].
+template <bool HAS_T>
+__device__ __forceinline__ void node_block(const KArgs& a, int blk) {
+  const long N = (long)a.nx * a.ny;
+  const long o = (long)blk * blockDim.x + threadIdx.x;
+  double mx = 0.0, my = 0.0;
+  if (o < N) {
+    double X[6];
+    if (HAS_T) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) X[k] = a.W[k * N + o];
+    } else {
+      X[0] = a.W[o]; X[1] = a.W[N + o]; X[2] = a.W[2 * N + o]; X[3] = 0.0;
+      X[4] = a.W[3 * N + o]; X[5] = a.W[4 * N + o];
+    }
+    double un, ut, p, c, h;
+    recover<HAS_T>(a.eos, X, un, ut, p, c, h);
+    double* P = a.Pw;
+    P[o] = un; P[N + o] = ut; P[2 * N + o] = p; P[3 * N + o] = c; P[4 * N + o] = h;
+    mx = fabs(un) + c;
+    my = fabs(ut) + c;
+  }
+  mx = wave_max(mx);
+  my = wave_max(my);
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = mx; red[1][w] = my; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a0 = red[0][0], a1v = red[1][0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { a0 = fmax(a0, red[0][k]); a1v = fmax(a1v, red[1][k]); }
+    a.partial[2 * blk] = a0;
+    a.partial[2 * blk + 1] = a1v;
+  }
+}
+
+// dt, sigma, lambda of one instance from its block maxima (one block)
+__device__ __forceinline__ void finalize_inst(const KArgs& a) {
+  double mx = 0.0, my = 0.0;
+  for (int b = threadIdx.x; b < a.nblk; b += blockDim.x) {
+    mx = fmax(mx, a.partial[2 * b]);
+    my = fmax(my, a.partial[2 * b + 1]);
+  }
+  mx = wave_max(mx);
+  my = wave_max(my);
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = mx; red[1][w] = my; }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 4; ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
+  double* step = (double*)a.step;
+  double dt;
+  if (a.dt_mode == DT_GIVEN) dt = a.dt_in;
+  else if (a.dt_mode == DT_KEEP) dt = step[0];
+  else dt = a.ndim == 1 ? a.cfl * a.dx / mx : a.cfl / (mx / a.dx + my / a.dy);
+  step[0] = dt;
+  if (a.ndim == 1) {
+    step[1] = dt / a.dx;
+    step[2] = 0.0;
+  } else {
+    double tx = mx / a.dx, ty = my / a.dy;
+    double sx = tx / (tx + ty), sy = ty / (tx + ty);
+    step[1] = dt / (a.dx * sx);
+    step[2] = dt / (a.dy * sy);
+  }
+  step[3] = mx;
+  step[4] = my;
+  if (a.dt_used) *a.dt_used = dt;
+}
+
 // x-sweep: one wave per tile of tile_x flattened cells.  Lane t < T owns the
 // left face of cell c0+t; lanes T.. own the right face of each row segment's
 // last cell.  Cell c0+t then takes G^+ of its own face and G^- of the lane
 // that owns its right face.
 template <bool HAS_T, bool DIRI, bool B32>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_x(KArgs a) {
+__device__ __forceinline__ void sweep_x_tile(const KArgs& a, long tile) {
   const int lane = threadIdx.x;
   const int nx = a.nx;
   const long N = (long)nx * a.ny;
   const int T = a.tile_x;
-  const long c0 = (long)blockIdx.x * T;
+  const long c0 = tile * T;
   const long c1 = (c0 + T < N ? c0 + T : N) - 1;
   const int j0 = (int)(c0 / nx), j1 = (int)(c1 / nx);
   int fj = 0, fk = 0;
@@ -559,17 +637,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   (void)nvs;
 }
 
-// y-sweep: block = Y_WAVES waves; wave w computes y-face row k = kb + w for
-// 64 columns.  Cell row kb + w (w < Y_WAVES-1) uses G^+ of its own face and
-// G^- of face row kb + w + 1 (through LDS).  The last face row of the tile
-// leaves G^+ in the edge buffer and the first one G^-; k_fixup_y finishes the
-// cell row in between.
-template <bool DIRI, bool B32>
-__global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
-  __shared__ double sGm[Y_WAVES][6][64];
+template <bool HAS_T, bool DIRI, bool B32>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_x(KArgs a) {
+  sweep_x_tile<HAS_T, DIRI, B32>(a, blockIdx.x);
+}
+
+// y-sweep: block = YW waves; wave w computes y-face row k = kb + w for 64
+// columns.  Cell row kb + w (w < YW-1) uses G^+ of its own face and G^- of
+// face row kb + w + 1 (through LDS).  The last face row of the tile leaves
+// G^+ in the edge buffer and the first one G^-; the fixup finishes the cell
+// row in between.
+template <int YW, bool DIRI, bool B32>
+__device__ __forceinline__ void sweep_y_tile(const KArgs& a, int bx, int by,
+                                             double (*sGm)[6][64]) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + lane;
-  const int kb = blockIdx.y * Y_WAVES;
+  const int i = bx * 64 + lane;
+  const int kb = by * YW;
   const int k = kb + w;                   // my face row (between cells k-1 and k)
   const int nx = a.nx, ny = a.ny;
   const long N = (long)nx * ny;
@@ -580,19 +663,19 @@ __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
   for (int v = 0; v < 6; ++v) sGm[w][v][lane] = Gm[v];
   // tile edges for the fixup of the straddling cell rows
   if (active) {
-    double* e = a.edge + (long)blockIdx.y * 12 * nx;
+    double* e = a.edge + (long)by * 12 * nx;
     if (w == 0) {
 #pragma unroll
       for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
     }
-    if (w == Y_WAVES - 1 || k == ny) {
+    if (w == YW - 1 || k == ny) {
 #pragma unroll
       for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
     }
   }
   __syncthreads();
   const int j = k;   // cell row between face rows k and k+1
-  if (!active || w == Y_WAVES - 1 || j >= ny) return;
+  if (!active || w == YW - 1 || j >= ny) return;
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
     double L;
@@ -605,14 +688,20 @@ __global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
   }
 }
 
-// cell rows j = (b+1)*Y_WAVES - 1 between y-tile b and b+1
-__global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
+template <bool DIRI, bool B32>
+__global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
+  __shared__ double sGm[Y_WAVES][6][64];
+  sweep_y_tile<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, sGm);
+}
+
+// cell rows j = (b+1)*YW - 1 between y-tile b and b+1 (t: flat index over
+// the boundary rows of one instance)
+__device__ __forceinline__ void fixup_cell(const KArgs& a, long t, int yw) {
   const int nx = a.nx, ny = a.ny;
   const long N = (long)nx * ny;
-  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const int b = (int)(t / nx), i = (int)(t % nx);
-  if (b >= nbr - 1) return;
-  const int j = (b + 1) * Y_WAVES - 1;
+  if (b >= a.nbr - 1) return;
+  const int j = (b + 1) * yw - 1;
   if (j >= ny) return;
   const double* lo = a.edge + (long)b * 12 * nx + 6 * nx;       // G^+ of face row j
   const double* hi = a.edge + (long)(b + 1) * 12 * nx;          // G^- of face row j+1
@@ -626,6 +715,11 @@ __global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
     }
     write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
   }
+}
+
+__global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
+  (void)nbr;
+  fixup_cell(a, (long)blockIdx.x * blockDim.x + threadIdx.x, Y_WAVES);
 }
 
 // Stand-alone flux limiter over the faces of one direction.

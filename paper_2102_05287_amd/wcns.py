@@ -58,7 +58,9 @@ _lib = None
 EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
            "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
            "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
-           "wcns_selftest_division", "wcns_status_str"]
+           "wcns_selftest_division", "wcns_batch_create", "wcns_batch_reset",
+           "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
+           "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_status_str"]
 PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other"]
 
 
@@ -88,6 +90,16 @@ def lib():
         L.wcns_profile.argtypes = [vp, C.c_int32]
         L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.wcns_selftest_division.argtypes = [dp, dp, dp, dp, C.c_int64, vp]
+        L.wcns_batch_create.argtypes = [C.c_int32, C.POINTER(_Grid), C.POINTER(_Eos), C.POINTER(_Params),
+                                        C.c_int32, C.POINTER(C.c_void_p), C.c_int64, C.POINTER(vp)]
+        L.wcns_batch_reset.argtypes = [vp, C.c_int32, C.POINTER(_Grid), C.POINTER(C.c_void_p)]
+        L.wcns_batch_configure.argtypes = [vp, C.c_int32, C.c_int32]
+        L.wcns_batch_step.argtypes = [vp, C.c_int32]
+        L.wcns_batch_rhs.argtypes = [vp]
+        L.wcns_batch_sync.argtypes = [vp]
+        L.wcns_batch_stream.argtypes = [vp, C.POINTER(vp)]
+        L.wcns_batch_dt.argtypes = [vp, C.POINTER(C.c_double)]
+        L.wcns_batch_destroy.argtypes = [vp]
         L.wcns_status_str.argtypes = [C.c_int]
         L.wcns_status_str.restype = C.c_char_p
         for name in EXPORTS:
@@ -246,3 +258,120 @@ def selftest_division(a, b):
                                         C.c_void_p(torch.cuda.current_stream().cuda_stream)),
            "wcns_selftest_division")
     return qi, qc
+
+
+def make_grid(ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4, dirichlet=None) -> _Grid:
+    g = _Grid()
+    g.ndim, g.nx, g.ny = ndim, nx, ny
+    g.x0, g.x1, g.y0, g.y1 = x0, x1, y0, y1
+    for k in range(4):
+        g.bc[k] = int(bc[k])
+        if dirichlet is not None and dirichlet[k] is not None:
+            for v, val in enumerate(dirichlet[k]):
+                g.dirichlet[k][v] = float(val)
+    return g
+
+
+def grid_of(spec) -> _Grid:
+    return make_grid(spec.ndim, spec.nx, spec.ny, spec.x0, spec.x1, spec.y0, spec.y1, spec.bc)
+
+
+class Batch:
+    """Many independent solves (same ndim, fluids, options, precision)
+    advanced together by the batched kernels.
+
+    grids: list of _Grid (see grid_of); states: list of device f64 tensors
+    [nvar][ny][nx], stepped in place.  Work runs on the batch's own stream;
+    step()/rhs() order it after the current torch stream and make the current
+    torch stream wait for it, so torch code sees the results in order."""
+
+    def __init__(self, grids, states, gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), precision=FP64,
+                 capacity_cells=0, **params):
+        import torch
+        n = len(grids)
+        G = (_Grid * n)(*grids)
+        e = _Eos()
+        e.gamma[0], e.gamma[1] = gamma
+        e.pinf[0], e.pinf[1] = pinf
+        p = default_params(**params)
+        ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in states])
+        ctx = C.c_void_p()
+        _check(lib().wcns_batch_create(n, G, C.byref(e), C.byref(p), int(precision), ptrs,
+                                       int(capacity_cells), C.byref(ctx)), "wcns_batch_create")
+        self._b = ctx
+        self.n = n
+        self.states = list(states)
+        st = C.c_void_p()
+        _check(lib().wcns_batch_stream(self._b, C.byref(st)), "wcns_batch_stream")
+        self.stream = torch.cuda.ExternalStream(st.value)
+
+    def _enter(self):
+        import torch
+        self.stream.wait_stream(torch.cuda.current_stream())
+
+    def _leave(self):
+        import torch
+        torch.cuda.current_stream().wait_stream(self.stream)
+
+    def configure(self, ytile=4, order=2):
+        _check(lib().wcns_batch_configure(self._b, int(ytile), int(order)), "wcns_batch_configure")
+
+    def reset(self, grids, states):
+        n = len(grids)
+        G = (_Grid * n)(*grids)
+        ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in states])
+        self._enter()
+        _check(lib().wcns_batch_reset(self._b, n, G, ptrs), "wcns_batch_reset")
+        self.n = n
+        self.states = list(states)
+
+    def step(self, nsteps=1):
+        self._enter()
+        _check(lib().wcns_batch_step(self._b, int(nsteps)), "wcns_batch_step")
+        self._leave()
+
+    def rhs(self):
+        self._enter()
+        _check(lib().wcns_batch_rhs(self._b), "wcns_batch_rhs")
+        self._leave()
+
+    def sync(self):
+        _check(lib().wcns_batch_sync(self._b), "wcns_batch_sync")
+
+    def dt(self):
+        out = (C.c_double * self.n)()
+        _check(lib().wcns_batch_dt(self._b, out), "wcns_batch_dt")
+        return np.array(out[:])
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            lib().wcns_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(batch, trials=3, candidates=None):
+    """Pick the batch schedule (y-tile height, task order) with the lowest
+    measured RHS time on the batch's own instances; returns
+    (best, {candidate: seconds})."""
+    import time
+    if candidates is None:
+        candidates = [(y, o) for y in (2, 4, 8) for o in (0, 1, 2)]
+    times = {}
+    for cand in candidates:
+        batch.configure(*cand)
+        batch.rhs()
+        batch.sync()
+        t0 = time.perf_counter()
+        for _ in range(trials):
+            batch.rhs()
+        batch.sync()
+        times[cand] = (time.perf_counter() - t0) / trials
+    best = min(times, key=times.get)
+    batch.configure(*best)
+    return best, times

@@ -1,0 +1,94 @@
+"""Batched form: many solves of uneven sizes advanced by the batched kernels
+must give, instance by instance, exactly the single-solve results (same
+arithmetic, bit for bit) whatever the schedule, in FP64 and FP32-bulk."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import oracle_setup, oracle_W, orc, pb
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_2102_05287_amd import wcns  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def instances(k, small=True):
+    specs = []
+    for i in range(k):
+        s = pb.random_instance(i)
+        if small:   # shrink to keep the test quick, keep the uneven mix
+            n = [16, 24, 33, 48, 64, 70, 96][i % 7]
+            s2 = pb.ProblemSpec(s.name, 2, n, n, 0.0, 1.0, 0.0, 1.0, bc=s.bc)
+            idx = ((np.arange(n) + 0.5) * s.nx / n).astype(int)
+            s2.prim = np.ascontiguousarray(s.prim[:, idx][:, :, idx])
+            s = s2
+        specs.append(s)
+    return specs
+
+
+@pytest.mark.parametrize("precision", [wcns.FP64, wcns.FP32_BULK])
+def test_batch_equals_single_solves(precision):
+    specs = instances(9)
+    s0 = oracle_setup(specs[0])
+    W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
+    # single-instance path
+    ref = []
+    for sp, w in zip(specs, W0):
+        sol = wcns.Solver.from_spec(sp, precision=precision)
+        Wd = dev(w)
+        for _ in range(3):
+            sol.step(Wd, 0.0)
+        ref.append(host(Wd))
+    for ytile, order in ((4, 0), (2, 1), (8, 2)):
+        states = [dev(w) for w in W0]
+        b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states, precision=precision)
+        b.configure(ytile, order)
+        b.step(3)
+        for k in range(len(specs)):
+            assert np.array_equal(host(states[k]), ref[k]), (ytile, order, k)
+        b.close()
+
+
+def test_batch_matches_oracle_and_reset():
+    specs = instances(5)
+    W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
+    states = [dev(w) for w in W0]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states, capacity_cells=200000)
+    b.step(2)
+    dts = b.dt()
+    for k, sp in enumerate(specs):
+        s = oracle_setup(sp)
+        W = W0[k]
+        for _ in range(2):
+            W, dt, bad = orc.ssprk3_step(s, W)
+        assert dt == dts[k]
+        assert np.array_equal(host(states[k]), W)
+    # rebind to another set inside the same scratch
+    specs2 = instances(7)[2:]
+    W2 = [oracle_W(sp, oracle_setup(sp)) for sp in specs2]
+    states2 = [dev(w) for w in W2]
+    b.reset([wcns.grid_of(sp) for sp in specs2], states2)
+    b.step(1)
+    for k, sp in enumerate(specs2):
+        W, dt, bad = orc.ssprk3_step(oracle_setup(sp), W2[k])
+        assert np.array_equal(host(states2[k]), W)
+    b.close()
+
+
+def test_autotune_picks_a_schedule():
+    specs = instances(6)
+    states = [dev(oracle_W(sp, oracle_setup(sp))) for sp in specs]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)
+    best, times = wcns.autotune(b, trials=1)
+    assert best in times and len(times) == 9
+    b.close()
