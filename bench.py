@@ -188,6 +188,24 @@ def batched_form(n_inst, steps, seq_steps):
     return out
 
 
+def serving_form(n_req, rate, budget_gib, chunk):
+    """Poisson request stream (seed 4) at `rate` req/s replayed in real time
+    through the continuous-batching server; mixed 1D (200-20000 cells) and 2D
+    (64^2-1024^2) water/air solves of 100-2000 steps, FP64 or FP32-bulk."""
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import serve
+    reqs = pb.serving_trace(n_req, rate, seed=4)
+    solves = [serve.Solve(r.rid, r.arrival, pb.request_problem(r), r.steps, r.fp32) for r in reqs]
+    srv = serve.Server(hbm_budget=budget_gib << 30, chunk=chunk)
+    done, summary = srv.run(solves, realtime=True)
+    offered = sum(3.0 * s.spec.nx * s.spec.ny * s.steps for s in solves) / (reqs[-1].arrival or 1.0)
+    summary.update({"workload": f"first {n_req} requests of the seed-4 trace at {rate} req/s "
+                                f"(Poisson), mixed 1D/2D, FP64/FP32-bulk",
+                    "offered_mcell_updates_per_s": offered / 1e6,
+                    "hbm_budget_gib": budget_gib, "peak_hbm_used_gib": srv.peak_used / 2**30})
+    return summary
+
+
 def cpu_baseline(spec, target_s=12.0):
     from oracle import oracle as orc
     s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy, bc=spec.bc)
@@ -303,6 +321,8 @@ def main():
         forms["precision_fp32_bulk"] = precision_form(2048, 20, 3)
         print("# batched form (512 instances) ...", flush=True)
         forms["batched"] = batched_form(512, 200, 20)
+        print("# serving form ...", flush=True)
+        forms["serving"] = serving_form(300, 200.0, 64, 20)
 
     cpu = None
     if not args.no_cpu:

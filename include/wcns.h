@@ -201,6 +201,20 @@ wcns_status wcns_batch_rhs(wcns_batch* b);
 wcns_status wcns_batch_sync(wcns_batch* b);
 wcns_status wcns_batch_stream(wcns_batch* b, void** stream);
 
+/* Per-instance step budgets for continuous batching: instance k takes only
+ * steps[k] more steps (>= 0); once its counter reaches 0 every later step
+ * skips it (its state stays as it is).  New instances start with an
+ * unlimited budget.  wcns_batch_steps_left reads the counters back.  Both
+ * synchronise the batch stream; host arrays of n int32. */
+wcns_status wcns_batch_set_steps(wcns_batch* b, const int32_t* steps);
+wcns_status wcns_batch_steps_left(wcns_batch* b, int32_t* steps);
+
+/* Context-free primitive -> conservative conversion of ncell cells (Sec. 2
+ * mixture EOS), V = (a1r1, a2r2, u, [v], p, a1) SoA -> W, device arrays,
+ * enqueued on `stream` (hipStream_t or NULL). */
+wcns_status wcns_prim_to_cons_n(const wcns_eos* eos, int32_t ndim, int64_t ncell, const double* V,
+                                double* W, void* stream);
+
 /* Host copy of every instance's last time step, dt[n] (synchronises). */
 wcns_status wcns_batch_dt(wcns_batch* b, double* dt);
 

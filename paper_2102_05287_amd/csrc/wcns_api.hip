@@ -559,6 +559,7 @@ struct wcns_batch {
   int n_node = 0, n_x = 0, n_y = 0, n_fix = 0;
   size_t o_node = 0, o_x = 0, o_y = 0, o_fix = 0;
   double* d_dt = nullptr;      // per-instance dt of the last step
+  int32_t* d_live = nullptr;   // per-instance steps left (frozen at 0)
   int dt_cap = 0;
   int ytile = 4, order = 2;
   hipGraph_t graph = nullptr;
@@ -669,6 +670,7 @@ static wcns_status batch_build(wcns_batch* b) {
     a.ndim = g.ndim;
     a.cfl = b->params.cfl;
     a.dt_used = b->d_dt + k;
+    a.live = b->d_live + k;
     const double* in[3] = {b->W[k], U1, U2};
     double* outs[3] = {U1, U2, b->W[k]};
     const double cA[3] = {0.0, 0.75, 1.0 / 3.0};
@@ -701,6 +703,7 @@ static wcns_status batch_build(wcns_batch* b) {
         x.Lout = g.ndim == 2 ? U2 : nullptr;
         x.Lx = U2;
         x.dt_used = nullptr;
+        x.live = nullptr;
       }
       ka[(size_t)s * n + k] = x;
     }
@@ -781,6 +784,8 @@ static void batch_stage(wcns_batch* b, int s) {
   if (b->ytile == 2) batch_stage_launches<2>(b, s);
   else if (b->ytile == 8) batch_stage_launches<8>(b, s);
   else batch_stage_launches<4>(b, s);
+  if (s == 2)
+    hipLaunchKernelGGL(kb_tick, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->d_live, b->n);
 }
 
 static wcns_status batch_layout(wcns_batch* b, int n, const wcns_grid* grids, double* const* W) {
@@ -797,10 +802,16 @@ static wcns_status batch_layout(wcns_batch* b, int n, const wcns_grid* grids, do
   b->off = off;
   if (n > b->dt_cap) {
     if (b->d_dt) (void)hipFree(b->d_dt);
+    if (b->d_live) (void)hipFree(b->d_live);
     b->d_dt = nullptr;
+    b->d_live = nullptr;
     if (hipMalloc((void**)&b->d_dt, sizeof(double) * n) != hipSuccess) return WCNS_ERR_NOMEM;
+    if (hipMalloc((void**)&b->d_live, sizeof(int32_t) * n) != hipSuccess) return WCNS_ERR_NOMEM;
     b->dt_cap = n;
   }
+  // every instance live for ever until told otherwise
+  std::vector<int32_t> live(n, 0x7fffffff);
+  HIP_TRY(hipMemcpy(b->d_live, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   return batch_build(b);
 }
 
@@ -814,6 +825,7 @@ wcns_status wcns_batch_destroy(wcns_batch* b) {
   if (b->d_ka) (void)hipFree(b->d_ka);
   if (b->d_tasks) (void)hipFree(b->d_tasks);
   if (b->d_dt) (void)hipFree(b->d_dt);
+  if (b->d_live) (void)hipFree(b->d_live);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return WCNS_OK;
@@ -940,6 +952,44 @@ wcns_status wcns_batch_sync(wcns_batch* b) {
 wcns_status wcns_batch_stream(wcns_batch* b, void** stream) {
   if (!b || !stream) return WCNS_ERR_ARG;
   *stream = (void*)b->stream;
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_set_steps(wcns_batch* b, const int32_t* steps) {
+  if (!b || !steps) return WCNS_ERR_ARG;
+  for (int k = 0; k < b->n; ++k)
+    if (steps[k] < 0) return WCNS_ERR_ARG;
+  HIP_TRY(hipMemcpyAsync(b->d_live, steps, sizeof(int32_t) * b->n, hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_steps_left(wcns_batch* b, int32_t* steps) {
+  if (!b || !steps) return WCNS_ERR_ARG;
+  HIP_TRY(hipMemcpyAsync(steps, b->d_live, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  return WCNS_OK;
+}
+
+wcns_status wcns_prim_to_cons_n(const wcns_eos* eos, int32_t ndim, int64_t ncell, const double* V,
+                                double* W, void* stream) {
+  if (!eos || !V || !W || (ndim != 1 && ndim != 2) || ncell < 1) return WCNS_ERR_ARG;
+  if (!eos_ok(eos)) return WCNS_ERR_EOS;
+  KArgs a;
+  memset(&a, 0, sizeof(a));
+  a.nx = (int32_t)std::min<int64_t>(ncell, 0x7fffffff);
+  a.ny = 1;
+  if (ncell > 0x7fffffff) return WCNS_ERR_ARG;
+  a.eos.g1 = 1.0 / (eos->gamma[0] - 1.0);
+  a.eos.g2 = 1.0 / (eos->gamma[1] - 1.0);
+  a.eos.q1 = eos->gamma[0] * eos->pinf[0] / (eos->gamma[0] - 1.0);
+  a.eos.q2 = eos->gamma[1] * eos->pinf[1] / (eos->gamma[1] - 1.0);
+  unsigned g = (unsigned)((ncell + 255) / 256);
+  if (ndim == 2)
+    hipLaunchKernelGGL(k_prim_to_cons<true>, dim3(g), dim3(256), 0, (hipStream_t)stream, a, V, W);
+  else
+    hipLaunchKernelGGL(k_prim_to_cons<false>, dim3(g), dim3(256), 0, (hipStream_t)stream, a, V, W);
+  LAUNCH_CHECK();
   return WCNS_OK;
 }
 

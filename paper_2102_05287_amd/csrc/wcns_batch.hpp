@@ -13,34 +13,55 @@ struct Task {
   int32_t inst, a, b, pad;   // instance and its tile coordinates
 };
 
+// An instance whose step counter reached 0 is frozen: every block of it
+// returns at once (the counter is uniform over the block, so no barrier is
+// skipped by part of a block).
+__device__ __forceinline__ bool frozen(const KArgs& a) { return a.live && *a.live <= 0; }
+
 template <bool HAS_T>
 __global__ __launch_bounds__(256) void kb_node(const KArgs* ka, const Task* t) {
   const Task task = t[blockIdx.x];
-  node_block<HAS_T>(ka[task.inst], task.a);
+  const KArgs& a = ka[task.inst];
+  if (frozen(a)) return;
+  node_block<HAS_T>(a, task.a);
 }
 
 __global__ __launch_bounds__(256) void kb_finalize(const KArgs* ka) {
-  finalize_inst(ka[blockIdx.x]);
+  const KArgs& a = ka[blockIdx.x];
+  if (frozen(a)) return;
+  finalize_inst(a);
 }
 
 template <bool HAS_T, bool B32>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void kb_sweep_x(
     const KArgs* ka, const Task* t) {
   const Task task = t[blockIdx.x];
-  sweep_x_tile<HAS_T, false, B32>(ka[task.inst], task.a);
+  const KArgs& a = ka[task.inst];
+  if (frozen(a)) return;
+  sweep_x_tile<HAS_T, false, B32>(a, task.a);
 }
 
 template <int YW, bool B32>
 __global__ __launch_bounds__(64 * YW) void kb_sweep_y(const KArgs* ka, const Task* t) {
   __shared__ double sGm[YW][6][64];
   const Task task = t[blockIdx.x];
-  sweep_y_tile<YW, false, B32>(ka[task.inst], task.a, task.b, sGm);
+  const KArgs& a = ka[task.inst];
+  if (frozen(a)) return;
+  sweep_y_tile<YW, false, B32>(a, task.a, task.b, sGm);
 }
 
 template <int YW>
 __global__ __launch_bounds__(256) void kb_fixup(const KArgs* ka, const Task* t) {
   const Task task = t[blockIdx.x];
-  fixup_cell(ka[task.inst], (long)task.a * 256 + threadIdx.x, YW);
+  const KArgs& a = ka[task.inst];
+  if (frozen(a)) return;
+  fixup_cell(a, (long)task.a * 256 + threadIdx.x, YW);
+}
+
+// end of a step: one step fewer for every live instance
+__global__ __launch_bounds__(256) void kb_tick(int32_t* live, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && live[k] > 0) live[k] -= 1;
 }
 
 }  // namespace wcns

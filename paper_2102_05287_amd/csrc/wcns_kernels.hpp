@@ -62,6 +62,7 @@ struct KArgs {
   int32_t dt_mode, pad3; // stage's time-step mode (DT_GIVEN/DT_CFL/DT_KEEP)
   double cfl, dt_in;
   double* dt_used;       // optional copy of dt
+  const int32_t* live;   // batched form: steps left for this instance (skip at 0)
 };
 
 // ------------------------------------------------------------------ nodes

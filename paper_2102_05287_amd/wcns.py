@@ -60,7 +60,8 @@ EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_strea
            "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
            "wcns_selftest_division", "wcns_batch_create", "wcns_batch_reset",
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
-           "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_status_str"]
+           "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
+           "wcns_batch_steps_left", "wcns_prim_to_cons_n", "wcns_status_str"]
 PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other"]
 
 
@@ -100,6 +101,9 @@ def lib():
         L.wcns_batch_stream.argtypes = [vp, C.POINTER(vp)]
         L.wcns_batch_dt.argtypes = [vp, C.POINTER(C.c_double)]
         L.wcns_batch_destroy.argtypes = [vp]
+        L.wcns_batch_set_steps.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.wcns_batch_steps_left.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.wcns_prim_to_cons_n.argtypes = [C.POINTER(_Eos), C.c_int32, C.c_int64, dp, dp, vp]
         L.wcns_status_str.argtypes = [C.c_int]
         L.wcns_status_str.restype = C.c_char_p
         for name in EXPORTS:
@@ -260,6 +264,21 @@ def selftest_division(a, b):
     return qi, qc
 
 
+def prim_to_cons(V, ndim, gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), W=None):
+    """Device primitive -> conservative conversion without a solver context
+    (V: device f64 [nvar][...]); enqueued on the current torch stream."""
+    import torch
+    W = torch.empty_like(V) if W is None else W
+    e = _Eos()
+    e.gamma[0], e.gamma[1] = gamma
+    e.pinf[0], e.pinf[1] = pinf
+    ncell = V.numel() // (5 if ndim == 1 else 6)
+    _check(lib().wcns_prim_to_cons_n(C.byref(e), int(ndim), int(ncell), _ptr(V), _ptr(W),
+                                     C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           "wcns_prim_to_cons_n")
+    return W
+
+
 def make_grid(ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4, dirichlet=None) -> _Grid:
     g = _Grid()
     g.ndim, g.nx, g.ny = ndim, nx, ny
@@ -337,6 +356,16 @@ class Batch:
 
     def sync(self):
         _check(lib().wcns_batch_sync(self._b), "wcns_batch_sync")
+
+    def set_steps(self, steps):
+        arr = (C.c_int32 * self.n)(*[int(x) for x in steps])
+        self._enter()
+        _check(lib().wcns_batch_set_steps(self._b, arr), "wcns_batch_set_steps")
+
+    def steps_left(self):
+        arr = (C.c_int32 * self.n)()
+        _check(lib().wcns_batch_steps_left(self._b, arr), "wcns_batch_steps_left")
+        return np.array(arr[:], dtype=np.int64)
 
     def dt(self):
         out = (C.c_double * self.n)()
