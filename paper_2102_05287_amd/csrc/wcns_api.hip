@@ -214,7 +214,10 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   a.tile_x = c->tile_x;
   c->x_grid = (int)((c->N + c->tile_x - 1) / c->tile_x);
   long ng = (c->N + 255) / 256;
-  c->node_grid = (int)(ng < 2048 ? ng : 2048);
+#ifndef WCNS_NODE_GRID_CAP
+#define WCNS_NODE_GRID_CAP 2048
+#endif
+  c->node_grid = (int)(ng < WCNS_NODE_GRID_CAP ? ng : WCNS_NODE_GRID_CAP);
   c->nbr = (g->ny + 1 + Y_WAVES - 1) / Y_WAVES;
   a.nbr = c->nbr;
 

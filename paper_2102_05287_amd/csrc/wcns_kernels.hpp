@@ -32,7 +32,10 @@ enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 enum { OUT_STORE = 0, OUT_RK = 1 };
 // y-face rows per y-sweep block (4 measured fastest against 2 and 8, and
 // against a one-wave form that marches up the rows)
-constexpr int Y_WAVES = 4;
+#ifndef WCNS_YTILE
+#define WCNS_YTILE 4
+#endif
+constexpr int Y_WAVES = WCNS_YTILE;
 
 struct KArgs {
   int32_t nx, ny, nv, tile_x;     // tile_x: cells per x-sweep wave
@@ -204,6 +207,85 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
   double UL[6], UR[6];
   float ULf[6], URf[6];
   const float eps32 = fmaxf((float)a.tol.weno_eps, 1e-30f);
+#ifndef WCNS_PREFETCH
+#define WCNS_PREFETCH 1
+#endif
+#if WCNS_PREFETCH
+  // Fields in three groups that share their node data: (u_n, p) -> fields 0
+  // and 5, (a1r1, a2r2, p) -> fields 1 and 2, (u_t, a1) -> fields 3 and 4.
+  // The next group's node values are loaded before the current group's
+  // interpolations run, so the cache latency overlaps the arithmetic.
+  auto weno_pair = [&](int f, const double u[6]) {
+    if constexpr (B32) {
+      float v[6];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) v[m] = (float)u[m];
+      ULf[f] = weno_is_f(v[0], v[1], v[2], v[3], v[4], eps32);
+      URf[f] = weno_is_f(v[5], v[4], v[3], v[2], v[1], eps32);
+    } else {
+      UL[f] = weno_is(u[0], u[1], u[2], u[3], u[4], a.tol.weno_eps);
+      UR[f] = weno_is(u[5], u[4], u[3], u[2], u[1], a.tol.weno_eps);
+    }
+  };
+  double ra[6], rb[6], rc[6];   // raw node values of the group being formed
+  phase_barrier();
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    NodeQ q;
+    load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+    ra[m] = q.un;
+    rb[m] = q.p;
+  }
+  {
+    // group (a1r1, a2r2, p) loaded ahead
+    double na[6], nb[6], np[6];
+    phase_barrier();
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      NodeQ q;
+      load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+      na[m] = q.w[0];
+      nb[m] = q.w[1];
+      np[m] = q.p;
+    }
+    double u0[6], u5[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      u0[m] = ra[m] - rb[m] * k1;
+      u5[m] = ra[m] + rb[m] * k1;
+    }
+    weno_pair(0, u0);
+    weno_pair(5, u5);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) { ra[m] = na[m]; rb[m] = nb[m]; rc[m] = np[m]; }
+  }
+  {
+    // group (u_t, a1) loaded ahead
+    double nt[6], nw[6];
+    phase_barrier();
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      NodeQ q;
+      load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+      nt[m] = q.ut;
+      nw[m] = q.w[5];
+    }
+    double u1[6], u2[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      u1[m] = ra[m] - fa1 * rc[m] * k2;
+      u2[m] = rb[m] - fa2 * rc[m] * k2;
+    }
+    weno_pair(1, u1);
+    weno_pair(2, u2);
+    if (HAS_T) {
+      weno_pair(3, nt);
+    } else {
+      UL[3] = 0.0; UR[3] = 0.0; ULf[3] = 0.0f; URf[3] = 0.0f;
+    }
+    weno_pair(4, nw);
+  }
+#else
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     if (!HAS_T && f == 3) { UL[3] = 0.0; UR[3] = 0.0; ULf[3] = 0.0f; URf[3] = 0.0f; continue; }
@@ -227,6 +309,7 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
       UR[f] = weno_is(u[5], u[4], u[3], u[2], u[1], a.tol.weno_eps);
     }
   }
+#endif
   phase_barrier();
   if constexpr (B32) {
     // back-projection V = R U in FP32 [App. A]
@@ -690,7 +773,7 @@ __device__ __forceinline__ void sweep_y_tile(const KArgs& a, int bx, int by,
 }
 
 template <bool DIRI, bool B32>
-__global__ __launch_bounds__(64 * Y_WAVES) void k_sweep_y(KArgs a) {
+__global__ __launch_bounds__(64 * Y_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_y(KArgs a) {
   __shared__ double sGm[Y_WAVES][6][64];
   sweep_y_tile<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, sGm);
 }
