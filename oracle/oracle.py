@@ -40,7 +40,7 @@ class _Problem(C.Structure):
         ("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("pad0", C.c_int32),
         ("dx", C.c_double), ("dy", C.c_double),
         ("bc", C.c_int32 * 4),
-        ("dirichlet", (C.c_double * 6) * 4),
+        ("dirichlet_rows", C.c_void_p * 4),
         ("gamma", C.c_double * 2), ("pinf", C.c_double * 2),
         ("eps_arho", C.c_double), ("eps_alpha", C.c_double), ("eps_rhoc2", C.c_double),
         ("hs_arho", C.c_double), ("hs_alpha", C.c_double), ("hs_rhoc2", C.c_double),
@@ -59,7 +59,10 @@ class Setup:
     dx: float = 1.0
     dy: float = 1.0
     bc: tuple = (BC_PERIODIC,) * 4
-    dirichlet: list = field(default_factory=lambda: [[0.0] * 6 for _ in range(4)])
+    # Dirichlet sides: primitive ghost state (a1r1, a2r2, u, [v], p, a1), one
+    # nvar-vector for the whole side or an array [n_side][nvar] per boundary
+    # row (x sides: ny rows) or column (y sides: nx columns)
+    dirichlet_prim: list = field(default_factory=lambda: [None] * 4)
     gamma: tuple = (6.12, 1.4)           # water, air   [Table 1]
     pinf: tuple = (3.43e8, 0.0)
     eps_arho: float = 1e-10              # [Sec. 5.1]
@@ -84,8 +87,6 @@ class Setup:
         p.dx, p.dy = self.dx, self.dy
         for k in range(4):
             p.bc[k] = int(self.bc[k])
-            for v in range(6):
-                p.dirichlet[k][v] = float(self.dirichlet[k][v]) if v < len(self.dirichlet[k]) else 0.0
         p.gamma[0], p.gamma[1] = self.gamma
         p.pinf[0], p.pinf[1] = self.pinf
         p.eps_arho, p.eps_alpha, p.eps_rhoc2 = self.eps_arho, self.eps_alpha, self.eps_rhoc2
@@ -94,6 +95,28 @@ class Setup:
         p.interp_limiter = int(bool(self.interp_limiter))
         p.flux_limiter = int(bool(self.flux_limiter))
         p.scheme = int(self.scheme)
+        # conservative ghost rows of the Dirichlet sides, made once per
+        # distinct input with the oracle's own EOS [Sec. 2] and kept alive
+        # on the Setup for the Problem's pointers
+        key = tuple((k, np.asarray(self.dirichlet_prim[k], dtype=np.float64).tobytes())
+                    for k in range(4) if self.bc[k] == BC_DIRICHLET)
+        key += (self.gamma, self.pinf, self.nx, self.ny, self.ndim)
+        if getattr(self, "_rows_key", None) != key:
+            rows = {}
+            for k in range(4):
+                if self.bc[k] != BC_DIRICHLET:
+                    continue
+                n_side = self.ny if k < 2 else self.nx
+                V = np.asarray(self.dirichlet_prim[k], dtype=np.float64).reshape(-1, self.nvar)
+                if V.shape[0] not in (1, n_side):
+                    raise ValueError(f"Dirichlet side {k}: need 1 or {n_side} rows")
+                Vt = np.ascontiguousarray(np.broadcast_to(V, (n_side, self.nvar)).T)
+                Wt = np.empty_like(Vt)
+                lib().oracle_prim_to_cons(C.byref(p), _dp(Vt), _dp(Wt), C.c_long(n_side))
+                rows[k] = np.ascontiguousarray(Wt.T)
+            self._rows, self._rows_key = rows, key
+        for k, Wr in self._rows.items():
+            p.dirichlet_rows[k] = Wr.ctypes.data
         return p
 
 

@@ -43,8 +43,11 @@ struct Problem {
   double dx, dy;
   int32_t bc[4];            // x-lo, x-hi, y-lo, y-hi: 0 periodic, 1 constant
                             // extrapolation, 2 reflective wall, 3 Dirichlet
-  double dirichlet[4][6];   // conservative ghost state per side (6 comps,
-                            // rotated-frame independent: a1r1,a2r2,ru,rv,E,a1)
+  const double* dirichlet_rows[4];  // Dirichlet sides: conservative ghost state
+                            // of each boundary row (x sides, ny rows) or
+                            // column (y sides, nx columns), nvar values each
+                            // in state order; a side's three ghost layers
+                            // share their row's state
   double gamma[2], pinf[2]; // phase 1 (liquid), phase 2 (gas)  [Table 1]
   double eps_arho, eps_alpha, eps_rhoc2;   // limiter tolerances  [Sec. 5.1]
   double hs_arho, hs_alpha, hs_rhoc2;      // hard-switch tolerances
@@ -504,7 +507,8 @@ inline void load_rotated(const Problem& P, const double* W, int dir, int line, i
   int s = ghost_source(lo, hi, g, n, flip);
   double Y[6];
   if (s < 0) {
-    const double* d = P.dirichlet[dir * 2 + (g < 0 ? 0 : 1)];
+    const int nv = P.ndim == 1 ? 5 : 6;
+    const double* d = P.dirichlet_rows[dir * 2 + (g < 0 ? 0 : 1)] + (size_t)line * nv;
     if (P.ndim == 1) { Y[0] = d[0]; Y[1] = d[1]; Y[2] = d[2]; Y[3] = 0.0; Y[4] = d[3]; Y[5] = d[4]; }
     else for (int v = 0; v < 6; ++v) Y[v] = d[v];
   } else if (dir == 0) {
@@ -527,7 +531,11 @@ inline void unrotate(int dir, const double R[6], double X[6]) {
   else { X[2] = R[3]; X[3] = R[2]; }
 }
 
-// Max wave speeds max(|u|+c), max(|v|+c) over interior cells [Sec. 3.3].
+// Max wave speeds max(|u|+c), max(|v|+c) [Sec. 3.3] over every state a face
+// flux of that direction sees: the interior cells and, on a Dirichlet side,
+// its ghost states (the other ghost kinds copy interior states).  Reading:
+// the CFL bound behind sigma and lambda must hold at the boundary faces too,
+// where an inflow state can be much faster than the interior (Sec. 6.7).
 void max_wavespeed(const Problem& P, const double* W, double amax[2]) {
   Eos e = make_eos(P);
   amax[0] = 0.0; amax[1] = 0.0;
@@ -539,6 +547,18 @@ void max_wavespeed(const Problem& P, const double* W, double amax[2]) {
       amax[0] = std::max(amax[0], std::fabs(n.un) + n.c);
       amax[1] = std::max(amax[1], std::fabs(n.ut) + n.c);
     }
+  for (int side = 0; side < (P.ndim == 1 ? 2 : 4); ++side) {
+    if (P.bc[side] != BC_DIRICHLET) continue;
+    const int dir = side / 2;
+    const int nline = dir == 0 ? P.ny : P.nx;
+    const int g = (side & 1) ? (dir == 0 ? P.nx : P.ny) : -1;
+    for (int l = 0; l < nline; ++l) {
+      double X[6];
+      load_rotated(P, W, dir, l, g, X);
+      Node<double> n = node_from_w(e, X);   // rotated frame: un normal to the side
+      amax[dir] = std::max(amax[dir], std::fabs(n.un) + n.c);
+    }
+  }
 }
 
 // Directional split sigma and lambda = dt/(dx sigma) [Sec. 3.3]; 1D: dt/dx.

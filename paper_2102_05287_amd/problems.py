@@ -229,6 +229,43 @@ def underwater_explosion(n: int = 2048, eps: float = 1e-6) -> ProblemSpec:
     return s
 
 
+def mach10_cylinder(nx: int = 1152, ny: int = 768) -> ProblemSpec:
+    """Mach 10 air shock hitting a water cylinder [Sec. 6.6]: domain
+    [0, 30L] x [-10L, 10L] with L = 1 mm, cylinder of diameter 8L centred at
+    (13L, 0), constant extrapolation on every side; pre-shock air (1.2, 1e5),
+    post-shock air (6.8571, u = 2817.9, 1.165e7), water (1000, 1e5), all with
+    the 1e-8 floors of the paper's table.  The shock starts at x = 9L, the
+    upstream edge of the cylinder (schematic of Sec. 6.6).  Runs to 16 us."""
+    L = 1e-3
+    s = ProblemSpec("mach10_cylinder", 2, nx, ny, 0.0, 30 * L, -10 * L, 10 * L,
+                    bc=(BC_EXTRAP,) * 4, t_end=16e-6, cfl=0.5)
+    x, y = s.centres()
+    X, Y = np.meshgrid(x, y)
+    V = _fill(6, (ny, nx), _gas(1.0e5, 1.2, 0.0, 0.0))
+    _set(V, X < 9 * L, _gas(1.165e7, 6.8571, 2.8179e3, 0.0))
+    _set(V, (X - 13 * L) ** 2 + Y ** 2 < (4 * L) ** 2, _water(1.0e5, 0.0, 0.0))
+    s.prim = V
+    return s
+
+
+def mach100_jet(nx: int = 1024, ny: int = 512) -> ProblemSpec:
+    """Mach 100 water jet entering air [Sec. 6.7]: domain [0, L] x
+    [-0.25L, 0.25L] with L = 1 m, ambient air (1, 1e5) at rest; the left side
+    is a Dirichlet boundary whose rows with |y| <= 0.05L carry water (1000,
+    u = 1.5e5, 1e5) and the others the ambient air; constant extrapolation
+    on the other three sides.  Runs to 4 us."""
+    s = ProblemSpec("mach100_jet", 2, nx, ny, 0.0, 1.0, -0.25, 0.25,
+                    bc=(BC_DIRICHLET, BC_EXTRAP, BC_EXTRAP, BC_EXTRAP), t_end=4e-6, cfl=0.5)
+    _, y = s.centres()
+    air = _gas(1.0e5, 1.0, 0.0, 0.0)
+    s.prim = _fill(6, (ny, nx), air)
+    rows = np.empty((ny, 6))
+    rows[:] = air
+    rows[np.abs(y) <= 0.05] = _water(1.0e5, 1.5e5, 0.0)
+    s.dirichlet_prim = [rows, None, None, None]
+    return s
+
+
 BATCH_SIDES = (64, 96, 128, 192, 256, 384, 512)
 
 

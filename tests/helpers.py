@@ -16,7 +16,8 @@ from paper_2102_05287_amd import problems as pb  # noqa: E402
 
 def oracle_setup(spec: pb.ProblemSpec, **kw) -> orc.Setup:
     s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy,
-                  bc=tuple(spec.bc), gamma=spec.gamma, pinf=spec.pinf, cfl=spec.cfl)
+                  bc=tuple(spec.bc), gamma=spec.gamma, pinf=spec.pinf, cfl=spec.cfl,
+                  dirichlet_prim=list(spec.dirichlet_prim))
     for k, v in kw.items():
         setattr(s, k, v)
     return s

@@ -599,3 +599,80 @@ def test_opcount_is_plausible():
     assert oc["node"]["div"] == 4 and oc["node"]["sqrt"] == 1
     assert 100 <= oc["face"]["div"] <= 140
     assert oc["face"]["sqrt"] == 2
+
+
+# --------------------------------------------------------------------------
+# Dirichlet sides with one ghost state per boundary row (the jet inflow of
+# Sec. 6.7) and their place in the CFL maxima (Sec. 3.3).
+# --------------------------------------------------------------------------
+def _banded_state(nx, ny):
+    """x-uniform state with water/air bands in y at one pressure, u = 30."""
+    V = np.empty((6, ny, nx))
+    for j in range(ny):
+        st = (1000.0, 1e-8, 30.0, 0.0, 1e5, 1 - 1e-8) if (j // 3) % 2 == 0 else \
+             (1e-8, 1.2, 30.0, 0.0, 1e5, 1e-8)
+        V[:, j, :] = np.array(st)[:, None]
+    return V
+
+
+def test_dirichlet_rows_follow_their_row():
+    """Each x-lo ghost row equal to its interior row: every x-face of a row
+    sees six identical states, so all n+1 faces of the row carry the same
+    split fluxes, the boundary faces included.  Reversing the profile makes
+    the boundary faces of the rows whose band changes differ."""
+    nx, ny = 9, 12
+    V = _banded_state(nx, ny)
+    rows = np.ascontiguousarray(V[:, :, 0].T)
+    s = orc.Setup(ndim=2, nx=nx, ny=ny, dx=1e-3, dy=1e-3,
+                  bc=(orc.BC_DIRICHLET, orc.BC_EXTRAP, orc.BC_EXTRAP, orc.BC_EXTRAP),
+                  dirichlet_prim=[rows, None, None, None])
+    W = orc.prim_to_cons(s, V)
+    Gm, Gp, _ = orc.faces(s, W, 0, 1e-9)
+    for j in range(ny):
+        assert np.array_equal(Gm[j], np.broadcast_to(Gm[j, -1], Gm[j].shape)), j
+        assert np.array_equal(Gp[j], np.broadcast_to(Gp[j, -1], Gp[j].shape)), j
+    s.dirichlet_prim = [np.ascontiguousarray(rows[::-1]), None, None, None]
+    Gm2, _, _ = orc.faces(s, W, 0, 1e-9)
+    changed = [j for j in range(ny) if (j // 3) % 2 != ((ny - 1 - j) // 3) % 2]
+    assert changed
+    for j in range(ny):
+        differs = not np.array_equal(Gm2[j, 0], Gm2[j, -1])
+        assert differs == (j in changed), j
+
+
+def test_dirichlet_supersonic_inflow_face_flux():
+    """1D supersonic inflow (water at 3000 m/s into air at 1000 m/s, both
+    faster than sound): the first-order HLLC flux of the inflow face is the
+    physical flux of the ghost state (Sec. 3.2, upwind case)."""
+    n = 8
+    ghost = (1000.0, 1e-8, 3000.0, 2e5, 1 - 1e-8)
+    V = np.empty((5, 1, n))
+    V[:, 0, :] = np.array((1e-8, 1.2, 1000.0, 1e5, 1e-8))[:, None]
+    s = orc.Setup(ndim=1, nx=n, dx=1e-3,
+                  bc=(orc.BC_DIRICHLET, orc.BC_EXTRAP, orc.BC_PERIODIC, orc.BC_PERIODIC),
+                  dirichlet_prim=[ghost, None, None, None], scheme=1)
+    W = orc.prim_to_cons(s, V)
+    Gm, Gp, _ = orc.faces(s, W, 0, 1e-9)
+    a1r1, a2r2, u, p, _ = ghost
+    rho = a1r1 + a2r2
+    want = (a1r1 * u, a2r2 * u, rho * u * u + p)
+    for k in range(3):
+        assert math.isclose(Gm[0, 0, k], want[k], rel_tol=1e-14), (k, Gm[0, 0, k], want[k])
+        assert math.isclose(Gp[0, 0, k], want[k], rel_tol=1e-14), k
+
+
+def test_dirichlet_ghosts_enter_the_cfl_maxima():
+    """Air at rest with a 1.5e5 m/s water inflow row (Sec. 6.7): the x
+    maximum is the inflow's |u| + c (c of water at 1e5 Pa about 1449 m/s),
+    the y maximum only sees the interior air."""
+    nx, ny = 16, 8
+    V = np.empty((6, ny, nx))
+    V[:] = np.array((1e-8, 1.0, 0.0, 0.0, 1e5, 1e-8))[:, None, None]
+    rows = np.tile(np.array((1e-8, 1.0, 0.0, 0.0, 1e5, 1e-8)), (ny, 1))
+    rows[3:5] = (1000.0, 1e-8, 1.5e5, 0.0, 1e5, 1 - 1e-8)
+    s = orc.Setup(ndim=2, nx=nx, ny=ny, dx=1e-3, dy=1e-3,
+                  bc=(orc.BC_DIRICHLET, orc.BC_EXTRAP, orc.BC_EXTRAP, orc.BC_EXTRAP),
+                  dirichlet_prim=[rows, None, None, None])
+    a = orc.max_wavespeed(s, orc.prim_to_cons(s, V))
+    assert 1.5e5 + 1440.0 < a[0] < 1.5e5 + 1460.0, a
+    assert 370.0 < a[1] < 380.0, a
