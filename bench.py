@@ -36,18 +36,19 @@ VALU_F64_SLOTS = 256 * 64 * 2.4e9
 W_DIV, W_SQRT = 11, 19   # VALU instructions of the IEEE FP64 divide / sqrt on gfx950
 
 
-def weighted(c):
-    return c["add"] + c["mul"] + c["cmp"] + W_DIV * c["div"] + W_SQRT * c["sqrt"]
+def weighted(c, w_div=W_DIV, w_sqrt=W_SQRT):
+    return c["add"] + c["mul"] + c["cmp"] + w_div * c["div"] + w_sqrt * c["sqrt"]
 
 
-def kernel_ops(nx, ny, scheme="ppwcnsis"):
-    """Algorithmic (issue-weighted) FP64 ops per launch of each kernel."""
+def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=W_DIV, w_sqrt=W_SQRT):
+    """Algorithmic (issue-weighted) FP64 ops per launch of each kernel;
+    w_div = w_sqrt = 1 gives the plain operation count."""
     with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
         oc = json.load(f)["counts"][scheme]
-    face = weighted(oc["face"])
-    node = weighted(oc["node"])
+    face = weighted(oc["face"], w_div, w_sqrt)
+    node = weighted(oc["node"], w_div, w_sqrt)
     cells = nx * ny
-    diff = 6 * (1 + W_DIV)                 # -(G^- - G^+)/dx per component
+    diff = 6 * (1 + w_div)                 # -(G^- - G^+)/dx per component
     rk = 6 * 5                             # ca*Un + cb*(W + dt*L)
     return {
         "node": cells * (node + 4),        # + |u|+c, |v|+c, two max
@@ -110,6 +111,20 @@ def precision_form(n, steps, warmup):
     t64, W64 = time_steps(s64, W0, steps, warmup)
     t32, W32 = time_steps(s32, W0, steps, warmup)
     cells = spec.nx * spec.ny
+    # per-kernel device time of the FP32-bulk sweeps (same op model as FP64)
+    W = W0.clone()
+    s32.profile(True)
+    for _ in range(steps):
+        s32.step(W, 0.0)
+    prof = s32.profile_read(reset=True)
+    s32.profile(False)
+    ops = kernel_ops(spec.nx, spec.ny)
+    roof32 = {}
+    for k in ("sweep_x", "sweep_y"):
+        avg = prof[k][0] / 1e3 / prof[k][1]
+        roof32[k] = {"avg_launch_ms": avg * 1e3, "achieved": ops[k] / avg / 1e12,
+                     "frac": ops[k] / avg / VALU_F64_SLOTS}
+    del W
     # step-aligned accuracy: same dt sequence (from the FP64 state)
     A, B = W0.clone(), W0.clone()
     dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -123,6 +138,11 @@ def precision_form(n, steps, warmup):
             "fp64_mcells_per_s": 3 * cells * steps / t64 / 1e6,
             "fp32_bulk_mcells_per_s": 3 * cells * steps / t32 / 1e6,
             "speedup_fp32_bulk": t64 / t32,
+            "roofline_fp32_bulk": {"bound": "alu", "peak": VALU_F64_SLOTS / 1e12, "unit": "TFLOP/s",
+                                   "kernels": roof32,
+                                   "note": "FP64 op model and FP64 issue peak; the FP32 "
+                                           "interpolation issues at the same per-wave rate "
+                                           "(no packed math is generated)"},
             "rel_l1_fp32_vs_fp64_per_variable": l1,
             "inadmissible_fp32": bad}
 
@@ -206,6 +226,89 @@ def serving_form(n_req, rate, budget_gib, chunk):
     return summary
 
 
+def time_to_solution_form():
+    """The paper's runs to their final times on the device time loop
+    (Solver.advance): the 1D water-air tube (400 cells, t = 2.4e-4 s), the
+    1D multi-material Sedov blast (401 cells, 4000 fixed steps), and the two
+    2D robustness problems, Mach 10 shock-water cylinder (1152 x 768, 16 us)
+    and Mach 100 water jet (1024 x 512, 4 us), with PP-WCNS-IS and with the
+    first-order HLLC scheme; plus the cylinder with both limiters off, which
+    has to fail."""
+    import torch
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import wcns
+    out = {}
+
+    def run(name, spec, **kw):
+        sol = wcns.Solver.from_spec(spec, **kw)
+        W = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if spec.dt_fixed > 0:
+            t, n = 0.0, 0
+            while t < spec.t_end:
+                dt = spec.dt_fixed if t + spec.dt_fixed <= spec.t_end else spec.t_end - t
+                sol.step(W, dt)
+                t += dt
+                n += 1
+        else:
+            n, t = sol.advance(W, spec.t_end, chunk=64 if spec.ndim == 2 else 32)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        a1 = W[-1]
+        rec = {"grid": [spec.nx, spec.ny] if spec.ndim == 2 else [spec.nx], "t_end": spec.t_end,
+               "steps": n, "wall_s": el, "ms_per_step": el / n * 1e3,
+               "mcell_updates_per_s": 3.0 * spec.nx * spec.ny * n / el / 1e6,
+               "inadmissible_at_end": sol.count_inadmissible(W),
+               "alpha1_min": float(a1.min()), "alpha1_max": float(a1.max())}
+        out[name] = rec
+        print(f"#   {name}: {n} steps in {el:.2f} s", flush=True)
+        sol.close()
+
+    run("water_air_tube_1d", pb.water_air_shock_tube(400))
+    run("sedov_1d", pb.sedov_multimaterial(401))
+    run("mach10_cylinder", pb.mach10_cylinder())
+    run("mach10_cylinder_hllc1", pb.mach10_cylinder(), scheme=1)
+    run("mach100_jet", pb.mach100_jet())
+    run("mach100_jet_hllc1", pb.mach100_jet(), scheme=1)
+    # negative control: no limiters, checked every 50 steps until it fails
+    spec = pb.mach10_cylinder()
+    sol = wcns.Solver.from_spec(spec, interp_limiter=False, flux_limiter=False)
+    W = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+    fail_at, n = None, 0
+    while n < 8000 and fail_at is None:
+        for _ in range(50):
+            sol.step(W, 0.0)
+        n += 50
+        if sol.count_inadmissible(W):
+            fail_at = n
+    out["mach10_cylinder_limiters_off"] = {"first_inadmissible_within_steps": fail_at,
+                                           "checked_every": 50, "max_steps": 8000}
+    sol.close()
+    return out
+
+
+def serving_rate_sweep(n_req=60, rates=(10.0, 20.0, 40.0, 200.0), budget_gib=64, chunk=20):
+    """The same first n_req requests of the seed-4 trace replayed at several
+    arrival rates: latency against offered load; the completion rate at the
+    highest (over-capacity) rate is the server's capacity."""
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import serve
+    rows = []
+    for r in rates:
+        reqs = pb.serving_trace(n_req, r, seed=4)
+        solves = [serve.Solve(q.rid, q.arrival, pb.request_problem(q), q.steps, q.fp32) for q in reqs]
+        srv = serve.Server(hbm_budget=budget_gib << 30, chunk=chunk)
+        _, sm = srv.run(solves, realtime=True)
+        rows.append({"rate_req_per_s": r, "solves_per_s": sm["solves_per_s"],
+                     "latency_p50_s": sm["latency_p50_s"], "latency_p99_s": sm["latency_p99_s"],
+                     "makespan_s": sm["makespan_s"]})
+        print(f"#   rate {r}: {sm['solves_per_s']:.1f} solves/s, p99 {sm['latency_p99_s']:.2f} s",
+              flush=True)
+    return {"requests_per_rate": n_req, "rates": rows,
+            "capacity_solves_per_s": rows[-1]["solves_per_s"]}
+
+
 def cpu_baseline(spec, target_s=12.0):
     from oracle import oracle as orc
     s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy, bc=spec.bc)
@@ -234,6 +337,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision/batched/serving forms")
+    ap.add_argument("--form", choices=("precision", "batched", "serving", "solutions", "rates"),
+                    default=None,
+                    help="run only this form and print its record")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -247,6 +353,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "copies": 3}))
+        return
+    if args.form:
+        import torch
+        torch.cuda.set_device(0)
+        run = {"precision": lambda: precision_form(2048, 20, 3),
+               "batched": lambda: batched_form(512, 200, 20),
+               "serving": lambda: serving_form(300, 200.0, 64, 20),
+               "solutions": time_to_solution_form,
+               "rates": serving_rate_sweep}[args.form]
+        print(json.dumps({"form": args.form, **run()}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -294,8 +410,10 @@ def main():
     avg_s = ms / 1e3 / n
     achieved = ops[dom] / avg_s / 1e12
     peak = VALU_F64_SLOTS / 1e12
+    ops1 = kernel_ops(spec.nx, spec.ny, w_div=1, w_sqrt=1)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
+                "frac_unweighted": ops1[dom] / avg_s / VALU_F64_SLOTS,
                 "avg_launch_ms": avg_s * 1e3,
                 "ops_per_launch": ops[dom],
                 "op_model": "oracle op count, div=11 and sqrt=19 VALU slots; peak = FP64 "
@@ -323,6 +441,10 @@ def main():
         forms["batched"] = batched_form(512, 200, 20)
         print("# serving form ...", flush=True)
         forms["serving"] = serving_form(300, 200.0, 64, 20)
+        print("# serving rate sweep ...", flush=True)
+        forms["serving_rate_sweep"] = serving_rate_sweep()
+        print("# time to solution (paper runs) ...", flush=True)
+        forms["time_to_solution"] = time_to_solution_form()
 
     cpu = None
     if not args.no_cpu:

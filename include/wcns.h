@@ -44,7 +44,7 @@ typedef enum {
   WCNS_BC_PERIODIC = 0,
   WCNS_BC_EXTRAP = 1,         /* constant (zeroth-order) extrapolation         */
   WCNS_BC_REFLECT = 2,        /* mirror state, negate wall-normal momentum     */
-  WCNS_BC_DIRICHLET = 3       /* fixed ghost state (grid.dirichlet)            */
+  WCNS_BC_DIRICHLET = 3       /* fixed ghost states (grid.dirichlet[_rows])    */
 } wcns_bc;
 
 typedef enum { WCNS_FP64 = 0, WCNS_FP32_BULK = 1 } wcns_precision;
@@ -62,8 +62,17 @@ typedef struct {
   int32_t nx, ny;             /* ny = 1 when ndim = 1                          */
   double x0, x1, y0, y1;
   int32_t bc[4];              /* wcns_bc of x-lo, x-hi, y-lo, y-hi             */
-  double dirichlet[4][6];     /* host; conservative ghost state per side, in   */
-                              /* the nvar order above (used for DIRICHLET)     */
+  double dirichlet[4][6];     /* host; PRIMITIVE ghost state per side          */
+                              /* (a1r1, a2r2, u, [v], p, a1), nvar values, for */
+                              /* DIRICHLET sides without a row profile         */
+  const double* dirichlet_rows[4];
+                              /* host, optional (NULL: dirichlet[side] for the */
+                              /* whole side): primitive ghost state of each    */
+                              /* boundary row, [n_side][nvar], n_side = ny for */
+                              /* x-lo/x-hi and nx for y-lo/y-hi (e.g. the jet  */
+                              /* inflow of Sec. 6.7).  The three ghost layers  */
+                              /* of a row share its state.  Copied at create;  */
+                              /* the caller keeps ownership.                   */
 } wcns_grid;
 
 /* Scheme options; wcns_params_default fills the paper's values. */
@@ -86,8 +95,10 @@ wcns_status wcns_params_default(wcns_params* p);
 
 /* Create a context for one grid.  Validates the fluids against Lemma 1
  * (WCNS_ERR_EOS), the grid (nx, ny >= 1, ndim in {1,2}, bc kinds, reflective
- * sides need >= 3 cells) and the parameters (WCNS_ERR_ARG), then allocates
- * all device scratch once (WCNS_ERR_NOMEM).  stream: hipStream_t or NULL for
+ * sides need >= 3 cells) and the parameters (WCNS_ERR_ARG), checks the
+ * Dirichlet ghost states (finite, partial densities >= 0 with a positive sum,
+ * 0 <= a1 <= 1; else WCNS_ERR_INADMISSIBLE), then allocates all device
+ * scratch once (WCNS_ERR_NOMEM).  stream: hipStream_t or NULL for
  * the default stream.  On success *out owns the scratch until wcns_destroy. */
 wcns_status wcns_create(const wcns_grid* grid, const wcns_eos* eos, const wcns_params* params,
                         int32_t precision, void* stream, wcns_ctx** out);
@@ -121,7 +132,10 @@ wcns_status wcns_rhs(wcns_ctx* ctx, const double* W, double* dWdt, double dt);
 wcns_status wcns_limit(wcns_ctx* ctx, int32_t dir, const double* W, const double* G_ho,
                        const double* G_lo, double* G_out, double* theta, double dt);
 
-/* Maximum wave speeds max(|u|+c), max(|v|+c) over the cells (Sec. 3.3).
+/* Maximum wave speeds max(|u|+c), max(|v|+c) (Sec. 3.3) over the cells and
+ * the ghost states of Dirichlet sides (those of the x sides count for the
+ * first, of the y sides for the second), i.e. over every state a face flux of
+ * that direction sees; the CFL time step and lambda use the same maxima.
  * d_amax: device double[2] (the second entry is 0 in 1D). */
 wcns_status wcns_max_wavespeed(wcns_ctx* ctx, const double* W, double* d_amax);
 

@@ -27,6 +27,7 @@ struct wcns_ctx {
   KArgs base;
   double *P, *L, *U1, *U2, *partial, *step, *dirW, *dirP, *edge;
   unsigned long long* count;
+  double* damax;  // Dirichlet ghost wave-speed maxima [2] (inside dirP), or null
   int node_grid, tile_x, x_grid, nbr;
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
@@ -235,46 +236,79 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   }
   alloc(&c->partial, 2 * (size_t)c->node_grid);
   alloc(&c->step, 8);
-  alloc(&c->dirW, 24);
-  alloc(&c->dirP, 20);
+  // Dirichlet ghost rows: x-lo, x-hi (ny each), y-lo, y-hi (nx each)
+  const int R = 2 * g->ny + 2 * g->nx;
+  alloc(&c->dirW, 6 * (size_t)R);
+  alloc(&c->dirP, 5 * (size_t)R + 2);
   if (st == WCNS_OK && hipMalloc((void**)&c->count, sizeof(unsigned long long)) != hipSuccess)
     st = WCNS_ERR_NOMEM;
   if (st != WCNS_OK) { wcns_destroy(c); return st; }
 
-  // Dirichlet ghost states (unrotated 6-component form) and their primitives
-  double dw[24];
+  // Dirichlet ghost rows: primitive states from the grid (per row, or one
+  // state for the whole side), converted on the device like any state
+  a.dir_off[0] = 0;
+  a.dir_off[1] = g->ny;
+  a.dir_off[2] = 2 * g->ny;
+  a.dir_off[3] = 2 * g->ny + g->nx;
+  const int nv = c->nv;
+  bool any_diri = false;
+  double* V = (double*)malloc(sizeof(double) * nv * (size_t)R);
+  if (!V) { wcns_destroy(c); return WCNS_ERR_NOMEM; }
   for (int s = 0; s < 4; ++s) {
-    const double* d = g->dirichlet[s];
-    bool used = g->bc[s] == WCNS_BC_DIRICHLET && (g->ndim == 2 || s < 2);
-    if (!used) {
-      // harmless admissible placeholder (never read)
-      double ph[6] = {1.0, 1.0, 0.0, 0.0, 1e6, 0.5};
-      memcpy(dw + 6 * s, ph, sizeof(ph));
-    } else if (g->ndim == 1) {
-      double x[6] = {d[0], d[1], d[2], 0.0, d[3], d[4]};
-      memcpy(dw + 6 * s, x, sizeof(x));
-    } else {
-      memcpy(dw + 6 * s, d, 6 * sizeof(double));
+    const int n_side = s < 2 ? g->ny : g->nx;
+    const bool used = g->bc[s] == WCNS_BC_DIRICHLET && (g->ndim == 2 || s < 2);
+    any_diri = any_diri || used;
+    for (int l = 0; l < n_side; ++l) {
+      const int r = a.dir_off[s] + l;
+      for (int k = 0; k < nv; ++k) {
+        double x;
+        if (!used)   // admissible placeholder, never read
+          x = k < 2 ? 1.0 : (k == nv - 2 ? 1e6 : (k == nv - 1 ? 0.5 : 0.0));
+        else
+          x = g->dirichlet_rows[s] ? g->dirichlet_rows[s][(size_t)l * nv + k] : g->dirichlet[s][k];
+        V[(size_t)k * R + r] = x;
+      }
+      if (used) {
+        const double a1r1 = V[r], a2r2 = V[(size_t)R + r], a1 = V[(size_t)(nv - 1) * R + r];
+        bool ok = a1r1 >= 0.0 && a2r2 >= 0.0 && a1r1 + a2r2 > 0.0 && a1 >= 0.0 && a1 <= 1.0;
+        for (int k = 0; k < nv; ++k) ok = ok && isfinite(V[(size_t)k * R + r]);
+        if (!ok) { free(V); wcns_destroy(c); return WCNS_ERR_INADMISSIBLE; }
+      }
     }
   }
-  if (hipMemcpy(c->dirW, dw, sizeof(dw), hipMemcpyHostToDevice) != hipSuccess) {
-    wcns_destroy(c);
-    return WCNS_ERR_HIP;
-  }
+  double *dV = nullptr, *dWg = nullptr;
+  bool fail = hipMalloc((void**)&dV, sizeof(double) * nv * (size_t)R) != hipSuccess ||
+              hipMalloc((void**)&dWg, sizeof(double) * nv * (size_t)R) != hipSuccess;
+  fail = fail || hipMemcpy(dV, V, sizeof(double) * nv * (size_t)R, hipMemcpyHostToDevice) != hipSuccess;
+  free(V);
   double zero8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (hipMemcpy(c->step, zero8, sizeof(zero8), hipMemcpyHostToDevice) != hipSuccess) {
-    wcns_destroy(c);
-    return WCNS_ERR_HIP;
-  }
+  fail = fail || hipMemcpy(c->step, zero8, sizeof(zero8), hipMemcpyHostToDevice) != hipSuccess;
   a.dirW = c->dirW;
   a.dirP = c->dirP;
   a.step = c->step;
   a.edge = c->edge;
-  if (g->ndim == 2)
-    hipLaunchKernelGGL(k_dirichlet_prims<true>, dim3(1), dim3(64), 0, c->stream, a, c->dirP);
-  else
-    hipLaunchKernelGGL(k_dirichlet_prims<false>, dim3(1), dim3(64), 0, c->stream, a, c->dirP);
-  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+  c->damax = any_diri ? c->dirP + 5 * (size_t)R : nullptr;
+  if (!fail) {
+    KArgs ar = a;   // the rows as a 1-row grid of R cells
+    ar.nx = R;
+    ar.ny = 1;
+    unsigned gr = (unsigned)((R + 255) / 256);
+    if (g->ndim == 2) {
+      hipLaunchKernelGGL(k_prim_to_cons<true>, dim3(gr), dim3(256), 0, c->stream, ar,
+                         (const double*)dV, dWg);
+      hipLaunchKernelGGL(k_dirichlet_rows<true>, dim3(1), dim3(256), 0, c->stream, a,
+                         (const double*)dWg, R, c->dirW, c->dirP, c->dirP + 5 * (size_t)R);
+    } else {
+      hipLaunchKernelGGL(k_prim_to_cons<false>, dim3(gr), dim3(256), 0, c->stream, ar,
+                         (const double*)dV, dWg);
+      hipLaunchKernelGGL(k_dirichlet_rows<false>, dim3(1), dim3(256), 0, c->stream, a,
+                         (const double*)dWg, R, c->dirW, c->dirP, c->dirP + 5 * (size_t)R);
+    }
+    fail = hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess;
+  }
+  if (dV) (void)hipFree(dV);
+  if (dWg) (void)hipFree(dWg);
+  if (fail) {
     wcns_destroy(c);
     return WCNS_ERR_HIP;
   }
@@ -310,6 +344,7 @@ static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mod
   f.dt_in = dt;
   f.step = c->step;
   f.dt_used = dt_used;
+  f.damax = c->damax;
   ProfScope ps(c, PROF_FIN);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
                      c->node_grid, f);

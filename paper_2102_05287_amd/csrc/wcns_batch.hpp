@@ -32,20 +32,25 @@ __global__ __launch_bounds__(256) void kb_finalize(const KArgs* ka) {
   finalize_inst(a);
 }
 
+// The sweeps copy their instance's arguments into registers first: read
+// through the pointer, every use would be a fresh scalar load (the stores of
+// the sweep may alias them), which measured 14% (FP64) and 28% (FP32-bulk)
+// slower than the copy.
 template <bool HAS_T, bool B32>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void kb_sweep_x(
     const KArgs* ka, const Task* t) {
   const Task task = t[blockIdx.x];
-  const KArgs& a = ka[task.inst];
+  const KArgs a = ka[task.inst];
   if (frozen(a)) return;
   sweep_x_tile<HAS_T, false, B32>(a, task.a);
 }
 
 template <int YW, bool B32>
-__global__ __launch_bounds__(64 * YW) void kb_sweep_y(const KArgs* ka, const Task* t) {
+__global__ __launch_bounds__(64 * YW) __attribute__((amdgpu_waves_per_eu(3))) void kb_sweep_y(
+    const KArgs* ka, const Task* t) {
   __shared__ double sGm[YW][6][64];
   const Task task = t[blockIdx.x];
-  const KArgs& a = ka[task.inst];
+  const KArgs a = ka[task.inst];
   if (frozen(a)) return;
   sweep_y_tile<YW, false, B32>(a, task.a, task.b, sGm);
 }

@@ -41,6 +41,7 @@ struct KArgs {
   int32_t nx, ny, nv, tile_x;     // tile_x: cells per x-sweep wave
   double dx, dy;
   int32_t bc[4];
+  int32_t dir_off[4];    // first Dirichlet ghost row of each side in dirW/dirP
   int32_t interp_limiter, flux_limiter, scheme, pad;
   EosC eos;
   Tol tol;
@@ -49,8 +50,9 @@ struct KArgs {
   const double* Wc[6];   // per-component bases of W in rotated-frame-free state
                          // order (1D: a1r1, a2r2, m, -, E, a1 with slot 3 unused)
   const double* Pc[5];   // per-component bases of P
-  const double* dirW;    // Dirichlet ghost states [4][6] (unrotated 6-comp)
-  const double* dirP;    // their primitives [4][5]
+  const double* dirW;    // Dirichlet ghost state of each boundary row/column
+                         // [rows][6] (unrotated 6-comp; 1D: slot 3 is 0)
+  const double* dirP;    // their node primitives [rows][5] (u, v, p, c, h)
   const double* step;    // [0] dt, [1] lam_x, [2] lam_y, [3] amax_x, [4] amax_y
   const double* Lx;      // x-part of L (read by the y-sweep)
   double* Lout;          // x-sweep output (L_x in 2D, full L in 1D)
@@ -90,6 +92,7 @@ __device__ __forceinline__ int ghost_src(int g, int n, int bc_lo, int bc_hi, boo
 struct Sten {
   uint32_t off[6];
   uint32_t flip, diri;
+  int32_t drow[2];   // Dirichlet ghost rows of the face's line (lo, hi side)
 };
 
 template <int DIR>
@@ -98,6 +101,8 @@ __device__ __forceinline__ Sten make_sten(const KArgs& a, int line, int g0) {
   Sten st;
   st.flip = 0;
   st.diri = 0;
+  st.drow[0] = a.dir_off[2 * DIR] + line;
+  st.drow[1] = a.dir_off[2 * DIR + 1] + line;
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
     const int g = g0 + m;
@@ -133,14 +138,14 @@ __device__ __forceinline__ void load_node(const KArgs& a, const Sten& st, int m,
   q.c = ldc(a.Pc[3], o);
   q.h = ldc(a.Pc[4], o);
   if (DIRI && ((st.diri >> m) & 1u)) {
-    const int side = 2 * DIR + (g0 + m < 0 ? 0 : 1);
+    const int r = st.drow[g0 + m < 0 ? 0 : 1];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) Y[k] = a.dirW[side * 6 + k];
-    u = a.dirP[side * 5 + 0];
-    v = a.dirP[side * 5 + 1];
-    q.p = a.dirP[side * 5 + 2];
-    q.c = a.dirP[side * 5 + 3];
-    q.h = a.dirP[side * 5 + 4];
+    for (int k = 0; k < 6; ++k) Y[k] = a.dirW[r * 6 + k];
+    u = a.dirP[r * 5 + 0];
+    v = a.dirP[r * 5 + 1];
+    q.p = a.dirP[r * 5 + 2];
+    q.c = a.dirP[r * 5 + 3];
+    q.h = a.dirP[r * 5 + 4];
   }
   q.w[0] = Y[0]; q.w[1] = Y[1]; q.w[4] = Y[4]; q.w[5] = Y[5];
   if (DIR == 0) { q.w[2] = Y[2]; q.w[3] = Y[3]; q.un = u; q.ut = v; }
@@ -493,6 +498,7 @@ struct FinArgs {
   double dx, dy, cfl, dt_in;
   double* step;       // [0] dt, [1] lam_x, [2] lam_y, [3] amax_x, [4] amax_y
   double* dt_used;    // optional copy of dt
+  const double* damax;  // Dirichlet ghost maxima [2] or null
 };
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -555,6 +561,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int nbl
   __syncthreads();
   if (threadIdx.x != 0) return;
   for (int k = 0; k < 4; ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
+  if (f.damax) { mx = fmax(mx, f.damax[0]); my = fmax(my, f.damax[1]); }
   double* step = f.step;
   double dt;
   if (f.dt_mode == DT_GIVEN) dt = f.dt_in;
@@ -575,18 +582,49 @@ __global__ __launch_bounds__(256) void k_finalize(const double* partial, int nbl
   if (f.dt_used) *f.dt_used = dt;
 }
 
-// primitives of the (up to 4) Dirichlet ghost states
+// Dirichlet ghost rows (one block): conservative states Wg (SoA [nvar][R],
+// from k_prim_to_cons) -> unrotated 6-component rows dirW [R][6] and their
+// node primitives dirP [R][5]; damax[d] = max(|u_d| + c) over the rows of
+// the Dirichlet sides of direction d (0 when there are none), which the time
+// step and lambda include [Sec. 3.3].
 template <bool HAS_T>
-__global__ void k_dirichlet_prims(KArgs a, double* dirP) {
-  int s = threadIdx.x;
-  if (s >= 4) return;
-  double X[6];
+__global__ __launch_bounds__(256) void k_dirichlet_rows(KArgs a, const double* Wg, int R,
+                                                        double* dirW, double* dirP, double* damax) {
+  double m[2] = {0.0, 0.0};
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    double X[6];
+    X[0] = Wg[r];
+    X[1] = Wg[R + r];
+    X[2] = Wg[2 * R + r];
+    X[3] = HAS_T ? Wg[3 * R + r] : 0.0;
+    X[4] = Wg[(HAS_T ? 4 : 3) * R + r];
+    X[5] = Wg[(HAS_T ? 5 : 4) * R + r];
 #pragma unroll
-  for (int k = 0; k < 6; ++k) X[k] = a.dirW[s * 6 + k];
-  double un, ut, p, c, h;
-  recover<HAS_T>(a.eos, X, un, ut, p, c, h);
-  dirP[s * 5 + 0] = un; dirP[s * 5 + 1] = ut; dirP[s * 5 + 2] = p;
-  dirP[s * 5 + 3] = c; dirP[s * 5 + 4] = h;
+    for (int k = 0; k < 6; ++k) dirW[r * 6 + k] = X[k];
+    double un, ut, p, c, h;
+    recover<HAS_T>(a.eos, X, un, ut, p, c, h);
+    dirP[r * 5 + 0] = un; dirP[r * 5 + 1] = ut; dirP[r * 5 + 2] = p;
+    dirP[r * 5 + 3] = c; dirP[r * 5 + 4] = h;
+    int side = 3;
+    while (side > 0 && r < a.dir_off[side]) --side;
+    if (a.bc[side] == BC_DIRICHLET) {
+      const int d = side >> 1;
+      m[d] = fmax(m[d], fabs(d == 0 ? un : ut) + c);
+    }
+  }
+  m[0] = wave_max(m[0]);
+  m[1] = wave_max(m[1]);
+  __shared__ double red[2][4];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = m[0]; red[1][w] = m[1]; }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+    red[0][0] = fmax(red[0][0], red[0][k]);
+    red[1][0] = fmax(red[1][0], red[1][k]);
+  }
+  damax[0] = red[0][0];
+  damax[1] = red[1][0];
 }
 
 // One block of the node pass of one instance (batched form): cells

@@ -38,7 +38,8 @@ class _Grid(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("pad", C.c_int32),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("bc", C.c_int32 * 4),
-                ("dirichlet", (C.c_double * 6) * 4)]
+                ("dirichlet", (C.c_double * 6) * 4),
+                ("dirichlet_rows", C.c_void_p * 4)]
 
 
 class _Eos(C.Structure):
@@ -135,27 +136,24 @@ def _ptr(t):
 class Solver:
     """One grid + fluids + options, bound to a device context.
 
-    grid: ndim, nx, ny, x0, x1, y0, y1, bc (4 kinds), dirichlet (4 host
-    conservative states, only for Dirichlet sides)."""
+    grid: ndim, nx, ny, x0, x1, y0, y1, bc (4 kinds), dirichlet (per side:
+    None, or the primitive ghost state (a1r1, a2r2, u, [v], p, a1) of a
+    Dirichlet side as one nvar-vector or as an array [n_side][nvar] of one
+    state per boundary row/column)."""
 
     def __init__(self, ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4,
                  gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), precision=FP64, stream=None,
                  dirichlet=None, **params):
         import torch
-        g = _Grid()
-        g.ndim, g.nx, g.ny = ndim, nx, ny
-        g.x0, g.x1, g.y0, g.y1 = x0, x1, y0, y1
-        for k in range(4):
-            g.bc[k] = int(bc[k])
-            if dirichlet is not None and dirichlet[k] is not None:
-                for v, val in enumerate(dirichlet[k]):
-                    g.dirichlet[k][v] = float(val)
+        g = make_grid(ndim, nx, ny, x0, x1, y0, y1, bc, dirichlet)
         e = _Eos()
         e.gamma[0], e.gamma[1] = gamma
         e.pinf[0], e.pinf[1] = pinf
         p = default_params(**params)
         self.ndim, self.nx, self.ny = ndim, nx, ny
         self.nvar = 5 if ndim == 1 else 6
+        self.dx = (x1 - x0) / nx
+        self.dy = (y1 - y0) / ny if ndim == 2 else 1.0
         self.params = p
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
@@ -169,7 +167,8 @@ class Solver:
     def from_spec(cls, spec, **kw):
         """Build from a seeded ProblemSpec (paper_2102_05287_amd.problems)."""
         return cls(spec.ndim, spec.nx, spec.ny, spec.x0, spec.x1, spec.y0, spec.y1,
-                   bc=spec.bc, gamma=spec.gamma, pinf=spec.pinf, cfl=spec.cfl, **kw)
+                   bc=spec.bc, gamma=spec.gamma, pinf=spec.pinf, cfl=spec.cfl,
+                   dirichlet=spec.dirichlet_prim, **kw)
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
@@ -218,6 +217,50 @@ class Solver:
         _check(lib().wcns_ssprk3_step(self._ctx, _ptr(W), float(dt), _ptr(dt_used)),
                "wcns_ssprk3_step")
         return W
+
+    def cfl_dt(self, amax) -> float:
+        """The CFL step of the device for wave-speed maxima amax (Sec. 3.3),
+        in the same floating-point operations."""
+        cfl = self.params.cfl
+        if self.ndim == 1:
+            return cfl * self.dx / amax[0]
+        return cfl / (amax[0] / self.dx + amax[1] / self.dy)
+
+    def advance(self, W, t_end, t=0.0, chunk=64, margin=8.0, max_steps=1 << 40):
+        """March W in place from time t to t_end with CFL steps, the last one
+        shortened to land on t_end (the time loop of the paper's runs).
+        Far from t_end the device picks every dt itself and the host reads
+        the chunk's time steps once per `chunk` steps; once t_end is within
+        margin * chunk * (largest recent dt) it takes one step at a time
+        from the device's wave-speed maxima.  Returns (steps, t)."""
+        import torch
+        buf = torch.empty(chunk, dtype=torch.float64, device="cuda")
+        steps, dt_last = 0, None
+        while t < t_end and steps < max_steps:
+            if dt_last is not None and t_end - t > margin * chunk * dt_last \
+                    and steps + chunk <= max_steps:
+                for k in range(chunk):
+                    self.step(W, 0.0, dt_used=buf[k:k + 1])
+                dts = buf.cpu().tolist()
+                for d in dts:
+                    t += d
+                steps += chunk
+                dt_last = max(dts)
+                if not all(d > 0.0 for d in dts):
+                    raise WcnsError(-6, "advance: non-positive or non-finite time step")
+                if t > t_end:
+                    raise WcnsError(-6, "advance: a chunk passed t_end (raise margin)")
+            else:
+                dt = self.cfl_dt(self.max_wavespeed(W).cpu().tolist())
+                if not dt > 0.0:
+                    raise WcnsError(-6, "advance: non-positive or non-finite time step")
+                if t + dt > t_end:
+                    dt = t_end - t
+                self.step(W, dt)
+                t += dt
+                steps += 1
+                dt_last = dt
+        return steps, t
 
     def max_wavespeed(self, W, out=None):
         import torch
@@ -280,19 +323,35 @@ def prim_to_cons(V, ndim, gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), W=None):
 
 
 def make_grid(ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4, dirichlet=None) -> _Grid:
+    """wcns_grid; dirichlet[side]: None, a primitive nvar-vector, or an array
+    [n_side][nvar] (the grid keeps the array alive until it is dropped)."""
     g = _Grid()
     g.ndim, g.nx, g.ny = ndim, nx, ny
     g.x0, g.x1, g.y0, g.y1 = x0, x1, y0, y1
+    nvar = 5 if ndim == 1 else 6
+    g._keep = []
     for k in range(4):
         g.bc[k] = int(bc[k])
-        if dirichlet is not None and dirichlet[k] is not None:
-            for v, val in enumerate(dirichlet[k]):
-                g.dirichlet[k][v] = float(val)
+        if dirichlet is None or dirichlet[k] is None:
+            continue
+        d = np.ascontiguousarray(np.asarray(dirichlet[k], dtype=np.float64))
+        if d.ndim == 1:
+            if d.size != nvar:
+                raise ValueError(f"Dirichlet side {k}: need {nvar} values")
+            for v in range(nvar):
+                g.dirichlet[k][v] = float(d[v])
+        else:
+            n_side = ny if k < 2 else nx
+            if d.shape != (n_side, nvar):
+                raise ValueError(f"Dirichlet side {k}: need shape ({n_side}, {nvar})")
+            g._keep.append(d)
+            g.dirichlet_rows[k] = d.ctypes.data
     return g
 
 
 def grid_of(spec) -> _Grid:
-    return make_grid(spec.ndim, spec.nx, spec.ny, spec.x0, spec.x1, spec.y0, spec.y1, spec.bc)
+    return make_grid(spec.ndim, spec.nx, spec.ny, spec.x0, spec.x1, spec.y0, spec.y1, spec.bc,
+                     spec.dirichlet_prim)
 
 
 class Batch:

@@ -1,0 +1,237 @@
+"""GPU path vs the oracle on Dirichlet sides and on the paper's robustness
+workloads, through the C ABI:
+
+  * Dirichlet sides with one ghost state per boundary row or column (the
+    jet inflow of Sec. 6.7), including their place in the CFL maxima;
+  * the Mach 100 water jet (Sec. 6.7) and the Mach 10 shock-water cylinder
+    (Sec. 6.6) at their full grid sizes;
+  * the planar multi-material Sedov blast (Sec. 6.4) to its final time, and
+    the same run without the two limiters, which has to fail;
+  * the first-order HLLC scheme (Sec. 3.2) as a product mode, to final time.
+
+Tolerances as in the other parity tests: 1e-12 per cell (scaled by the
+variable's maximum) after one RHS or step, 1e-9 relative L1 at final time.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import oracle_setup, oracle_W, orc, pb
+from test_gpu_parity import assert_parity, dev, host, rhs_case, solver_for
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _random_rows(rng, n, nvar):
+    """n admissible primitive states: water or air, random p, u, v."""
+    rows = np.empty((n, nvar))
+    for r in range(n):
+        water = rng.random() < 0.5
+        p = float(np.exp(rng.uniform(np.log(1e5), np.log(1e8))))
+        vel = list(rng.uniform(-200.0, 200.0, size=nvar - 4))
+        if water:
+            rows[r] = [rng.uniform(900.0, 1100.0), 1e-8] + vel + [p, 1 - 1e-6]
+        else:
+            rows[r] = [1e-8, rng.uniform(0.5, 5.0)] + vel + [p, 1e-6]
+    return rows
+
+
+def _step_parity(spec, s, W, what):
+    """One device-CFL SSP-RK3 step from host state W on both sides."""
+    sol = solver_for(spec)
+    Wd = dev(W)
+    sol.step(Wd, 0.0)
+    ref, _, bad = orc.ssprk3_step(s, W)
+    assert bad == 0 and sol.count_inadmissible(Wd) == 0
+    assert_parity(host(Wd), ref, what=what)
+    sol.close()
+
+
+def test_dirichlet_rows_all_sides_2d():
+    """Random per-row Dirichlet profiles on all four sides of a ragged 2D
+    grid with a shock and a bubble inside: RHS and one step."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    spec = pb.random_smooth_state(70, 45, seed=12)
+    spec.bc = (pb.BC_DIRICHLET,) * 4
+    spec.dirichlet_prim = [_random_rows(rng, spec.ny if k < 2 else spec.nx, 6) for k in range(4)]
+    rhs_case(spec)
+    s = oracle_setup(spec)
+    _step_parity(spec, s, oracle_W(spec, s), "dirichlet 2D step")
+
+
+def test_dirichlet_mixed_sides_2d():
+    """Dirichlet on x-hi and y-lo only (one constant state, one profile),
+    the other sides reflective / extrapolated."""
+    rng = np.random.Generator(np.random.PCG64(78))
+    spec = pb.random_smooth_state(131, 66, seed=13)
+    spec.bc = (pb.BC_REFLECT, pb.BC_DIRICHLET, pb.BC_DIRICHLET, pb.BC_EXTRAP)
+    spec.dirichlet_prim = [None, _random_rows(rng, 1, 6)[0], _random_rows(rng, spec.nx, 6), None]
+    rhs_case(spec)
+
+
+def test_dirichlet_1d_both_sides():
+    """1D water-air tube held by its own end states on both sides."""
+    spec = pb.water_air_shock_tube(400)
+    spec.bc = (pb.BC_DIRICHLET, pb.BC_DIRICHLET, pb.BC_EXTRAP, pb.BC_EXTRAP)
+    spec.dirichlet_prim = [spec.prim[:, 0, 0].copy(), spec.prim[:, 0, -1].copy(), None, None]
+    rhs_case(spec)
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    sol = solver_for(spec)
+    Wd = dev(W)
+    for _ in range(20):
+        sol.step(Wd, 0.0)
+        W, _, bad = orc.ssprk3_step(s, W)
+        assert bad == 0
+    assert_parity(host(Wd), W, what="dirichlet 1D 20 steps")
+
+
+def test_dirichlet_ghosts_set_the_time_step():
+    """The jet's inflow state (1.5e5 m/s) bounds the first CFL step although
+    the interior is air at rest."""
+    spec = pb.mach100_jet(256, 128)
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    sol = solver_for(spec)
+    a = host(sol.max_wavespeed(dev(W)))
+    ref = orc.max_wavespeed(s, W)
+    assert a[0] == ref[0] and a[1] == ref[1] and a[0] > 1.5e5
+    dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Wd = dev(W)
+    sol.step(Wd, 0.0, dt_used=dtu)
+    assert host(dtu)[0] == orc.cfl_dt(s, W)
+
+
+def test_mach100_jet_full_size():
+    """Sec. 6.7 at 1024 x 512: RHS at the initial state; 150 device-CFL
+    steps stay admissible (checked every 50); RHS and one step from there."""
+    spec = pb.mach100_jet()
+    rhs_case(spec)
+    s = oracle_setup(spec)
+    sol = solver_for(spec)
+    Wd = dev(oracle_W(spec, s))
+    for k in range(150):
+        sol.step(Wd, 0.0)
+        if (k + 1) % 50 == 0:
+            assert sol.count_inadmissible(Wd) == 0, k
+    W = host(Wd)
+    dt = orc.cfl_dt(s, W)
+    got = host(sol.rhs(dev(W), dt=dt))
+    assert_parity(got, orc.rhs(s, W, dt), what="jet after 150 steps")
+    _step_parity(spec, s, W, "jet step 151")
+
+
+def test_mach10_cylinder_full_size():
+    """Sec. 6.6 at 1152 x 768: RHS at the initial state; 300 device-CFL
+    steps stay admissible (checked every 100); one step from there."""
+    spec = pb.mach10_cylinder()
+    rhs_case(spec)
+    s = oracle_setup(spec)
+    sol = solver_for(spec)
+    Wd = dev(oracle_W(spec, s))
+    for k in range(300):
+        sol.step(Wd, 0.0)
+        if (k + 1) % 100 == 0:
+            assert sol.count_inadmissible(Wd) == 0, k
+    _step_parity(spec, s, host(Wd), "cylinder step 301")
+
+
+def test_sedov_blast_to_final_time():
+    """Sec. 6.4: 4000 fixed steps to t = 1e-3; every step admissible on
+    the oracle side, the GPU final state equal to it."""
+    spec = pb.sedov_multimaterial(401)
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    ref, steps, t = orc.run(s, W0, spec.t_end, spec.dt_fixed)
+    assert steps == 4000
+    sol = solver_for(spec)
+    Wd = dev(W0)
+    # the oracle's time loop: fixed steps, the last one shortened to t_end
+    tt, n = 0.0, 0
+    while tt < spec.t_end:
+        dt = spec.dt_fixed
+        if tt + dt > spec.t_end:
+            dt = spec.t_end - tt
+        sol.step(Wd, dt)
+        tt += dt
+        n += 1
+    assert n == steps and tt == t
+    assert sol.count_inadmissible(Wd) == 0
+    got = host(Wd)
+    assert_parity(got, ref, what="sedov t_end")
+    for v in range(5):
+        l1 = np.abs(got[v] - ref[v]).sum() / np.abs(ref[v]).sum()
+        assert l1 <= 1e-9, (v, l1)
+
+
+def test_sedov_without_limiters_fails():
+    """Negative control (Sec. 5 motivation): with both limiters off the same
+    Sedov run leaves the admissible set on the GPU too."""
+    spec = pb.sedov_multimaterial(401)
+    s = oracle_setup(spec)
+    sol = solver_for(spec, interp_limiter=False, flux_limiter=False)
+    Wd = dev(oracle_W(spec, s))
+    bad = 0
+    for k in range(4000):
+        sol.step(Wd, spec.dt_fixed)
+        if (k + 1) % 500 == 0:
+            bad = sol.count_inadmissible(Wd)
+            if bad:
+                break
+    print(f"  limiters off: {bad} inadmissible cells after {k + 1} steps", flush=True)
+    assert bad > 0
+
+
+def test_hllc1_water_air_tube_to_final_time():
+    """First-order HLLC (the paper's comparison scheme) as a product mode:
+    the 1D water-air tube to t = 2.4e-4 s against the oracle."""
+    spec = pb.water_air_shock_tube(400)
+    s = oracle_setup(spec, scheme=1)
+    W0 = oracle_W(spec, s)
+    ref, steps, t_ref = orc.run(s, W0, spec.t_end)
+    sol = solver_for(spec, scheme=1)
+    Wd = dev(W0)
+    t, n = 0.0, 0
+    while t < spec.t_end:
+        a = host(sol.max_wavespeed(Wd))
+        dt = spec.cfl * spec.dx / a[0]
+        if t + dt > spec.t_end:
+            dt = spec.t_end - t
+        sol.step(Wd, dt)
+        t += dt
+        n += 1
+    assert n == steps and t == t_ref
+    assert sol.count_inadmissible(Wd) == 0
+    got = host(Wd)
+    for v in range(5):
+        l1 = np.abs(got[v] - ref[v]).sum() / np.abs(ref[v]).sum()
+        assert l1 <= 1e-9, (v, l1)
+
+
+def test_hllc1_mach10_cylinder_rhs():
+    """First-order HLLC on the full Mach 10 cylinder grid."""
+    rhs_case(pb.mach10_cylinder(), scheme=1)
+
+
+@pytest.mark.parametrize("case", ["tube_1d", "shock_bubble_2d"])
+def test_advance_matches_the_oracle_time_loop(case):
+    """Solver.advance (device time steps, host reads once per chunk, exact
+    steps near the end) lands on t_end with the oracle's step sequence."""
+    if case == "tube_1d":
+        spec, chunk = pb.water_air_shock_tube(400), 16
+        t_end = spec.t_end
+    else:
+        spec, chunk = pb.shock_bubble(128), 8
+        s0 = oracle_setup(spec)
+        t_end = 60 * orc.cfl_dt(s0, oracle_W(spec, s0))
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    ref, steps, t_ref = orc.run(s, W0, t_end)
+    sol = solver_for(spec)
+    Wd = dev(W0)
+    n, t = sol.advance(Wd, t_end, chunk=chunk)
+    print(f"  {case}: {n} steps to t = {t!r} (oracle {steps}, {t_ref!r})", flush=True)
+    assert n == steps and t == t_ref
+    assert_parity(host(Wd), ref, what=f"advance {case}")
