@@ -10,11 +10,11 @@
 // m_t) is the HAS_T = false instantiation: every tangential term is dropped
 // at compile time.
 //
-// Evaluation order of the primitive recovery, the mixture EOS and the
-// limiters follows the canonical order documented in the design doc so that FP64
-// results track the CPU reference to round-off; FMA contraction is switched
-// off in those routines (the liquid pressure recovery at low pressure
-// cancels ~4 decimal digits, so an extra rounding there is visible).
+// Every FP64 expression is evaluated in the order the serial reference
+// writes it, with FMA contraction switched off and IEEE-rounded divides and
+// square roots, so results are bit-identical to it: the liquid pressure
+// recovery at low pressure cancels ~4 decimal digits and the limiters divide
+// by differences of order 1e-8, so any extra or different rounding shows.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

@@ -23,7 +23,7 @@
 // serial reference (no FMA contraction, IEEE divides and square roots): the
 // positivity limiters divide by differences of order 1e-8 near material
 // interfaces, so any change of rounding upstream would move their blends by
-// ~1e-8 relative ("bit-reproducible FP64").
+// ~1e-8 relative.
 #pragma clang fp contract(off)
 
 namespace wcns {
