@@ -47,6 +47,8 @@ class _Problem(C.Structure):
         ("weno_eps", C.c_double), ("cfl", C.c_double),
         ("interp_limiter", C.c_int32), ("flux_limiter", C.c_int32), ("scheme", C.c_int32),
         ("pad1", C.c_int32),
+        ("nz", C.c_int32), ("bcz", C.c_int32 * 2), ("pad2", C.c_int32),
+        ("dz", C.c_double),
     ]
 
 
@@ -58,7 +60,9 @@ class Setup:
     ny: int = 1
     dx: float = 1.0
     dy: float = 1.0
-    bc: tuple = (BC_PERIODIC,) * 4
+    bc: tuple = (BC_PERIODIC,) * 4       # x-lo, x-hi, y-lo, y-hi [, z-lo, z-hi]
+    nz: int = 1                          # 3D only
+    dz: float = 1.0
     # Dirichlet sides: primitive ghost state (a1r1, a2r2, u, [v], p, a1), one
     # nvar-vector for the whole side or an array [n_side][nvar] per boundary
     # row (x sides: ny rows) or column (y sides: nx columns)
@@ -79,14 +83,22 @@ class Setup:
 
     @property
     def nvar(self) -> int:
-        return 5 if self.ndim == 1 else 6
+        return {1: 5, 2: 6, 3: 7}[self.ndim]
+
+    @property
+    def ncell(self) -> int:
+        return self.nx * self.ny * (self.nz if self.ndim == 3 else 1)
 
     def c(self) -> _Problem:
         p = _Problem()
         p.ndim, p.nx, p.ny = self.ndim, self.nx, self.ny
         p.dx, p.dy = self.dx, self.dy
+        p.nz = self.nz if self.ndim == 3 else 1
+        p.dz = self.dz
         for k in range(4):
             p.bc[k] = int(self.bc[k])
+        for k in range(2):
+            p.bcz[k] = int(self.bc[4 + k]) if len(self.bc) > 4 else BC_PERIODIC
         p.gamma[0], p.gamma[1] = self.gamma
         p.pinf[0], p.pinf[1] = self.pinf
         p.eps_arho, p.eps_alpha, p.eps_rhoc2 = self.eps_arho, self.eps_alpha, self.eps_rhoc2
@@ -222,12 +234,20 @@ def rhs_cells(s: Setup, W: np.ndarray, dt: float, cells: np.ndarray) -> np.ndarr
 
 def faces(s: Setup, W: np.ndarray, direction: int, dt: float):
     """Limited G^-, G^+ and theta of every face, rotated frame:
-    arrays [nline][n+1][6] and [nline][n+1]."""
+    arrays [nline][n+1][NR] and [nline][n+1] (NR = 6, or 7 in 3D, where the
+    lines of x, y, z run over (k, j), (k, i), (j, i))."""
     W = _arr(W)
-    nline = s.ny if direction == 0 else s.nx
-    n = s.nx if direction == 0 else s.ny
-    Gm = np.empty((nline, n + 1, 6))
-    Gp = np.empty((nline, n + 1, 6))
+    if s.ndim == 3:
+        dims = (s.nx, s.ny, s.nz)
+        n = dims[direction]
+        nline = s.ncell // n
+        nr = 7
+    else:
+        nline = s.ny if direction == 0 else s.nx
+        n = s.nx if direction == 0 else s.ny
+        nr = 6
+    Gm = np.empty((nline, n + 1, nr))
+    Gp = np.empty((nline, n + 1, nr))
     th = np.empty((nline, n + 1))
     rc = lib().oracle_faces(C.byref(s.c()), _dp(W), direction, float(dt), _dp(Gm), _dp(Gp), _dp(th))
     if rc != 0:
@@ -236,13 +256,13 @@ def faces(s: Setup, W: np.ndarray, direction: int, dt: float):
 
 
 def max_wavespeed(s: Setup, W: np.ndarray) -> np.ndarray:
-    a = np.zeros(2)
+    a = np.zeros(3 if s.ndim == 3 else 2)
     lib().oracle_max_wavespeed(C.byref(s.c()), _dp(_arr(W)), _dp(a))
     return a
 
 
 def stage_lambda(s: Setup, W: np.ndarray, dt: float) -> np.ndarray:
-    lam = np.zeros(2)
+    lam = np.zeros(3 if s.ndim == 3 else 2)
     lib().oracle_stage_lambda(C.byref(s.c()), _dp(_arr(W)), float(dt), _dp(lam))
     return lam
 
@@ -260,6 +280,8 @@ def ssprk3_step(s: Setup, W: np.ndarray, dt: float = 0.0):
     W = _arr(W).copy()
     dtu = C.c_double(0.0)
     bad = lib().oracle_ssprk3_step(C.byref(s.c()), _dp(W), float(dt), C.byref(dtu))
+    if bad < 0:
+        raise ValueError(f"oracle_ssprk3_step failed: {bad}")
     return W, dtu.value, int(bad)
 
 

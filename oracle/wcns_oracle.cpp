@@ -17,7 +17,8 @@
 // source, instantiated with an operation-counting scalar, yields the
 // algorithmic operation count of one cell update (used for the roofline).
 //
-// State layout (SoA): W[v][j][i], v over
+// State layout (SoA): W[v][k][j][i], v over
+//   3D: (a1r1, a2r2, rho*u, rho*v, rho*w, E, a1)   (the direct 3D extension)
 //   2D: (a1r1, a2r2, rho*u, rho*v, E, a1)     (paper Sec. 3, conservative W)
 //   1D: (a1r1, a2r2, rho*u, E, a1)             (rho*v dropped, Sec. 2)
 // Internally every sweep works on a 6-component state rotated into the sweep
@@ -55,6 +56,10 @@ struct Problem {
   double cfl;
   int32_t interp_limiter, flux_limiter, scheme;  // scheme 0 PP-WCNS-IS, 1 HLLC1
   int32_t pad1;
+  int32_t nz;               // 1 unless ndim = 3
+  int32_t bcz[2];           // z-lo, z-hi (3D; Dirichlet not supported there)
+  int32_t pad2;
+  double dz;
 };
 
 enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
@@ -123,38 +128,56 @@ template <class T> inline T mix_Pi(const Eos& e, T a1) {
   return a1 * T(e.q1) + a2 * T(e.q2);
 }
 
-// Node quantities of a rotated 6-component state X = (a1r1,a2r2,mn,mt,E,a1)
-template <class T> struct Node {
-  T w[6];
-  T rho, un, ut, p, c, h;   // h = rho*ctilde^2 = rho e - pbar_inf  [Sec. 5.1]
-  T g[6];                   // flux G = F + (0,..,0, a1 u)  [Sec. 3.2]
+// Rotated states have NR = 6 components (1D, 2D) or NR = 7 (3D):
+//   X = (a1r1, a2r2, m_n, m_t, [m_s,] E, a1)
+// with m_n the normal and m_t (m_s) the tangential momenta.  In 3D the second
+// tangential momentum is one more passive component (Sec. 2: the extension of
+// the system to three dimensions is direct).  E sits at NR-2, a1 at NR-1.
+template <int NR> struct Lay {
+  static_assert(NR == 6 || NR == 7, "rotated states have 6 or 7 components");
+  static constexpr int IE = NR - 2, IA = NR - 1;
+};
+
+// Node quantities of a rotated state
+template <class T, int NR = 6> struct Node {
+  T w[NR];
+  T rho, un, ut, us, p, c, h;   // us: second tangential velocity (0 unless NR = 7)
+                                // h = rho*ctilde^2 = rho e - pbar_inf  [Sec. 5.1]
+  T g[NR];                      // flux G = F + (0,..,0, a1 u)  [Sec. 3.2]
 };
 
 // rho*ctilde^2 of a state (the third limiter test function) [Sec. 5.1]
-template <class T> inline T rhoc2_tilde(const Eos& e, const T X[6]) {
+template <int NR = 6, class T> inline T rhoc2_tilde(const Eos& e, const T* X) {
+  constexpr int IE = Lay<NR>::IE, IA = Lay<NR>::IA;
   T rho = X[0] + X[1];
   T irho = T(1.0) / rho;
   T un = X[2] * irho;
   T ut = X[3] * irho;
-  T rhoe = X[4] - T(0.5) * (X[2] * un + X[3] * ut);
-  T Gam = mix_Gamma(e, X[5]);
-  T Pi = mix_Pi(e, X[5]);
+  T ke = X[2] * un + X[3] * ut;
+  if (NR == 7) ke = ke + X[4] * (X[4] * irho);
+  T rhoe = X[IE] - T(0.5) * ke;
+  T Gam = mix_Gamma(e, X[IA]);
+  T Pi = mix_Pi(e, X[IA]);
   T pinf_bar = Pi / (T(1.0) + Gam);
   return rhoe - pinf_bar;
 }
 
 // Conservative -> primitive, sound speed and node flux [Sec. 2; Sec. 3.2
 // flux-source form; WCNS steps 1 and 7].
-template <class T> inline Node<T> node_from_w(const Eos& e, const T X[6]) {
-  Node<T> n;
-  for (int v = 0; v < 6; ++v) n.w[v] = X[v];
+template <int NR = 6, class T> inline Node<T, NR> node_from_w(const Eos& e, const T* X) {
+  constexpr int IE = Lay<NR>::IE, IA = Lay<NR>::IA;
+  Node<T, NR> n;
+  for (int v = 0; v < NR; ++v) n.w[v] = X[v];
   n.rho = X[0] + X[1];
   T irho = T(1.0) / n.rho;
   n.un = X[2] * irho;
   n.ut = X[3] * irho;
-  T rhoe = X[4] - T(0.5) * (X[2] * n.un + X[3] * n.ut);
-  T Gam = mix_Gamma(e, X[5]);
-  T Pi = mix_Pi(e, X[5]);
+  n.us = NR == 7 ? X[4] * irho : T(0.0);
+  T ke = X[2] * n.un + X[3] * n.ut;
+  if (NR == 7) ke = ke + X[4] * n.us;
+  T rhoe = X[IE] - T(0.5) * ke;
+  T Gam = mix_Gamma(e, X[IA]);
+  T Pi = mix_Pi(e, X[IA]);
   n.p = (rhoe - Pi) / Gam;
   T pinf_bar = Pi / (T(1.0) + Gam);
   T gbar = T(1.0) + T(1.0) / Gam;
@@ -165,18 +188,20 @@ template <class T> inline Node<T> node_from_w(const Eos& e, const T X[6]) {
   n.g[1] = X[1] * n.un;
   n.g[2] = X[2] * n.un + n.p;
   n.g[3] = X[3] * n.un;
-  n.g[4] = (X[4] + n.p) * n.un;
-  n.g[5] = X[5] * n.un;
+  if (NR == 7) n.g[4] = X[4] * n.un;
+  n.g[IE] = (X[IE] + n.p) * n.un;
+  n.g[IA] = X[IA] * n.un;
   return n;
 }
 
 // ---------------------------------------------------------------------------
 // HLLC approximate Riemann solver [Sec. 3.1 star states, Einfeldt speeds,
 // Batten contact speed; Sec. 3.2 conservative flux, u* and f_alpha].
-// Outputs F (5 conservative components), f_alpha and s*.
+// Outputs F (the NR-1 conservative components), f_alpha and s*.
 // ---------------------------------------------------------------------------
-template <class T>
-inline void hllc(const Node<T>& L, const Node<T>& R, T F[5], T& falpha, T& sstar) {
+template <class T, int NR>
+inline void hllc(const Node<T, NR>& L, const Node<T, NR>& R, T* F, T& falpha, T& sstar) {
+  constexpr int IE = Lay<NR>::IE, IA = Lay<NR>::IA;
   T ubar = T(0.5) * (L.un + R.un);
   T cbar = T(0.5) * (L.c + R.c);
   T sL = tmin(ubar - cbar, L.un - L.c);
@@ -188,29 +213,31 @@ inline void hllc(const Node<T>& L, const Node<T>& R, T F[5], T& falpha, T& sstar
   // star states W*_K
   T chiL = (sL - L.un) / (sL - ss);
   T chiR = (sR - R.un) / (sR - ss);
-  T WsL[5], WsR[5];
+  T WsL[NR - 1], WsR[NR - 1];
   WsL[0] = chiL * L.w[0];
   WsL[1] = chiL * L.w[1];
   WsL[2] = chiL * L.rho * ss;
   WsL[3] = chiL * L.rho * L.ut;
-  WsL[4] = chiL * (L.w[4] + (ss - L.un) * (L.rho * ss + L.p / (sL - L.un)));
+  if (NR == 7) WsL[4] = chiL * L.rho * L.us;
+  WsL[IE] = chiL * (L.w[IE] + (ss - L.un) * (L.rho * ss + L.p / (sL - L.un)));
   WsR[0] = chiR * R.w[0];
   WsR[1] = chiR * R.w[1];
   WsR[2] = chiR * R.rho * ss;
   WsR[3] = chiR * R.rho * R.ut;
-  WsR[4] = chiR * (R.w[4] + (ss - R.un) * (R.rho * ss + R.p / (sR - R.un)));
+  if (NR == 7) WsR[4] = chiR * R.rho * R.us;
+  WsR[IE] = chiR * (R.w[IE] + (ss - R.un) * (R.rho * ss + R.p / (sR - R.un)));
   T sm = tmin(T(0.0), sL);
   T sp = tmax(T(0.0), sR);
   T sg = tsgn(ss);
   T wl = (T(1.0) + sg) * T(0.5);
   T wr = (T(1.0) - sg) * T(0.5);
   // F_K is the conservative flux: the node flux g without its alpha part
-  for (int v = 0; v < 5; ++v) {
+  for (int v = 0; v < NR - 1; ++v) {
     T fl = L.g[v] + sm * (WsL[v] - L.w[v]);
     T fr = R.g[v] + sp * (WsR[v] - R.w[v]);
     F[v] = wl * fl + wr * fr;
   }
-  falpha = wl * (L.w[5] * ss) + wr * (R.w[5] * ss);
+  falpha = wl * (L.w[IA] * ss) + wr * (R.w[IA] * ss);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,26 +289,28 @@ template <class T> inline T limiter_theta(T qA, T qB, double eps) {
   return T(1.0);
 }
 
-// Test function k of a rotated 6-state: 0 a1r1, 1 a2r2, 2 a1, 3 a2 = 1-a1,
+// Test function k of a rotated state: 0 a1r1, 1 a2r2, 2 a1, 3 a2 = 1-a1,
 // 4 rho*ctilde^2.
-template <class T> inline T test_fn(const Eos& e, int k, const T X[6]) {
+template <int NR = 6, class T> inline T test_fn(const Eos& e, int k, const T* X) {
+  constexpr int IA = Lay<NR>::IA;
   switch (k) {
     case 0: return X[0];
     case 1: return X[1];
-    case 2: return X[5];
-    case 3: return T(1.0) - X[5];
-    default: return rhoc2_tilde(e, X);
+    case 2: return X[IA];
+    case 3: return T(1.0) - X[IA];
+    default: return rhoc2_tilde<NR>(e, X);
   }
 }
 
 // true when a state fails the hard-switch tolerances [Sec. 5.1, 5.2]
-template <class T>
-inline bool hard_switch_fails(const Eos& e, const Problem& P, const T X[6]) {
+template <int NR = 6, class T>
+inline bool hard_switch_fails(const Eos& e, const Problem& P, const T* X) {
+  constexpr int IA = Lay<NR>::IA;
   if (X[0] < T(P.hs_arho)) return true;
   if (X[1] < T(P.hs_arho)) return true;
-  if (X[5] < T(P.hs_alpha)) return true;
-  if (T(1.0) - X[5] < T(P.hs_alpha)) return true;
-  if (rhoc2_tilde(e, X) < T(P.hs_rhoc2)) return true;
+  if (X[IA] < T(P.hs_alpha)) return true;
+  if (T(1.0) - X[IA] < T(P.hs_alpha)) return true;
+  if (rhoc2_tilde<NR>(e, X) < T(P.hs_rhoc2)) return true;
   return false;
 }
 
@@ -292,16 +321,16 @@ inline double tol_of(const Problem& P, int k) {
 // Interpolation limiter, Algorithms 1-3 plus the hard switch [Sec. 5.1]:
 // B (the WENO-interpolated state) is pulled toward A (the node state on its
 // side: W_i for the left-biased value, W_{i+1} for the right-biased one).
-template <class T>
-inline void interp_limit(const Eos& e, const Problem& P, const T A[6], T B[6]) {
+template <int NR = 6, class T>
+inline void interp_limit(const Eos& e, const Problem& P, const T* A, T* B) {
   for (int k = 0; k < 5; ++k) {
-    T th = limiter_theta(test_fn(e, k, A), test_fn(e, k, B), tol_of(P, k));
+    T th = limiter_theta(test_fn<NR>(e, k, A), test_fn<NR>(e, k, B), tol_of(P, k));
     // the blend with theta = 1 is the identity: only a theta < 1 changes B
     if (val(th) != 1.0)
-      for (int v = 0; v < 6; ++v) B[v] = (T(1.0) - th) * A[v] + th * B[v];
+      for (int v = 0; v < NR; ++v) B[v] = (T(1.0) - th) * A[v] + th * B[v];
   }
-  if (hard_switch_fails(e, P, B))
-    for (int v = 0; v < 6; ++v) B[v] = A[v];
+  if (hard_switch_fails<NR>(e, P, B))
+    for (int v = 0; v < NR; ++v) B[v] = A[v];
 }
 
 // Flux limiter, Algorithms 4-6 plus the hard switch [Sec. 5.2].
@@ -309,15 +338,15 @@ inline void interp_limit(const Eos& e, const Problem& P, const T A[6], T B[6]) {
 // Wl/Wr: node states W_i, W_{i+1}; Fl/Fr: their conservative fluxes F (alpha
 // component 0).  lam = dt/(dx*sigma).  Returns the last theta used (1 when
 // no limiting happened, 0 when the hard switch fired).
-template <class T>
-inline T flux_limit(const Eos& e, const Problem& P, const T Wl[6], const T Wr[6],
-                    const T Fl[6], const T Fr[6], T lam, const T Hm[6], const T Hp[6],
-                    T Gm[6], T Gp[6]) {
-  T PH[6], MH[6], PG[6], MG[6];
+template <int NR = 6, class T>
+inline T flux_limit(const Eos& e, const Problem& P, const T* Wl, const T* Wr,
+                    const T* Fl, const T* Fr, T lam, const T* Hm, const T* Hp,
+                    T* Gm, T* Gp) {
+  T PH[NR], MH[NR], PG[NR], MG[NR];
   // half-cell states W_i^{+} = W_i - 2 lam (G^- - F_i),
   //                 W_{i+1}^{-} = W_{i+1} + 2 lam (G^+ - F_{i+1})
-  auto states = [&](const T gm[6], const T gp[6], T Ps[6], T Ms[6]) {
-    for (int v = 0; v < 6; ++v) {
+  auto states = [&](const T* gm, const T* gp, T* Ps, T* Ms) {
+    for (int v = 0; v < NR; ++v) {
       Ps[v] = Wl[v] - T(2.0) * lam * (gm[v] - Fl[v]);
       Ms[v] = Wr[v] + T(2.0) * lam * (gp[v] - Fr[v]);
     }
@@ -327,11 +356,11 @@ inline T flux_limit(const Eos& e, const Problem& P, const T Wl[6], const T Wr[6]
   T thmin = T(1.0);
   for (int k = 0; k < 5; ++k) {
     double eps = tol_of(P, k);
-    T thp = limiter_theta(test_fn(e, k, PH), test_fn(e, k, PG), eps);
-    T thm = limiter_theta(test_fn(e, k, MH), test_fn(e, k, MG), eps);
+    T thp = limiter_theta(test_fn<NR>(e, k, PH), test_fn<NR>(e, k, PG), eps);
+    T thm = limiter_theta(test_fn<NR>(e, k, MH), test_fn<NR>(e, k, MG), eps);
     T th = tmin(thp, thm);
     if (val(th) != 1.0) {   // theta = 1 leaves both fluxes unchanged
-      for (int v = 0; v < 6; ++v) {
+      for (int v = 0; v < NR; ++v) {
         Gp[v] = (T(1.0) - th) * Hp[v] + th * Gp[v];
         Gm[v] = (T(1.0) - th) * Hm[v] + th * Gm[v];
       }
@@ -341,8 +370,8 @@ inline T flux_limit(const Eos& e, const Problem& P, const T Wl[6], const T Wr[6]
       thmin = tmin(thmin, th);
     }
   }
-  if (hard_switch_fails(e, P, PG) || hard_switch_fails(e, P, MG)) {
-    for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
+  if (hard_switch_fails<NR>(e, P, PG) || hard_switch_fails<NR>(e, P, MG)) {
+    for (int v = 0; v < NR; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
     thmin = T(0.0);
   }
   return thmin;
@@ -353,7 +382,8 @@ inline T flux_limit(const Eos& e, const Problem& P, const T Wl[6], const T Wr[6]
 // density and speed of sound].
 template <class T> struct FaceAvg { T a1, a2, rho, c, k1, k2; };
 
-template <class T> inline FaceAvg<T> face_avg(const Node<T>& L, const Node<T>& R) {
+template <class T, int NR>
+inline FaceAvg<T> face_avg(const Node<T, NR>& L, const Node<T, NR>& R) {
   FaceAvg<T> f;
   f.a1 = T(0.5) * (L.w[0] + R.w[0]);
   f.a2 = T(0.5) * (L.w[1] + R.w[1]);
@@ -364,32 +394,42 @@ template <class T> inline FaceAvg<T> face_avg(const Node<T>& L, const Node<T>& R
   return f;
 }
 
-// U = R^{-1} V with V = (a1r1, a2r2, u_n, u_t, p, a1)
-template <class T> inline void project(const FaceAvg<T>& f, const Node<T>& n, T U[6]) {
+// U = R^{-1} V with V = (a1r1, a2r2, u_n, u_t, [u_s,] p, a1); the fields are
+// (u_n - p/(rho c), a1r1 - a1 p/(rho c^2), a2r2 - a2 p/(rho c^2), u_t,
+// [u_s,] a1, u_n + p/(rho c))
+template <class T, int NR>
+inline void project(const FaceAvg<T>& f, const Node<T, NR>& n, T* U) {
   U[0] = n.un - n.p * f.k1;
   U[1] = n.w[0] - f.a1 * n.p * f.k2;
   U[2] = n.w[1] - f.a2 * n.p * f.k2;
   U[3] = n.ut;
-  U[4] = n.w[5];
-  U[5] = n.un + n.p * f.k1;
+  if (NR == 7) U[4] = n.us;
+  U[NR - 2] = n.w[Lay<NR>::IA];
+  U[NR - 1] = n.un + n.p * f.k1;
 }
 
 // V = R U, then V -> W  [App. A; Sec. 2 mixture EOS for E]
-template <class T>
-inline void back_project_to_w(const Eos& e, const FaceAvg<T>& f, const T U[6], T X[6]) {
-  T a1r1 = U[1] + f.a1 * (U[5] - U[0]) / (T(2.0) * f.c);
-  T a2r2 = U[2] + f.a2 * (U[5] - U[0]) / (T(2.0) * f.c);
-  T un = T(0.5) * (U[0] + U[5]);
+template <int NR = 6, class T>
+inline void back_project_to_w(const Eos& e, const FaceAvg<T>& f, const T* U, T* X) {
+  constexpr int IE = Lay<NR>::IE, IA = Lay<NR>::IA;
+  const T& Uplus = U[NR - 1];
+  T a1r1 = U[1] + f.a1 * (Uplus - U[0]) / (T(2.0) * f.c);
+  T a2r2 = U[2] + f.a2 * (Uplus - U[0]) / (T(2.0) * f.c);
+  T un = T(0.5) * (U[0] + Uplus);
   T ut = U[3];
-  T p = T(0.5) * f.rho * f.c * (U[5] - U[0]);
-  T a1 = U[4];
+  T us = NR == 7 ? U[4] : T(0.0);
+  T p = T(0.5) * f.rho * f.c * (Uplus - U[0]);
+  T a1 = U[NR - 2];
   T rho = a1r1 + a2r2;
   X[0] = a1r1;
   X[1] = a2r2;
   X[2] = rho * un;
   X[3] = rho * ut;
-  X[4] = mix_Gamma(e, a1) * p + mix_Pi(e, a1) + T(0.5) * rho * (un * un + ut * ut);
-  X[5] = a1;
+  if (NR == 7) X[4] = rho * us;
+  T ke = un * un + ut * ut;
+  if (NR == 7) ke = ke + us * us;
+  X[IE] = mix_Gamma(e, a1) * p + mix_Pi(e, a1) + T(0.5) * rho * ke;
+  X[IA] = a1;
 }
 
 // HCS implied reconstructed flux, psi = 256/175  [Sec. 4.1]:
@@ -405,62 +445,68 @@ inline T hcs(T gt, T gm2, T gm1, T g0, T gp1, T gp2, T gp3) {
 // One face i+1/2 of one sweep: the nine WCNS steps [Sec. 4.2] with the
 // interpolation limiter [Sec. 5.1] and the flux limiter [Sec. 5.2].
 // nd[0..5] are the node quantities of nodes i-2 .. i+3 (rotated frame).
-// Outputs G^-_{i+1/2} and G^+_{i+1/2} (6 components each).
+// Outputs G^-_{i+1/2} and G^+_{i+1/2} (NR components each).
 // ---------------------------------------------------------------------------
-template <class T>
-inline T face_flux(const Eos& e, const Problem& P, const Node<T> nd[6], T lam, T Gm[6], T Gp[6]) {
-  const Node<T>& nl = nd[2];
-  const Node<T>& nr = nd[3];
+template <class T, int NR>
+inline T face_flux(const Eos& e, const Problem& P, const Node<T, NR> nd[6], T lam, T* Gm,
+                   T* Gp) {
+  constexpr int IA = Lay<NR>::IA;
+  const Node<T, NR>& nl = nd[2];
+  const Node<T, NR>& nr = nd[3];
   // first-order HLLC at the face from W_i, W_{i+1}  [Sec. 3.2]
-  T Fh[5], fah, ush;
+  T Fh[NR - 1], fah, ush;
   hllc(nl, nr, Fh, fah, ush);
-  T Hm[6], Hp[6];
-  for (int v = 0; v < 5; ++v) { Hm[v] = Fh[v]; Hp[v] = Fh[v]; }
-  Hm[5] = fah - nl.w[5] * ush;     // G^{-}: alpha of cell i      [Sec. 3.2]
-  Hp[5] = fah - nr.w[5] * ush;     // G^{+}: alpha of cell i+1
+  T Hm[NR], Hp[NR];
+  for (int v = 0; v < NR - 1; ++v) { Hm[v] = Fh[v]; Hp[v] = Fh[v]; }
+  Hm[IA] = fah - nl.w[IA] * ush;   // G^{-}: alpha of cell i      [Sec. 3.2]
+  Hp[IA] = fah - nr.w[IA] * ush;   // G^{+}: alpha of cell i+1
   if (P.scheme == 1) {             // first-order HLLC scheme (theta = 0)
-    for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
+    for (int v = 0; v < NR; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
     return T(0.0);
   }
   // step 2: characteristic projection of the stencil nodes
   FaceAvg<T> fa = face_avg(nl, nr);
-  T U[6][6];
+  T U[6][NR];
   for (int m = 0; m < 6; ++m) project(fa, nd[m], U[m]);
   // step 3: left- and right-biased IS-WENO interpolation per field
-  T UL[6], UR[6];
-  for (int k = 0; k < 6; ++k) {
+  T UL[NR], UR[NR];
+  for (int k = 0; k < NR; ++k) {
     UL[k] = weno_is(U[0][k], U[1][k], U[2][k], U[3][k], U[4][k], P.weno_eps);
     UR[k] = weno_is(U[5][k], U[4][k], U[3][k], U[2][k], U[1][k], P.weno_eps);
   }
   // steps 4-5: back to primitive, then conservative
-  T WL[6], WR[6];
-  back_project_to_w(e, fa, UL, WL);
-  back_project_to_w(e, fa, UR, WR);
+  T WL[NR], WR[NR];
+  back_project_to_w<NR>(e, fa, UL, WL);
+  back_project_to_w<NR>(e, fa, UR, WR);
   // interpolation limiter toward W_i (left) and W_{i+1} (right)
   if (P.interp_limiter) {
-    interp_limit(e, P, nl.w, WL);
-    interp_limit(e, P, nr.w, WR);
+    interp_limit<NR>(e, P, nl.w, WL);
+    interp_limit<NR>(e, P, nr.w, WR);
   }
   // step 6: high-order midpoint flux and velocity from the Riemann solver
-  Node<T> tl = node_from_w(e, WL);
-  Node<T> tr = node_from_w(e, WR);
-  T Ft[5], fat, ust;
+  Node<T, NR> tl = node_from_w<NR>(e, WL);
+  Node<T, NR> tr = node_from_w<NR>(e, WR);
+  T Ft[NR - 1], fat, ust;
   hllc(tl, tr, Ft, fat, ust);
-  T gt[6] = {Ft[0], Ft[1], Ft[2], Ft[3], Ft[4], fat};
+  T gt[NR];
+  for (int v = 0; v < NR - 1; ++v) gt[v] = Ft[v];
+  gt[IA] = fat;
   // steps 7-8: node fluxes and HCS reconstruction of the flux and velocity
-  T Gh[6];
-  for (int v = 0; v < 6; ++v)
+  T Gh[NR];
+  for (int v = 0; v < NR; ++v)
     Gh[v] = hcs(gt[v], nd[0].g[v], nd[1].g[v], nd[2].g[v], nd[3].g[v], nd[4].g[v], nd[5].g[v]);
   T uh = hcs(ust, nd[0].un, nd[1].un, nd[2].un, nd[3].un, nd[4].un, nd[5].un);
   // step 9: non-conservative split fluxes G^{+-}
-  for (int v = 0; v < 5; ++v) { Gm[v] = Gh[v]; Gp[v] = Gh[v]; }
-  Gm[5] = Gh[5] - nl.w[5] * uh;
-  Gp[5] = Gh[5] - nr.w[5] * uh;
+  for (int v = 0; v < NR - 1; ++v) { Gm[v] = Gh[v]; Gp[v] = Gh[v]; }
+  Gm[IA] = Gh[IA] - nl.w[IA] * uh;
+  Gp[IA] = Gh[IA] - nr.w[IA] * uh;
   // flux limiter toward the first-order HLLC fluxes
   if (P.flux_limiter) {
-    T Fl[6] = {nl.g[0], nl.g[1], nl.g[2], nl.g[3], nl.g[4], T(0.0)};
-    T Fr[6] = {nr.g[0], nr.g[1], nr.g[2], nr.g[3], nr.g[4], T(0.0)};
-    return flux_limit(e, P, nl.w, nr.w, Fl, Fr, lam, Hm, Hp, Gm, Gp);
+    T Fl[NR], Fr[NR];
+    for (int v = 0; v < NR - 1; ++v) { Fl[v] = nl.g[v]; Fr[v] = nr.g[v]; }
+    Fl[IA] = T(0.0);
+    Fr[IA] = T(0.0);
+    return flux_limit<NR>(e, P, nl.w, nr.w, Fl, Fr, lam, Hm, Hp, Gm, Gp);
   }
   return T(1.0);
 }
@@ -468,7 +514,10 @@ inline T face_flux(const Eos& e, const Problem& P, const Node<T> nd[6], T lam, T
 // ---------------------------------------------------------------------------
 // Grid plumbing: ghost cells, rotation, sweeps.
 // ---------------------------------------------------------------------------
-inline int nvar_of(const Problem& P) { return P.ndim == 1 ? 5 : 6; }
+inline int nvar_of(const Problem& P) { return P.ndim == 1 ? 5 : (P.ndim == 2 ? 6 : 7); }
+inline long ncell_of(const Problem& P) {
+  return (long)P.nx * P.ny * (P.ndim == 3 ? P.nz : 1);
+}
 
 // full 6-component state of cell (i,j) in the unrotated frame
 inline void load_cell(const Problem& P, const double* W, int i, int j, double X[6]) {
@@ -595,8 +644,10 @@ void sweep_line(const Problem& P, const double* W, int dir, int line, double lam
   }
 }
 
+void rhs3(const Problem& P, const double* W, double* L, double dt);
 // Semi-discrete RHS L(W) [Sec. 4.1, flux-difference form with G^{+-}].
 void rhs(const Problem& P, const double* W, double* L, double dt) {
+  if (P.ndim == 3) { rhs3(P, W, L, dt); return; }
   const int nv = nvar_of(P);
   const long ncell = (long)P.nx * P.ny;
   double lam[2];
@@ -675,7 +726,9 @@ void rhs_cells(const Problem& P, const double* W, double dt, const int64_t* cell
 }
 
 // Admissible set G [Sec. 2]: 0 <= a1 <= 1, a_k r_k >= 0, rho e - pbar_inf > 0.
+long count_inadmissible3(const Problem& P, const double* W);
 long count_inadmissible(const Problem& P, const double* W) {
+  if (P.ndim == 3) return count_inadmissible3(P, W);
   Eos e = make_eos(P);
   long bad = 0;
   for (int j = 0; j < P.ny; ++j)
@@ -689,10 +742,179 @@ long count_inadmissible(const Problem& P, const double* W) {
   return bad;
 }
 
+// ---------------------------------------------------------------------------
+// Three dimensions (the direct extension of Sec. 2): W[7][nz][ny][nx] =
+// (a1r1, a2r2, rho u, rho v, rho w, E, a1).  Rotated frames, with the two
+// tangential momenta passive:
+//   x: (m_n, m_t, m_s) = (rho u, rho v, rho w)
+//   y: (rho v, rho u, rho w)
+//   z: (rho w, rho u, rho v)
+// A line in direction d is addressed by the two other cell indices (a, b):
+// x (j, k), y (i, k), z (i, j).  Periodic, extrapolation and reflective
+// sides only.
+// ---------------------------------------------------------------------------
+inline int len3(const Problem& P, int d) { return d == 0 ? P.nx : (d == 1 ? P.ny : P.nz); }
+inline double h3(const Problem& P, int d) { return d == 0 ? P.dx : (d == 1 ? P.dy : P.dz); }
+inline int bc3(const Problem& P, int side) { return side < 4 ? P.bc[side] : P.bcz[side - 4]; }
+inline long cell3(const Problem& P, int i, int j, int k) {
+  return ((long)k * P.ny + j) * P.nx + i;
+}
+inline long line_cell3(const Problem& P, int d, int a, int b, int pos) {
+  return d == 0 ? cell3(P, pos, a, b) : (d == 1 ? cell3(P, a, pos, b) : cell3(P, a, b, pos));
+}
+
+inline void load_cell3(const Problem& P, const double* W, long o, double X[7]) {
+  const long n = ncell_of(P);
+  for (int v = 0; v < 7; ++v) X[v] = W[v * n + o];
+}
+
+inline void load_rotated3(const Problem& P, const double* W, int d, int a, int b, int g,
+                          double X[7]) {
+  bool flip;
+  int s = ghost_source(bc3(P, 2 * d), bc3(P, 2 * d + 1), g, len3(P, d), flip);
+  double Y[7];
+  load_cell3(P, W, line_cell3(P, d, a, b, s), Y);
+  if (flip) Y[2 + d] = -Y[2 + d];
+  X[0] = Y[0]; X[1] = Y[1]; X[5] = Y[5]; X[6] = Y[6];
+  if (d == 0) { X[2] = Y[2]; X[3] = Y[3]; X[4] = Y[4]; }
+  else if (d == 1) { X[2] = Y[3]; X[3] = Y[2]; X[4] = Y[4]; }
+  else { X[2] = Y[4]; X[3] = Y[2]; X[4] = Y[3]; }
+}
+
+inline void unrotate3(int d, const double R[7], double X[7]) {
+  X[0] = R[0]; X[1] = R[1]; X[5] = R[5]; X[6] = R[6];
+  if (d == 0) { X[2] = R[2]; X[3] = R[3]; X[4] = R[4]; }
+  else if (d == 1) { X[3] = R[2]; X[2] = R[3]; X[4] = R[4]; }
+  else { X[4] = R[2]; X[2] = R[3]; X[3] = R[4]; }
+}
+
+// max(|u|+c), max(|v|+c), max(|w|+c) over the cells [Sec. 3.3]
+void max_wavespeed3(const Problem& P, const double* W, double amax[3]) {
+  Eos e = make_eos(P);
+  amax[0] = amax[1] = amax[2] = 0.0;
+  const long n = ncell_of(P);
+  for (long o = 0; o < n; ++o) {
+    double X[7];
+    load_cell3(P, W, o, X);
+    Node<double, 7> nd = node_from_w<7>(e, X);   // x frame: un = u, ut = v, us = w
+    amax[0] = std::max(amax[0], std::fabs(nd.un) + nd.c);
+    amax[1] = std::max(amax[1], std::fabs(nd.ut) + nd.c);
+    amax[2] = std::max(amax[2], std::fabs(nd.us) + nd.c);
+  }
+}
+
+// Reading (3D split of Sec. 3.3): sigma_d = tau_d/(tau_x + tau_y + tau_z),
+// tau_d = max(|u_d|+c)/h_d, lambda_d = dt/(h_d sigma_d).
+void stage_lambda3(const Problem& P, const double* W, double dt, double lam[3]) {
+  double a[3];
+  max_wavespeed3(P, W, a);
+  double t[3] = {a[0] / P.dx, a[1] / P.dy, a[2] / P.dz};
+  double tot = t[0] + t[1] + t[2];
+  for (int d = 0; d < 3; ++d) lam[d] = dt / (h3(P, d) * (t[d] / tot));
+}
+
+double cfl_dt3(const Problem& P, const double* W) {
+  double a[3];
+  max_wavespeed3(P, W, a);
+  return P.cfl / (a[0] / P.dx + a[1] / P.dy + a[2] / P.dz);
+}
+
+void sweep_line3(const Problem& P, const double* W, int d, int a, int b, double lam,
+                 std::vector<double>& Gm, std::vector<double>& Gp, double* theta_out) {
+  Eos e = make_eos(P);
+  const int n = len3(P, d);
+  std::vector<Node<double, 7>> nodes(n + 6);
+  for (int g = -3; g < n + 3; ++g) {
+    double X[7];
+    load_rotated3(P, W, d, a, b, g, X);
+    nodes[g + 3] = node_from_w<7>(e, X);
+  }
+  Gm.assign((size_t)(n + 1) * 7, 0.0);
+  Gp.assign((size_t)(n + 1) * 7, 0.0);
+  for (int f = 0; f <= n; ++f) {
+    double th = face_flux(e, P, &nodes[f], lam, &Gm[(size_t)f * 7], &Gp[(size_t)f * 7]);
+    if (theta_out) theta_out[f] = th;
+  }
+}
+
+// L = (L_x + L_y) + L_z, each -(G^-_{i+1/2} - G^+_{i-1/2})/h  [Sec. 4.1]
+void rhs3(const Problem& P, const double* W, double* L, double dt) {
+  const long n = ncell_of(P);
+  double lam[3];
+  stage_lambda3(P, W, dt, lam);
+  std::vector<double> Ld[3];
+  std::vector<double> Gm, Gp;
+  for (int d = 0; d < 3; ++d) {
+    Ld[d].assign((size_t)n * 7, 0.0);
+    const int na = d == 0 ? P.ny : P.nx, nb = d == 2 ? P.ny : P.nz;
+    for (int b = 0; b < nb; ++b)
+      for (int a = 0; a < na; ++a) {
+        sweep_line3(P, W, d, a, b, lam[d], Gm, Gp, nullptr);
+        for (int pos = 0; pos < len3(P, d); ++pos) {
+          double Xm[7], Xp[7];
+          unrotate3(d, &Gm[(size_t)(pos + 1) * 7], Xm);
+          unrotate3(d, &Gp[(size_t)pos * 7], Xp);
+          const long o = line_cell3(P, d, a, b, pos);
+          for (int v = 0; v < 7; ++v) Ld[d][(size_t)o * 7 + v] = -(Xm[v] - Xp[v]) / h3(P, d);
+        }
+      }
+  }
+  for (long o = 0; o < n; ++o)
+    for (int v = 0; v < 7; ++v)
+      L[(long)v * n + o] = Ld[0][(size_t)o * 7 + v] + Ld[1][(size_t)o * 7 + v] +
+                           Ld[2][(size_t)o * 7 + v];
+}
+
+// the same RHS on a list of cells, each from its own stencils
+void rhs_cells3(const Problem& P, const double* W, double dt, const int64_t* cells, long nc,
+                double* out) {
+  Eos e = make_eos(P);
+  double lam[3];
+  stage_lambda3(P, W, dt, lam);
+  for (long q = 0; q < nc; ++q) {
+    const int i = (int)(cells[q] % P.nx), j = (int)((cells[q] / P.nx) % P.ny);
+    const int k = (int)(cells[q] / ((long)P.nx * P.ny));
+    double Lsum[7];
+    for (int d = 0; d < 3; ++d) {
+      const int a = d == 0 ? j : i, b = d == 2 ? j : k, pos = d == 0 ? i : (d == 1 ? j : k);
+      Node<double, 7> nodes[7];
+      for (int g = 0; g < 7; ++g) {
+        double X[7];
+        load_rotated3(P, W, d, a, b, pos - 3 + g, X);
+        nodes[g] = node_from_w<7>(e, X);
+      }
+      double Gm_lo[7], Gp_lo[7], Gm_hi[7], Gp_hi[7], Xm[7], Xp[7];
+      face_flux(e, P, &nodes[0], lam[d], Gm_lo, Gp_lo);
+      face_flux(e, P, &nodes[1], lam[d], Gm_hi, Gp_hi);
+      unrotate3(d, Gm_hi, Xm);
+      unrotate3(d, Gp_lo, Xp);
+      for (int v = 0; v < 7; ++v) {
+        double part = -(Xm[v] - Xp[v]) / h3(P, d);
+        Lsum[v] = d == 0 ? part : Lsum[v] + part;
+      }
+    }
+    for (int v = 0; v < 7; ++v) out[q * 7 + v] = Lsum[v];
+  }
+}
+
+long count_inadmissible3(const Problem& P, const double* W) {
+  Eos e = make_eos(P);
+  long bad = 0;
+  const long n = ncell_of(P);
+  for (long o = 0; o < n; ++o) {
+    double X[7];
+    load_cell3(P, W, o, X);
+    double h = rhoc2_tilde<7>(e, X);
+    bool ok = X[6] >= 0.0 && X[6] <= 1.0 && X[0] >= 0.0 && X[1] >= 0.0 && h > 0.0;
+    if (!ok) ++bad;
+  }
+  return bad;
+}
+
 // Three-stage SSP Runge-Kutta (TVD-RK3, Shu-Osher form) [Sec. 5.3, Sec. 6].
 // Returns the number of inadmissible cells seen after any stage.
 long ssprk3_step(const Problem& P, double* W, double dt) {
-  const long n = (long)nvar_of(P) * P.nx * P.ny;
+  const long n = (long)nvar_of(P) * ncell_of(P);
   std::vector<double> W0(W, W + n), W1(n), L(n);
   long bad = 0;
   rhs(P, W, L.data(), dt);
@@ -710,6 +932,7 @@ long ssprk3_step(const Problem& P, double* W, double dt) {
 // CFL time step from the state at the start of the step [Sec. 3.3]:
 // dt = CFL/(tau_x + tau_y), tau = max(|u|+c)/dx.
 double cfl_dt(const Problem& P, const double* W) {
+  if (P.ndim == 3) return cfl_dt3(P, W);
   double a[2];
   max_wavespeed(P, W, a);
   if (P.ndim == 1) return P.cfl * P.dx / a[0];
@@ -736,29 +959,45 @@ extern "C" {
 
 int oracle_eos_valid(const Problem* P) { return eos_valid(*P) ? 1 : 0; }
 
-// primitive (a1r1, a2r2, u, [v], p, a1) -> conservative, SoA [nv][n]
+// primitive (a1r1, a2r2, u, [v, [w,]] p, a1) -> conservative, SoA [nv][n]
 int oracle_prim_to_cons(const Problem* P, const double* V, double* W, long n) {
   Eos e = make_eos(*P);
   const int nv = nvar_of(*P);
   for (long q = 0; q < n; ++q) {
     double a1r1 = V[0 * n + q], a2r2 = V[1 * n + q], u = V[2 * n + q];
-    double v = nv == 6 ? V[3 * n + q] : 0.0;
+    double v = nv >= 6 ? V[3 * n + q] : 0.0;
+    double w = nv == 7 ? V[4 * n + q] : 0.0;
     double p = V[(nv - 2) * n + q], a1 = V[(nv - 1) * n + q];
     double rho = a1r1 + a2r2;
     W[0 * n + q] = a1r1;
     W[1 * n + q] = a2r2;
     W[2 * n + q] = rho * u;
-    if (nv == 6) W[3 * n + q] = rho * v;
-    W[(nv - 2) * n + q] = mix_Gamma(e, a1) * p + mix_Pi(e, a1) + 0.5 * rho * (u * u + v * v);
+    if (nv >= 6) W[3 * n + q] = rho * v;
+    if (nv == 7) W[4 * n + q] = rho * w;
+    double ke = u * u + v * v;
+    if (nv == 7) ke = ke + w * w;
+    W[(nv - 2) * n + q] = mix_Gamma(e, a1) * p + mix_Pi(e, a1) + 0.5 * rho * ke;
     W[(nv - 1) * n + q] = a1;
   }
   return 0;
 }
 
-// conservative -> primitive (a1r1, a2r2, u, [v], p, a1) plus c, SoA
+// conservative -> primitive (a1r1, a2r2, u, [v, [w,]] p, a1) plus c, SoA
 int oracle_cons_to_prim(const Problem* P, const double* W, double* V, double* c, long n) {
   Eos e = make_eos(*P);
   const int nv = nvar_of(*P);
+  if (nv == 7) {
+    for (long q = 0; q < n; ++q) {
+      double X[7];
+      for (int v = 0; v < 7; ++v) X[v] = W[v * n + q];
+      Node<double, 7> nd = node_from_w<7>(e, X);
+      V[0 * n + q] = X[0]; V[1 * n + q] = X[1];
+      V[2 * n + q] = nd.un; V[3 * n + q] = nd.ut; V[4 * n + q] = nd.us;
+      V[5 * n + q] = nd.p; V[6 * n + q] = X[6];
+      if (c) c[q] = nd.c;
+    }
+    return 0;
+  }
   for (long q = 0; q < n; ++q) {
     double X[6];
     X[0] = W[0 * n + q]; X[1] = W[1 * n + q]; X[2] = W[2 * n + q];
@@ -773,9 +1012,18 @@ int oracle_cons_to_prim(const Problem* P, const double* W, double* V, double* c,
   return 0;
 }
 
+// grid checks shared by the entry points: sizes, and no Dirichlet side in 3D
+static bool grid_ok(const Problem* P) {
+  if (P->nx < 1 || P->ny < 1 || (P->ndim == 3 && P->nz < 1)) return false;
+  if (P->ndim == 3)
+    for (int s = 0; s < 6; ++s)
+      if (bc3(*P, s) == BC_DIRICHLET) return false;
+  return true;
+}
+
 int oracle_rhs(const Problem* P, const double* W, double* L, double dt) {
   if (!eos_valid(*P)) return -2;
-  if (P->nx < 1 || P->ny < 1) return -1;
+  if (!grid_ok(P)) return -1;
   rhs(*P, W, L, dt);
   return 0;
 }
@@ -783,7 +1031,9 @@ int oracle_rhs(const Problem* P, const double* W, double* L, double dt) {
 int oracle_rhs_cells(const Problem* P, const double* W, double dt, const int64_t* cells,
                      long nc, double* out) {
   if (!eos_valid(*P)) return -2;
-  rhs_cells(*P, W, dt, cells, nc, out);
+  if (!grid_ok(P)) return -1;
+  if (P->ndim == 3) rhs_cells3(*P, W, dt, cells, nc, out);
+  else rhs_cells(*P, W, dt, cells, nc, out);
   return 0;
 }
 
@@ -792,6 +1042,23 @@ int oracle_rhs_cells(const Problem* P, const double* W, double dt, const int64_t
 int oracle_faces(const Problem* P, const double* W, int dir, double dt, double* Gm, double* Gp,
                  double* theta) {
   if (!eos_valid(*P)) return -2;
+  if (!grid_ok(P)) return -1;
+  if (P->ndim == 3) {
+    // lines ordered by (b, a): x (k, j), y (k, i), z (j, i); [nline][n+1][7]
+    double lam3[3];
+    stage_lambda3(*P, W, dt, lam3);
+    const int n = len3(*P, dir);
+    const int na = dir == 0 ? P->ny : P->nx, nb = dir == 2 ? P->ny : P->nz;
+    std::vector<double> gm, gp;
+    for (int b = 0; b < nb; ++b)
+      for (int a = 0; a < na; ++a) {
+        const long l = (long)b * na + a;
+        sweep_line3(*P, W, dir, a, b, lam3[dir], gm, gp, theta ? theta + l * (n + 1) : nullptr);
+        std::memcpy(Gm + l * (n + 1) * 7, gm.data(), sizeof(double) * (n + 1) * 7);
+        std::memcpy(Gp + l * (n + 1) * 7, gp.data(), sizeof(double) * (n + 1) * 7);
+      }
+    return 0;
+  }
   double lam[2];
   stage_lambda(*P, W, dt, lam);
   const int nline = dir == 0 ? P->ny : P->nx;
@@ -868,12 +1135,15 @@ void oracle_back_project(const Problem* P, const double* XL, const double* XR, c
   back_project_to_w(e, f, U, X);
 }
 
+// amax: 2 values (1D/2D) or 3 (3D)
 void oracle_max_wavespeed(const Problem* P, const double* W, double* amax) {
-  max_wavespeed(*P, W, amax);
+  if (P->ndim == 3) max_wavespeed3(*P, W, amax);
+  else max_wavespeed(*P, W, amax);
 }
 
 void oracle_stage_lambda(const Problem* P, const double* W, double dt, double* lam) {
-  stage_lambda(*P, W, dt, lam);
+  if (P->ndim == 3) stage_lambda3(*P, W, dt, lam);
+  else stage_lambda(*P, W, dt, lam);
 }
 
 long oracle_count_inadmissible(const Problem* P, const double* W) {
@@ -885,6 +1155,7 @@ double oracle_cfl_dt(const Problem* P, const double* W) { return cfl_dt(*P, W); 
 // One SSP-RK3 step; dt <= 0 selects the CFL time step. Returns the number of
 // inadmissible cells seen after any stage (0 expected); *dt_used receives dt.
 long oracle_ssprk3_step(const Problem* P, double* W, double dt, double* dt_used) {
+  if (!grid_ok(P)) return -1;
   if (dt <= 0.0) dt = cfl_dt(*P, W);
   if (dt_used) *dt_used = dt;
   return ssprk3_step(*P, W, dt);
@@ -896,6 +1167,7 @@ long oracle_ssprk3_step(const Problem* P, double* W, double dt, double* dt_used)
 long oracle_run(const Problem* P, double* W, double t_end, double dt_fixed, long max_steps,
                 double* t_out) {
   if (!eos_valid(*P)) return -2;
+  if (!grid_ok(P)) return -1;
   double t = 0.0;
   long steps = 0;
   while (t < t_end && steps < max_steps) {
