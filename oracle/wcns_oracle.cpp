@@ -768,17 +768,43 @@ inline void load_cell3(const Problem& P, const double* W, long o, double X[7]) {
   for (int v = 0; v < 7; ++v) X[v] = W[v * n + o];
 }
 
-inline void load_rotated3(const Problem& P, const double* W, int d, int a, int b, int g,
-                          double X[7]) {
+// Node quantities of a cell for a sweep in direction d.  Reading (3D
+// primitive recovery): the recovery runs once per cell on the unrotated
+// state, so its kinetic energy is (rho u u + rho v v) + rho w w for every
+// sweep (with three momenta the rotated order would round differently per
+// direction); the velocities and momenta are then permuted into the
+// direction's frame and the node flux formed there [Sec. 2; Sec. 3.2].
+inline Node<double, 7> node_rotated3(const Eos& e, const double Y[7], int d) {
+  Node<double, 7> c = node_from_w<7>(e, Y);   // x frame: un = u, ut = v, us = w
+  Node<double, 7> n = c;
+  const double vel[3] = {c.un, c.ut, c.us};
+  n.w[0] = Y[0]; n.w[1] = Y[1]; n.w[5] = Y[5]; n.w[6] = Y[6];
+  if (d == 0) return c;
+  if (d == 1) {
+    n.w[2] = Y[3]; n.w[3] = Y[2]; n.w[4] = Y[4];
+    n.un = vel[1]; n.ut = vel[0]; n.us = vel[2];
+  } else {
+    n.w[2] = Y[4]; n.w[3] = Y[2]; n.w[4] = Y[3];
+    n.un = vel[2]; n.ut = vel[0]; n.us = vel[1];
+  }
+  n.g[0] = n.w[0] * n.un;
+  n.g[1] = n.w[1] * n.un;
+  n.g[2] = n.w[2] * n.un + n.p;
+  n.g[3] = n.w[3] * n.un;
+  n.g[4] = n.w[4] * n.un;
+  n.g[5] = (n.w[5] + n.p) * n.un;
+  n.g[6] = n.w[6] * n.un;
+  return n;
+}
+
+// the unrotated state of the (possibly ghost) node g of a line, reflective
+// ghosts mirrored with the wall-normal momentum negated
+inline void load_line3(const Problem& P, const double* W, int d, int a, int b, int g,
+                       double Y[7]) {
   bool flip;
   int s = ghost_source(bc3(P, 2 * d), bc3(P, 2 * d + 1), g, len3(P, d), flip);
-  double Y[7];
   load_cell3(P, W, line_cell3(P, d, a, b, s), Y);
   if (flip) Y[2 + d] = -Y[2 + d];
-  X[0] = Y[0]; X[1] = Y[1]; X[5] = Y[5]; X[6] = Y[6];
-  if (d == 0) { X[2] = Y[2]; X[3] = Y[3]; X[4] = Y[4]; }
-  else if (d == 1) { X[2] = Y[3]; X[3] = Y[2]; X[4] = Y[4]; }
-  else { X[2] = Y[4]; X[3] = Y[2]; X[4] = Y[3]; }
 }
 
 inline void unrotate3(int d, const double R[7], double X[7]) {
@@ -825,9 +851,9 @@ void sweep_line3(const Problem& P, const double* W, int d, int a, int b, double 
   const int n = len3(P, d);
   std::vector<Node<double, 7>> nodes(n + 6);
   for (int g = -3; g < n + 3; ++g) {
-    double X[7];
-    load_rotated3(P, W, d, a, b, g, X);
-    nodes[g + 3] = node_from_w<7>(e, X);
+    double Y[7];
+    load_line3(P, W, d, a, b, g, Y);
+    nodes[g + 3] = node_rotated3(e, Y, d);
   }
   Gm.assign((size_t)(n + 1) * 7, 0.0);
   Gp.assign((size_t)(n + 1) * 7, 0.0);
@@ -879,9 +905,9 @@ void rhs_cells3(const Problem& P, const double* W, double dt, const int64_t* cel
       const int a = d == 0 ? j : i, b = d == 2 ? j : k, pos = d == 0 ? i : (d == 1 ? j : k);
       Node<double, 7> nodes[7];
       for (int g = 0; g < 7; ++g) {
-        double X[7];
-        load_rotated3(P, W, d, a, b, pos - 3 + g, X);
-        nodes[g] = node_from_w<7>(e, X);
+        double Y[7];
+        load_line3(P, W, d, a, b, pos - 3 + g, Y);
+        nodes[g] = node_rotated3(e, Y, d);
       }
       double Gm_lo[7], Gp_lo[7], Gm_hi[7], Gp_hi[7], Xm[7], Xp[7];
       face_flux(e, P, &nodes[0], lam[d], Gm_lo, Gp_lo);
