@@ -9,6 +9,8 @@
  *  - Every function returns a wcns_status; no exception crosses the ABI.
  *  - State arrays are DEVICE pointers to float64, structure-of-arrays
  *    [nvar][ny][nx] (x fastest), interior cells only (no ghost layers).
+ *      3D: nvar = 7, (a1*rho1, a2*rho2, rho*u, rho*v, rho*w, E, a1),
+ *          layout [7][nz][ny][nx]
  *      2D: nvar = 6, (a1*rho1, a2*rho2, rho*u, rho*v, E, a1)
  *      1D: nvar = 5, (a1*rho1, a2*rho2, rho*u, E, a1)           (ny = 1)
  *    This is the conservative vector W of the paper (Sec. 2, Sec. 3).
@@ -58,7 +60,7 @@ typedef struct {
 
 /* Uniform Cartesian grid (Sec. 3: cells of size dx = (x1-x0)/nx). */
 typedef struct {
-  int32_t ndim;               /* 1 or 2                                        */
+  int32_t ndim;               /* 1, 2 or 3 (3D: the direct extension of Sec. 2) */
   int32_t nx, ny;             /* ny = 1 when ndim = 1                          */
   double x0, x1, y0, y1;
   int32_t bc[4];              /* wcns_bc of x-lo, x-hi, y-lo, y-hi             */
@@ -73,6 +75,10 @@ typedef struct {
                               /* inflow of Sec. 6.7).  The three ghost layers  */
                               /* of a row share its state.  Copied at create;  */
                               /* the caller keeps ownership.                   */
+  int32_t nz;                 /* 3D: cells along z (ignored below 3D)          */
+  int32_t bc_z[2];            /* 3D: wcns_bc of z-lo, z-hi                     */
+  int32_t reserved_z;
+  double z0, z1;              /* 3D: z extent                                  */
 } wcns_grid;
 
 /* Scheme options; wcns_params_default fills the paper's values. */
@@ -99,7 +105,10 @@ wcns_status wcns_params_default(wcns_params* p);
  * Dirichlet ghost states (finite, partial densities >= 0 with a positive sum,
  * 0 <= a1 <= 1; else WCNS_ERR_INADMISSIBLE), then allocates all device
  * scratch once (WCNS_ERR_NOMEM).  stream: hipStream_t or NULL for
- * the default stream.  On success *out owns the scratch until wcns_destroy. */
+ * the default stream.  On success *out owns the scratch until wcns_destroy.
+ * 3D grids (ndim = 3): FP64 only, sides periodic, extrapolated or
+ * reflective (no Dirichlet), nx*ny*nz < 2^29, nz <= 65535 (WCNS_ERR_ARG
+ * otherwise); wcns_limit is not available in 3D. */
 wcns_status wcns_create(const wcns_grid* grid, const wcns_eos* eos, const wcns_params* params,
                         int32_t precision, void* stream, wcns_ctx** out);
 
@@ -136,7 +145,8 @@ wcns_status wcns_limit(wcns_ctx* ctx, int32_t dir, const double* W, const double
  * the ghost states of Dirichlet sides (those of the x sides count for the
  * first, of the y sides for the second), i.e. over every state a face flux of
  * that direction sees; the CFL time step and lambda use the same maxima.
- * d_amax: device double[2] (the second entry is 0 in 1D). */
+ * d_amax: device double[2] (the second entry is 0 in 1D); double[3] in 3D
+ * (the third maximum is max(|w|+c)). */
 wcns_status wcns_max_wavespeed(wcns_ctx* ctx, const double* W, double* d_amax);
 
 /* One three-stage SSP Runge-Kutta step (TVD-RK3, Sec. 5.3, Sec. 6) in place

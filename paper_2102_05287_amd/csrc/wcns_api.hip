@@ -9,6 +9,7 @@
 
 #include "../../include/wcns.h"
 #include "wcns_batch.hpp"
+#include "wcns_3d.hpp"
 
 #include <algorithm>
 #include <vector>
@@ -28,6 +29,10 @@ struct wcns_ctx {
   double *P, *L, *U1, *U2, *partial, *step, *dirW, *dirP, *edge;
   unsigned long long* count;
   double* damax;  // Dirichlet ghost wave-speed maxima [2] (inside dirP), or null
+  // 3D: arguments shared by its kernels, strided-pass edge buffer, tile rows
+  K3Args base3;
+  double* edge3;
+  int nbr_y3, nbr_z3;
   int node_grid, tile_x, x_grid, nbr;
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
@@ -148,14 +153,19 @@ wcns_status wcns_destroy(wcns_ctx* c) {
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->count) (void)hipFree(c->count);
+  if (c->edge3) (void)hipFree(c->edge3);
   free(c);
   return WCNS_OK;
 }
+
+static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
+                           int32_t precision, void* stream, wcns_ctx** out);
 
 wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
                         int32_t precision, void* stream, wcns_ctx** out) {
   if (!g || !eos || !prm || !out) return WCNS_ERR_ARG;
   *out = nullptr;
+  if (g->ndim == 3) return create3(g, eos, prm, precision, stream, out);
   if (g->ndim != 1 && g->ndim != 2) return WCNS_ERR_ARG;
   if (g->nx < 1 || g->ny < 1 || (g->ndim == 1 && g->ny != 1)) return WCNS_ERR_ARG;
   // node loads use 32-bit byte offsets within one component array
@@ -316,6 +326,180 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   return WCNS_OK;
 }
 
+// ---------------------------------------------------------------- 3D
+// The direct 3D extension (Sec. 2): state [7][nz][ny][nx], FP64 only, sides
+// periodic, extrapolated or reflective.
+static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
+                           int32_t precision, void* stream, wcns_ctx** out) {
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nz > 65535) return WCNS_ERR_ARG;
+  const long N = (long)g->nx * g->ny * g->nz;
+  if (N >= (1L << 29)) return WCNS_ERR_ARG;   // 32-bit byte offsets of node loads
+  if (!(g->x1 > g->x0) || !(g->y1 > g->y0) || !(g->z1 > g->z0)) return WCNS_ERR_ARG;
+  const int bc6[6] = {g->bc[0], g->bc[1], g->bc[2], g->bc[3], g->bc_z[0], g->bc_z[1]};
+  const int len[3] = {g->nx, g->ny, g->nz};
+  for (int d = 0; d < 3; ++d) {
+    const int lo = bc6[2 * d], hi = bc6[2 * d + 1];
+    for (int b : {lo, hi})
+      if (b < WCNS_BC_PERIODIC || b > WCNS_BC_REFLECT) return WCNS_ERR_ARG;
+    if ((lo == WCNS_BC_PERIODIC) != (hi == WCNS_BC_PERIODIC)) return WCNS_ERR_ARG;
+    if ((lo == WCNS_BC_REFLECT || hi == WCNS_BC_REFLECT) && len[d] < 3) return WCNS_ERR_ARG;
+  }
+  if (!eos_ok(eos)) return WCNS_ERR_EOS;
+  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5)) return WCNS_ERR_ARG;
+  if (!(prm->weno_eps > 0.0)) return WCNS_ERR_ARG;
+  if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
+  if (precision != WCNS_FP64) return WCNS_ERR_ARG;
+
+  wcns_ctx* c = (wcns_ctx*)calloc(1, sizeof(wcns_ctx));
+  if (!c) return WCNS_ERR_NOMEM;
+  c->grid = *g;
+  c->eos = *eos;
+  c->params = *prm;
+  c->precision = precision;
+  c->stream = (hipStream_t)stream;
+  c->nv = 7;
+  c->N = N;
+  c->dx = (g->x1 - g->x0) / g->nx;
+  c->dy = (g->y1 - g->y0) / g->ny;
+  K3Args& a = c->base3;
+  memset(&a, 0, sizeof(a));
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.nz = g->nz;
+  a.dx = c->dx;
+  a.dy = c->dy;
+  a.dz = (g->z1 - g->z0) / g->nz;
+  for (int k = 0; k < 6; ++k) a.bc[k] = bc6[k];
+  a.interp_limiter = prm->interp_limiter ? 1 : 0;
+  a.flux_limiter = prm->flux_limiter ? 1 : 0;
+  a.scheme = prm->scheme;
+  a.eos.g1 = 1.0 / (eos->gamma[0] - 1.0);
+  a.eos.g2 = 1.0 / (eos->gamma[1] - 1.0);
+  a.eos.q1 = eos->gamma[0] * eos->pinf[0] / (eos->gamma[0] - 1.0);
+  a.eos.q2 = eos->gamma[1] * eos->pinf[1] / (eos->gamma[1] - 1.0);
+  a.tol.eps_arho = prm->eps_arho;
+  a.tol.eps_alpha = prm->eps_alpha;
+  a.tol.eps_rhoc2 = prm->eps_rhoc2;
+  a.tol.hs_arho = prm->hs_arho;
+  a.tol.hs_alpha = prm->hs_alpha;
+  a.tol.hs_rhoc2 = prm->hs_rhoc2;
+  a.tol.weno_eps = prm->weno_eps;
+  c->tile_x = pick_tile_x(g->nx);
+  a.tile_x = c->tile_x;
+  c->x_grid = (int)((N + c->tile_x - 1) / c->tile_x);
+  const long ng = (N + 255) / 256;
+  c->node_grid = (int)(ng < WCNS_NODE_GRID_CAP ? ng : WCNS_NODE_GRID_CAP);
+  c->nbr_y3 = (g->ny + 1 + YW3 - 1) / YW3;
+  c->nbr_z3 = (g->nz + 1 + YW3 - 1) / YW3;
+  const size_t plane = (size_t)g->nx * g->ny;
+  const size_t ey = (size_t)g->nz * c->nbr_y3 * 14 * g->nx, ez = (size_t)c->nbr_z3 * 14 * plane;
+
+  wcns_status st = WCNS_OK;
+  auto alloc = [&](double** p, size_t n) {
+    if (st != WCNS_OK) return;
+    if (hipMalloc((void**)p, n * sizeof(double)) != hipSuccess) { *p = nullptr; st = WCNS_ERR_NOMEM; }
+  };
+  alloc(&c->P, 6 * (size_t)N);
+  alloc(&c->U1, 7 * (size_t)N);
+  alloc(&c->U2, 7 * (size_t)N);
+  alloc(&c->L, 7 * (size_t)N);
+  alloc(&c->edge3, ey > ez ? ey : ez);
+  alloc(&c->partial, 3 * (size_t)c->node_grid);
+  alloc(&c->step, 8);
+  if (st == WCNS_OK && hipMalloc((void**)&c->count, sizeof(unsigned long long)) != hipSuccess)
+    st = WCNS_ERR_NOMEM;
+  if (st != WCNS_OK) { wcns_destroy(c); return st; }
+  double zero8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (hipMemcpy(c->step, zero8, sizeof(zero8), hipMemcpyHostToDevice) != hipSuccess) {
+    wcns_destroy(c);
+    return WCNS_ERR_HIP;
+  }
+  a.step = c->step;
+  for (int k = 0; k < 6; ++k) a.Pc[k] = c->P + (size_t)k * N;
+  *out = c;
+  return WCNS_OK;
+}
+
+static void set_bases3(const wcns_ctx* c, K3Args& a, const double* W) {
+  a.W = W;
+  for (int k = 0; k < 7; ++k) a.Wc[k] = W + (size_t)k * c->N;
+}
+
+static wcns_status launch_node_finalize3(wcns_ctx* c, const double* W, int dt_mode, double dt,
+                                         double* dt_used) {
+  K3Args a = c->base3;
+  set_bases3(c, a, W);
+  {
+    ProfScope ps(c, PROF_NODE);
+    hipLaunchKernelGGL(k3_node, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
+  }
+  LAUNCH_CHECK();
+  {
+    ProfScope ps(c, PROF_FIN);
+    hipLaunchKernelGGL(k3_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
+                       c->node_grid, dt_mode, dt, c->params.cfl, a.dx, a.dy, a.dz, c->step,
+                       dt_used);
+  }
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+// x, y and z passes of state W into `out` (mode STORE: L; RK: next stage)
+static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int mode,
+                                  const double* Un, double ca, double cb) {
+  K3Args a = c->base3;
+  set_bases3(c, a, W);
+  a.Un = Un;
+  a.ca = ca;
+  a.cb = cb;
+  a.out_mode = mode;
+  a.Lout = c->L;
+  a.edge = c->edge3;
+  const long nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
+  {
+    ProfScope ps(c, PROF_X);
+    hipLaunchKernelGGL(k3_sweep_x, dim3(c->x_grid), dim3(64), 0, c->stream, a);
+  }
+  LAUNCH_CHECK();
+  K3Args ay = a;   // y pass: L = L_x + L_y in place
+  ay.Lin = c->L;
+  ay.out = c->L;
+  ay.last = 0;
+  ay.nbr = c->nbr_y3;
+  {
+    ProfScope ps(c, PROF_Y);
+    hipLaunchKernelGGL((k3_sweep_l<1>), dim3((unsigned)((nx + 63) / 64), c->nbr_y3, (unsigned)nz),
+                       dim3(64 * YW3), 0, c->stream, ay);
+  }
+  LAUNCH_CHECK();
+  if (c->nbr_y3 > 1) {
+    const long nt = (long)(c->nbr_y3 - 1) * nx * nz;
+    ProfScope ps(c, PROF_FIX);
+    hipLaunchKernelGGL((k3_fixup<1>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+                       ay);
+    LAUNCH_CHECK();
+  }
+  K3Args az = a;   // z pass: L = (L_x + L_y) + L_z, then the output
+  az.Lin = c->L;
+  az.out = out;
+  az.last = 1;
+  az.nbr = c->nbr_z3;
+  {
+    ProfScope ps(c, PROF_Y);
+    hipLaunchKernelGGL((k3_sweep_l<2>), dim3((unsigned)((nx * ny + 63) / 64), c->nbr_z3, 1),
+                       dim3(64 * YW3), 0, c->stream, az);
+  }
+  LAUNCH_CHECK();
+  if (c->nbr_z3 > 1) {
+    const long nt = (long)(c->nbr_z3 - 1) * nx * ny;
+    ProfScope ps(c, PROF_FIX);
+    hipLaunchKernelGGL((k3_fixup<2>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+                       az);
+    LAUNCH_CHECK();
+  }
+  return WCNS_OK;
+}
+
 wcns_status wcns_set_stream(wcns_ctx* c, void* stream) {
   if (!c) return WCNS_ERR_ARG;
   c->stream = (hipStream_t)stream;
@@ -437,6 +621,12 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
 
 wcns_status wcns_prim_to_cons(wcns_ctx* c, const double* V, double* W) {
   if (!c || !V || !W) return WCNS_ERR_ARG;
+  if (c->grid.ndim == 3) {
+    unsigned g = (unsigned)((c->N + 255) / 256);
+    hipLaunchKernelGGL(k3_prim_to_cons, dim3(g), dim3(256), 0, c->stream, c->base3, V, W);
+    LAUNCH_CHECK();
+    return WCNS_OK;
+  }
   KArgs a = c->base;
   unsigned g = (unsigned)((c->N + 255) / 256);
   if (c->grid.ndim == 2)
@@ -450,6 +640,11 @@ wcns_status wcns_prim_to_cons(wcns_ctx* c, const double* V, double* W) {
 wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
   if (!c || !W || !dWdt || W == dWdt) return WCNS_ERR_ARG;
   if (!(dt >= 0.0) || !isfinite(dt)) return WCNS_ERR_CFL;
+  if (c->grid.ndim == 3) {
+    wcns_status s = launch_node_finalize3(c, W, DT_GIVEN, dt, nullptr);
+    if (s != WCNS_OK) return s;
+    return launch_sweeps3(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
+  }
   wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr);
   if (s != WCNS_OK) return s;
   return launch_sweeps(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
@@ -465,6 +660,13 @@ wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used)
   const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
   for (int s = 0; s < 3; ++s) {
     int mode = s == 0 ? (dt > 0.0 ? DT_GIVEN : DT_CFL) : DT_KEEP;
+    if (c->grid.ndim == 3) {
+      wcns_status st = launch_node_finalize3(c, in[s], mode, dt, s == 0 ? dt_used : nullptr);
+      if (st != WCNS_OK) return st;
+      st = launch_sweeps3(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
+      if (st != WCNS_OK) return st;
+      continue;
+    }
     wcns_status st = launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr);
     if (st != WCNS_OK) return st;
     st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
@@ -475,6 +677,14 @@ wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used)
 
 wcns_status wcns_max_wavespeed(wcns_ctx* c, const double* W, double* d_amax) {
   if (!c || !W || !d_amax) return WCNS_ERR_ARG;
+  if (c->grid.ndim == 3) {
+    wcns_status s = launch_node_finalize3(c, W, DT_GIVEN, 0.0, nullptr);
+    if (s != WCNS_OK) return s;
+    hipLaunchKernelGGL(k3_copy_amax, dim3(1), dim3(64), 0, c->stream, (const double*)c->step,
+                       d_amax);
+    LAUNCH_CHECK();
+    return WCNS_OK;
+  }
   wcns_status s = launch_node_finalize(c, W, DT_GIVEN, 0.0, nullptr);
   if (s != WCNS_OK) return s;
   hipLaunchKernelGGL(k_copy_amax, dim3(1), dim3(64), 0, c->stream, (const double*)c->step, d_amax,
@@ -486,6 +696,7 @@ wcns_status wcns_max_wavespeed(wcns_ctx* c, const double* W, double* d_amax) {
 wcns_status wcns_limit(wcns_ctx* c, int32_t dir, const double* W, const double* G_ho,
                        const double* G_lo, double* G_out, double* theta, double dt) {
   if (!c || !W || !G_ho || !G_lo || !G_out) return WCNS_ERR_ARG;
+  if (c->grid.ndim == 3) return WCNS_ERR_ARG;
   if (dir != 0 && !(dir == 1 && c->grid.ndim == 2)) return WCNS_ERR_ARG;
   if (!(dt >= 0.0) || !isfinite(dt)) return WCNS_ERR_CFL;
   wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr);
@@ -512,7 +723,12 @@ wcns_status wcns_check_admissible(wcns_ctx* c, const double* W, long long* n_bad
   a.W = W;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->count, 1);
   LAUNCH_CHECK();
-  if (c->grid.ndim == 2)
+  if (c->grid.ndim == 3) {
+    K3Args a3 = c->base3;
+    a3.W = W;
+    hipLaunchKernelGGL(k3_admissible, dim3((unsigned)((c->N + 255) / 256)), dim3(256), 0,
+                       c->stream, a3, c->count);
+  } else if (c->grid.ndim == 2)
     hipLaunchKernelGGL(k_admissible<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->count);
   else
     hipLaunchKernelGGL(k_admissible<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->count);

@@ -14,6 +14,7 @@
 //               epilogue sums L_x + L_y and (for a step) applies the SSP-RK3
 //               stage combination.
 //   k_fixup_y   finishes the cell rows that straddle two y-tiles.
+#pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 

@@ -47,10 +47,25 @@ class ProblemSpec:
     dirichlet_prim: list = field(default_factory=lambda: [None] * 4)
     gamma: tuple = GAMMA
     pinf: tuple = PINF
+    nz: int = 1                        # 3D only; bc then has 6 entries
+    z0: float = 0.0
+    z1: float = 1.0
 
     @property
     def nvar(self) -> int:
-        return 5 if self.ndim == 1 else 6
+        return {1: 5, 2: 6, 3: 7}[self.ndim]
+
+    @property
+    def dz(self) -> float:
+        return (self.z1 - self.z0) / self.nz if self.ndim == 3 else 1.0
+
+    def centres3(self):
+        """cell-centre grids X, Y, Z of shape [nz][ny][nx] (3D)."""
+        x = self.x0 + (np.arange(self.nx) + 0.5) * self.dx
+        y = self.y0 + (np.arange(self.ny) + 0.5) * self.dy
+        z = self.z0 + (np.arange(self.nz) + 0.5) * self.dz
+        Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+        return X, Y, Z
 
     @property
     def dx(self) -> float:
@@ -58,7 +73,7 @@ class ProblemSpec:
 
     @property
     def dy(self) -> float:
-        return (self.y1 - self.y0) / self.ny if self.ndim == 2 else 1.0
+        return (self.y1 - self.y0) / self.ny if self.ndim >= 2 else 1.0
 
     def centres(self):
         x = self.x0 + (np.arange(self.nx) + 0.5) * self.dx
@@ -263,6 +278,78 @@ def mach100_jet(nx: int = 1024, ny: int = 512) -> ProblemSpec:
     rows[:] = air
     rows[np.abs(y) <= 0.05] = _water(1.0e5, 1.5e5, 0.0)
     s.dirichlet_prim = [rows, None, None, None]
+    return s
+
+
+# ------------------------------------------------------------------ 3D cases
+def random_smooth_state_3d(nx: int, ny: int, nz: int, seed: int, with_bubble: bool = True,
+                           with_shock: bool = True, eps: float = 1e-6) -> ProblemSpec:
+    """3D parity input: water with smooth random perturbations of p, u, v, w
+    and rho (random Fourier modes), an air sphere and a water shock; the
+    sides are extrapolated, reflective or periodic."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = ProblemSpec(f"random_smooth3d_{seed}", 3, nx, ny, 0.0, 1.0, 0.0, ny / nx,
+                    bc=(BC_EXTRAP, BC_REFLECT, BC_PERIODIC, BC_PERIODIC, BC_REFLECT, BC_EXTRAP),
+                    nz=nz, z0=0.0, z1=nz / nx)
+    X, Y, Z = s.centres3()
+
+    def modes(amp):
+        f = np.zeros_like(X)
+        for _ in range(3):
+            kx, ky, kz = rng.integers(1, 4, size=3)
+            ph = rng.uniform(0, 2 * np.pi)
+            f += amp * rng.uniform(0.3, 1.0) * np.sin(2 * np.pi * (kx * X + ky * Y + kz * Z) + ph)
+        return f
+
+    V = np.empty((7,) + X.shape)
+    V[0] = 1000.0 + modes(20.0)
+    V[1] = ABSENT_PARTIAL_DENSITY
+    V[2] = modes(30.0)
+    V[3] = modes(30.0)
+    V[4] = modes(30.0)
+    V[5] = 2e5 + modes(5e4)
+    V[6] = 1.0 - eps
+    if with_shock:
+        _set(V, X < 0.25, [1214.6, ABSENT_PARTIAL_DENSITY, 420.0, 0.0, 0.0, 1e9, 1.0 - eps])
+    if with_bubble:
+        cy, cz = 0.5 * (s.y1 - s.y0), 0.5 * (s.z1 - s.z0)
+        m = (X - 0.55) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2 < 0.12 ** 2
+        _set(V, m, [ABSENT_PARTIAL_DENSITY, 1.0, 0.0, 0.0, 0.0, 1e5, eps])
+    s.prim = V
+    return s
+
+
+def underwater_explosion_3d(n: int = 256, eps: float = 1e-6) -> ProblemSpec:
+    """3D underwater explosion near a wall on [-1,1]x[-1,1]x[0,2]: gas sphere
+    (r 0.12 at (0,0,0.5), rho 1270, p 8.29e8) in water (rho 1000, p 1e5); wall
+    (reflective) at z = 0, outflow elsewhere (the 2D workload's 3D form)."""
+    s = ProblemSpec("underwater_explosion_3d", 3, n, n, -1.0, 1.0, -1.0, 1.0,
+                    bc=(BC_EXTRAP, BC_EXTRAP, BC_EXTRAP, BC_EXTRAP, BC_REFLECT, BC_EXTRAP),
+                    nz=n, z0=0.0, z1=2.0)
+    X, Y, Z = s.centres3()
+    V = np.empty((7,) + X.shape)
+    for k, x in enumerate([1000.0, ABSENT_PARTIAL_DENSITY, 0.0, 0.0, 0.0, 1e5, 1.0 - eps]):
+        V[k] = x
+    _set(V, X ** 2 + Y ** 2 + (Z - 0.5) ** 2 < 0.12 ** 2,
+         [ABSENT_PARTIAL_DENSITY, 1270.0, 0.0, 0.0, 0.0, 8.29e8, eps])
+    s.prim = V
+    return s
+
+
+def sedov_blast_3d(n: int = 24) -> ProblemSpec:
+    """3D multi-material blast in the style of Sec. 6.4: water at -3e7 Pa on
+    [0,1]^3 with a 2x2x2 block of air at 1.28e6/dx Pa in the middle; the
+    limiters act on many faces from the first step."""
+    s = ProblemSpec("sedov_blast_3d", 3, n, n, 0.0, 1.0, 0.0, 1.0, bc=(BC_EXTRAP,) * 6,
+                    nz=n, z0=0.0, z1=1.0)
+    V = np.empty((7, n, n, n))
+    for k, x in enumerate([1000.0, 1e-8, 0.0, 0.0, 0.0, -3.0e7, 1.0 - 1e-8]):
+        V[k] = x
+    c = n // 2 - 1
+    blk = (slice(c, c + 2),) * 3
+    for k, x in enumerate([1e-8, 1.0, 0.0, 0.0, 0.0, 1.28e6 / s.dx, 1e-8]):
+        V[k][blk] = x
+    s.prim = V
     return s
 
 

@@ -39,7 +39,9 @@ class _Grid(C.Structure):
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
                 ("bc", C.c_int32 * 4),
                 ("dirichlet", (C.c_double * 6) * 4),
-                ("dirichlet_rows", C.c_void_p * 4)]
+                ("dirichlet_rows", C.c_void_p * 4),
+                ("nz", C.c_int32), ("bc_z", C.c_int32 * 2), ("reserved_z", C.c_int32),
+                ("z0", C.c_double), ("z1", C.c_double)]
 
 
 class _Eos(C.Structure):
@@ -136,24 +138,26 @@ def _ptr(t):
 class Solver:
     """One grid + fluids + options, bound to a device context.
 
-    grid: ndim, nx, ny, x0, x1, y0, y1, bc (4 kinds), dirichlet (per side:
-    None, or the primitive ghost state (a1r1, a2r2, u, [v], p, a1) of a
+    grid: ndim, nx, ny, x0, x1, y0, y1, bc (4 kinds; 6 in 3D), dirichlet (per
+    side: None, or the primitive ghost state (a1r1, a2r2, u, [v], p, a1) of a
     Dirichlet side as one nvar-vector or as an array [n_side][nvar] of one
-    state per boundary row/column)."""
+    state per boundary row/column); 3D: nz, z0, z1 (state [7][nz][ny][nx])."""
 
     def __init__(self, ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4,
                  gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), precision=FP64, stream=None,
-                 dirichlet=None, **params):
+                 dirichlet=None, nz=1, z0=0.0, z1=1.0, **params):
         import torch
-        g = make_grid(ndim, nx, ny, x0, x1, y0, y1, bc, dirichlet)
+        g = make_grid(ndim, nx, ny, x0, x1, y0, y1, bc, dirichlet, nz, z0, z1)
         e = _Eos()
         e.gamma[0], e.gamma[1] = gamma
         e.pinf[0], e.pinf[1] = pinf
         p = default_params(**params)
         self.ndim, self.nx, self.ny = ndim, nx, ny
-        self.nvar = 5 if ndim == 1 else 6
+        self.nz = nz if ndim == 3 else 1
+        self.nvar = {1: 5, 2: 6, 3: 7}[ndim]
         self.dx = (x1 - x0) / nx
-        self.dy = (y1 - y0) / ny if ndim == 2 else 1.0
+        self.dy = (y1 - y0) / ny if ndim >= 2 else 1.0
+        self.dz = (z1 - z0) / nz if ndim == 3 else 1.0
         self.params = p
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
@@ -168,7 +172,7 @@ class Solver:
         """Build from a seeded ProblemSpec (paper_2102_05287_amd.problems)."""
         return cls(spec.ndim, spec.nx, spec.ny, spec.x0, spec.x1, spec.y0, spec.y1,
                    bc=spec.bc, gamma=spec.gamma, pinf=spec.pinf, cfl=spec.cfl,
-                   dirichlet=spec.dirichlet_prim, **kw)
+                   dirichlet=spec.dirichlet_prim, nz=spec.nz, z0=spec.z0, z1=spec.z1, **kw)
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
@@ -188,12 +192,14 @@ class Solver:
     # ----------------------------------------------------------- buffers
     def empty_state(self, dtype=None):
         import torch
-        return torch.empty((self.nvar, self.ny, self.nx), dtype=torch.float64, device="cuda")
+        shape = (self.nvar, self.nz, self.ny, self.nx) if self.ndim == 3 else \
+            (self.nvar, self.ny, self.nx)
+        return torch.empty(shape, dtype=torch.float64, device="cuda")
 
     def _chk(self, t):
         import torch
         assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "device f64 contiguous"
-        assert t.numel() == self.nvar * self.nx * self.ny, "shape [nvar][ny][nx]"
+        assert t.numel() == self.nvar * self.nx * self.ny * self.nz, "shape [nvar]([nz])[ny][nx]"
 
     # ----------------------------------------------------------- entry points
     def prim_to_cons(self, V, W=None):
@@ -224,6 +230,8 @@ class Solver:
         cfl = self.params.cfl
         if self.ndim == 1:
             return cfl * self.dx / amax[0]
+        if self.ndim == 3:
+            return cfl / (amax[0] / self.dx + amax[1] / self.dy + amax[2] / self.dz)
         return cfl / (amax[0] / self.dx + amax[1] / self.dy)
 
     def advance(self, W, t_end, t=0.0, chunk=64, margin=8.0, max_steps=1 << 40):
@@ -265,7 +273,8 @@ class Solver:
     def max_wavespeed(self, W, out=None):
         import torch
         self._chk(W)
-        out = torch.zeros(2, dtype=torch.float64, device="cuda") if out is None else out
+        if out is None:
+            out = torch.zeros(3 if self.ndim == 3 else 2, dtype=torch.float64, device="cuda")
         _check(lib().wcns_max_wavespeed(self._ctx, _ptr(W), _ptr(out)), "wcns_max_wavespeed")
         return out
 
@@ -322,13 +331,18 @@ def prim_to_cons(V, ndim, gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), W=None):
     return W
 
 
-def make_grid(ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4, dirichlet=None) -> _Grid:
+def make_grid(ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4, dirichlet=None,
+              nz=1, z0=0.0, z1=1.0) -> _Grid:
     """wcns_grid; dirichlet[side]: None, a primitive nvar-vector, or an array
-    [n_side][nvar] (the grid keeps the array alive until it is dropped)."""
+    [n_side][nvar] (the grid keeps the array alive until it is dropped);
+    3D: nz, z0, z1 and bc[4:6] for z-lo, z-hi."""
     g = _Grid()
     g.ndim, g.nx, g.ny = ndim, nx, ny
     g.x0, g.x1, g.y0, g.y1 = x0, x1, y0, y1
-    nvar = 5 if ndim == 1 else 6
+    g.nz, g.z0, g.z1 = (nz, z0, z1) if ndim == 3 else (1, 0.0, 1.0)
+    if ndim == 3:
+        g.bc_z[0], g.bc_z[1] = int(bc[4]), int(bc[5])
+    nvar = {1: 5, 2: 6, 3: 7}[ndim]
     g._keep = []
     for k in range(4):
         g.bc[k] = int(bc[k])
@@ -351,7 +365,7 @@ def make_grid(ndim, nx, ny, x0, x1, y0=0.0, y1=1.0, bc=(BC_EXTRAP,) * 4, dirichl
 
 def grid_of(spec) -> _Grid:
     return make_grid(spec.ndim, spec.nx, spec.ny, spec.x0, spec.x1, spec.y0, spec.y1, spec.bc,
-                     spec.dirichlet_prim)
+                     spec.dirichlet_prim, spec.nz, spec.z0, spec.z1)
 
 
 class Batch:

@@ -17,7 +17,7 @@ from paper_2102_05287_amd import problems as pb  # noqa: E402
 def oracle_setup(spec: pb.ProblemSpec, **kw) -> orc.Setup:
     s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy,
                   bc=tuple(spec.bc), gamma=spec.gamma, pinf=spec.pinf, cfl=spec.cfl,
-                  dirichlet_prim=list(spec.dirichlet_prim))
+                  dirichlet_prim=list(spec.dirichlet_prim), nz=spec.nz, dz=spec.dz)
     for k, v in kw.items():
         setattr(s, k, v)
     return s

@@ -48,6 +48,9 @@ def _create(**kw):
     g.x0, g.x1, g.y0, g.y1 = 0.0, 1.0, 0.0, 1.0
     for k, b in enumerate(kw.get("bc", (1, 1, 1, 1))):
         g.bc[k] = b
+    g.nz, g.z0, g.z1 = kw.get("nz", 0), 0.0, kw.get("z1", 1.0)
+    for k, b in enumerate(kw.get("bc_z", (1, 1))):
+        g.bc_z[k] = b
     e = wcns._Eos()
     e.gamma[0], e.gamma[1] = kw.get("gamma", (6.12, 1.4))
     e.pinf[0], e.pinf[1] = kw.get("pinf", (3.43e8, 0.0))
@@ -66,7 +69,15 @@ def _create(**kw):
     (dict(gamma=(1.0, 1.4)), -2),
     (dict(nx=0), -1),                           # empty grid
     (dict(ndim=1, ny=2), -1),
-    (dict(ndim=3), -1),
+    (dict(ndim=3), -1),                         # 3D needs nz >= 1
+    (dict(ndim=4, nz=4), -1),
+    (dict(ndim=3, nz=4, bc=(3, 1, 1, 1)), -1),  # no Dirichlet side in 3D
+    (dict(ndim=3, nz=4, bc_z=(3, 3)), -1),
+    (dict(ndim=3, nz=4, bc_z=(0, 1)), -1),      # periodic on one z side only
+    (dict(ndim=3, nz=2, bc_z=(2, 2)), -1),      # reflective z wall needs 3 cells
+    (dict(ndim=3, nz=4, z1=0.0), -1),           # empty z extent
+    (dict(ndim=3, nz=70000, nx=1, ny=1), -1),   # nz limit of the launch grid
+    (dict(ndim=3, nz=4, precision=1), -1),      # 3D is FP64 only
     (dict(bc=(0, 1, 1, 1)), -1),                # periodic on one side only
     (dict(bc=(2, 2, 1, 1), nx=2), -1),          # reflective wall needs 3 cells
     (dict(bc=(7, 1, 1, 1)), -1),
