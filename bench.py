@@ -226,6 +226,48 @@ def serving_form(n_req, rate, budget_gib, chunk):
     return summary
 
 
+def three_d_form(n=256, steps=10, warmup=2):
+    """3D underwater explosion near a wall at n^3 (FP64, the direct 3D
+    extension): Mcell-updates/s per RHS, per-kernel device time and the
+    x-sweep and y+z-sweep roofline fractions (3D face op count)."""
+    import torch
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import wcns
+    spec = pb.underwater_explosion_3d(n)
+    sol = wcns.Solver.from_spec(spec)
+    W0 = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+    spec.prim = None
+    el, W = time_steps(sol, W0, steps, warmup)
+    cells = n ** 3
+    W.copy_(W0)
+    sol.profile(True)
+    for _ in range(steps):
+        sol.step(W, 0.0)
+    prof = sol.profile_read(reset=True)
+    sol.profile(False)
+    bad = sol.count_inadmissible(W)
+    with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
+        oc = json.load(f)["counts"]["ppwcnsis_3d"]
+    face = weighted(oc["face"])
+    diff = 7 * (1 + W_DIV)
+    ops_x = (n + 1) * n * n * face + cells * diff
+    ops_yz = 2 * (n + 1) * n * n * face + cells * (2 * diff + 14 + 7 * 5)
+    nrhs = 3 * steps
+    roof = {}
+    for k, ops in (("sweep_x", ops_x), ("sweep_y", ops_yz)):
+        t = prof[k][0] / 1e3 / nrhs          # seconds per RHS in this class
+        roof["sweep_x" if k == "sweep_x" else "sweep_y_plus_z"] = {
+            "ms_per_rhs": t * 1e3, "achieved": ops / t / 1e12, "frac": ops / t / VALU_F64_SLOTS}
+    del W, W0
+    sol.close()
+    return {"workload": f"3D underwater explosion near a wall, {n}^3 ({cells} cells), FP64",
+            "steps": steps, "mcells_per_s": 3 * cells * steps / el / 1e6,
+            "ms_per_step": el / steps * 1e3, "inadmissible_after": bad,
+            "per_kernel_ms_per_rhs": {k: v[0] / nrhs for k, v in prof.items() if v[1]},
+            "roofline": {"bound": "alu", "peak": VALU_F64_SLOTS / 1e12, "unit": "TFLOP/s",
+                         "face_ops_weighted": face, "kernels": roof}}
+
+
 def time_to_solution_form():
     """The paper's runs to their final times on the device time loop
     (Solver.advance): the 1D water-air tube (400 cells, t = 2.4e-4 s), the
@@ -337,7 +379,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision/batched/serving forms")
-    ap.add_argument("--form", choices=("precision", "batched", "serving", "solutions", "rates"),
+    ap.add_argument("--form", choices=("precision", "batched", "serving", "solutions", "rates",
+                                       "3d"),
                     default=None,
                     help="run only this form and print its record")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -361,7 +404,8 @@ def main():
                "batched": lambda: batched_form(512, 200, 20),
                "serving": lambda: serving_form(300, 200.0, 64, 20),
                "solutions": time_to_solution_form,
-               "rates": serving_rate_sweep}[args.form]
+               "rates": serving_rate_sweep,
+               "3d": three_d_form}[args.form]
         print(json.dumps({"form": args.form, **run()}), flush=True)
         return
     if args.gpus != 1:
@@ -443,6 +487,8 @@ def main():
         forms["serving"] = serving_form(300, 200.0, 64, 20)
         print("# serving rate sweep ...", flush=True)
         forms["serving_rate_sweep"] = serving_rate_sweep()
+        print("# 3D form ...", flush=True)
+        forms["three_d"] = three_d_form()
         print("# time to solution (paper runs) ...", flush=True)
         forms["time_to_solution"] = time_to_solution_form()
 

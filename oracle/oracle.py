@@ -173,6 +173,7 @@ def lib():
         L.oracle_run.argtypes = [P, dp, C.c_double, C.c_double, C.c_long, dp]
         L.oracle_run.restype = C.c_long
         L.oracle_opcount_face.argtypes = [P, dp, C.c_double, C.POINTER(C.c_longlong)]
+        L.oracle_opcount_face3.argtypes = [P, dp, C.c_double, C.POINTER(C.c_longlong)]
         _lib = L
     return _lib
 
@@ -356,9 +357,14 @@ def flux_limit_face(s: Setup, Wl, Wr, lam, Hm, Hp, Gm, Gp):
 
 
 def opcount_face(s: Setup, stencil, lam: float) -> dict:
-    """Operation counts: per node (primitive recovery) and per face."""
-    st = _arr(stencil, 36)
+    """Operation counts: per node (primitive recovery) and per face; a
+    [6][6] rotated stencil, or [6][7] for a 3D face."""
+    st = _arr(stencil)
     out = (C.c_longlong * 10)()
-    lib().oracle_opcount_face(C.byref(s.c()), _dp(st), float(lam), out)
+    if st.size == 42:
+        lib().oracle_opcount_face3(C.byref(s.c()), _dp(st), float(lam), out)
+    else:
+        assert st.size == 36
+        lib().oracle_opcount_face(C.byref(s.c()), _dp(st), float(lam), out)
     keys = ["add", "mul", "div", "sqrt", "cmp"]
     return {"node": dict(zip(keys, out[0:5])), "face": dict(zip(keys, out[5:10]))}

@@ -1233,4 +1233,25 @@ void oracle_opcount_face(const Problem* P, const double* stencil /* [6][6] */, d
   out[5] = f.add; out[6] = f.mul; out[7] = f.div; out[8] = f.sqrt; out[9] = f.cmp;
 }
 
+// The same for a 3D face (rotated frame, 6 nodes x 7 components).
+void oracle_opcount_face3(const Problem* P, const double* stencil /* [6][7] */, double lam,
+                          long long* out) {
+  Eos e = make_eos(*P);
+  Node<Cnt, 7> nd[6];
+  g_ops = OpCounts{0, 0, 0, 0, 0};
+  for (int m = 0; m < 6; ++m) {
+    Cnt X[7];
+    for (int v = 0; v < 7; ++v) X[v] = Cnt(stencil[m * 7 + v]);
+    nd[m] = node_from_w<7>(e, X);
+  }
+  OpCounts six = g_ops;
+  g_ops = OpCounts{0, 0, 0, 0, 0};
+  Cnt Gm[7], Gp[7];
+  face_flux(e, *P, nd, Cnt(lam), Gm, Gp);
+  OpCounts f = g_ops;
+  out[0] = six.add / 6; out[1] = six.mul / 6; out[2] = six.div / 6;
+  out[3] = six.sqrt / 6; out[4] = six.cmp / 6;
+  out[5] = f.add; out[6] = f.mul; out[7] = f.div; out[8] = f.sqrt; out[9] = f.cmp;
+}
+
 }  // extern "C"

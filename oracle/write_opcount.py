@@ -29,6 +29,18 @@ def main():
         W = orc.prim_to_cons(s, V)
         st = np.array([[W[v, 3, i] for v in range(6)] for i in range(6)])
         out["counts"][name] = orc.opcount_face(s, st, 1e-6)
+    # 3D face: the same mixture extruded in z with w = 10 (7 components)
+    s3 = orc.Setup(ndim=3, nx=16, ny=16, nz=4, dx=2.0 / 16, dy=2.0 / 16, dz=2.0 / 16)
+    x = -1.0 + (np.arange(16) + 0.5) * 2.0 / 16
+    X, Y = np.meshgrid(x, x)
+    a1 = 0.5 + 0.25 * np.sin(np.pi * (X + Y))
+    V = np.stack([1000.0 * a1, 1.0 - a1, 10 + 0 * a1, 10 + 0 * a1, 10 + 0 * a1,
+                  101325 + 0 * a1, a1])
+    V3 = np.repeat(V[:, None], 4, axis=1)
+    W3 = orc.prim_to_cons(s3, V3)
+    st3 = np.array([[W3[v, 0, 3, i] for v in range(7)] for i in range(6)])
+    out["counts"]["ppwcnsis_3d"] = orc.opcount_face(s3, st3, 1e-6)
+    out["state_3d"] = "the same mixture extruded along z with w = 10, 16x16x4, x-face"
     path = os.path.join(os.path.dirname(HERE), "tests", "golden", "opcount.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
