@@ -182,6 +182,15 @@ wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int3
 wcns_status wcns_selftest_division(const double* a, const double* b, double* q_ieee,
                                    double* q_core, int64_t n, void* stream);
 
+/* Verification aid: the kernels divide by a constant b (the HCS divisor
+ * 2100 of Sec. 4.1, the grid spacings of the flux difference) through its
+ * rounded reciprocal and one FMA correction when that reciprocal is accurate
+ * to 2^-55; this runs that path for the n device values a[] and one b:
+ * q_core[i], with the compiler's IEEE a[i]/b in q_ieee[i].  WCNS_ERR_ARG when
+ * b does not take the path (the kernels then use the division core). */
+wcns_status wcns_selftest_division_by(const double* a, double b, double* q_ieee, double* q_core,
+                                      int64_t n, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: many independent solves of uneven sizes advanced together.
  * Every phase of a Runge-Kutta stage is one launch over all instances (a

@@ -33,6 +33,7 @@ constexpr int YW3 = WCNS_YTILE3;
 struct K3Args {
   int32_t nx, ny, nz, tile_x;
   double dx, dy, dz;
+  double rdx, rdy, rdz;       // checked reciprocals of the spacings (0: divide)
   int32_t bc[6];              // x-lo, x-hi, y-lo, y-hi, z-lo, z-hi
   int32_t interp_limiter, flux_limiter, scheme, out_mode;
   int32_t nbr, last;          // strided pass: tile rows; 1 when it finishes the cell
@@ -450,7 +451,7 @@ __device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, d
       double sum = v < 7 ? ga[v] + gb[v] : qa.un + qb.un;
       if (pr == 0) acc[v] = 3072.0 * acc[v] - 505.0 * sum;
       else if (pr == 1) acc[v] = acc[v] + 20.0 * sum;
-      else acc[v] = ddiv(acc[v] - sum, 2100.0);
+      else acc[v] = cdiv(acc[v] - sum, 2100.0, R2100);
     }
   }
   const double uh = acc[7];
@@ -592,7 +593,7 @@ __global__ __launch_bounds__(64) void k3_sweep_x(K3Args a) {
   for (int v = 0; v < 7; ++v) Gr[v] = __shfl(Gm[v], src, 64);
   if (!owns_cell) return;
 #pragma unroll
-  for (int v = 0; v < 7; ++v) a.Lout[v * N + c] = ddiv(-(Gr[v] - Gp[v]), a.dx);
+  for (int v = 0; v < 7; ++v) a.Lout[v * N + c] = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
 }
 
 // Strided pass of direction DIR (1: y-lines in z slab blockIdx.z; 2: z-lines
@@ -611,6 +612,7 @@ __global__ __launch_bounds__(64 * YW3) void k3_sweep_l(K3Args a) {
   const long stride = DIR == 1 ? a.nx : plane;
   const long slab = DIR == 1 ? (long)blockIdx.z * plane : 0;
   const double h = DIR == 1 ? a.dy : a.dz;
+  const double rh = DIR == 1 ? a.rdy : a.rdz;
   const long col = (long)blockIdx.x * 64 + lane;
   const int by = blockIdx.y;
   const int k = by * YW3 + w;
@@ -639,7 +641,7 @@ __global__ __launch_bounds__(64 * YW3) void k3_sweep_l(K3Args a) {
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const int s = state_index3(DIR, v);
-    const double L = a.Lin[s * N + idx] + ddiv(-(sGm[w + 1][v][lane] - Gp[v]), h);
+    const double L = a.Lin[s * N + idx] + hdiv(-(sGm[w + 1][v][lane] - Gp[v]), h, rh);
     if (a.last) write_cell3(a, idx, N, s, L);
     else a.out[s * N + idx] = L;
   }
@@ -663,13 +665,14 @@ __global__ __launch_bounds__(256) void k3_fixup(K3Args a) {
   const int j = (b + 1) * YW3 - 1;
   if (j >= nline) return;
   const double h = DIR == 1 ? a.dy : a.dz;
+  const double rh = DIR == 1 ? a.rdy : a.rdz;
   const double* lo = a.edge + ((sl * a.nbr + b) * 14 + 7) * ncol;   // G^+ of face row j
   const double* hi = a.edge + ((sl * a.nbr + b + 1) * 14) * ncol;   // G^- of face row j+1
   const long idx = sl * plane + (long)j * stride + col;
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const int s = state_index3(DIR, v);
-    const double L = a.Lin[s * N + idx] + ddiv(-(hi[v * ncol + col] - lo[v * ncol + col]), h);
+    const double L = a.Lin[s * N + idx] + hdiv(-(hi[v * ncol + col] - lo[v * ncol + col]), h, rh);
     if (a.last) write_cell3(a, idx, N, s, L);
     else a.out[s * N + idx] = L;
   }

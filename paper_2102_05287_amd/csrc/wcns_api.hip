@@ -123,6 +123,16 @@ static bool eos_ok(const wcns_eos* e) {
   return false;
 }
 
+// 1/h rounded once, if it is accurate to 2^-55 relative (the condition under
+// which the kernels' reciprocal-and-correction divide by h is correctly
+// rounded); 0 otherwise (the kernels then use the division core)
+static double checked_recip(double h) {
+  if (!(h > 0.0) || !isfinite(h)) return 0.0;
+  const double y = 1.0 / h;
+  const double e = fma(-h, y, 1.0);   // 1 - h*y: the relative error of y
+  return fabs(e) <= ldexp(1.0, -55) ? y : 0.0;
+}
+
 static int pick_tile_x(int nx) {
   // largest T with T + (rows a run of T cells can touch) <= 64
   for (int T = 62; T >= 1; --T) {
@@ -204,6 +214,8 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   a.nv = c->nv;
   a.dx = c->dx;
   a.dy = c->dy;
+  a.rdx = checked_recip(a.dx);
+  a.rdy = checked_recip(a.dy);
   for (int k = 0; k < 4; ++k) a.bc[k] = g->bc[k];
   if (g->ndim == 1) { a.bc[2] = WCNS_BC_PERIODIC; a.bc[3] = WCNS_BC_PERIODIC; }
   a.interp_limiter = prm->interp_limiter ? 1 : 0;
@@ -369,6 +381,9 @@ static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_p
   a.dx = c->dx;
   a.dy = c->dy;
   a.dz = (g->z1 - g->z0) / g->nz;
+  a.rdx = checked_recip(a.dx);
+  a.rdy = checked_recip(a.dy);
+  a.rdz = checked_recip(a.dz);
   for (int k = 0; k < 6; ++k) a.bc[k] = bc6[k];
   a.interp_limiter = prm->interp_limiter ? 1 : 0;
   a.flux_limiter = prm->flux_limiter ? 1 : 0;
@@ -751,6 +766,19 @@ wcns_status wcns_selftest_division(const double* a, const double* b, double* q_i
   return WCNS_OK;
 }
 
+wcns_status wcns_selftest_division_by(const double* a, double b, double* q_ieee, double* q_core,
+                                      int64_t n, void* stream) {
+  if (!a || !q_ieee || !q_core || n < 0) return WCNS_ERR_ARG;
+  const double y = b == 2100.0 ? 1.0 / 2100.0 : checked_recip(b);
+  if (y == 0.0) return WCNS_ERR_ARG;   // b does not take this path
+  if (n == 0) return WCNS_OK;
+  unsigned g = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_selftest_cdiv, dim3(g), dim3(256), 0, (hipStream_t)stream, a, b, y, q_ieee,
+                     q_core, (long)n);
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
 wcns_status wcns_profile(wcns_ctx* c, int32_t enable) {
   if (!c) return WCNS_ERR_ARG;
   if (enable && !c->prof_on) {
@@ -907,6 +935,8 @@ static wcns_status batch_build(wcns_batch* b) {
     a.ny = g.ny;
     a.dx = (g.x1 - g.x0) / g.nx;
     a.dy = g.ndim == 2 ? (g.y1 - g.y0) / g.ny : 1.0;
+    a.rdx = checked_recip(a.dx);
+    a.rdy = checked_recip(a.dy);
     for (int q = 0; q < 4; ++q) a.bc[q] = g.bc[q];
     if (g.ndim == 1) { a.bc[2] = WCNS_BC_PERIODIC; a.bc[3] = WCNS_BC_PERIODIC; }
     int T = 62;

@@ -81,6 +81,24 @@ __device__ __forceinline__ double ddiv(double a, double b) {
   return __builtin_fma(rem, r, q);
 }
 
+// a/b for a divisor whose correctly rounded reciprocal y = RN(1/b) is
+// accurate to 2^-55 relative or better: q0 = a*y is then within one ulp of
+// a/b, the residual a - b*q0 is exact (FMA), and one correction q0 + r*y
+// rounds to the IEEE quotient (Markstein's theorem); 3 VALU instructions.
+// 1/2100 (HCS) is accurate to 2^-60; grid spacings are checked on the host,
+// which passes y = 0 when the check fails (hdiv then uses ddiv).
+__device__ __forceinline__ double cdiv(double a, double b, double y) {
+  double q = a * y;
+  double r = __builtin_fma(-b, q, a);
+  return __builtin_fma(r, y, q);
+}
+constexpr double R2100 = 1.0 / 2100.0;
+
+// division by a grid spacing h with its checked reciprocal y (0: none)
+__device__ __forceinline__ double hdiv(double a, double h, double y) {
+  return y != 0.0 ? cdiv(a, h, y) : ddiv(a, h);
+}
+
 // Division used by the face pipeline: the IEEE core, or the refined
 // reciprocal when FAST.
 template <bool FAST>
@@ -533,7 +551,7 @@ __device__ __forceinline__ double flux_limit(const EosC& e, const Tol& t, const 
 // [3072 gt - 505 (g_i + g_{i+1}) + 20 (g_{i-1} + g_{i+2}) - (g_{i-2} + g_{i+3})]/2100
 __device__ __forceinline__ double hcs(double gt, double s01, double s12, double s03) {
 #pragma clang fp contract(off)
-  return ddiv(3072.0 * gt - 505.0 * s01 + 20.0 * s12 - s03, 2100.0);
+  return cdiv(3072.0 * gt - 505.0 * s01 + 20.0 * s12 - s03, 2100.0, R2100);
 }
 
 }  // namespace wcns

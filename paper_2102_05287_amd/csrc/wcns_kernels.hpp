@@ -41,6 +41,7 @@ constexpr int Y_WAVES = WCNS_YTILE;
 struct KArgs {
   int32_t nx, ny, nv, tile_x;     // tile_x: cells per x-sweep wave
   double dx, dy;
+  double rdx, rdy;                // checked reciprocals of dx, dy (0: divide)
   int32_t bc[4];
   int32_t dir_off[4];    // first Dirichlet ghost row of each side in dirW/dirP
   int32_t interp_limiter, flux_limiter, scheme, pad;
@@ -441,7 +442,7 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
         double sum = v < 6 ? ga[v] + gb[v] : qa.un + qb.un;
         if (pr == 0) acc[v] = 3072.0 * acc[v] - 505.0 * sum;
         else if (pr == 1) acc[v] = acc[v] + 20.0 * sum;
-        else acc[v] = ddiv(acc[v] - sum, 2100.0);
+        else acc[v] = cdiv(acc[v] - sum, 2100.0, R2100);
       }
     }
   }
@@ -748,7 +749,7 @@ __device__ __forceinline__ void sweep_x_tile(const KArgs& a, long tile) {
     if (!HAS_T && v == 3) continue;
     double L;
     {
-      L = ddiv(-(Gr[v] - Gp[v]), a.dx);
+      L = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
     }
     const int k = state_index(0, v, HAS_T);
     if (HAS_T) {
@@ -803,7 +804,7 @@ __device__ __forceinline__ void sweep_y_tile(const KArgs& a, int bx, int by,
   for (int v = 0; v < 6; ++v) {
     double L;
     {
-      double Ly = ddiv(-(sGm[w + 1][v][lane] - Gp[v]), a.dy);
+      double Ly = hdiv(-(sGm[w + 1][v][lane] - Gp[v]), a.dy, a.rdy);
       const int s = state_index(1, v, true);
       L = a.Lx[s * N + (long)j * nx + i] + Ly;
     }
@@ -832,7 +833,7 @@ __device__ __forceinline__ void fixup_cell(const KArgs& a, long t, int yw) {
   for (int v = 0; v < 6; ++v) {
     double L;
     {
-      double Ly = ddiv(-(hi[v * nx + i] - lo[v * nx + i]), a.dy);
+      double Ly = hdiv(-(hi[v * nx + i] - lo[v * nx + i]), a.dy, a.rdy);
       const int s = state_index(1, v, true);
       L = a.Lx[s * N + (long)j * nx + i] + Ly;
     }
@@ -949,6 +950,15 @@ __global__ __launch_bounds__(256) void k_selftest_div(const double* a, const dou
   if (t >= n) return;
   q_ieee[t] = a[t] / b[t];
   q_core[t] = ddiv(a[t], b[t]);
+}
+
+// The same for one divisor b and its checked reciprocal y (cdiv).
+__global__ __launch_bounds__(256) void k_selftest_cdiv(const double* a, double b, double y,
+                                                        double* q_ieee, double* q_core, long n) {
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  q_ieee[t] = a[t] / b;
+  q_core[t] = cdiv(a[t], b, y);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {

@@ -61,7 +61,7 @@ _lib = None
 EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
            "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
            "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
-           "wcns_selftest_division", "wcns_batch_create", "wcns_batch_reset",
+           "wcns_selftest_division", "wcns_selftest_division_by", "wcns_batch_create", "wcns_batch_reset",
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
            "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
            "wcns_batch_steps_left", "wcns_prim_to_cons_n", "wcns_status_str"]
@@ -94,6 +94,7 @@ def lib():
         L.wcns_profile.argtypes = [vp, C.c_int32]
         L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.wcns_selftest_division.argtypes = [dp, dp, dp, dp, C.c_int64, vp]
+        L.wcns_selftest_division_by.argtypes = [dp, C.c_double, dp, dp, C.c_int64, vp]
         L.wcns_batch_create.argtypes = [C.c_int32, C.POINTER(_Grid), C.POINTER(_Eos), C.POINTER(_Params),
                                         C.c_int32, C.POINTER(C.c_void_p), C.c_int64, C.POINTER(vp)]
         L.wcns_batch_reset.argtypes = [vp, C.c_int32, C.POINTER(_Grid), C.POINTER(C.c_void_p)]
@@ -234,21 +235,48 @@ class Solver:
             return cfl / (amax[0] / self.dx + amax[1] / self.dy + amax[2] / self.dz)
         return cfl / (amax[0] / self.dx + amax[1] / self.dy)
 
-    def advance(self, W, t_end, t=0.0, chunk=64, margin=8.0, max_steps=1 << 40):
+    def capture_steps(self, W, n, dt_used):
+        """A HIP graph of n device-CFL SSP-RK3 steps of W in place, step k
+        writing its dt to dt_used[k]; replay() runs them on the current torch
+        stream.  (The library only enqueues kernels inside a step, so the
+        captured graph holds kernel nodes only.)"""
+        import torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        old = self._stream
+        g = torch.cuda.CUDAGraph()
+        self.set_stream(s.cuda_stream)
+        try:
+            with torch.cuda.graph(g, stream=s):
+                for k in range(n):
+                    self.step(W, 0.0, dt_used=dt_used[k:k + 1])
+        finally:
+            self.set_stream(old)
+        return g
+
+    def advance(self, W, t_end, t=0.0, chunk=64, margin=8.0, max_steps=1 << 40, graph=False):
         """March W in place from time t to t_end with CFL steps, the last one
         shortened to land on t_end (the time loop of the paper's runs).
         Far from t_end the device picks every dt itself and the host reads
-        the chunk's time steps once per `chunk` steps; once t_end is within
-        margin * chunk * (largest recent dt) it takes one step at a time
-        from the device's wave-speed maxima.  Returns (steps, t)."""
+        the chunk's time steps once per `chunk` steps (the chunk replayed as
+        one HIP graph when `graph`: measured no faster than eager launches
+        for the 400-cell tube, 78 vs 70 us per step, so off by default);
+        once t_end is within margin * chunk * (largest recent dt) it takes
+        one step at a time from the device's wave-speed maxima.  Returns
+        (steps, t)."""
         import torch
-        buf = torch.empty(chunk, dtype=torch.float64, device="cuda")
-        steps, dt_last = 0, None
+        buf = torch.zeros(chunk, dtype=torch.float64, device="cuda")
+        steps, dt_last, g = 0, None, None
         while t < t_end and steps < max_steps:
             if dt_last is not None and t_end - t > margin * chunk * dt_last \
                     and steps + chunk <= max_steps:
-                for k in range(chunk):
-                    self.step(W, 0.0, dt_used=buf[k:k + 1])
+                if graph:
+                    if g is None:
+                        g = self.capture_steps(W, chunk, buf)
+                    g.replay()
+                else:
+                    for k in range(chunk):
+                        self.step(W, 0.0, dt_used=buf[k:k + 1])
                 dts = buf.cpu().tolist()
                 for d in dts:
                     t += d
@@ -313,6 +341,20 @@ def selftest_division(a, b):
     _check(lib().wcns_selftest_division(_ptr(a), _ptr(b), _ptr(qi), _ptr(qc), a.numel(),
                                         C.c_void_p(torch.cuda.current_stream().cuda_stream)),
            "wcns_selftest_division")
+    return qi, qc
+
+
+def selftest_division_by(a, b: float):
+    """(IEEE quotient, kernels' constant-divisor path) of device tensor a and
+    the scalar b; None when b does not take that path."""
+    import torch
+    qi = torch.empty_like(a)
+    qc = torch.empty_like(a)
+    rc = lib().wcns_selftest_division_by(_ptr(a), float(b), _ptr(qi), _ptr(qc), a.numel(),
+                                         C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc == -1:
+        return None
+    _check(rc, "wcns_selftest_division_by")
     return qi, qc
 
 

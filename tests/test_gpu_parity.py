@@ -87,6 +87,28 @@ def test_division_core_is_ieee():
     assert same.all(), (a[~same][:5], b[~same][:5])
 
 
+def test_constant_divisor_path_is_ieee():
+    """Division by the HCS constant 2100 and by grid spacings through the
+    rounded reciprocal and one FMA correction equals the IEEE quotient bit
+    for bit; spacings whose reciprocal is not accurate enough are refused
+    (the kernels then divide with the core)."""
+    rng = np.random.default_rng(321)
+    n = 1 << 22
+    a = rng.choice([-1.0, 1.0], n) * rng.uniform(1, 2, n) * 2.0 ** rng.uniform(-250, 250, n)
+    a = np.concatenate([a, np.arange(-5000, 5001.0), [0.0, 1e-300, 2100.0 * 3, 1e300]])
+    taken = 0
+    for b in [2100.0, 2.0 / 1024, 1.0 / 400, 4.0 / 2048, 30e-3 / 1152, 20e-3 / 768, 1.0 / 1024,
+              0.5 / 512, 1.0 / 1000, 3.0 / 7, 1e-3, 1.3e-3, 0.8e-3]:
+        r = wcns.selftest_division_by(dev(a), b)
+        if r is None:
+            continue
+        taken += 1
+        qi, qc = host(r[0]), host(r[1])
+        assert np.array_equal(qi, a / b), b
+        assert np.array_equal(qi, qc), (b, a[qi != qc][:5])
+    assert taken >= 5
+
+
 def test_prim_to_cons_matches_oracle():
     for spec in (pb.water_air_shock_tube(400), pb.shock_bubble(96)):
         s = oracle_setup(spec)

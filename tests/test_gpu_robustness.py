@@ -235,3 +235,38 @@ def test_advance_matches_the_oracle_time_loop(case):
     print(f"  {case}: {n} steps to t = {t!r} (oracle {steps}, {t_ref!r})", flush=True)
     assert n == steps and t == t_ref
     assert_parity(host(Wd), ref, what=f"advance {case}")
+
+
+def test_captured_steps_replay_like_eager_steps():
+    """A graph of 5 device-CFL steps, replayed three times with eager reads
+    and synchronisations between the replays, gives after every replay the
+    state and time steps of 5 eager steps (2D and 1D)."""
+    for spec in (pb.random_smooth_state(70, 45, seed=21), pb.water_air_shock_tube(400)):
+        s = oracle_setup(spec)
+        W0 = oracle_W(spec, s)
+        sol = solver_for(spec)
+        Wg, We = dev(W0), dev(W0)
+        buf = torch.zeros(5, dtype=torch.float64, device="cuda")
+        ebuf = torch.zeros(5, dtype=torch.float64, device="cuda")
+        g = sol.capture_steps(Wg, 5, buf)
+        for r in range(3):
+            g.replay()
+            for k in range(5):
+                sol.step(We, 0.0, dt_used=ebuf[k:k + 1])
+            torch.cuda.synchronize()
+            assert torch.equal(Wg, We), (spec.name, r)
+            assert torch.equal(buf, ebuf), (spec.name, r)
+            assert sol.count_inadmissible(Wg) == 0
+
+
+def test_advance_with_and_without_graphs_agree():
+    spec = pb.water_air_shock_tube(400)
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    ref, steps, t_ref = orc.run(s, W0, spec.t_end)
+    sol = solver_for(spec)
+    for graph in (True, False):
+        Wd = dev(W0)
+        n, t = sol.advance(Wd, spec.t_end, chunk=32, graph=graph)
+        assert n == steps and t == t_ref, graph
+        assert_parity(host(Wd), ref, what=f"advance graph={graph}")
