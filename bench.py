@@ -309,6 +309,20 @@ def time_to_solution_form():
 
     run("water_air_tube_1d", pb.water_air_shock_tube(400))
     run("sedov_1d", pb.sedov_multimaterial(401))
+    # the same two 1D runs with the whole time loop in one workgroup (wcns_run)
+    for name, spec in (("water_air_tube_1d_device_loop", pb.water_air_shock_tube(400)),
+                       ("sedov_1d_device_loop", pb.sedov_multimaterial(401))):
+        sol = wcns.Solver.from_spec(spec)
+        W = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+        sol.run(W.clone(), spec.t_end, dt_fixed=spec.dt_fixed, max_steps=3)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n, t = sol.run(W, spec.t_end, dt_fixed=spec.dt_fixed)
+        el = time.perf_counter() - t0
+        out[name] = {"grid": [spec.nx], "t_end": spec.t_end, "steps": n, "wall_s": el,
+                     "ms_per_step": el / n * 1e3, "inadmissible_at_end": sol.count_inadmissible(W)}
+        print(f"#   {name}: {n} steps in {el:.3f} s", flush=True)
+        sol.close()
     run("mach10_cylinder", pb.mach10_cylinder())
     run("mach10_cylinder_hllc1", pb.mach10_cylinder(), scheme=1)
     run("mach100_jet", pb.mach100_jet())

@@ -141,6 +141,20 @@ wcns_status wcns_rhs(wcns_ctx* ctx, const double* W, double* dWdt, double dt);
 wcns_status wcns_limit(wcns_ctx* ctx, int32_t dir, const double* W, const double* G_ho,
                        const double* G_lo, double* G_out, double* theta, double dt);
 
+/* A whole run of a small 1D problem (nx <= 4096; the paper's Sec. 6.2-6.4
+ * experiments) with the time loop on the device: SSP-RK3 steps of W (device,
+ * in place) from time t0 until t_end or max_steps steps, each step the CFL
+ * step of Sec. 3.3 (dt_fixed = 0) or dt_fixed, the last one shortened to land
+ * on t_end; every step is the arithmetic of wcns_ssprk3_step, so the result
+ * equals stepping with it.  One workgroup runs the whole loop (one launch
+ * instead of five per stage).  dts (device, optional): dt of step k at
+ * dts[k] for k < dts_cap.  Synchronous: *steps_out and *t_out (host) receive
+ * the steps taken and the final time.  WCNS_ERR_ARG for 2D/3D or larger
+ * grids, WCNS_ERR_CFL for non-finite times or a negative dt_fixed. */
+wcns_status wcns_run(wcns_ctx* ctx, double* W, double t0, double t_end, double dt_fixed,
+                     int64_t max_steps, double* dts, int64_t dts_cap, int64_t* steps_out,
+                     double* t_out);
+
 /* Maximum wave speeds max(|u|+c), max(|v|+c) (Sec. 3.3) over the cells and
  * the ghost states of Dirichlet sides (those of the x sides count for the
  * first, of the y sides for the second), i.e. over every state a face flux of

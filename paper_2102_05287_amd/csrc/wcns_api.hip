@@ -10,6 +10,7 @@
 #include "../../include/wcns.h"
 #include "wcns_batch.hpp"
 #include "wcns_3d.hpp"
+#include "wcns_run1d.hpp"
 
 #include <algorithm>
 #include <vector>
@@ -33,6 +34,9 @@ struct wcns_ctx {
   K3Args base3;
   double* edge3;
   int nbr_y3, nbr_z3;
+  // 1D runs inside one workgroup (nx <= RUN1D_MAX_CELLS): face buffer, run record
+  double* run_G;
+  Run1D* run_dev;
   int node_grid, tile_x, x_grid, nbr;
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
@@ -164,6 +168,8 @@ wcns_status wcns_destroy(wcns_ctx* c) {
     if (b) (void)hipFree(b);
   if (c->count) (void)hipFree(c->count);
   if (c->edge3) (void)hipFree(c->edge3);
+  if (c->run_G) (void)hipFree(c->run_G);
+  if (c->run_dev) (void)hipFree(c->run_dev);
   free(c);
   return WCNS_OK;
 }
@@ -258,6 +264,11 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   }
   alloc(&c->partial, 2 * (size_t)c->node_grid);
   alloc(&c->step, 8);
+  if (g->ndim == 1 && g->nx <= RUN1D_MAX_CELLS) {
+    alloc(&c->run_G, 12 * ((size_t)g->nx + 1));
+    if (st == WCNS_OK && hipMalloc((void**)&c->run_dev, sizeof(Run1D)) != hipSuccess)
+      st = WCNS_ERR_NOMEM;
+  }
   // Dirichlet ghost rows: x-lo, x-hi (ny each), y-lo, y-hi (nx each)
   const int R = 2 * g->ny + 2 * g->nx;
   alloc(&c->dirW, 6 * (size_t)R);
@@ -687,6 +698,51 @@ wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used)
     st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
     if (st != WCNS_OK) return st;
   }
+  return WCNS_OK;
+}
+
+wcns_status wcns_run(wcns_ctx* c, double* W, double t0, double t_end, double dt_fixed,
+                     int64_t max_steps, double* dts, int64_t dts_cap, int64_t* steps_out,
+                     double* t_out) {
+  if (!c || !W || !steps_out || !t_out || max_steps < 0 || dts_cap < 0) return WCNS_ERR_ARG;
+  if (dts_cap > 0 && !dts) return WCNS_ERR_ARG;
+  if (!c->run_dev) return WCNS_ERR_ARG;   // 1D grids of at most RUN1D_MAX_CELLS cells only
+  if (!isfinite(t0) || !isfinite(t_end) || !(dt_fixed >= 0.0) || !isfinite(dt_fixed))
+    return WCNS_ERR_CFL;
+  Run1D r;
+  memset(&r, 0, sizeof(r));
+  r.a = c->base;
+  r.a.W = W;
+  r.a.P = c->P;
+  r.U1 = c->U1;
+  r.U2 = c->U2;
+  r.P = c->P;
+  r.G = c->run_G;
+  r.damax = c->damax;
+  r.dts = dts;
+  r.dts_cap = dts_cap;
+  r.t = t0;
+  r.t_end = t_end;
+  r.dt_fixed = dt_fixed;
+  r.cfl = c->params.cfl;
+  r.max_steps = max_steps;
+  HIP_TRY(hipMemcpyAsync(c->run_dev, &r, sizeof(r), hipMemcpyHostToDevice, c->stream));
+  const bool d = diri(c, 0), b32 = c->precision == WCNS_FP32_BULK;
+  {
+    ProfScope ps(c, PROF_OTHER);
+    if (b32) {
+      if (d) hipLaunchKernelGGL((k_run1d<true, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+      else hipLaunchKernelGGL((k_run1d<false, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+    } else {
+      if (d) hipLaunchKernelGGL((k_run1d<true, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+      else hipLaunchKernelGGL((k_run1d<false, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+    }
+  }
+  LAUNCH_CHECK();
+  HIP_TRY(hipMemcpyAsync(&r, c->run_dev, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *steps_out = r.steps;
+  *t_out = r.t;
   return WCNS_OK;
 }
 

@@ -61,7 +61,7 @@ _lib = None
 EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
            "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
            "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
-           "wcns_selftest_division", "wcns_selftest_division_by", "wcns_batch_create", "wcns_batch_reset",
+           "wcns_selftest_division", "wcns_selftest_division_by", "wcns_run", "wcns_batch_create", "wcns_batch_reset",
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
            "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
            "wcns_batch_steps_left", "wcns_prim_to_cons_n", "wcns_status_str"]
@@ -95,6 +95,8 @@ def lib():
         L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.wcns_selftest_division.argtypes = [dp, dp, dp, dp, C.c_int64, vp]
         L.wcns_selftest_division_by.argtypes = [dp, C.c_double, dp, dp, C.c_int64, vp]
+        L.wcns_run.argtypes = [vp, dp, C.c_double, C.c_double, C.c_double, C.c_int64, dp, C.c_int64,
+                               C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.wcns_batch_create.argtypes = [C.c_int32, C.POINTER(_Grid), C.POINTER(_Eos), C.POINTER(_Params),
                                         C.c_int32, C.POINTER(C.c_void_p), C.c_int64, C.POINTER(vp)]
         L.wcns_batch_reset.argtypes = [vp, C.c_int32, C.POINTER(_Grid), C.POINTER(C.c_void_p)]
@@ -297,6 +299,18 @@ class Solver:
                 steps += 1
                 dt_last = dt
         return steps, t
+
+    def run(self, W, t_end, t=0.0, dt_fixed=0.0, max_steps=1 << 40, dts=None):
+        """1D grids of at most 4096 cells: the whole time loop to t_end in
+        one device launch (wcns_run); W in place.  dts: optional device f64
+        tensor receiving the dt of each step.  Returns (steps, t)."""
+        self._chk(W)
+        n = C.c_int64(0)
+        tt = C.c_double(0.0)
+        cap = 0 if dts is None else dts.numel()
+        _check(lib().wcns_run(self._ctx, _ptr(W), float(t), float(t_end), float(dt_fixed),
+                              int(max_steps), _ptr(dts), cap, C.byref(n), C.byref(tt)), "wcns_run")
+        return int(n.value), tt.value
 
     def max_wavespeed(self, W, out=None):
         import torch
