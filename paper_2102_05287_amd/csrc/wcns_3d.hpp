@@ -556,7 +556,7 @@ __global__ __launch_bounds__(256) void k3_finalize(const double* partial, int nb
 
 // x pass: one wave per tile of tile_x flattened cells (rows of nx); lanes
 // past the tile own the right faces of its row segments (as in 2D)
-__global__ __launch_bounds__(64) void k3_sweep_x(K3Args a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k3_sweep_x(K3Args a) {
   const int lane = threadIdx.x;
   const int nx = a.nx;
   const long N = (long)nx * a.ny * a.nz;
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(64) void k3_sweep_x(K3Args a) {
 // G^- of face row k+1 through LDS; the tile's first G^- and last G^+ go to
 // the edge buffer for k3_fixup.
 template <int DIR>
-__global__ __launch_bounds__(64 * YW3) void k3_sweep_l(K3Args a) {
+__global__ __launch_bounds__(64 * YW3) __attribute__((amdgpu_waves_per_eu(3))) void k3_sweep_l(K3Args a) {
   __shared__ double sGm[YW3][7][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long plane = (long)a.nx * a.ny;
