@@ -38,6 +38,7 @@ struct wcns_ctx {
   double* run_G;
   Run1D* run_dev;
   int node_grid, tile_x, x_grid, nbr;
+  int x_lds, xl_grid;   // x-sweep with LDS windows (rows of >= XLDS_MIN_NX cells)
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
   hipEvent_t* ev;
@@ -242,6 +243,8 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   c->tile_x = pick_tile_x(g->nx);
   a.tile_x = c->tile_x;
   c->x_grid = (int)((c->N + c->tile_x - 1) / c->tile_x);
+  c->x_lds = g->nx >= XLDS_MIN_NX;
+  c->xl_grid = (int)(((long)g->ny * ((g->nx + XC - 1) / XC) + XW - 1) / XW);
   long ng = (c->N + 255) / 256;
 #ifndef WCNS_NODE_GRID_CAP
 #define WCNS_NODE_GRID_CAP 2048
@@ -578,6 +581,17 @@ static bool diri(const wcns_ctx* c, int dir) {
   return c->grid.bc[2 * dir] == WCNS_BC_DIRICHLET || c->grid.bc[2 * dir + 1] == WCNS_BC_DIRICHLET;
 }
 
+// the x-sweep of arguments `a`: LDS windows for rows of >= XLDS_MIN_NX cells,
+// the flattened tiling otherwise
+#define XSWEEP(HT, DI, BF)                                                                   \
+  do {                                                                                       \
+    if (c->x_lds)                                                                            \
+      hipLaunchKernelGGL((k_sweep_xl<HT, DI, BF>), dim3(c->xl_grid), dim3(64 * XW), 0,       \
+                         c->stream, a);                                                      \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_sweep_x<HT, DI, BF>), dim3(c->x_grid), dim3(64), 0, c->stream, a); \
+  } while (0)
+
 // x-sweep and (2D) y-sweep of state W into `out`; mode STORE (L) or RK.
 static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int mode,
                                  const double* Un, double ca, double cb) {
@@ -596,11 +610,11 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
     ProfScope ps(c, PROF_X);
     const bool d = diri(c, 0);
     if (b32) {
-      if (d) hipLaunchKernelGGL((k_sweep_x<false, true, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
-      else hipLaunchKernelGGL((k_sweep_x<false, false, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      if (d) XSWEEP(false, true, true);
+      else XSWEEP(false, false, true);
     } else {
-      if (d) hipLaunchKernelGGL((k_sweep_x<false, true, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
-      else hipLaunchKernelGGL((k_sweep_x<false, false, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      if (d) XSWEEP(false, true, false);
+      else XSWEEP(false, false, false);
     }
     LAUNCH_CHECK();
     return WCNS_OK;
@@ -614,11 +628,11 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
     ProfScope ps(c, PROF_X);
     const bool d = diri(c, 0);
     if (b32) {
-      if (d) hipLaunchKernelGGL((k_sweep_x<true, true, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
-      else hipLaunchKernelGGL((k_sweep_x<true, false, true>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      if (d) XSWEEP(true, true, true);
+      else XSWEEP(true, false, true);
     } else {
-      if (d) hipLaunchKernelGGL((k_sweep_x<true, true, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
-      else hipLaunchKernelGGL((k_sweep_x<true, false, false>), dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      if (d) XSWEEP(true, true, false);
+      else XSWEEP(true, false, false);
     }
   }
   LAUNCH_CHECK();

@@ -140,7 +140,7 @@ __device__ __forceinline__ void load_node(const KArgs& a, const Sten& st, int m,
   q.c = ldc(a.Pc[3], o);
   q.h = ldc(a.Pc[4], o);
   if (DIRI && ((st.diri >> m) & 1u)) {
-    const int r = st.drow[g0 + m < 0 ? 0 : 1];
+    const int r = (g0 + m < 0) ? st.drow[0] : st.drow[1];
 #pragma unroll
     for (int k = 0; k < 6; ++k) Y[k] = a.dirW[r * 6 + k];
     u = a.dirP[r * 5 + 0];
@@ -173,24 +173,60 @@ __device__ __forceinline__ double char_field(int f, const NodeQ& q, double fa1, 
   }
 }
 
+// Node loaders of the face pipeline: ld(m, q) fills node m (0..5 = i-2 ..
+// i+3) of the face in the sweep's rotated frame.
+// From global memory through the face's stencil offsets:
+template <int DIR, bool HAS_T, bool DIRI>
+struct GlobalLoad {
+  const KArgs* a;
+  Sten st;
+  int g0;
+  __device__ __forceinline__ void operator()(int m, NodeQ& q) const {
+    load_node<DIR, HAS_T, DIRI>(*a, st, m, g0, q);
+  }
+};
+
+// From a y-tile staged in LDS: value c (0..5 state, 6..10 node primitives)
+// of tile row r, column `lane` at tile[(c * rows + r) * 64 + lane]; node m of
+// the face of wave w is tile row w + m.  Ghost rows are staged already
+// mapped (reflective ones with the wall-normal momentum and velocity
+// negated), so the node comes out as load_node would give it.
+struct LdsLoadY {
+  const double* tile;
+  int rows, w, lane;
+  __device__ __forceinline__ void operator()(int m, NodeQ& q) const {
+    const double* t = tile + (w + m) * 64 + lane;
+    const int cs = rows * 64;
+    q.w[0] = t[0];
+    q.w[1] = t[cs];
+    q.w[2] = t[3 * cs];        // rho v: normal momentum of the y frame
+    q.w[3] = t[2 * cs];
+    q.w[4] = t[4 * cs];
+    q.w[5] = t[5 * cs];
+    q.ut = t[6 * cs];
+    q.un = t[7 * cs];
+    q.p = t[8 * cs];
+    q.c = t[9 * cs];
+    q.h = t[10 * cs];
+  }
+};
+
 // One face i+1/2 of a sweep: WCNS steps 1-9 [Sec. 4.2] with the
 // interpolation limiter [Sec. 5.1] and the flux limiter [Sec. 5.2].
-// Stencil nodes i-2 .. i+3 are g0 .. g0+5 along the line.  Node data are
-// re-read from the cache in each phase (phase_barrier) to keep the live
-// register set small.
-template <int DIR, bool HAS_T, bool DIRI, bool B32 = false>
-__device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, double lam,
-                                            double Gm[6], double Gp[6]) {
+// Node data are re-read (from the cache or the LDS tile) in each phase
+// (phase_barrier) to keep the live register set small.
+template <int DIR, bool HAS_T, bool B32, class LD>
+__device__ __forceinline__ double face_flux_core(const KArgs& a, const LD& ld, double lam,
+                                                 double Gm[6], double Gp[6]) {
   const EosC& e = a.eos;
-  const Sten st = make_sten<DIR>(a, line, g0);
   // first-order HLLC flux from W_i, W_{i+1} and its split [Sec. 3.2];
   // face averages for the projection [Sec. 4.2; App. A]
   double Hm[6], Hp[6];
   double fa1, fa2, frho, fc, k1, k2;
   {
     NodeQ nl, nr;
-    load_node<DIR, HAS_T, DIRI>(a, st, 2, g0, nl);
-    load_node<DIR, HAS_T, DIRI>(a, st, 3, g0, nr);
+    ld(2, nl);
+    ld(3, nr);
     HllcOut h1;
     hllc<HAS_T>(nl, nr, h1);
 #pragma unroll
@@ -239,7 +275,7 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
 #pragma unroll
   for (int m = 0; m < 6; ++m) {
     NodeQ q;
-    load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+    ld(m, q);
     ra[m] = q.un;
     rb[m] = q.p;
   }
@@ -250,7 +286,7 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       NodeQ q;
-      load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+      ld(m, q);
       na[m] = q.w[0];
       nb[m] = q.w[1];
       np[m] = q.p;
@@ -273,7 +309,7 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       NodeQ q;
-      load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+      ld(m, q);
       nt[m] = q.ut;
       nw[m] = q.w[5];
     }
@@ -301,7 +337,7 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       NodeQ q;
-      load_node<DIR, HAS_T, DIRI>(a, st, m, g0, q);
+      ld(m, q);
       u[m] = char_field(f, q, fa1, fa2, k1, k2);
     }
     if constexpr (B32) {
@@ -378,10 +414,10 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
   // interpolation limiter toward W_i (left value) and W_{i+1} (right value)
   if (a.interp_limiter) {
     NodeQ q;
-    load_node<DIR, HAS_T, DIRI>(a, st, 2, g0, q);
+    ld(2, q);
     interp_limit<HAS_T>(e, a.tol, q.w, q.h, WL);
     phase_barrier();
-    load_node<DIR, HAS_T, DIRI>(a, st, 3, g0, q);
+    ld(3, q);
     interp_limit<HAS_T>(e, a.tol, q.w, q.h, WR);
     phase_barrier();
   }
@@ -426,8 +462,8 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
     phase_barrier();
     const int ma = 2 - pr, mb = 3 + pr;
     NodeQ qa, qb;
-    load_node<DIR, HAS_T, DIRI>(a, st, ma, g0, qa);
-    load_node<DIR, HAS_T, DIRI>(a, st, mb, g0, qb);
+    ld(ma, qa);
+    ld(mb, qb);
     double ga[6], gb[6];
     node_flux<HAS_T>(qa, ga);
     node_flux<HAS_T>(qb, gb);
@@ -454,8 +490,8 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
   // split fluxes G^{-+} [Sec. 3.2, WCNS step 9] and the flux limiter
   phase_barrier();
   NodeQ nl, nr;
-  load_node<DIR, HAS_T, DIRI>(a, st, 2, g0, nl);
-  load_node<DIR, HAS_T, DIRI>(a, st, 3, g0, nr);
+  ld(2, nl);
+  ld(3, nr);
 #pragma unroll
   for (int v = 0; v < 5; ++v) { Gm[v] = acc[v]; Gp[v] = acc[v]; }
   Gm[5] = acc[5] - nl.w[5] * uh;
@@ -469,6 +505,16 @@ __device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, do
     return flux_limit<HAS_T>(e, a.tol, nl.w, nr.w, gl, gr, lam, Hm, Hp, Gm, Gp);
   }
   return 1.0;
+}
+
+// Stencil nodes i-2 .. i+3 are g0 .. g0+5 along the line, read from global
+// memory.
+template <int DIR, bool HAS_T, bool DIRI, bool B32 = false>
+__device__ __forceinline__ double face_flux(const KArgs& a, int line, int g0, double lam,
+                                            double Gm[6], double Gp[6]) {
+  const Sten st = make_sten<DIR>(a, line, g0);
+  const GlobalLoad<DIR, HAS_T, DIRI> ld{&a, st, g0};
+  return face_flux_core<DIR, HAS_T, B32>(a, ld, lam, Gm, Gp);
 }
 
 // map rotated flux component v of direction dir to the state index
@@ -766,6 +812,100 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   sweep_x_tile<HAS_T, DIRI, B32>(a, blockIdx.x);
 }
 
+// x-sweep with each wave's stencil window staged in LDS.  A wave takes one
+// chunk of XC = 63 cells of one row: lane t < 63 owns the left face of cell
+// x0 + t, lane 63 the right face of the chunk's last cell; the window holds
+// cells x0 - 3 .. x0 + 65 (69) x 11 values (state and node primitives), ghost
+// cells mapped while staging.  Rows in chunks avoid the row crossings of the
+// flattened tiling; rows narrower than XLDS_MIN_NX use the flattened kernel.
+constexpr int XW = 4, XC = 63, XWIN = XC + 6, XLDS_MIN_NX = 256;
+
+template <bool HAS_T>
+struct LdsLoadX {
+  const double* win;   // this wave's window [11][XWIN]
+  int lane;
+  __device__ __forceinline__ void operator()(int m, NodeQ& q) const {
+    const double* t = win + lane + m;
+    q.w[0] = t[0];
+    q.w[1] = t[XWIN];
+    q.w[2] = t[2 * XWIN];
+    q.w[3] = HAS_T ? t[3 * XWIN] : 0.0;
+    q.w[4] = t[4 * XWIN];
+    q.w[5] = t[5 * XWIN];
+    q.un = t[6 * XWIN];
+    q.ut = HAS_T ? t[7 * XWIN] : 0.0;
+    q.p = t[8 * XWIN];
+    q.c = t[9 * XWIN];
+    q.h = t[10 * XWIN];
+  }
+};
+
+template <bool HAS_T, bool DIRI, bool B32>
+__global__ __launch_bounds__(64 * XW) void k_sweep_xl(KArgs a) {
+  __shared__ double tile[XW][11 * XWIN];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nx = a.nx;
+  const int chunks = (nx + XC - 1) / XC;
+  const long wid = (long)blockIdx.x * XW + w;
+  const bool wave_on = wid < (long)a.ny * chunks;
+  const int j = wave_on ? (int)(wid / chunks) : 0;
+  const int x0 = (int)(wid % chunks) * XC;
+  double* win = tile[w];
+  if (wave_on) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int wc = lane + 64 * q;
+      const int g = x0 - 3 + wc;
+      // cells past nx + 2 are read by no face
+      if (wc < XWIN && g <= nx + 2) {
+        bool flip;
+        const int s = ghost_src(g, nx, a.bc[0], a.bc[1], flip);
+        double v[11];
+        if (DIRI && s < 0) {
+          const int r = a.dir_off[g < 0 ? 0 : 1] + j;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) v[c] = a.dirW[r * 6 + c];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) v[6 + c] = a.dirP[r * 5 + c];
+        } else {
+          const uint32_t o = ((uint32_t)j * (uint32_t)nx + (uint32_t)s) * 8u;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) v[c] = (!HAS_T && c == 3) ? 0.0 : ldc(a.Wc[c], o);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) v[6 + c] = (!HAS_T && c == 1) ? 0.0 : ldc(a.Pc[c], o);
+        }
+        if (flip) { v[2] = -v[2]; v[6] = -v[6]; }   // rho u and u change sign at the wall
+#pragma unroll
+        for (int c = 0; c < 11; ++c) win[c * XWIN + wc] = v[c];
+      }
+    }
+  }
+  __syncthreads();
+  const int f = x0 + lane;   // face between cells f-1 and f
+  const bool active = wave_on && f <= nx;
+  double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
+  if (active) {
+    const LdsLoadX<HAS_T> ld{win, lane};
+    face_flux_core<0, HAS_T, B32>(a, ld, a.step[1], Gm, Gp);
+  }
+  double Gr[6];
+#pragma unroll
+  for (int v = 0; v < 6; ++v) Gr[v] = __shfl(Gm[v], (lane + 1) & 63, 64);
+  const int i = x0 + lane;   // my cell; its right face is lane + 1
+  if (!wave_on || lane >= XC || i >= nx) return;
+  const long N = (long)nx * a.ny;
+  const long c = (long)j * nx + i;
+  double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    if (!HAS_T && v == 3) continue;
+    const double L = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
+    const int k = state_index(0, v, HAS_T);
+    if (HAS_T) dst[k * N + c] = L;
+    else write_cell(a, a.out, c, N, k, L);
+  }
+}
+
 // y-sweep: block = YW waves; wave w computes y-face row k = kb + w for 64
 // columns.  Cell row kb + w (w < YW-1) uses G^+ of its own face and G^- of
 // face row kb + w + 1 (through LDS).  The last face row of the tile leaves
@@ -812,10 +952,103 @@ __device__ __forceinline__ void sweep_y_tile(const KArgs& a, int bx, int by,
   }
 }
 
+// The same y-tile with its stencil rows staged in LDS first: rows kb-3 ..
+// kb+YW+1 (YW+5 rows) x 64 columns x 11 values (state and node primitives),
+// ghost rows mapped while staging; the face pipeline then reads every node
+// from LDS.  The tile's LDS is reused for the G^- exchange.
+template <int YW>
+constexpr int ytile_lds_doubles() { return 11 * (YW + 5) * 64; }
+
+template <int YW, bool DIRI, bool B32>
+__device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by, double* tile) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = bx * 64 + lane;
+  const int kb = by * YW;
+  const int k = kb + w;
+  const int nx = a.nx, ny = a.ny;
+  const long N = (long)nx * ny;
+  constexpr int ROWS = YW + 5;
+  // stage: tile row tr holds global row g = kb - 3 + tr; wave w stages rows
+  // w, w + YW, ... with all eleven loads of a row in flight together (rows
+  // past ny + 2 are read by no active face and are left unset)
+#pragma unroll
+  for (int q = 0; q < (ROWS + YW - 1) / YW; ++q) {
+    const int tr = w + q * YW;
+    const int g = kb - 3 + tr;
+    if (tr < ROWS && g <= ny + 2 && i < nx) {
+      bool flip;
+      const int s = ghost_src(g, ny, a.bc[2], a.bc[3], flip);
+      double v[11];
+      if (DIRI && s < 0) {
+        const int r = a.dir_off[g < 0 ? 2 : 3] + i;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = a.dirW[r * 6 + c];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v[6 + c] = a.dirP[r * 5 + c];
+      } else {
+        const uint32_t o = ((uint32_t)s * (uint32_t)nx + (uint32_t)i) * 8u;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = ldc(a.Wc[c], o);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v[6 + c] = ldc(a.Pc[c], o);
+      }
+      if (flip) { v[3] = -v[3]; v[7] = -v[7]; }   // rho v and v change sign at the wall
+#pragma unroll
+      for (int c = 0; c < 11; ++c) tile[(c * ROWS + tr) * 64 + lane] = v[c];
+    }
+  }
+  __syncthreads();
+  const bool active = i < nx && k <= ny;
+  double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
+  if (active) {
+    const LdsLoadY ld{tile, ROWS, w, lane};
+    face_flux_core<1, true, B32>(a, ld, a.step[2], Gm, Gp);
+  }
+  __syncthreads();   // every face has read the tile: reuse it for G^-
+  double (*sGm)[6][64] = reinterpret_cast<double (*)[6][64]>(tile);
+#pragma unroll
+  for (int v = 0; v < 6; ++v) sGm[w][v][lane] = Gm[v];
+  if (active) {
+    double* e = a.edge + (long)by * 12 * nx;
+    if (w == 0) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
+    }
+    if (w == YW - 1 || k == ny) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
+    }
+  }
+  __syncthreads();
+  const int j = k;
+  if (!active || w == YW - 1 || j >= ny) return;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    double L;
+    {
+      double Ly = hdiv(-(sGm[w + 1][v][lane] - Gp[v]), a.dy, a.rdy);
+      const int s = state_index(1, v, true);
+      L = a.Lx[s * N + (long)j * nx + i] + Ly;
+    }
+    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
+  }
+}
+
+// 1: y-tiles staged in LDS (measured 111 us against 127 us per 1024^2
+// launch, 126 VGPRs instead of 168 + 44 bytes of spills per lane)
+#ifndef WCNS_YLDS
+#define WCNS_YLDS 1
+#endif
+
 template <bool DIRI, bool B32>
 __global__ __launch_bounds__(64 * Y_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_y(KArgs a) {
+#if WCNS_YLDS
+  __shared__ double tile[ytile_lds_doubles<Y_WAVES>()];
+  sweep_y_tile_lds<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile);
+#else
   __shared__ double sGm[Y_WAVES][6][64];
   sweep_y_tile<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, sGm);
+#endif
 }
 
 // cell rows j = (b+1)*YW - 1 between y-tile b and b+1 (t: flat index over

@@ -143,6 +143,24 @@ def test_rhs_1d_sizes(n, seed):
     rhs_case(spec, dt=1e-8)
 
 
+@pytest.mark.parametrize("bc", [(pb.BC_PERIODIC,) * 2, (pb.BC_REFLECT,) * 2, (pb.BC_EXTRAP, pb.BC_REFLECT),
+                                (pb.BC_DIRICHLET, pb.BC_DIRICHLET)])
+def test_rhs_wide_rows_all_x_sides(bc):
+    """Rows of 256 cells and more take the x-sweep with LDS windows (chunks of
+    63 cells per wave, ghost cells mapped while staging): every x side kind,
+    ragged last chunk, 2D and 1D."""
+    rng = np.random.Generator(np.random.PCG64(91))
+    for spec in (pb.random_smooth_state(301, 37, 33), pb.random_smooth_state(257, 1, 34, ndim=1)):
+        spec.bc = tuple(bc) + tuple(spec.bc[2:])
+        if bc[0] == pb.BC_DIRICHLET:
+            nv = spec.nvar
+            rows = np.empty((spec.ny, nv))
+            rows[:] = spec.prim[:, :, 0].T
+            rows[:, 2] += rng.uniform(-50, 50, spec.ny)
+            spec.dirichlet_prim = [rows, spec.prim[:, 0, -1].copy(), None, None]
+        rhs_case(spec)
+
+
 def test_rhs_2d_degenerate_shapes():
     for nx, ny in ((1, 1), (1, 7), (9, 1)):
         spec = pb.random_smooth_state(nx, ny, 20 + nx, with_bubble=False, with_shock=False)
