@@ -38,7 +38,7 @@ struct wcns_ctx {
   double* run_G;
   Run1D* run_dev;
   int node_grid, tile_x, x_grid, nbr;
-  int x_lds, xl_grid;   // x-sweep with LDS windows (rows of >= XLDS_MIN_NX cells)
+  int x_lds, xl_grid;   // x-sweep with LDS windows (rows of >= XLDS_MIN_NX cells), its grid
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
   hipEvent_t* ev;
@@ -244,7 +244,7 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   a.tile_x = c->tile_x;
   c->x_grid = (int)((c->N + c->tile_x - 1) / c->tile_x);
   c->x_lds = g->nx >= XLDS_MIN_NX;
-  c->xl_grid = (int)(((long)g->ny * ((g->nx + XC - 1) / XC) + XW - 1) / XW);
+  c->xl_grid = (int)(((c->N + XT - 1) / XT + XW - 1) / XW);
   long ng = (c->N + 255) / 256;
 #ifndef WCNS_NODE_GRID_CAP
 #define WCNS_NODE_GRID_CAP 2048
@@ -914,6 +914,7 @@ struct wcns_batch {
   int32_t* d_live = nullptr;   // per-instance steps left (frozen at 0)
   int dt_cap = 0;
   int ytile = 4, order = 2;
+  bool x_lds = false;   // x-sweep with LDS windows (every instance has nx >= XLDS_MIN_NX)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool dirty = true;
@@ -1062,13 +1063,15 @@ static wcns_status batch_build(wcns_batch* b) {
       ka[(size_t)s * n + k] = x;
     }
   }
+  b->x_lds = true;
+  for (int k = 0; k < n; ++k) b->x_lds = b->x_lds && b->grids[k].nx >= XLDS_MIN_NX;
   for (int k : inst_order) {
     const wcns_grid& g = b->grids[k];
     const long N = (long)g.nx * g.ny;
     const int nblk = (int)((N + 255) / 256);
     for (int q = 0; q < nblk; ++q) tn.push_back({k, q, 0, 0});
-    const int T = ka[k].tile_x;
-    const long nt = (N + T - 1) / T;
+    // x tasks: one tile of tile_x cells, or XW window tiles of XT cells
+    const long nt = b->x_lds ? ((N + XT - 1) / XT + XW - 1) / XW : (N + ka[k].tile_x - 1) / ka[k].tile_x;
     for (long q = 0; q < nt; ++q) tx.push_back({k, (int)q, 0, 0});
     if (g.ndim == 2) {
       const int nbr = ka[k].nbr;
@@ -1121,16 +1124,25 @@ static void batch_stage_launches(wcns_batch* b, int s) {
   else
     hipLaunchKernelGGL(kb_node<false>, dim3(b->n_node), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_node);
   hipLaunchKernelGGL(kb_finalize, dim3(b->n), dim3(256), 0, b->stream, ka);
+  const Task* tx = b->d_tasks + b->o_x;
   if (b->ndim == 2) {
-    if (b32) hipLaunchKernelGGL((kb_sweep_x<true, true>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
-    else hipLaunchKernelGGL((kb_sweep_x<true, false>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
+    if (b->x_lds) {
+      if (b32) hipLaunchKernelGGL((kb_sweep_xl<true, true>), dim3(b->n_x), dim3(64 * XW), 0, b->stream, ka, tx);
+      else hipLaunchKernelGGL((kb_sweep_xl<true, false>), dim3(b->n_x), dim3(64 * XW), 0, b->stream, ka, tx);
+    } else {
+      if (b32) hipLaunchKernelGGL((kb_sweep_x<true, true>), dim3(b->n_x), dim3(64), 0, b->stream, ka, tx);
+      else hipLaunchKernelGGL((kb_sweep_x<true, false>), dim3(b->n_x), dim3(64), 0, b->stream, ka, tx);
+    }
     if (b32) hipLaunchKernelGGL((kb_sweep_y<YW, true>), dim3(b->n_y), dim3(64 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
     else hipLaunchKernelGGL((kb_sweep_y<YW, false>), dim3(b->n_y), dim3(64 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
     if (b->n_fix > 0)
       hipLaunchKernelGGL(kb_fixup<YW>, dim3(b->n_fix), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_fix);
+  } else if (b->x_lds) {
+    if (b32) hipLaunchKernelGGL((kb_sweep_xl<false, true>), dim3(b->n_x), dim3(64 * XW), 0, b->stream, ka, tx);
+    else hipLaunchKernelGGL((kb_sweep_xl<false, false>), dim3(b->n_x), dim3(64 * XW), 0, b->stream, ka, tx);
   } else {
-    if (b32) hipLaunchKernelGGL((kb_sweep_x<false, true>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
-    else hipLaunchKernelGGL((kb_sweep_x<false, false>), dim3(b->n_x), dim3(64), 0, b->stream, ka, b->d_tasks + b->o_x);
+    if (b32) hipLaunchKernelGGL((kb_sweep_x<false, true>), dim3(b->n_x), dim3(64), 0, b->stream, ka, tx);
+    else hipLaunchKernelGGL((kb_sweep_x<false, false>), dim3(b->n_x), dim3(64), 0, b->stream, ka, tx);
   }
 }
 

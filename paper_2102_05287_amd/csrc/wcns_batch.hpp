@@ -45,6 +45,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void kb
   sweep_x_tile<HAS_T, false, B32>(a, task.a);
 }
 
+// x-sweep with LDS windows: task.a = group of XW tiles of XT cells
+template <bool HAS_T, bool B32>
+__global__ __launch_bounds__(64 * XW) void kb_sweep_xl(const KArgs* ka, const Task* t) {
+  __shared__ double tile[XW][11 * XWIN];
+  const Task task = t[blockIdx.x];
+  const KArgs a = ka[task.inst];
+  if (frozen(a)) return;
+  const int w = threadIdx.x >> 6;
+  const long tl = (long)task.a * XW + w;
+  sweep_x_window<HAS_T, false, B32>(a, tl, tl * XT < (long)a.nx * a.ny, tile[w]);
+}
+
 template <int YW, bool B32>
 __global__ __launch_bounds__(64 * YW) __attribute__((amdgpu_waves_per_eu(3))) void kb_sweep_y(
     const KArgs* ka, const Task* t) {

@@ -555,6 +555,26 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Maxima over the per-block pairs (partial[2b], partial[2b+1]), b < nblk, of
+// this thread's share: eight pairs per round with all loads issued together
+// (fmax is exact, so the grouping does not change the result).
+__device__ __forceinline__ void partial_max(const double* partial, int nblk, double& mx, double& my) {
+  const double2* p2 = reinterpret_cast<const double2*>(partial);
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += 8 * (int)blockDim.x) {
+    double2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int b = b0 + k * (int)blockDim.x;
+      v[k] = b < nblk ? p2[b] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      mx = fmax(mx, v[k].x);
+      my = fmax(my, v[k].y);
+    }
+  }
+}
+
 // Node primitives (u, v, p, c, rho*ctilde^2) of every cell [Sec. 2] and the
 // per-block wave-speed maxima.  (A last-block reduction here instead of
 // k_finalize was measured 4x slower: its device-scope fence has to make the
@@ -597,10 +617,7 @@ __global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partia
 // block), so a whole step needs no host round trip.
 __global__ __launch_bounds__(256) void k_finalize(const double* partial, int nblk, FinArgs f) {
   double mx = 0.0, my = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-    mx = fmax(mx, partial[2 * b]);
-    my = fmax(my, partial[2 * b + 1]);
-  }
+  partial_max(partial, nblk, mx, my);
   mx = wave_max(mx);
   my = wave_max(my);
   __shared__ double red[2][4];
@@ -715,10 +732,7 @@ __device__ __forceinline__ void node_block(const KArgs& a, int blk) {
 // dt, sigma, lambda of one instance from its block maxima (one block)
 __device__ __forceinline__ void finalize_inst(const KArgs& a) {
   double mx = 0.0, my = 0.0;
-  for (int b = threadIdx.x; b < a.nblk; b += blockDim.x) {
-    mx = fmax(mx, a.partial[2 * b]);
-    my = fmax(my, a.partial[2 * b + 1]);
-  }
+  partial_max(a.partial, a.nblk, mx, my);
   mx = wave_max(mx);
   my = wave_max(my);
   __shared__ double red[2][4];
@@ -812,20 +826,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
   sweep_x_tile<HAS_T, DIRI, B32>(a, blockIdx.x);
 }
 
-// x-sweep with each wave's stencil window staged in LDS.  A wave takes one
-// chunk of XC = 63 cells of one row: lane t < 63 owns the left face of cell
-// x0 + t, lane 63 the right face of the chunk's last cell; the window holds
-// cells x0 - 3 .. x0 + 65 (69) x 11 values (state and node primitives), ghost
-// cells mapped while staging.  Rows in chunks avoid the row crossings of the
-// flattened tiling; rows narrower than XLDS_MIN_NX use the flattened kernel.
-constexpr int XW = 4, XC = 63, XWIN = XC + 6, XLDS_MIN_NX = 256;
+// x-sweep with each wave's stencil window staged in LDS.  Waves take
+// flattened (row-major) tiles of XT = 62 cells, which touch at most two rows
+// when nx >= XLDS_MIN_NX.  The window holds 11 values (state and node
+// primitives) per slot, ghost cells mapped while staging:
+//   segment A, first row j0: faces k0 .. eA (nA faces), cells k0-3 .. eA+2 in
+//              slots 0 .. nA+4;
+//   segment B, row j0+1 when the tile crosses a row end: faces 0 .. eB (nB
+//              faces), cells -3 .. eB+2 in slots nA+5 .. nA+nB+9.
+// Lane L < nA computes face k0+L from slots L .. L+5, lane nA <= L < nA+nB
+// face L-nA of row j0+1 from slots L+5 .. L+10.  A lane that does not hold
+// the last face of its row owns the cell to the right of its face, whose
+// right face is on lane L+1.
+constexpr int XW = 4, XT = 62, XWIN = XT + 12, XLDS_MIN_NX = 61;
 
 template <bool HAS_T>
 struct LdsLoadX {
   const double* win;   // this wave's window [11][XWIN]
-  int lane;
+  int base;            // slot of the face's first stencil node
   __device__ __forceinline__ void operator()(int m, NodeQ& q) const {
-    const double* t = win + lane + m;
+    const double* t = win + base + m;
     q.w[0] = t[0];
     q.w[1] = t[XWIN];
     q.w[2] = t[2 * XWIN];
@@ -840,35 +860,45 @@ struct LdsLoadX {
   }
 };
 
+// One tile per wave (`on` false: the wave only joins the block barrier).
 template <bool HAS_T, bool DIRI, bool B32>
-__global__ __launch_bounds__(64 * XW) void k_sweep_xl(KArgs a) {
-  __shared__ double tile[XW][11 * XWIN];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+__device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool on, double* win) {
+  const int lane = threadIdx.x & 63;
   const int nx = a.nx;
-  const int chunks = (nx + XC - 1) / XC;
-  const long wid = (long)blockIdx.x * XW + w;
-  const bool wave_on = wid < (long)a.ny * chunks;
-  const int j = wave_on ? (int)(wid / chunks) : 0;
-  const int x0 = (int)(wid % chunks) * XC;
-  double* win = tile[w];
-  if (wave_on) {
+  const long N = (long)nx * a.ny;
+  const long c0 = tile * XT;
+  int j0 = 0, k0 = 0, nA = 0, nB = 0;
+  if (on) {
+    const long c1 = (c0 + XT < N ? c0 + XT : N) - 1;
+    j0 = (int)(c0 / nx);
+    k0 = (int)(c0 - (long)j0 * nx);
+    const int j1 = (int)(c1 / nx);
+    const int e1 = (int)(c1 - (long)j1 * nx) + 1;   // last face of the tile in row j1
+    if (j1 == j0) {
+      nA = e1 - k0 + 1;
+    } else {
+      nA = nx - k0 + 1;
+      nB = e1 + 1;
+    }
+    const int slots = nA + 5 + (nB > 0 ? nB + 5 : 0);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int wc = lane + 64 * q;
-      const int g = x0 - 3 + wc;
-      // cells past nx + 2 are read by no face
-      if (wc < XWIN && g <= nx + 2) {
+      const int sl = lane + 64 * q;
+      if (sl < slots) {
+        const bool segA = sl < nA + 5;
+        const int j = segA ? j0 : j0 + 1;
+        const int g = segA ? k0 - 3 + sl : sl - nA - 8;
         bool flip;
-        const int s = ghost_src(g, nx, a.bc[0], a.bc[1], flip);
+        const int src = ghost_src(g, nx, a.bc[0], a.bc[1], flip);
         double v[11];
-        if (DIRI && s < 0) {
+        if (DIRI && src < 0) {
           const int r = a.dir_off[g < 0 ? 0 : 1] + j;
 #pragma unroll
           for (int c = 0; c < 6; ++c) v[c] = a.dirW[r * 6 + c];
 #pragma unroll
           for (int c = 0; c < 5; ++c) v[6 + c] = a.dirP[r * 5 + c];
         } else {
-          const uint32_t o = ((uint32_t)j * (uint32_t)nx + (uint32_t)s) * 8u;
+          const uint32_t o = ((uint32_t)j * (uint32_t)nx + (uint32_t)src) * 8u;
 #pragma unroll
           for (int c = 0; c < 6; ++c) v[c] = (!HAS_T && c == 3) ? 0.0 : ldc(a.Wc[c], o);
 #pragma unroll
@@ -876,25 +906,23 @@ __global__ __launch_bounds__(64 * XW) void k_sweep_xl(KArgs a) {
         }
         if (flip) { v[2] = -v[2]; v[6] = -v[6]; }   // rho u and u change sign at the wall
 #pragma unroll
-        for (int c = 0; c < 11; ++c) win[c * XWIN + wc] = v[c];
+        for (int c = 0; c < 11; ++c) win[c * XWIN + sl] = v[c];
       }
     }
   }
   __syncthreads();
-  const int f = x0 + lane;   // face between cells f-1 and f
-  const bool active = wave_on && f <= nx;
+  const bool active = lane < nA + nB;
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
-    const LdsLoadX<HAS_T> ld{win, lane};
+    const LdsLoadX<HAS_T> ld{win, lane < nA ? lane : lane + 5};
     face_flux_core<0, HAS_T, B32>(a, ld, a.step[1], Gm, Gp);
   }
   double Gr[6];
 #pragma unroll
   for (int v = 0; v < 6; ++v) Gr[v] = __shfl(Gm[v], (lane + 1) & 63, 64);
-  const int i = x0 + lane;   // my cell; its right face is lane + 1
-  if (!wave_on || lane >= XC || i >= nx) return;
-  const long N = (long)nx * a.ny;
-  const long c = (long)j * nx + i;
+  const bool owner = lane < nA - 1 || (lane >= nA && lane < nA + nB - 1);
+  if (!owner) return;
+  const long c = c0 + (lane < nA ? lane : lane - 1);
   double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
@@ -904,6 +932,15 @@ __global__ __launch_bounds__(64 * XW) void k_sweep_xl(KArgs a) {
     if (HAS_T) dst[k * N + c] = L;
     else write_cell(a, a.out, c, N, k, L);
   }
+}
+
+template <bool HAS_T, bool DIRI, bool B32>
+__global__ __launch_bounds__(64 * XW) void k_sweep_xl(KArgs a) {
+  __shared__ double tile[XW][11 * XWIN];
+  const int w = threadIdx.x >> 6;
+  const long t = (long)blockIdx.x * XW + w;
+  const long N = (long)a.nx * a.ny;
+  sweep_x_window<HAS_T, DIRI, B32>(a, t, t * XT < N, tile[w]);
 }
 
 // y-sweep: block = YW waves; wave w computes y-face row k = kb + w for 64

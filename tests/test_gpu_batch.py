@@ -22,12 +22,12 @@ def host(t):
     return t.cpu().numpy()
 
 
-def instances(k, small=True):
+def instances(k, small=True, sides=(16, 24, 33, 48, 64, 70, 96)):
     specs = []
     for i in range(k):
         s = pb.random_instance(i)
         if small:   # shrink to keep the test quick, keep the uneven mix
-            n = [16, 24, 33, 48, 64, 70, 96][i % 7]
+            n = sides[i % len(sides)]
             s2 = pb.ProblemSpec(s.name, 2, n, n, 0.0, 1.0, 0.0, 1.0, bc=s.bc)
             idx = ((np.arange(n) + 0.5) * s.nx / n).astype(int)
             s2.prim = np.ascontiguousarray(s.prim[:, idx][:, :, idx])
@@ -91,4 +91,45 @@ def test_autotune_picks_a_schedule():
     b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)
     best, times = wcns.autotune(b, trials=1)
     assert best in times and len(times) == 9
+    b.close()
+
+
+@pytest.mark.parametrize("precision", [wcns.FP64, wcns.FP32_BULK])
+def test_batch_wide_rows_window_x_sweep(precision):
+    """Every instance at least 61 cells wide: the batched x-sweep stages its
+    stencil windows in LDS (tiles of 62 cells crossing row ends); results
+    equal the single-solve path bit for bit and, in FP64, the oracle."""
+    specs = instances(6, sides=(61, 62, 64, 77, 96, 130))
+    W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
+    states = [dev(w) for w in W0]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states, precision=precision)
+    b.step(2)
+    for k, sp in enumerate(specs):
+        sol = wcns.Solver.from_spec(sp, precision=precision)
+        Wd = dev(W0[k])
+        for _ in range(2):
+            sol.step(Wd, 0.0)
+        ref = host(Wd)
+        assert np.array_equal(host(states[k]), ref), k
+        if precision == wcns.FP64:
+            s, W = oracle_setup(sp), W0[k]
+            for _ in range(2):
+                W, dt, bad = orc.ssprk3_step(s, W)
+            assert np.array_equal(ref, W), k
+    b.close()
+
+
+def test_batch_1d_window_x_sweep():
+    """1D instances of 61 cells and more through the windowed batched x-sweep
+    against the oracle."""
+    specs = [pb.water_air_shock_tube(n) for n in (61, 62, 200, 401)]
+    W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
+    states = [dev(w) for w in W0]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)
+    b.step(3)
+    for k, sp in enumerate(specs):
+        s, W = oracle_setup(sp), W0[k]
+        for _ in range(3):
+            W, dt, bad = orc.ssprk3_step(s, W)
+        assert np.array_equal(host(states[k]), W), k
     b.close()

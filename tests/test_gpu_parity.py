@@ -146,11 +146,13 @@ def test_rhs_1d_sizes(n, seed):
 @pytest.mark.parametrize("bc", [(pb.BC_PERIODIC,) * 2, (pb.BC_REFLECT,) * 2, (pb.BC_EXTRAP, pb.BC_REFLECT),
                                 (pb.BC_DIRICHLET, pb.BC_DIRICHLET)])
 def test_rhs_wide_rows_all_x_sides(bc):
-    """Rows of 256 cells and more take the x-sweep with LDS windows (chunks of
-    63 cells per wave, ghost cells mapped while staging): every x side kind,
-    ragged last chunk, 2D and 1D."""
+    """Rows of 61 cells and more take the x-sweep with LDS windows (tiles of
+    62 cells that cross row ends, ghost cells mapped while staging): every x
+    side kind, ragged last tile, the narrowest widths, 2D and 1D."""
     rng = np.random.Generator(np.random.PCG64(91))
-    for spec in (pb.random_smooth_state(301, 37, 33), pb.random_smooth_state(257, 1, 34, ndim=1)):
+    for spec in (pb.random_smooth_state(301, 37, 33), pb.random_smooth_state(61, 9, 35),
+                 pb.random_smooth_state(62, 5, 36), pb.random_smooth_state(125, 6, 37),
+                 pb.random_smooth_state(257, 1, 34, ndim=1), pb.random_smooth_state(61, 1, 38, ndim=1)):
         spec.bc = tuple(bc) + tuple(spec.bc[2:])
         if bc[0] == pb.BC_DIRICHLET:
             nv = spec.nvar
