@@ -179,11 +179,12 @@ wcns_status wcns_check_admissible(wcns_ctx* ctx, const double* W, long long* n_b
  * the context launches is bracketed by a pair of HIP events recorded on the
  * context's stream; wcns_profile_read synchronises the stream and returns,
  * per kernel class, the summed device time in milliseconds and the number of
- * launches since the last reset.  Classes (WCNS_NPROF = 6): 0 node
+ * launches since the last reset.  Classes (WCNS_NPROF = 7): 0 node
  * primitives + wave-speed maxima, 1 dt/lambda finalize, 2 x-sweep,
- * 3 y-sweep, 4 y-tile fixup, 5 other.  Enabling allocates the event pool (so it is not
+ * 3 y-sweep, 4 tile fixups, 5 other, 6 z-sweep (3D).  `ms` and `launches`
+ * hold WCNS_NPROF entries.  Enabling allocates the event pool (so it is not
  * graph-capturable); disabling releases it. */
-#define WCNS_NPROF 6
+#define WCNS_NPROF 7
 wcns_status wcns_profile(wcns_ctx* ctx, int32_t enable);
 wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
 

@@ -12,9 +12,12 @@
 //
 //   k3_node      primitives + block maxima of |u|+c, |v|+c, |w|+c
 //   k3_finalize  dt and the three-way split sigma, lambda (Sec. 3.3)
-//   k3_sweep_x   one wave per tile of 62 flattened cells along x: L_x
+//   k3_sweep_xl  x pass, one wave per flattened tile of 62 cells with its
+//                stencil window in LDS: L_x (k3_sweep_x, global loads, for
+//                rows narrower than 61 cells)
 //   k3_sweep_l   y-lines (per z slab) or z-lines: one block of YW3 waves over
-//                64 consecutive columns x YW3 face rows; the y pass adds L_y
+//                64 consecutive columns x YW3 face rows, stencil rows staged
+//                in LDS; the y pass adds L_y
 //                to L in place, the z pass finishes L = (L_x + L_y) + L_z and
 //                applies the SSP-RK3 stage combination
 //   k3_fixup     the cell rows between two tiles of a strided pass
@@ -25,6 +28,8 @@
 
 namespace wcns {
 
+// face rows per strided-pass block (4: an even share of the block's waves
+// on each SIMD; 6 measured 1.5x slower)
 #ifndef WCNS_YTILE3
 #define WCNS_YTILE3 4
 #endif
@@ -339,17 +344,84 @@ __device__ __forceinline__ int state_index3(int dir, int v) {
   return v == 2 ? 4 : (v == 3 ? 2 : 3);
 }
 
-// One face of a 3D sweep: WCNS steps 1-9 [Sec. 4.2] with both limiters.
+// Stencil node m from global memory (offsets and wall flips of a Sten3)
 template <int DIR>
-__device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, double lam,
-                                             double Gm[7], double Gp[7]) {
+struct GlobalLoad3 {
+  const K3Args* a;
+  Sten3 st;
+  __device__ __forceinline__ void operator()(int m, NodeQ3& q) const { load_node3<DIR>(*a, st, m, q); }
+};
+
+// Stencil node m from LDS: value c of node m at p[m * sm + c * sc], values in
+// the order w[0..6], un, ut, us, p, c, h of the sweep's frame
+struct LdsLoad3 {
+  const double* p;
+  int sm, sc;
+  __device__ __forceinline__ void operator()(int m, NodeQ3& q) const {
+    const double* t = p + m * sm;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) q.w[k] = t[k * sc];
+    q.un = t[7 * sc];
+    q.ut = t[8 * sc];
+    q.us = t[9 * sc];
+    q.p = t[10 * sc];
+    q.c = t[11 * sc];
+    q.h = t[12 * sc];
+  }
+};
+
+// Stencil node m from LDS holding 11 values per node (w[0..6], un, ut, us,
+// p); the sound speed and rho ctilde^2, which the face pipeline reads only at
+// the two nodes next to the face (m = 2, 3), come from registers.
+struct LdsLoad3C {
+  const double* p;
+  int sm, sc;
+  double c2, h2, c3, h3;
+  __device__ __forceinline__ void operator()(int m, NodeQ3& q) const {
+    const double* t = p + m * sm;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) q.w[k] = t[k * sc];
+    q.un = t[7 * sc];
+    q.ut = t[8 * sc];
+    q.us = t[9 * sc];
+    q.p = t[10 * sc];
+    q.c = m == 2 ? c2 : (m == 3 ? c3 : 0.0);
+    q.h = m == 2 ? h2 : (m == 3 ? h3 : 0.0);
+  }
+};
+
+// The 13 staged values of the cell at byte offset o in the frame of DIR,
+// normal momentum and velocity negated for a reflective ghost (the same
+// values load_node3 returns)
+template <int DIR>
+__device__ __forceinline__ void node_values3(const K3Args& a, uint32_t o, bool flip, double v[13]) {
+  double Y[7], P[6];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) Y[k] = ldc(a.Wc[k], o);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) P[k] = ldc(a.Pc[k], o);
+  v[0] = Y[0]; v[1] = Y[1]; v[5] = Y[5]; v[6] = Y[6];
+  if (DIR == 0) { v[2] = Y[2]; v[3] = Y[3]; v[4] = Y[4]; v[7] = P[0]; v[8] = P[1]; v[9] = P[2]; }
+  else if (DIR == 1) { v[2] = Y[3]; v[3] = Y[2]; v[4] = Y[4]; v[7] = P[1]; v[8] = P[0]; v[9] = P[2]; }
+  else { v[2] = Y[4]; v[3] = Y[2]; v[4] = Y[3]; v[7] = P[2]; v[8] = P[0]; v[9] = P[1]; }
+  v[10] = P[3];
+  v[11] = P[4];
+  v[12] = P[5];
+  if (flip) { v[2] = -v[2]; v[7] = -v[7]; }
+}
+
+// One face of a 3D sweep: WCNS steps 1-9 [Sec. 4.2] with both limiters, the
+// stencil nodes (in the frame of DIR) from the loader `ld`.
+template <int DIR, class LD>
+__device__ __forceinline__ double face_flux3_core(const K3Args& a, const LD& ld, double lam,
+                                                  double Gm[7], double Gp[7]) {
   const EosC& e = a.eos;
   double Hm[7], Hp[7];
   double fa1, fa2, frho, fc, k1, k2;
   {
     NodeQ3 nl, nr;
-    load_node3<DIR>(a, st, 2, nl);
-    load_node3<DIR>(a, st, 3, nr);
+    ld(2, nl);
+    ld(3, nr);
     HllcOut3 h1;
     hllc3(nl, nr, h1);
 #pragma unroll
@@ -377,7 +449,7 @@ __device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, d
 #pragma unroll
     for (int m = 0; m < 6; ++m) {
       NodeQ3 q;
-      load_node3<DIR>(a, st, m, q);
+      ld(m, q);
       u[m] = char_field3(f, q, fa1, fa2, k1, k2);
     }
     UL[f] = weno_is(u[0], u[1], u[2], u[3], u[4], a.tol.weno_eps);
@@ -414,10 +486,10 @@ __device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, d
   }
   if (a.interp_limiter) {
     NodeQ3 q;
-    load_node3<DIR>(a, st, 2, q);
+    ld(2, q);
     interp_limit3(e, a.tol, q.w, q.h, WL);
     phase_barrier();
-    load_node3<DIR>(a, st, 3, q);
+    ld(3, q);
     interp_limit3(e, a.tol, q.w, q.h, WR);
     phase_barrier();
   }
@@ -441,8 +513,8 @@ __device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, d
   for (int pr = 0; pr < 3; ++pr) {
     phase_barrier();
     NodeQ3 qa, qb;
-    load_node3<DIR>(a, st, 2 - pr, qa);
-    load_node3<DIR>(a, st, 3 + pr, qb);
+    ld(2 - pr, qa);
+    ld(3 + pr, qb);
     double ga[7], gb[7];
     node_flux3(qa, ga);
     node_flux3(qb, gb);
@@ -458,8 +530,8 @@ __device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, d
   // split fluxes G^{-+} [Sec. 3.2, WCNS step 9] and the flux limiter
   phase_barrier();
   NodeQ3 nl, nr;
-  load_node3<DIR>(a, st, 2, nl);
-  load_node3<DIR>(a, st, 3, nr);
+  ld(2, nl);
+  ld(3, nr);
 #pragma unroll
   for (int v = 0; v < 6; ++v) { Gm[v] = acc[v]; Gp[v] = acc[v]; }
   Gm[6] = acc[6] - nl.w[6] * uh;
@@ -473,6 +545,13 @@ __device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, d
     return flux_limit3(e, a.tol, nl.w, nr.w, gl, gr, lam, Hm, Hp, Gm, Gp);
   }
   return 1.0;
+}
+
+template <int DIR>
+__device__ __forceinline__ double face_flux3(const K3Args& a, const Sten3& st, double lam,
+                                             double Gm[7], double Gp[7]) {
+  const GlobalLoad3<DIR> ld{&a, st};
+  return face_flux3_core<DIR>(a, ld, lam, Gm, Gp);
 }
 
 // final write of one cell: L or the SSP-RK3 stage combination
@@ -596,14 +675,75 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k3
   for (int v = 0; v < 7; ++v) a.Lout[v * N + c] = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
 }
 
+// x pass with each wave's stencil window staged in LDS (rows of at least
+// XLDS_MIN_NX cells): flattened tiles of XT cells over the ny*nz rows with
+// the window geometry of the 2D sweep, 13 values per slot in the x frame.
+__global__ __launch_bounds__(64 * XW) void k3_sweep_xl(K3Args a) {
+  __shared__ double tile[XW][13 * XWIN];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nx = a.nx;
+  const long N = (long)nx * a.ny * a.nz;
+  const long tl = (long)blockIdx.x * XW + w;
+  double* win = tile[w];
+  XWin t{};
+  if (tl * XT < N) {
+    t = x_window(nx, N, tl);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int sl = lane + 64 * q;
+      if (sl < t.slots) {
+        int j, g;
+        t.slot_cell(sl, j, g);
+        bool flip;
+        const int src = ghost_src(g, nx, a.bc[0], a.bc[1], flip);
+        double v[13];
+        node_values3<0>(a, ((uint32_t)j * (uint32_t)nx + (uint32_t)src) * 8u, flip, v);
+#pragma unroll
+        for (int c = 0; c < 13; ++c) win[c * XWIN + sl] = v[c];
+      }
+    }
+  }
+  __syncthreads();
+  double Gm[7] = {0, 0, 0, 0, 0, 0, 0}, Gp[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (lane < t.nA + t.nB) {
+    const LdsLoad3 ld{win + t.base(lane), 1, XWIN};
+    face_flux3_core<0>(a, ld, a.step[1], Gm, Gp);
+  }
+  double Gr[7];
+#pragma unroll
+  for (int v = 0; v < 7; ++v) Gr[v] = __shfl(Gm[v], (lane + 1) & 63, 64);
+  if (!t.owner(lane)) return;
+  const long c = t.cell(lane);
+#pragma unroll
+  for (int v = 0; v < 7; ++v) a.Lout[v * N + c] = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
+}
+
 // Strided pass of direction DIR (1: y-lines in z slab blockIdx.z; 2: z-lines
-// over the nx*ny columns).  Wave w computes face row k = kb + w for 64
-// consecutive columns; cell row k (w < YW3-1) takes G^+ of its own face and
-// G^- of face row k+1 through LDS; the tile's first G^- and last G^+ go to
-// the edge buffer for k3_fixup.
-template <int DIR>
+// over the nx*ny columns).  The block first stages stencil rows kb-3 ..
+// kb+YW3+1 of its 64 consecutive columns in LDS (13 values per node in the
+// frame of DIR, ghost rows mapped while staging; wave w stages rows w,
+// w+YW3, ... with all loads of a row in flight together).  Wave w then
+// computes face row k = kb + w from LDS; cell row k (w < YW3-1) takes G^+ of
+// its own face and G^- of face row k+1 through LDS (the staged rows' space
+// reused); the tile's first G^- and last G^+ go to the edge buffer for
+// k3_fixup.
+// LDS: 0 every node loaded from global memory at its use instead; 1 all 13
+// values staged (60 KB per block, two blocks per CU); 2 11 values staged
+// (50.7 KB, three blocks per CU) and the sound speed and rho ctilde^2 of the
+// face's two centre nodes loaded from global memory into registers.
+// Measured at 256^3 (ms per y / z pass): 0: 2.62 / 2.99, 1: 2.12 / 2.45,
+// 2: 1.81 / 1.93.
+#ifndef WCNS_L3LDS_Y
+#define WCNS_L3LDS_Y 2
+#endif
+#ifndef WCNS_L3LDS_Z
+#define WCNS_L3LDS_Z 2
+#endif
+template <int DIR, int LDS>
 __global__ __launch_bounds__(64 * YW3) __attribute__((amdgpu_waves_per_eu(3))) void k3_sweep_l(K3Args a) {
-  __shared__ double sGm[YW3][7][64];
+  constexpr int ROWS = YW3 + 5;
+  constexpr int NV = LDS == 2 ? 11 : 13;
+  __shared__ double tile[LDS ? NV * ROWS * 64 : 7 * YW3 * 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long plane = (long)a.nx * a.ny;
   const long N = plane * a.nz;
@@ -617,11 +757,43 @@ __global__ __launch_bounds__(64 * YW3) __attribute__((amdgpu_waves_per_eu(3))) v
   const int by = blockIdx.y;
   const int k = by * YW3 + w;
   const bool active = col < ncol && k <= nline;
+  const int kb = by * YW3;
+#pragma unroll
+  for (int q = 0; q < (LDS ? (ROWS + YW3 - 1) / YW3 : 0); ++q) {
+    const int tr = w + q * YW3;
+    const int g = kb - 3 + tr;
+    // rows past nline + 2 are read by no active face and are left unset
+    if (tr < ROWS && g <= nline + 2 && col < ncol) {
+      bool flip;
+      const int s = ghost_src(g, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
+      double v[13];
+      node_values3<DIR>(a, (uint32_t)(slab + (long)s * stride + col) * 8u, flip, v);
+#pragma unroll
+      for (int c = 0; c < NV; ++c) tile[(c * ROWS + tr) * 64 + lane] = v[c];
+    }
+  }
+  if (LDS) __syncthreads();
   double Gm[7] = {0, 0, 0, 0, 0, 0, 0}, Gp[7] = {0, 0, 0, 0, 0, 0, 0};
   if (active) {
-    const Sten3 st = make_sten3(k - 3, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], slab + col, stride);
-    face_flux3<DIR>(a, st, a.step[1 + DIR], Gm, Gp);
+    if (LDS == 1) {
+      const LdsLoad3 ld{tile + w * 64 + lane, 64, ROWS * 64};
+      face_flux3_core<DIR>(a, ld, a.step[1 + DIR], Gm, Gp);
+    } else if (LDS == 2) {
+      bool flip;
+      const int s2 = ghost_src(k - 1, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
+      const int s3 = ghost_src(k, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
+      const uint32_t o2 = (uint32_t)(slab + (long)s2 * stride + col) * 8u;
+      const uint32_t o3 = (uint32_t)(slab + (long)s3 * stride + col) * 8u;
+      const LdsLoad3C ld{tile + w * 64 + lane, 64, ROWS * 64,
+                         ldc(a.Pc[4], o2), ldc(a.Pc[5], o2), ldc(a.Pc[4], o3), ldc(a.Pc[5], o3)};
+      face_flux3_core<DIR>(a, ld, a.step[1 + DIR], Gm, Gp);
+    } else {
+      const Sten3 st = make_sten3(k - 3, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], slab + col, stride);
+      face_flux3<DIR>(a, st, a.step[1 + DIR], Gm, Gp);
+    }
   }
+  if (LDS) __syncthreads();   // every face has read the tile: reuse it for G^-
+  double (*sGm)[7][64] = reinterpret_cast<double (*)[7][64]>(tile);
 #pragma unroll
   for (int v = 0; v < 7; ++v) sGm[w][v][lane] = Gm[v];
   if (active) {

@@ -76,7 +76,7 @@ struct ProfScope {
     if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
   }
 };
-enum { PROF_NODE = 0, PROF_FIN = 1, PROF_X = 2, PROF_Y = 3, PROF_FIX = 4, PROF_OTHER = 5 };
+enum { PROF_NODE = 0, PROF_FIN = 1, PROF_X = 2, PROF_Y = 3, PROF_FIX = 4, PROF_OTHER = 5, PROF_Z = 6 };
 
 #define HIP_TRY(x)                                   \
   do {                                               \
@@ -416,6 +416,8 @@ static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_p
   c->tile_x = pick_tile_x(g->nx);
   a.tile_x = c->tile_x;
   c->x_grid = (int)((N + c->tile_x - 1) / c->tile_x);
+  c->x_lds = g->nx >= XLDS_MIN_NX;
+  c->xl_grid = (int)(((N + XT - 1) / XT + XW - 1) / XW);
   const long ng = (N + 255) / 256;
   c->node_grid = (int)(ng < WCNS_NODE_GRID_CAP ? ng : WCNS_NODE_GRID_CAP);
   c->nbr_y3 = (g->ny + 1 + YW3 - 1) / YW3;
@@ -487,7 +489,10 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   const long nx = c->grid.nx, ny = c->grid.ny, nz = c->grid.nz;
   {
     ProfScope ps(c, PROF_X);
-    hipLaunchKernelGGL(k3_sweep_x, dim3(c->x_grid), dim3(64), 0, c->stream, a);
+    if (c->x_lds)
+      hipLaunchKernelGGL(k3_sweep_xl, dim3(c->xl_grid), dim3(64 * XW), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL(k3_sweep_x, dim3(c->x_grid), dim3(64), 0, c->stream, a);
   }
   LAUNCH_CHECK();
   K3Args ay = a;   // y pass: L = L_x + L_y in place
@@ -497,7 +502,7 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   ay.nbr = c->nbr_y3;
   {
     ProfScope ps(c, PROF_Y);
-    hipLaunchKernelGGL((k3_sweep_l<1>), dim3((unsigned)((nx + 63) / 64), c->nbr_y3, (unsigned)nz),
+    hipLaunchKernelGGL((k3_sweep_l<1, WCNS_L3LDS_Y>), dim3((unsigned)((nx + 63) / 64), c->nbr_y3, (unsigned)nz),
                        dim3(64 * YW3), 0, c->stream, ay);
   }
   LAUNCH_CHECK();
@@ -514,8 +519,8 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   az.last = 1;
   az.nbr = c->nbr_z3;
   {
-    ProfScope ps(c, PROF_Y);
-    hipLaunchKernelGGL((k3_sweep_l<2>), dim3((unsigned)((nx * ny + 63) / 64), c->nbr_z3, 1),
+    ProfScope ps(c, PROF_Z);
+    hipLaunchKernelGGL((k3_sweep_l<2, WCNS_L3LDS_Z>), dim3((unsigned)((nx * ny + 63) / 64), c->nbr_z3, 1),
                        dim3(64 * YW3), 0, c->stream, az);
   }
   LAUNCH_CHECK();

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(64 * XW) void kb_sweep_xl(const KArgs* ka, const Ta
 }
 
 template <int YW, bool B32>
-__global__ __launch_bounds__(64 * YW) __attribute__((amdgpu_waves_per_eu(3))) void kb_sweep_y(
+__global__ __launch_bounds__(64 * YW) __attribute__((amdgpu_waves_per_eu(YW >= 8 ? 4 : 3))) void kb_sweep_y(
     const KArgs* ka, const Task* t) {
 #if WCNS_YLDS
   __shared__ double tile[ytile_lds_doubles<YW>()];

@@ -31,10 +31,12 @@ namespace wcns {
 
 enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 enum { OUT_STORE = 0, OUT_RK = 1 };
-// y-face rows per y-sweep block (4 measured fastest against 2 and 8, and
-// against a one-wave form that marches up the rows)
+// y-face rows per y-sweep block: 8 with the LDS-staged tile of 9 values
+// (two 8-wave blocks per CU, four waves per SIMD; half the straddling cell
+// rows of 4-row tiles), measured 1.03x (FP64) and 1.09x (FP32 bulk) faster
+// per y-sweep + fixup than 4-row tiles
 #ifndef WCNS_YTILE
-#define WCNS_YTILE 4
+#define WCNS_YTILE 8
 #endif
 constexpr int Y_WAVES = WCNS_YTILE;
 
@@ -191,9 +193,14 @@ struct GlobalLoad {
 // the face of wave w is tile row w + m.  Ghost rows are staged already
 // mapped (reflective ones with the wall-normal momentum and velocity
 // negated), so the node comes out as load_node would give it.
+// With CH the tile holds values 0..8 only: the sound speed and rho ctilde^2,
+// which the face pipeline reads only at the two nodes next to the face
+// (m = 2, 3), come from registers.
+template <bool CH = false>
 struct LdsLoadY {
   const double* tile;
   int rows, w, lane;
+  double c2 = 0.0, h2 = 0.0, c3 = 0.0, h3 = 0.0;
   __device__ __forceinline__ void operator()(int m, NodeQ& q) const {
     const double* t = tile + (w + m) * 64 + lane;
     const int cs = rows * 64;
@@ -206,8 +213,13 @@ struct LdsLoadY {
     q.ut = t[6 * cs];
     q.un = t[7 * cs];
     q.p = t[8 * cs];
-    q.c = t[9 * cs];
-    q.h = t[10 * cs];
+    if (CH) {
+      q.c = m == 2 ? c2 : (m == 3 ? c3 : 0.0);
+      q.h = m == 2 ? h2 : (m == 3 ? h3 : 0.0);
+    } else {
+      q.c = t[9 * cs];
+      q.h = t[10 * cs];
+    }
   }
 };
 
@@ -860,34 +872,57 @@ struct LdsLoadX {
   }
 };
 
+// Geometry of window tile `tile` over N cells in rows of nx (nx >= XLDS_MIN_NX)
+struct XWin {
+  long c0;
+  int j0, k0, nA, nB, slots;
+  // row and in-row position (ghosts -3 .. nx+2) of window slot sl < slots
+  __device__ __forceinline__ void slot_cell(int sl, int& j, int& g) const {
+    const bool segA = sl < nA + 5;
+    j = segA ? j0 : j0 + 1;
+    g = segA ? k0 - 3 + sl : sl - nA - 8;
+  }
+  // first stencil slot of the face on lane L < nA + nB
+  __device__ __forceinline__ int base(int L) const { return L < nA ? L : L + 5; }
+  // lane L owns the cell right of its face (flat index cell(L)); its right face is on L + 1
+  __device__ __forceinline__ bool owner(int L) const { return L < nA - 1 || (L >= nA && L < nA + nB - 1); }
+  __device__ __forceinline__ long cell(int L) const { return c0 + (L < nA ? L : L - 1); }
+};
+
+__device__ __forceinline__ XWin x_window(int nx, long N, long tile) {
+  XWin t;
+  t.c0 = tile * XT;
+  const long c1 = (t.c0 + XT < N ? t.c0 + XT : N) - 1;
+  t.j0 = (int)(t.c0 / nx);
+  t.k0 = (int)(t.c0 - (long)t.j0 * nx);
+  const int j1 = (int)(c1 / nx);
+  const int e1 = (int)(c1 - (long)j1 * nx) + 1;   // last face of the tile in row j1
+  if (j1 == t.j0) {
+    t.nA = e1 - t.k0 + 1;
+    t.nB = 0;
+  } else {
+    t.nA = nx - t.k0 + 1;
+    t.nB = e1 + 1;
+  }
+  t.slots = t.nA + 5 + (t.nB > 0 ? t.nB + 5 : 0);
+  return t;
+}
+
 // One tile per wave (`on` false: the wave only joins the block barrier).
 template <bool HAS_T, bool DIRI, bool B32>
 __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool on, double* win) {
   const int lane = threadIdx.x & 63;
   const int nx = a.nx;
   const long N = (long)nx * a.ny;
-  const long c0 = tile * XT;
-  int j0 = 0, k0 = 0, nA = 0, nB = 0;
+  XWin t{};
   if (on) {
-    const long c1 = (c0 + XT < N ? c0 + XT : N) - 1;
-    j0 = (int)(c0 / nx);
-    k0 = (int)(c0 - (long)j0 * nx);
-    const int j1 = (int)(c1 / nx);
-    const int e1 = (int)(c1 - (long)j1 * nx) + 1;   // last face of the tile in row j1
-    if (j1 == j0) {
-      nA = e1 - k0 + 1;
-    } else {
-      nA = nx - k0 + 1;
-      nB = e1 + 1;
-    }
-    const int slots = nA + 5 + (nB > 0 ? nB + 5 : 0);
+    t = x_window(nx, N, tile);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int sl = lane + 64 * q;
-      if (sl < slots) {
-        const bool segA = sl < nA + 5;
-        const int j = segA ? j0 : j0 + 1;
-        const int g = segA ? k0 - 3 + sl : sl - nA - 8;
+      if (sl < t.slots) {
+        int j, g;
+        t.slot_cell(sl, j, g);
         bool flip;
         const int src = ghost_src(g, nx, a.bc[0], a.bc[1], flip);
         double v[11];
@@ -911,18 +946,17 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
     }
   }
   __syncthreads();
-  const bool active = lane < nA + nB;
+  const bool active = lane < t.nA + t.nB;
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
-    const LdsLoadX<HAS_T> ld{win, lane < nA ? lane : lane + 5};
+    const LdsLoadX<HAS_T> ld{win, t.base(lane)};
     face_flux_core<0, HAS_T, B32>(a, ld, a.step[1], Gm, Gp);
   }
   double Gr[6];
 #pragma unroll
   for (int v = 0; v < 6; ++v) Gr[v] = __shfl(Gm[v], (lane + 1) & 63, 64);
-  const bool owner = lane < nA - 1 || (lane >= nA && lane < nA + nB - 1);
-  if (!owner) return;
-  const long c = c0 + (lane < nA ? lane : lane - 1);
+  if (!t.owner(lane)) return;
+  const long c = t.cell(lane);
   double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
@@ -934,8 +968,12 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
   }
 }
 
+// waves per SIMD the windowed x-sweep is compiled for (VGPR budget 512 / this)
+#ifndef WCNS_XWPE
+#define WCNS_XWPE 4
+#endif
 template <bool HAS_T, bool DIRI, bool B32>
-__global__ __launch_bounds__(64 * XW) void k_sweep_xl(KArgs a) {
+__global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(WCNS_XWPE))) void k_sweep_xl(KArgs a) {
   __shared__ double tile[XW][11 * XWIN];
   const int w = threadIdx.x >> 6;
   const long t = (long)blockIdx.x * XW + w;
@@ -993,10 +1031,17 @@ __device__ __forceinline__ void sweep_y_tile(const KArgs& a, int bx, int by,
 // kb+YW+1 (YW+5 rows) x 64 columns x 11 values (state and node primitives),
 // ghost rows mapped while staging; the face pipeline then reads every node
 // from LDS.  The tile's LDS is reused for the G^- exchange.
-template <int YW>
-constexpr int ytile_lds_doubles() { return 11 * (YW + 5) * 64; }
+// 1: the y-tile stages 9 values per node and keeps the sound speed and
+// rho ctilde^2 of the face's two centre nodes in registers (LdsLoadY<true>)
+#ifndef WCNS_YCH
+#define WCNS_YCH 1
+#endif
+constexpr bool Y_CH = WCNS_YCH != 0;
 
-template <int YW, bool DIRI, bool B32>
+template <int YW, bool CH = Y_CH>
+constexpr int ytile_lds_doubles() { return (CH ? 9 : 11) * (YW + 5) * 64; }
+
+template <int YW, bool DIRI, bool B32, bool CH = Y_CH>
 __device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by, double* tile) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = bx * 64 + lane;
@@ -1031,14 +1076,34 @@ __device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by,
       }
       if (flip) { v[3] = -v[3]; v[7] = -v[7]; }   // rho v and v change sign at the wall
 #pragma unroll
-      for (int c = 0; c < 11; ++c) tile[(c * ROWS + tr) * 64 + lane] = v[c];
+      for (int c = 0; c < (CH ? 9 : 11); ++c) tile[(c * ROWS + tr) * 64 + lane] = v[c];
     }
   }
   __syncthreads();
   const bool active = i < nx && k <= ny;
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
-    const LdsLoadY ld{tile, ROWS, w, lane};
+    LdsLoadY<CH> ld{tile, ROWS, w, lane};
+    if (CH) {
+      // c and rho ctilde^2 of cell rows k-1 and k (ghost rows mapped)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int g = k - 1 + q;
+        bool flip;
+        const int s = ghost_src(g, ny, a.bc[2], a.bc[3], flip);
+        double c, h;
+        if (DIRI && s < 0) {
+          const int r = a.dir_off[g < 0 ? 2 : 3] + i;
+          c = a.dirP[r * 5 + 3];
+          h = a.dirP[r * 5 + 4];
+        } else {
+          const uint32_t o = ((uint32_t)s * (uint32_t)nx + (uint32_t)i) * 8u;
+          c = ldc(a.Pc[3], o);
+          h = ldc(a.Pc[4], o);
+        }
+        if (q == 0) { ld.c2 = c; ld.h2 = h; } else { ld.c3 = c; ld.h3 = h; }
+      }
+    }
     face_flux_core<1, true, B32>(a, ld, a.step[2], Gm, Gp);
   }
   __syncthreads();   // every face has read the tile: reuse it for G^-
@@ -1077,8 +1142,12 @@ __device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by,
 #define WCNS_YLDS 1
 #endif
 
+// waves per SIMD the y-sweep is compiled for (VGPR budget 512 / this)
+#ifndef WCNS_YWPE
+#define WCNS_YWPE (Y_WAVES >= 8 ? 4 : 3)
+#endif
 template <bool DIRI, bool B32>
-__global__ __launch_bounds__(64 * Y_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_y(KArgs a) {
+__global__ __launch_bounds__(64 * Y_WAVES) __attribute__((amdgpu_waves_per_eu(WCNS_YWPE))) void k_sweep_y(KArgs a) {
 #if WCNS_YLDS
   __shared__ double tile[ytile_lds_doubles<Y_WAVES>()];
   sweep_y_tile_lds<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile);

@@ -65,7 +65,7 @@ EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_strea
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
            "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
            "wcns_batch_steps_left", "wcns_prim_to_cons_n", "wcns_status_str"]
-PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other"]
+PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other", "sweep_z"]
 
 
 def lib():

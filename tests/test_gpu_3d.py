@@ -22,6 +22,19 @@ def test_rhs_3d_random_states(shape, seed):
     rhs_case(pb.random_smooth_state_3d(*shape, seed=seed))
 
 
+@pytest.mark.parametrize("shape,bc", [
+    ((61, 13, 8), (pb.BC_PERIODIC,) * 2 + (pb.BC_REFLECT, pb.BC_EXTRAP) + (pb.BC_EXTRAP, pb.BC_REFLECT)),
+    ((62, 7, 19), (pb.BC_REFLECT,) * 2 + (pb.BC_PERIODIC,) * 2 + (pb.BC_PERIODIC,) * 2),
+    ((97, 12, 6), (pb.BC_EXTRAP,) * 4 + (pb.BC_REFLECT,) * 2)])
+def test_rhs_3d_lds_windows_and_tiles(shape, bc):
+    """x pass with LDS windows (rows of 61 cells and more, tiles crossing row
+    and slab ends) under every x side kind; strided passes whose lines end
+    inside a staged tile (ragged last tile) or fill whole tiles."""
+    spec = pb.random_smooth_state_3d(*shape, seed=sum(shape))
+    spec.bc = bc
+    rhs_case(spec)
+
+
 def test_rhs_3d_degenerate_shapes():
     """one cell along an axis (periodic there) and short lines"""
     for shape in ((17, 9, 1), (1, 20, 30), (33, 1, 12), (3, 3, 3)):
