@@ -33,16 +33,34 @@ METRIC = "Mcell-updates/s per RHS, FP64 vs FP32/batched; solves/s and p99 latenc
 # FP64 VALU: 256 CUs x 64 lanes x 2.4 GHz = 39.3e12 issue slots/s
 # (78.6 TFLOP/s when every slot is an FMA counted as 2 flops)
 VALU_F64_SLOTS = 256 * 64 * 2.4e9
-W_DIV, W_SQRT = 11, 19   # VALU instructions of the IEEE FP64 divide / sqrt on gfx950
+# Issue cost of an IEEE FP64 divide and square root in FMA issue slots:
+# measured at start-up with the library's issue probe (wcns_issue_probe,
+# time per operation over the FMA's at equal work, median of 3 runs); the
+# VALU instruction counts of the compiler's sequences (11 and 19) until then.
+OP_WEIGHTS = {"div": 11.0, "sqrt": 19.0, "source": "VALU instruction count"}
 
 
-def weighted(c, w_div=W_DIV, w_sqrt=W_SQRT):
+def measure_weights():
+    import statistics
+    from paper_2102_05287_amd import wcns
+    runs = [wcns.issue_weights(4096) for _ in range(3)]
+    for op in ("div", "sqrt", "div_core"):
+        OP_WEIGHTS[op] = round(statistics.median(r["weights"][op] for r in runs), 2)
+    OP_WEIGHTS["source"] = "issue probe (wcns_issue_probe), median of 3"
+    OP_WEIGHTS["fma_slots_per_s"] = statistics.median(r["fma_slots_per_s"] for r in runs)
+
+
+def weighted(c, w_div=None, w_sqrt=None):
+    w_div = OP_WEIGHTS["div"] if w_div is None else w_div
+    w_sqrt = OP_WEIGHTS["sqrt"] if w_sqrt is None else w_sqrt
     return c["add"] + c["mul"] + c["cmp"] + w_div * c["div"] + w_sqrt * c["sqrt"]
 
 
-def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=W_DIV, w_sqrt=W_SQRT):
+def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=None, w_sqrt=None):
     """Algorithmic (issue-weighted) FP64 ops per launch of each kernel;
     w_div = w_sqrt = 1 gives the plain operation count."""
+    w_div = OP_WEIGHTS["div"] if w_div is None else w_div
+    w_sqrt = OP_WEIGHTS["sqrt"] if w_sqrt is None else w_sqrt
     with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
         oc = json.load(f)["counts"][scheme]
     face = weighted(oc["face"], w_div, w_sqrt)
@@ -249,7 +267,7 @@ def three_d_form(n=256, steps=10, warmup=2):
     with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
         oc = json.load(f)["counts"]["ppwcnsis_3d"]
     face = weighted(oc["face"])
-    diff = 7 * (1 + W_DIV)
+    diff = 7 * (1 + OP_WEIGHTS["div"])
     faces = (n + 1) * n * n
     ops_x = faces * face + cells * diff
     ops_y = faces * face + cells * (diff + 7)             # + L_x
@@ -266,7 +284,7 @@ def three_d_form(n=256, steps=10, warmup=2):
             "ms_per_step": el / steps * 1e3, "inadmissible_after": bad,
             "per_kernel_ms_per_rhs": {k: v[0] / nrhs for k, v in prof.items() if v[1]},
             "roofline": {"bound": "alu", "peak": VALU_F64_SLOTS / 1e12, "unit": "TFLOP/s",
-                         "face_ops_weighted": face, "kernels": roof}}
+                         "face_ops_weighted": face, "op_weights": dict(OP_WEIGHTS), "kernels": roof}}
 
 
 def time_to_solution_form():
@@ -415,6 +433,7 @@ def main():
     if args.form:
         import torch
         torch.cuda.set_device(0)
+        measure_weights()
         run = {"precision": lambda: precision_form(2048, 20, 3),
                "batched": lambda: batched_form(512, 200, 20),
                "serving": lambda: serving_form(300, 200.0, 64, 20),
@@ -434,6 +453,7 @@ def main():
     from paper_2102_05287_amd import wcns
 
     torch.cuda.set_device(0)
+    measure_weights()
     spec = pb.shock_bubble(args.n)
     sol = wcns.Solver.from_spec(spec)
     V = torch.from_numpy(spec.prim).cuda()
@@ -475,8 +495,10 @@ def main():
                 "frac_unweighted": ops1[dom] / avg_s / VALU_F64_SLOTS,
                 "avg_launch_ms": avg_s * 1e3,
                 "ops_per_launch": ops[dom],
-                "op_model": "oracle op count, div=11 and sqrt=19 VALU slots; peak = FP64 "
-                            "VALU issue rate 256 CU x 64 lanes x 2.4 GHz"}
+                "op_model": "oracle op count per face (tests/golden/opcount.json), divide "
+                            "and sqrt weighted by op_weights; peak = FP64 VALU issue rate "
+                            "256 CU x 64 lanes x 2.4 GHz",
+                "op_weights": dict(OP_WEIGHTS)}
     per_kernel = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
 
     # pure RHS rate (no stage combination) for reference

@@ -11,6 +11,7 @@
 #include "wcns_batch.hpp"
 #include "wcns_3d.hpp"
 #include "wcns_run1d.hpp"
+#include "wcns_probe.hpp"
 
 #include <algorithm>
 #include <vector>
@@ -586,16 +587,40 @@ static bool diri(const wcns_ctx* c, int dir) {
   return c->grid.bc[2 * dir] == WCNS_BC_DIRICHLET || c->grid.bc[2 * dir + 1] == WCNS_BC_DIRICHLET;
 }
 
-// the x-sweep of arguments `a`: LDS windows for rows of >= XLDS_MIN_NX cells,
-// the flattened tiling otherwise
-#define XSWEEP(HT, DI, BF)                                                                   \
+// the x-sweep of arguments `a`: LDS windows for rows of >= XLDS_MIN_NX cells
+// (XG blocks), the flattened tiling otherwise
+#define XSWEEP(HT, DI, BF, XG)                                                               \
   do {                                                                                       \
     if (c->x_lds)                                                                            \
-      hipLaunchKernelGGL((k_sweep_xl<HT, DI, BF>), dim3(c->xl_grid), dim3(64 * XW), 0,       \
-                         c->stream, a);                                                      \
+      hipLaunchKernelGGL((k_sweep_xl<HT, DI, BF>), dim3(XG), dim3(64 * XW), 0, c->stream, a); \
     else                                                                                     \
       hipLaunchKernelGGL((k_sweep_x<HT, DI, BF>), dim3(c->x_grid), dim3(64), 0, c->stream, a); \
   } while (0)
+
+#define XSWEEP_ALL(XG)                                \
+  do {                                                \
+    const bool d = diri(c, 0);                        \
+    if (b32) {                                        \
+      if (d) XSWEEP(true, true, true, XG);            \
+      else XSWEEP(true, false, true, XG);             \
+    } else {                                          \
+      if (d) XSWEEP(true, true, false, XG);           \
+      else XSWEEP(true, false, false, XG);            \
+    }                                                 \
+  } while (0)
+
+// y-sweep of tile rows [a.ytile0, a.ytile0 + rows) on stream s
+static void ysweep(const wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
+  dim3 gy((c->grid.nx + 63) / 64, rows);
+  const bool d = diri(c, 1);
+  if (b32) {
+    if (d) hipLaunchKernelGGL((k_sweep_y<true, true>), gy, dim3(64 * Y_WAVES), 0, s, a);
+    else hipLaunchKernelGGL((k_sweep_y<false, true>), gy, dim3(64 * Y_WAVES), 0, s, a);
+  } else {
+    if (d) hipLaunchKernelGGL((k_sweep_y<true, false>), gy, dim3(64 * Y_WAVES), 0, s, a);
+    else hipLaunchKernelGGL((k_sweep_y<false, false>), gy, dim3(64 * Y_WAVES), 0, s, a);
+  }
+}
 
 // x-sweep and (2D) y-sweep of state W into `out`; mode STORE (L) or RK.
 static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int mode,
@@ -615,11 +640,11 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
     ProfScope ps(c, PROF_X);
     const bool d = diri(c, 0);
     if (b32) {
-      if (d) XSWEEP(false, true, true);
-      else XSWEEP(false, false, true);
+      if (d) XSWEEP(false, true, true, c->xl_grid);
+      else XSWEEP(false, false, true, c->xl_grid);
     } else {
-      if (d) XSWEEP(false, true, false);
-      else XSWEEP(false, false, false);
+      if (d) XSWEEP(false, true, false, c->xl_grid);
+      else XSWEEP(false, false, false, c->xl_grid);
     }
     LAUNCH_CHECK();
     return WCNS_OK;
@@ -631,27 +656,12 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   a.Lx = lx;
   {
     ProfScope ps(c, PROF_X);
-    const bool d = diri(c, 0);
-    if (b32) {
-      if (d) XSWEEP(true, true, true);
-      else XSWEEP(true, false, true);
-    } else {
-      if (d) XSWEEP(true, true, false);
-      else XSWEEP(true, false, false);
-    }
+    XSWEEP_ALL(c->xl_grid);
   }
   LAUNCH_CHECK();
-  dim3 gy((c->grid.nx + 63) / 64, c->nbr);
   {
     ProfScope ps(c, PROF_Y);
-    const bool d = diri(c, 1);
-    if (b32) {
-      if (d) hipLaunchKernelGGL((k_sweep_y<true, true>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
-      else hipLaunchKernelGGL((k_sweep_y<false, true>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
-    } else {
-      if (d) hipLaunchKernelGGL((k_sweep_y<true, false>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
-      else hipLaunchKernelGGL((k_sweep_y<false, false>), gy, dim3(64 * Y_WAVES), 0, c->stream, a);
-    }
+    ysweep(c, a, b32, c->nbr, c->stream);
   }
   LAUNCH_CHECK();
   if (c->nbr > 1) {
@@ -852,6 +862,43 @@ wcns_status wcns_selftest_division_by(const double* a, double b, double* q_ieee,
                      q_core, (long)n);
   LAUNCH_CHECK();
   return WCNS_OK;
+}
+
+wcns_status wcns_issue_probe(int32_t op, int32_t iters, int32_t blocks, double* ms, void* stream) {
+  if (op < PROBE_FMA || op > PROBE_DIV_CORE || iters < 1 || !ms) return WCNS_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  int dev = 0, ncu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return WCNS_ERR_HIP;
+  if (blocks <= 0) blocks = 32 * ncu;   // 8 waves on each of 4 SIMDs per CU
+  double* out = nullptr;
+  if (hipMalloc((void**)&out, (size_t)blocks * 256 * sizeof(double)) != hipSuccess) return WCNS_ERR_NOMEM;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  wcns_status st = WCNS_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = WCNS_ERR_HIP;
+  const double c = 0.999999, d = 1e-6;
+  if (st == WCNS_OK) {
+    (void)hipEventRecord(e0, s);
+    switch (op) {
+      case PROBE_FMA: hipLaunchKernelGGL(k_issue_probe<PROBE_FMA>, dim3(blocks), dim3(256), 0, s, out, iters, c, d); break;
+      case PROBE_ADD: hipLaunchKernelGGL(k_issue_probe<PROBE_ADD>, dim3(blocks), dim3(256), 0, s, out, iters, c, d); break;
+      case PROBE_MUL: hipLaunchKernelGGL(k_issue_probe<PROBE_MUL>, dim3(blocks), dim3(256), 0, s, out, iters, c, d); break;
+      case PROBE_DIV: hipLaunchKernelGGL(k_issue_probe<PROBE_DIV>, dim3(blocks), dim3(256), 0, s, out, iters, c, 1.5); break;
+      case PROBE_SQRT: hipLaunchKernelGGL(k_issue_probe<PROBE_SQRT>, dim3(blocks), dim3(256), 0, s, out, iters, c, d); break;
+      default: hipLaunchKernelGGL(k_issue_probe<PROBE_DIV_CORE>, dim3(blocks), dim3(256), 0, s, out, iters, c, 1.5); break;
+    }
+    if (hipGetLastError() != hipSuccess) st = WCNS_ERR_HIP;
+    (void)hipEventRecord(e1, s);
+    float f = 0.0f;
+    if (st == WCNS_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&f, e0, e1) != hipSuccess))
+      st = WCNS_ERR_HIP;
+    *ms = f;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  return st;
 }
 
 wcns_status wcns_profile(wcns_ctx* c, int32_t enable) {

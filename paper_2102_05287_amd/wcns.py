@@ -61,7 +61,8 @@ _lib = None
 EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
            "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
            "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
-           "wcns_selftest_division", "wcns_selftest_division_by", "wcns_run", "wcns_batch_create", "wcns_batch_reset",
+           "wcns_selftest_division", "wcns_selftest_division_by", "wcns_issue_probe", "wcns_run",
+           "wcns_batch_create", "wcns_batch_reset",
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
            "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
            "wcns_batch_steps_left", "wcns_prim_to_cons_n", "wcns_status_str"]
@@ -95,6 +96,7 @@ def lib():
         L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
         L.wcns_selftest_division.argtypes = [dp, dp, dp, dp, C.c_int64, vp]
         L.wcns_selftest_division_by.argtypes = [dp, C.c_double, dp, dp, C.c_int64, vp]
+        L.wcns_issue_probe.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double), vp]
         L.wcns_run.argtypes = [vp, dp, C.c_double, C.c_double, C.c_double, C.c_int64, dp, C.c_int64,
                                C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.wcns_batch_create.argtypes = [C.c_int32, C.POINTER(_Grid), C.POINTER(_Eos), C.POINTER(_Params),
@@ -370,6 +372,39 @@ def selftest_division_by(a, b: float):
         return None
     _check(rc, "wcns_selftest_division_by")
     return qi, qc
+
+
+PROBE_OPS = {"fma": 0, "add": 1, "mul": 2, "div": 3, "sqrt": 4, "div_core": 5}
+
+
+def issue_probe(op: str, iters: int, blocks: int = 0) -> float:
+    """Device time (ms) of `iters` rounds of 8 independent chains of one FP64
+    operation per lane over a grid that fills every SIMD (wcns_issue_probe)."""
+    import torch
+    ms = C.c_double(0.0)
+    _check(lib().wcns_issue_probe(PROBE_OPS[op], int(iters), int(blocks), C.byref(ms),
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           "wcns_issue_probe")
+    return ms.value
+
+
+def issue_weights(iters: int = 2048) -> dict:
+    """Issue cost of each probed FP64 operation in FMA slots: its time over
+    the time of an FMA probe of equal work run just before it (so clock
+    changes between probes cancel), plus the measured FMA issue rate in
+    slots/s."""
+    for _ in range(4):                            # warm-up: code load, clocks up
+        issue_probe("fma", iters)
+    t, w = {}, {}
+    for op in PROBE_OPS:
+        tf = issue_probe("fma", iters)
+        t[op] = issue_probe(op, iters)
+        w[op] = t[op] / tf
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    lanes = 32 * props.multi_processor_count * 256
+    return {"weights": w, "fma_slots_per_s": lanes * 8.0 * iters / (t["fma"] / 1e3),
+            "ms": t, "iters": iters}
 
 
 def prim_to_cons(V, ndim, gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), W=None):
