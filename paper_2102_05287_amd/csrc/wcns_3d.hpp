@@ -15,11 +15,11 @@
 //   k3_sweep_xl  x pass, one wave per flattened tile of 62 cells with its
 //                stencil window in LDS: L_x (k3_sweep_x, global loads, for
 //                rows narrower than 61 cells)
-//   k3_sweep_l   y-lines (per z slab) or z-lines: one block of YW3 waves over
-//                64 consecutive columns x YW3 face rows, stencil rows staged
-//                in LDS; the y pass adds L_y
-//                to L in place, the z pass finishes L = (L_x + L_y) + L_z and
-//                applies the SSP-RK3 stage combination
+//   k3_sweep_l   y-lines (per z slab) or z-lines: one block over 32
+//                consecutive columns x 8 face rows (4 waves), stencil rows
+//                staged in LDS; the y pass adds L_y to L in place, the z
+//                pass finishes L = (L_x + L_y) + L_z and applies the SSP-RK3
+//                stage combination
 //   k3_fixup     the cell rows between two tiles of a strided pass
 #pragma once
 #include "wcns_kernels.hpp"
@@ -28,12 +28,18 @@
 
 namespace wcns {
 
-// face rows per strided-pass block (4: an even share of the block's waves
-// on each SIMD; 6 measured 1.5x slower)
-#ifndef WCNS_YTILE3
-#define WCNS_YTILE3 4
+// Strided-pass tiles: 32 columns x 8 face rows (4 waves, four blocks per
+// CU) or 64 columns x 4 face rows (one face row per wave; 6 rows measured
+// 1.5x slower: a 6-wave block cannot spread evenly over a CU's 4 SIMDs).
+#ifndef WCNS_L3CW
+#define WCNS_L3CW 32
 #endif
-constexpr int YW3 = WCNS_YTILE3;
+constexpr int L3_CW = WCNS_L3CW;
+#ifndef WCNS_YTILE3
+#define WCNS_YTILE3 (WCNS_L3CW == 32 ? 8 : 4)
+#endif
+constexpr int YW3 = WCNS_YTILE3;   // face rows per tile
+constexpr int L3_THREADS = L3_CW == 32 ? 32 * YW3 : 64 * YW3;
 
 struct K3Args {
   int32_t nx, ny, nz, tile_x;
@@ -740,10 +746,12 @@ __global__ __launch_bounds__(64 * XW) void k3_sweep_xl(K3Args a) {
 #define WCNS_L3LDS_Z 2
 #endif
 template <int DIR, int LDS>
-__global__ __launch_bounds__(64 * YW3) __attribute__((amdgpu_waves_per_eu(3))) void k3_sweep_l(K3Args a) {
+constexpr int tile3_doubles() { return LDS ? (LDS == 2 ? 11 : 13) * (YW3 + 5) * 64 : 7 * YW3 * 64; }
+
+template <int DIR, int LDS>
+__device__ __forceinline__ void sweep3_tile64(const K3Args& a, double* tile) {
   constexpr int ROWS = YW3 + 5;
   constexpr int NV = LDS == 2 ? 11 : 13;
-  __shared__ double tile[LDS ? NV * ROWS * 64 : 7 * YW3 * 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long plane = (long)a.nx * a.ny;
   const long N = plane * a.nz;
@@ -816,6 +824,106 @@ __global__ __launch_bounds__(64 * YW3) __attribute__((amdgpu_waves_per_eu(3))) v
     const double L = a.Lin[s * N + idx] + hdiv(-(sGm[w + 1][v][lane] - Gp[v]), h, rh);
     if (a.last) write_cell3(a, idx, N, s, L);
     else a.out[s * N + idx] = L;
+  }
+}
+
+// The strided tile on 32 columns: a block of YW3/2 waves covers 32
+// consecutive columns x YW3 face rows; lane (r = lane / 32, col = lane % 32)
+// of wave w computes face row kb + 2w + r.  Stencil rows kb-3 .. kb+YW3+1
+// are staged first (11 values per node in the frame of DIR; c and
+// rho ctilde^2 of the two centre nodes from global memory into registers).
+// Cell row kb + 2w takes G^- of face row kb + 2w + 1 from lane + 32 of its
+// own wave; cell row kb + 2w + 1 takes it from wave w + 1 through LDS; the
+// tile's first G^- and last G^+ go to the edge buffer for k3_fixup.  The
+// tile is 36.6 KB: four 4-wave blocks per CU.
+template <int DIR>
+__device__ __forceinline__ void sweep3_tile32(const K3Args& a, double* tile) {
+  constexpr int FR = YW3, W = YW3 / 2, ROWS = YW3 + 5;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane >> 5, cl = lane & 31;
+  const long plane = (long)a.nx * a.ny;
+  const long N = plane * a.nz;
+  const long ncol = DIR == 1 ? a.nx : plane;
+  const int nline = DIR == 1 ? a.ny : a.nz;
+  const long stride = DIR == 1 ? a.nx : plane;
+  const long slab = DIR == 1 ? (long)blockIdx.z * plane : 0;
+  const double h = DIR == 1 ? a.dy : a.dz;
+  const double rh = DIR == 1 ? a.rdy : a.rdz;
+  const long col = (long)blockIdx.x * 32 + cl;
+  const int by = blockIdx.y;
+  const int kb = by * FR;
+  const int fr = 2 * w + r;
+  const int k = kb + fr;
+  const bool active = col < ncol && k <= nline;
+  // stage: slot t = thread + 64W q holds tile row t / 32, column t % 32
+#pragma unroll
+  for (int q = 0; q < (ROWS * 32 + 64 * W - 1) / (64 * W); ++q) {
+    const int t = (int)threadIdx.x + 64 * W * q;
+    const int tr = t >> 5;
+    const long cc = (long)blockIdx.x * 32 + (t & 31);
+    const int g = kb - 3 + tr;
+    if (tr < ROWS && g <= nline + 2 && cc < ncol) {
+      bool flip;
+      const int s = ghost_src(g, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
+      double v[13];
+      node_values3<DIR>(a, (uint32_t)(slab + (long)s * stride + cc) * 8u, flip, v);
+#pragma unroll
+      for (int c = 0; c < 11; ++c) tile[(c * ROWS + tr) * 32 + (t & 31)] = v[c];
+    }
+  }
+  __syncthreads();
+  double Gm[7] = {0, 0, 0, 0, 0, 0, 0}, Gp[7] = {0, 0, 0, 0, 0, 0, 0};
+  if (active) {
+    bool flip;
+    const int s2 = ghost_src(k - 1, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
+    const int s3 = ghost_src(k, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
+    const uint32_t o2 = (uint32_t)(slab + (long)s2 * stride + col) * 8u;
+    const uint32_t o3 = (uint32_t)(slab + (long)s3 * stride + col) * 8u;
+    const LdsLoad3C ld{tile + fr * 32 + cl, 32, ROWS * 32,
+                       ldc(a.Pc[4], o2), ldc(a.Pc[5], o2), ldc(a.Pc[4], o3), ldc(a.Pc[5], o3)};
+    face_flux3_core<DIR>(a, ld, a.step[1 + DIR], Gm, Gp);
+  }
+  double Gn[7];   // G^- of face row k + 1 when r == 0 (same wave, upper half)
+#pragma unroll
+  for (int v = 0; v < 7; ++v) Gn[v] = __shfl(Gm[v], (lane + 32) & 63, 64);
+  __syncthreads();   // every face has read the tile: reuse it for G^-
+  double* sG = tile;   // [W][7][32]: G^- of each wave's lower face row
+  if (r == 0) {
+#pragma unroll
+    for (int v = 0; v < 7; ++v) sG[(w * 7 + v) * 32 + cl] = Gm[v];
+  }
+  if (active) {
+    double* e = a.edge + (((long)(DIR == 1 ? blockIdx.z : 0) * a.nbr + by) * 14) * ncol;
+    if (fr == 0) {
+#pragma unroll
+      for (int v = 0; v < 7; ++v) e[v * ncol + col] = Gm[v];
+    }
+    if (fr == FR - 1 || k == nline) {
+#pragma unroll
+      for (int v = 0; v < 7; ++v) e[(7 + v) * ncol + col] = Gp[v];
+    }
+  }
+  __syncthreads();
+  if (!active || fr == FR - 1 || k >= nline) return;
+  const long idx = slab + (long)k * stride + col;
+#pragma unroll
+  for (int v = 0; v < 7; ++v) {
+    const int s = state_index3(DIR, v);
+    const double up = r == 0 ? Gn[v] : sG[((w + 1) * 7 + v) * 32 + cl];
+    const double L = a.Lin[s * N + idx] + hdiv(-(up - Gp[v]), h, rh);
+    if (a.last) write_cell3(a, idx, N, s, L);
+    else a.out[s * N + idx] = L;
+  }
+}
+
+template <int DIR, int LDS>
+__global__ __launch_bounds__(L3_THREADS) __attribute__((amdgpu_waves_per_eu(L3_CW == 32 ? 4 : 3))) void k3_sweep_l(K3Args a) {
+  if constexpr (L3_CW == 32) {
+    __shared__ double tile32[11 * (YW3 + 5) * 32];
+    sweep3_tile32<DIR>(a, tile32);
+  } else {
+    __shared__ double tile[tile3_doubles<DIR, LDS>()];
+    sweep3_tile64<DIR, LDS>(a, tile);
   }
 }
 

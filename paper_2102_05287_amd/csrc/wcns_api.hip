@@ -503,8 +503,8 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   ay.nbr = c->nbr_y3;
   {
     ProfScope ps(c, PROF_Y);
-    hipLaunchKernelGGL((k3_sweep_l<1, WCNS_L3LDS_Y>), dim3((unsigned)((nx + 63) / 64), c->nbr_y3, (unsigned)nz),
-                       dim3(64 * YW3), 0, c->stream, ay);
+    hipLaunchKernelGGL((k3_sweep_l<1, WCNS_L3LDS_Y>), dim3((unsigned)((nx + L3_CW - 1) / L3_CW), c->nbr_y3, (unsigned)nz),
+                       dim3(L3_THREADS), 0, c->stream, ay);
   }
   LAUNCH_CHECK();
   if (c->nbr_y3 > 1) {
@@ -521,8 +521,8 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   az.nbr = c->nbr_z3;
   {
     ProfScope ps(c, PROF_Z);
-    hipLaunchKernelGGL((k3_sweep_l<2, WCNS_L3LDS_Z>), dim3((unsigned)((nx * ny + 63) / 64), c->nbr_z3, 1),
-                       dim3(64 * YW3), 0, c->stream, az);
+    hipLaunchKernelGGL((k3_sweep_l<2, WCNS_L3LDS_Z>), dim3((unsigned)((nx * ny + L3_CW - 1) / L3_CW), c->nbr_z3, 1),
+                       dim3(L3_THREADS), 0, c->stream, az);
   }
   LAUNCH_CHECK();
   if (c->nbr_z3 > 1) {
@@ -611,14 +611,14 @@ static bool diri(const wcns_ctx* c, int dir) {
 
 // y-sweep of tile rows [a.ytile0, a.ytile0 + rows) on stream s
 static void ysweep(const wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
-  dim3 gy((c->grid.nx + 63) / 64, rows);
+  dim3 gy((c->grid.nx + Y_CW - 1) / Y_CW, rows);
   const bool d = diri(c, 1);
   if (b32) {
-    if (d) hipLaunchKernelGGL((k_sweep_y<true, true>), gy, dim3(64 * Y_WAVES), 0, s, a);
-    else hipLaunchKernelGGL((k_sweep_y<false, true>), gy, dim3(64 * Y_WAVES), 0, s, a);
+    if (d) hipLaunchKernelGGL((k_sweep_y<true, true>), gy, dim3(Y_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_sweep_y<false, true>), gy, dim3(Y_THREADS), 0, s, a);
   } else {
-    if (d) hipLaunchKernelGGL((k_sweep_y<true, false>), gy, dim3(64 * Y_WAVES), 0, s, a);
-    else hipLaunchKernelGGL((k_sweep_y<false, false>), gy, dim3(64 * Y_WAVES), 0, s, a);
+    if (d) hipLaunchKernelGGL((k_sweep_y<true, false>), gy, dim3(Y_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_sweep_y<false, false>), gy, dim3(Y_THREADS), 0, s, a);
   }
 }
 

@@ -60,19 +60,11 @@ __global__ __launch_bounds__(64 * XW) void kb_sweep_xl(const KArgs* ka, const Ta
 template <int YW, bool B32>
 __global__ __launch_bounds__(64 * YW) __attribute__((amdgpu_waves_per_eu(YW >= 8 ? 4 : 3))) void kb_sweep_y(
     const KArgs* ka, const Task* t) {
-#if WCNS_YLDS
   __shared__ double tile[ytile_lds_doubles<YW>()];
-#else
-  __shared__ double sGm[YW][6][64];
-#endif
   const Task task = t[blockIdx.x];
   const KArgs a = ka[task.inst];
   if (frozen(a)) return;
-#if WCNS_YLDS
   sweep_y_tile_lds<YW, false, B32>(a, task.a, task.b, tile);
-#else
-  sweep_y_tile<YW, false, B32>(a, task.a, task.b, sGm);
-#endif
 }
 
 template <int YW>

@@ -6,11 +6,14 @@
 //               and |v|+c (Sec. 3.3 wave speeds).
 //   k_finalize  one block: global maxima -> dt (CFL), sigma, lambda (Sec. 3.3)
 //               kept on the device so a whole step can be graph-captured.
-//   k_sweep_x   one wave per tile of flattened (row-major) cells; each lane
-//               computes one x-face with the full per-face pipeline and the
-//               flux difference uses a cross-lane shuffle (no LDS).
-//   k_sweep_y   one block = R waves over 64 columns x R y-face rows; every
-//               face is computed once; neighbours exchanged through LDS; the
+//   k_sweep_xl  one wave per flattened (row-major) tile of 62 cells with its
+//               stencil window staged in LDS; each lane computes one x-face
+//               with the full per-face pipeline and the flux difference uses
+//               a cross-lane shuffle (k_sweep_x: the same tiling with global
+//               loads, for rows narrower than 61 cells).
+//   k_sweep_y   one block over 32 columns x 8 y-face rows (4 waves, two face
+//               rows each), stencil rows staged in LDS; every face is
+//               computed once; neighbours exchanged by shuffle and LDS; the
 //               epilogue sums L_x + L_y and (for a step) applies the SSP-RK3
 //               stage combination.
 //   k_fixup_y   finishes the cell rows that straddle two y-tiles.
@@ -196,14 +199,15 @@ struct GlobalLoad {
 // With CH the tile holds values 0..8 only: the sound speed and rho ctilde^2,
 // which the face pipeline reads only at the two nodes next to the face
 // (m = 2, 3), come from registers.
-template <bool CH = false>
+// (CW: columns of the tile; w: the face's row in the tile, lane: its column.)
+template <bool CH = false, int CW = 64>
 struct LdsLoadY {
   const double* tile;
   int rows, w, lane;
   double c2 = 0.0, h2 = 0.0, c3 = 0.0, h3 = 0.0;
   __device__ __forceinline__ void operator()(int m, NodeQ& q) const {
-    const double* t = tile + (w + m) * 64 + lane;
-    const int cs = rows * 64;
+    const double* t = tile + (w + m) * CW + lane;
+    const int cs = rows * CW;
     q.w[0] = t[0];
     q.w[1] = t[cs];
     q.w[2] = t[3 * cs];        // rho v: normal momentum of the y frame
@@ -981,56 +985,14 @@ __global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(WCNS_XW
   sweep_x_window<HAS_T, DIRI, B32>(a, t, t * XT < N, tile[w]);
 }
 
-// y-sweep: block = YW waves; wave w computes y-face row k = kb + w for 64
-// columns.  Cell row kb + w (w < YW-1) uses G^+ of its own face and G^- of
-// face row kb + w + 1 (through LDS).  The last face row of the tile leaves
-// G^+ in the edge buffer and the first one G^-; the fixup finishes the cell
-// row in between.
-template <int YW, bool DIRI, bool B32>
-__device__ __forceinline__ void sweep_y_tile(const KArgs& a, int bx, int by,
-                                             double (*sGm)[6][64]) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = bx * 64 + lane;
-  const int kb = by * YW;
-  const int k = kb + w;                   // my face row (between cells k-1 and k)
-  const int nx = a.nx, ny = a.ny;
-  const long N = (long)nx * ny;
-  const bool active = i < nx && k <= ny;
-  double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
-  if (active) face_flux<1, true, DIRI, B32>(a, i, k - 3, a.step[2], Gm, Gp);
-#pragma unroll
-  for (int v = 0; v < 6; ++v) sGm[w][v][lane] = Gm[v];
-  // tile edges for the fixup of the straddling cell rows
-  if (active) {
-    double* e = a.edge + (long)by * 12 * nx;
-    if (w == 0) {
-#pragma unroll
-      for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
-    }
-    if (w == YW - 1 || k == ny) {
-#pragma unroll
-      for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
-    }
-  }
-  __syncthreads();
-  const int j = k;   // cell row between face rows k and k+1
-  if (!active || w == YW - 1 || j >= ny) return;
-#pragma unroll
-  for (int v = 0; v < 6; ++v) {
-    double L;
-    {
-      double Ly = hdiv(-(sGm[w + 1][v][lane] - Gp[v]), a.dy, a.rdy);
-      const int s = state_index(1, v, true);
-      L = a.Lx[s * N + (long)j * nx + i] + Ly;
-    }
-    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
-  }
-}
-
-// The same y-tile with its stencil rows staged in LDS first: rows kb-3 ..
-// kb+YW+1 (YW+5 rows) x 64 columns x 11 values (state and node primitives),
-// ghost rows mapped while staging; the face pipeline then reads every node
-// from LDS.  The tile's LDS is reused for the G^- exchange.
+// y-sweep tile: block = YW waves; wave w computes y-face row k = kb + w for
+// 64 columns.  The block first stages stencil rows kb-3 .. kb+YW+1 (YW+5
+// rows) x 64 columns in LDS, ghost rows mapped while staging, and the face
+// pipeline reads every node from LDS (measured 111 against 127 us per
+// 1024^2 launch for per-node global loads).  Cell row kb + w (w < YW-1)
+// uses G^+ of its own face and G^- of face row kb + w + 1 through the
+// reused tile; the last face row of the tile leaves G^+ in the edge buffer
+// and the first one G^-; the fixup finishes the cell row in between.
 // 1: the y-tile stages 9 values per node and keeps the sound speed and
 // rho ctilde^2 of the face's two centre nodes in registers (LdsLoadY<true>)
 #ifndef WCNS_YCH
@@ -1136,25 +1098,137 @@ __device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by,
   }
 }
 
-// 1: y-tiles staged in LDS (measured 111 us against 127 us per 1024^2
-// launch, 126 VGPRs instead of 168 + 44 bytes of spills per lane)
-#ifndef WCNS_YLDS
-#define WCNS_YLDS 1
+// The y-tile on 32 columns: a block of FR/2 waves covers 32 columns x FR
+// face rows; lane (r = lane / 32, col = lane % 32) of wave w computes face
+// row kb + 2w + r.  Stencil rows kb-3 .. kb+FR+1 are staged first (9 values
+// per node, c and rho ctilde^2 of the two centre nodes from global memory,
+// as in the 64-column tile).  Cell row kb + 2w takes G^- of face row
+// kb + 2w + 1 from lane + 32 of its own wave (shuffle); cell row kb + 2w + 1
+// takes it from wave w + 1 through LDS; the tile's first G^- and last G^+
+// go to the edge buffer for the fixup.  Half the columns of the 64-column
+// tile at the same face rows: a quarter of the LDS per wave pair, so four
+// 4-wave blocks share a CU instead of two 8-wave ones.
+template <int FR, bool DIRI, bool B32>
+__device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, double* tile) {
+  constexpr int W = FR / 2;
+  constexpr int ROWS = FR + 5;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r = lane >> 5, col = lane & 31;
+  const int i = bx * 32 + col;
+  const int kb = by * FR;
+  const int fr = 2 * w + r;
+  const int k = kb + fr;
+  const int nx = a.nx, ny = a.ny;
+  const long N = (long)nx * ny;
+  // stage: slot t = thread + 64W q holds tile row t / 32, column t % 32
+#pragma unroll
+  for (int q = 0; q < (ROWS * 32 + 64 * W - 1) / (64 * W); ++q) {
+    const int t = (int)threadIdx.x + 64 * W * q;
+    const int tr = t >> 5, ii = bx * 32 + (t & 31);
+    const int g = kb - 3 + tr;
+    if (tr < ROWS && g <= ny + 2 && ii < nx) {
+      bool flip;
+      const int s = ghost_src(g, ny, a.bc[2], a.bc[3], flip);
+      double v[9];
+      if (DIRI && s < 0) {
+        const int rr = a.dir_off[g < 0 ? 2 : 3] + ii;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = a.dirW[rr * 6 + c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[6 + c] = a.dirP[rr * 5 + c];
+      } else {
+        const uint32_t o = ((uint32_t)s * (uint32_t)nx + (uint32_t)ii) * 8u;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = ldc(a.Wc[c], o);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[6 + c] = ldc(a.Pc[c], o);
+      }
+      if (flip) { v[3] = -v[3]; v[7] = -v[7]; }   // rho v and v change sign at the wall
+#pragma unroll
+      for (int c = 0; c < 9; ++c) tile[(c * ROWS + tr) * 32 + (t & 31)] = v[c];
+    }
+  }
+  __syncthreads();
+  const bool active = i < nx && k <= ny;
+  double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
+  if (active) {
+    LdsLoadY<true, 32> ld{tile, ROWS, fr, col};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {   // c and rho ctilde^2 of cell rows k-1 and k
+      const int g = k - 1 + q;
+      bool flip;
+      const int s = ghost_src(g, ny, a.bc[2], a.bc[3], flip);
+      double c, h;
+      if (DIRI && s < 0) {
+        const int rr = a.dir_off[g < 0 ? 2 : 3] + i;
+        c = a.dirP[rr * 5 + 3];
+        h = a.dirP[rr * 5 + 4];
+      } else {
+        const uint32_t o = ((uint32_t)s * (uint32_t)nx + (uint32_t)i) * 8u;
+        c = ldc(a.Pc[3], o);
+        h = ldc(a.Pc[4], o);
+      }
+      if (q == 0) { ld.c2 = c; ld.h2 = h; } else { ld.c3 = c; ld.h3 = h; }
+    }
+    face_flux_core<1, true, B32>(a, ld, a.step[2], Gm, Gp);
+  }
+  double Gn[6];   // G^- of face row k + 1 when r == 0 (same wave, upper half)
+#pragma unroll
+  for (int v = 0; v < 6; ++v) Gn[v] = __shfl(Gm[v], (lane + 32) & 63, 64);
+  __syncthreads();   // every face has read the tile: reuse it for G^-
+  double* sG = tile;   // [W][6][32]: G^- of each wave's lower face row
+  if (r == 0) {
+#pragma unroll
+    for (int v = 0; v < 6; ++v) sG[(w * 6 + v) * 32 + col] = Gm[v];
+  }
+  if (active) {
+    double* e = a.edge + (long)by * 12 * nx;
+    if (fr == 0) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
+    }
+    if (fr == FR - 1 || k == ny) {
+#pragma unroll
+      for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
+    }
+  }
+  __syncthreads();
+  const int j = k;
+  if (!active || fr == FR - 1 || j >= ny) return;
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    double L;
+    {
+      const double up = r == 0 ? Gn[v] : sG[((w + 1) * 6 + v) * 32 + col];
+      double Ly = hdiv(-(up - Gp[v]), a.dy, a.rdy);
+      const int s = state_index(1, v, true);
+      L = a.Lx[s * N + (long)j * nx + i] + Ly;
+    }
+    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
+  }
+}
+
+// y-tile columns of the single-grid y-sweep: 32 (sweep_y_tile32) or 64
+#ifndef WCNS_YCW
+#define WCNS_YCW 32
 #endif
+constexpr int Y_CW = WCNS_YCW;
+// threads per y-sweep block
+constexpr int Y_THREADS = Y_CW == 32 ? 32 * Y_WAVES : 64 * Y_WAVES;
 
 // waves per SIMD the y-sweep is compiled for (VGPR budget 512 / this)
 #ifndef WCNS_YWPE
 #define WCNS_YWPE (Y_WAVES >= 8 ? 4 : 3)
 #endif
 template <bool DIRI, bool B32>
-__global__ __launch_bounds__(64 * Y_WAVES) __attribute__((amdgpu_waves_per_eu(WCNS_YWPE))) void k_sweep_y(KArgs a) {
-#if WCNS_YLDS
-  __shared__ double tile[ytile_lds_doubles<Y_WAVES>()];
-  sweep_y_tile_lds<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile);
-#else
-  __shared__ double sGm[Y_WAVES][6][64];
-  sweep_y_tile<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, sGm);
-#endif
+__global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(WCNS_YWPE))) void k_sweep_y(KArgs a) {
+  if constexpr (Y_CW == 32) {
+    __shared__ double tile32[9 * (Y_WAVES + 5) * 32];
+    sweep_y_tile32<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile32);
+  } else {
+    __shared__ double tile[ytile_lds_doubles<Y_WAVES>()];
+    sweep_y_tile_lds<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile);
+  }
 }
 
 // cell rows j = (b+1)*YW - 1 between y-tile b and b+1 (t: flat index over
