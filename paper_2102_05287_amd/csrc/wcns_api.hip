@@ -609,7 +609,7 @@ static bool diri(const wcns_ctx* c, int dir) {
     }                                                 \
   } while (0)
 
-// y-sweep of tile rows [a.ytile0, a.ytile0 + rows) on stream s
+// y-sweep of the first `rows` tile rows on stream s
 static void ysweep(const wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
   dim3 gy((c->grid.nx + Y_CW - 1) / Y_CW, rows);
   const bool d = diri(c, 1);
@@ -1127,7 +1127,7 @@ static wcns_status batch_build(wcns_batch* b) {
     for (long q = 0; q < nt; ++q) tx.push_back({k, (int)q, 0, 0});
     if (g.ndim == 2) {
       const int nbr = ka[k].nbr;
-      const int nbx = (g.nx + 63) / 64;
+      const int nbx = (g.nx + 31) / 32;
       for (int by = 0; by < nbr; ++by)
         for (int bx = 0; bx < nbx; ++bx) ty.push_back({k, bx, by, 0});
       const long nfc = (long)(nbr - 1) * g.nx;
@@ -1185,8 +1185,8 @@ static void batch_stage_launches(wcns_batch* b, int s) {
       if (b32) hipLaunchKernelGGL((kb_sweep_x<true, true>), dim3(b->n_x), dim3(64), 0, b->stream, ka, tx);
       else hipLaunchKernelGGL((kb_sweep_x<true, false>), dim3(b->n_x), dim3(64), 0, b->stream, ka, tx);
     }
-    if (b32) hipLaunchKernelGGL((kb_sweep_y<YW, true>), dim3(b->n_y), dim3(64 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
-    else hipLaunchKernelGGL((kb_sweep_y<YW, false>), dim3(b->n_y), dim3(64 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
+    if (b32) hipLaunchKernelGGL((kb_sweep_y<YW, true>), dim3(b->n_y), dim3(32 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
+    else hipLaunchKernelGGL((kb_sweep_y<YW, false>), dim3(b->n_y), dim3(32 * YW), 0, b->stream, ka, b->d_tasks + b->o_y);
     if (b->n_fix > 0)
       hipLaunchKernelGGL(kb_fixup<YW>, dim3(b->n_fix), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_fix);
   } else if (b->x_lds) {

@@ -57,14 +57,16 @@ __global__ __launch_bounds__(64 * XW) void kb_sweep_xl(const KArgs* ka, const Ta
   sweep_x_window<HAS_T, false, B32>(a, tl, tl * XT < (long)a.nx * a.ny, tile[w]);
 }
 
+// y-sweep over 32-column tiles of YW face rows (YW/2 waves): task.a = column
+// block, task.b = tile row
 template <int YW, bool B32>
-__global__ __launch_bounds__(64 * YW) __attribute__((amdgpu_waves_per_eu(YW >= 8 ? 4 : 3))) void kb_sweep_y(
+__global__ __launch_bounds__(32 * YW) __attribute__((amdgpu_waves_per_eu(4))) void kb_sweep_y(
     const KArgs* ka, const Task* t) {
-  __shared__ double tile[ytile_lds_doubles<YW>()];
+  __shared__ double tile[9 * (YW + 5) * 32];
   const Task task = t[blockIdx.x];
   const KArgs a = ka[task.inst];
   if (frozen(a)) return;
-  sweep_y_tile_lds<YW, false, B32>(a, task.a, task.b, tile);
+  sweep_y_tile32<YW, false, B32>(a, task.a, task.b, tile);
 }
 
 template <int YW>
