@@ -62,9 +62,11 @@ def weighted(c, w_div=None, w_sqrt=None):
     return c["add"] + c["mul"] + c["cmp"] + w_div * c["div"] + w_sqrt * c["sqrt"]
 
 
-def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=None, w_sqrt=None):
+def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=None, w_sqrt=None, fused=2.0 / 3.0):
     """Algorithmic (issue-weighted) FP64 ops per launch of each kernel;
-    w_div = w_sqrt = 1 gives the plain operation count."""
+    w_div = w_sqrt = 1 gives the plain operation count.  `fused`: share of
+    the y-sweep launches that also recover the next stage's node primitives
+    (stages 1 and 2 of an SSP-RK3 step, in place of k_node)."""
     w_div = OP_WEIGHTS["div"] if w_div is None else w_div
     w_sqrt = OP_WEIGHTS["sqrt"] if w_sqrt is None else w_sqrt
     with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
@@ -77,7 +79,7 @@ def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=None, w_sqrt=None):
     return {
         "node": cells * (node + 4),        # + |u|+c, |v|+c, two max
         "sweep_x": (nx + 1) * ny * face + cells * diff,
-        "sweep_y": nx * (ny + 1) * face + cells * (diff + 6 + rk),
+        "sweep_y": nx * (ny + 1) * face + cells * (diff + 6 + rk) + fused * cells * (node + 4),
     }
 
 

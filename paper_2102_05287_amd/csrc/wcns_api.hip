@@ -3,6 +3,7 @@
 // RHS, the stand-alone flux limiter, the wave-speed reduction and the SSP-RK3
 // step.  No allocation happens after wcns_create.
 #include <hip/hip_runtime.h>
+#include <utility>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -29,6 +30,12 @@ struct wcns_ctx {
   double dx, dy;
   KArgs base;
   double *P, *L, *U1, *U2, *partial, *step, *dirW, *dirP, *edge;
+  // 2D steps: the y-sweep and fixup of stages 1 and 2 write the next
+  // stage's node primitives into P2 (the two buffers alternate) and their
+  // block maxima into `partial` (nfused pairs), so only k_finalize runs
+  // before stages 2 and 3
+  double* P2;
+  int fuse, nfused;
   unsigned long long* count;
   double* damax;  // Dirichlet ghost wave-speed maxima [2] (inside dirP), or null
   // 3D: arguments shared by its kernels, strided-pass edge buffer, tile rows
@@ -165,7 +172,7 @@ wcns_status wcns_destroy(wcns_ctx* c) {
   if (!c) return WCNS_ERR_ARG;
   prof_release(c);
   (void)hipStreamSynchronize(c->stream);
-  double* bufs[] = {c->P, c->L, c->U1, c->U2, c->partial, c->step, c->dirW, c->dirP, c->edge};
+  double* bufs[] = {c->P, c->P2, c->L, c->U1, c->U2, c->partial, c->step, c->dirW, c->dirP, c->edge};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->count) (void)hipFree(c->count);
@@ -266,7 +273,16 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
     alloc(&c->L, (size_t)c->nv * c->N);
     alloc(&c->edge, (size_t)c->nbr * 12 * g->nx);
   }
-  alloc(&c->partial, 2 * (size_t)c->node_grid);
+  // fused node primitives: 2D with the 32-column y-tiles (whose epilogue
+  // and the fixup's write them)
+  c->fuse = g->ndim == 2 && Y_CW == 32;
+  if (c->fuse) {
+    const long nyb = (long)((g->nx + Y_CW - 1) / Y_CW) * c->nbr;
+    const long nfb = c->nbr > 1 ? ((long)(c->nbr - 1) * g->nx + 255) / 256 : 0;
+    c->nfused = (int)(nyb + nfb);
+    alloc(&c->P2, 5 * (size_t)c->N);
+  }
+  alloc(&c->partial, 2 * (size_t)(c->nfused > c->node_grid ? c->nfused : c->node_grid));
   alloc(&c->step, 8);
   if (g->ndim == 1 && g->nx <= RUN1D_MAX_CELLS) {
     alloc(&c->run_G, 12 * ((size_t)g->nx + 1));
@@ -541,19 +557,8 @@ wcns_status wcns_set_stream(wcns_ctx* c, void* stream) {
   return WCNS_OK;
 }
 
-// node primitives + wave-speed maxima, then dt/lambda of state W
-static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mode, double dt,
-                                        double* dt_used) {
-  KArgs a = c->base;
-  a.W = W;
-  {
-    ProfScope ps(c, PROF_NODE);
-    if (c->grid.ndim == 2)
-      hipLaunchKernelGGL(k_node<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
-    else
-      hipLaunchKernelGGL(k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
-  }
-  LAUNCH_CHECK();
+// dt/lambda from the nblk block-maxima pairs in c->partial
+static wcns_status launch_finalize(wcns_ctx* c, int nblk, int dt_mode, double dt, double* dt_used) {
   FinArgs f;
   f.ndim = c->grid.ndim;
   f.dt_mode = dt_mode;
@@ -566,13 +571,30 @@ static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mod
   f.damax = c->damax;
   ProfScope ps(c, PROF_FIN);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
-                     c->node_grid, f);
+                     nblk, f);
   LAUNCH_CHECK();
   return WCNS_OK;
 }
 
+// node primitives of state W into P + wave-speed maxima, then dt/lambda
+static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mode, double dt,
+                                        double* dt_used, double* P = nullptr) {
+  if (!P) P = c->P;
+  KArgs a = c->base;
+  a.W = W;
+  {
+    ProfScope ps(c, PROF_NODE);
+    if (c->grid.ndim == 2)
+      hipLaunchKernelGGL(k_node<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, P, c->partial);
+    else
+      hipLaunchKernelGGL(k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, P, c->partial);
+  }
+  LAUNCH_CHECK();
+  return launch_finalize(c, c->node_grid, dt_mode, dt, dt_used);
+}
+
 // per-component base pointers of a state and of the node primitives
-static void set_bases(wcns_ctx* c, KArgs& a, const double* W) {
+static void set_bases(wcns_ctx* c, KArgs& a, const double* W, const double* P) {
   const long N = c->N;
   if (c->grid.ndim == 2) {
     for (int k = 0; k < 6; ++k) a.Wc[k] = W + k * N;
@@ -580,7 +602,7 @@ static void set_bases(wcns_ctx* c, KArgs& a, const double* W) {
     a.Wc[0] = W; a.Wc[1] = W + N; a.Wc[2] = W + 2 * N; a.Wc[3] = W;
     a.Wc[4] = W + 3 * N; a.Wc[5] = W + 4 * N;
   }
-  for (int k = 0; k < 5; ++k) a.Pc[k] = c->P + k * N;
+  for (int k = 0; k < 5; ++k) a.Pc[k] = P + k * N;
 }
 
 static bool diri(const wcns_ctx* c, int dir) {
@@ -623,17 +645,21 @@ static void ysweep(const wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStr
 }
 
 // x-sweep and (2D) y-sweep of state W into `out`; mode STORE (L) or RK.
+// (P: node primitives of W; Pn: when not null, the finished cells' next
+// stage primitives go there and their block maxima to c->partial)
 static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int mode,
-                                 const double* Un, double ca, double cb) {
+                                 const double* Un, double ca, double cb,
+                                 const double* P = nullptr, double* Pn = nullptr) {
+  if (!P) P = c->P;
   KArgs a = c->base;
   a.W = W;
-  a.P = c->P;
+  a.P = P;
   a.out = out;
   a.Un = Un;
   a.ca = ca;
   a.cb = cb;
   a.out_mode = mode;
-  set_bases(c, a, W);
+  set_bases(c, a, W, P);
   const bool b32 = c->precision == WCNS_FP32_BULK;
   if (c->grid.ndim == 1) {
     a.Lout = nullptr;
@@ -654,6 +680,11 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   double* lx = mode == OUT_STORE ? out : c->L;
   a.Lout = lx;
   a.Lx = lx;
+  if (Pn) {
+    a.Pn = Pn;
+    a.partn = c->partial;
+    a.fuse_off = (int)((long)((c->grid.nx + Y_CW - 1) / Y_CW) * c->nbr);
+  }
   {
     ProfScope ps(c, PROF_X);
     XSWEEP_ALL(c->xl_grid);
@@ -713,6 +744,8 @@ wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used)
   double* outs[3] = {c->U1, c->U2, W};
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
   const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  double* Pcur = c->P;
+  double* Pnext = c->P2;
   for (int s = 0; s < 3; ++s) {
     int mode = s == 0 ? (dt > 0.0 ? DT_GIVEN : DT_CFL) : DT_KEEP;
     if (c->grid.ndim == 3) {
@@ -722,10 +755,16 @@ wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used)
       if (st != WCNS_OK) return st;
       continue;
     }
-    wcns_status st = launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr);
+    // stages 2 and 3 take the node primitives and block maxima that the
+    // previous stage's y-sweep and fixup left (c->fuse)
+    wcns_status st = s > 0 && c->fuse
+                         ? launch_finalize(c, c->nfused, mode, dt, nullptr)
+                         : launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr, Pcur);
     if (st != WCNS_OK) return st;
-    st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
+    double* Pn = c->fuse && s < 2 ? Pnext : nullptr;
+    st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s], Pcur, Pn);
     if (st != WCNS_OK) return st;
+    if (Pn) std::swap(Pcur, Pnext);
   }
   return WCNS_OK;
 }
@@ -804,7 +843,7 @@ wcns_status wcns_limit(wcns_ctx* c, int32_t dir, const double* W, const double* 
   KArgs a = c->base;
   a.W = W;
   a.P = c->P;
-  set_bases(c, a, W);
+  set_bases(c, a, W, c->P);
   long nf = dir == 0 ? (long)(c->grid.nx + 1) * c->grid.ny : (long)c->grid.nx * (c->grid.ny + 1);
   unsigned g = (unsigned)((nf + 255) / 256);
   if (c->grid.ndim == 2)

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(64 * XW) void kb_sweep_xl(const KArgs* ka, const Ta
 // y-sweep over 32-column tiles of YW face rows (YW/2 waves): task.a = column
 // block, task.b = tile row
 template <int YW, bool B32>
-__global__ __launch_bounds__(32 * YW) __attribute__((amdgpu_waves_per_eu(4))) void kb_sweep_y(
+__global__ __launch_bounds__(32 * YW) __attribute__((amdgpu_waves_per_eu(YW >= 4 ? 4 : 3))) void kb_sweep_y(
     const KArgs* ka, const Task* t) {
   __shared__ double tile[9 * (YW + 5) * 32];
   const Task task = t[blockIdx.x];
@@ -74,7 +74,9 @@ __global__ __launch_bounds__(256) void kb_fixup(const KArgs* ka, const Task* t) 
   const Task task = t[blockIdx.x];
   const KArgs& a = ka[task.inst];
   if (frozen(a)) return;
-  fixup_cell(a, (long)task.a * 256 + threadIdx.x, YW);
+  long idx;
+  double X[6];
+  (void)fixup_cell(a, (long)task.a * 256 + threadIdx.x, YW, idx, X);
 }
 
 // end of a step: one step fewer for every live instance

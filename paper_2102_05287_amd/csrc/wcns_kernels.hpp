@@ -75,6 +75,13 @@ struct KArgs {
   double cfl, dt_in;
   double* dt_used;       // optional copy of dt
   const int32_t* live;   // batched form: steps left for this instance (skip at 0)
+  // Next stage's node primitives computed where the stage state is
+  // finished (y-sweep epilogue and fixup) instead of by k_node: Pn [5][N]
+  // (null: off) and per-block wave-speed maxima at partn[2b], partn[2b+1]
+  // (y-sweep blocks first, the fixup's from fuse_off on)
+  double* Pn;
+  double* partn;
+  int32_t fuse_off, pad5;
 };
 
 // ------------------------------------------------------------------ nodes
@@ -541,13 +548,51 @@ __device__ __forceinline__ int state_index(int dir, int v, bool has_t) {
 }
 
 // final write of one cell: L (store) or the SSP-RK3 combination
-__device__ __forceinline__ void write_cell(const KArgs& a, double* dst, long idx, long N, int k,
-                                           double L) {
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ double write_cell(const KArgs& a, double* dst, long idx, long N, int k,
+                                             double L) {
+  double v;
   if (a.out_mode == OUT_STORE) {
-    dst[k * N + idx] = L;
+    v = L;
   } else {
     double dt = a.step[0];
-    dst[k * N + idx] = a.ca * a.Un[k * N + idx] + a.cb * (a.W[k * N + idx] + dt * L);
+    v = a.ca * a.Un[k * N + idx] + a.cb * (a.W[k * N + idx] + dt * L);
+  }
+  dst[k * N + idx] = v;
+  return v;
+}
+
+// Node primitives of a finished cell of the next stage's state X (state
+// order) into a.Pn, and its wave speeds |u|+c, |v|+c into the running
+// maxima: k_node's arithmetic [Sec. 2, 3.3] on the values just written.
+__device__ __forceinline__ void next_prims(const KArgs& a, long idx, long N, const double X[6],
+                                           double& mx, double& my) {
+  double un, ut, p, c, h;
+  recover<true>(a.eos, X, un, ut, p, c, h);
+  double* P = a.Pn;
+  P[idx] = un; P[N + idx] = ut; P[2 * N + idx] = p; P[3 * N + idx] = c; P[4 * N + idx] = h;
+  mx = fmax(mx, fabs(un) + c);
+  my = fmax(my, fabs(ut) + c);
+}
+
+// Block maxima of (mx, my) to out2[0], out2[1]; every thread of the block
+// calls it (at most 16 waves).
+__device__ __forceinline__ void block_max_out(double mx, double my, double* out2) {
+  __shared__ double red[2][16];
+  mx = wave_max(mx);
+  my = wave_max(my);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) { red[0][w] = mx; red[1][w] = my; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
+    out2[0] = mx;
+    out2[1] = my;
   }
 }
 
@@ -564,12 +609,6 @@ struct FinArgs {
   double* dt_used;    // optional copy of dt
   const double* damax;  // Dirichlet ghost maxima [2] or null
 };
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
 
 // Maxima over the per-block pairs (partial[2b], partial[2b+1]), b < nblk, of
 // this thread's share: eight pairs per round with all loads issued together
@@ -1194,18 +1233,25 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
   }
   __syncthreads();
   const int j = k;
-  if (!active || fr == FR - 1 || j >= ny) return;
+  const bool own = active && fr != FR - 1 && j < ny;
+  double mx = 0.0, my = 0.0;
+  if (own) {
+    const long idx = (long)j * nx + i;
+    double X[6];
 #pragma unroll
-  for (int v = 0; v < 6; ++v) {
-    double L;
-    {
-      const double up = r == 0 ? Gn[v] : sG[((w + 1) * 6 + v) * 32 + col];
-      double Ly = hdiv(-(up - Gp[v]), a.dy, a.rdy);
+    for (int v = 0; v < 6; ++v) {
       const int s = state_index(1, v, true);
-      L = a.Lx[s * N + (long)j * nx + i] + Ly;
+      double L;
+      {
+        const double up = r == 0 ? Gn[v] : sG[((w + 1) * 6 + v) * 32 + col];
+        double Ly = hdiv(-(up - Gp[v]), a.dy, a.rdy);
+        L = a.Lx[s * N + idx] + Ly;
+      }
+      X[s] = write_cell(a, a.out, idx, N, s, L);
     }
-    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
+    if (a.Pn) next_prims(a, idx, N, X, mx, my);
   }
+  if (a.Pn) block_max_out(mx, my, a.partn + 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x));
 }
 
 // y-tile columns of the single-grid y-sweep: 32 (sweep_y_tile32) or 64
@@ -1233,30 +1279,41 @@ __global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(WCNS_
 
 // cell rows j = (b+1)*YW - 1 between y-tile b and b+1 (t: flat index over
 // the boundary rows of one instance)
-__device__ __forceinline__ void fixup_cell(const KArgs& a, long t, int yw) {
+// (returns false for t past the boundary rows; else the cell's flat index
+// and the values written, in state order)
+__device__ __forceinline__ bool fixup_cell(const KArgs& a, long t, int yw, long& idx, double X[6]) {
   const int nx = a.nx, ny = a.ny;
   const long N = (long)nx * ny;
   const int b = (int)(t / nx), i = (int)(t % nx);
-  if (b >= a.nbr - 1) return;
+  if (b >= a.nbr - 1) return false;
   const int j = (b + 1) * yw - 1;
-  if (j >= ny) return;
+  if (j >= ny) return false;
   const double* lo = a.edge + (long)b * 12 * nx + 6 * nx;       // G^+ of face row j
   const double* hi = a.edge + (long)(b + 1) * 12 * nx;          // G^- of face row j+1
+  idx = (long)j * nx + i;
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
+    const int s = state_index(1, v, true);
     double L;
     {
       double Ly = hdiv(-(hi[v * nx + i] - lo[v * nx + i]), a.dy, a.rdy);
-      const int s = state_index(1, v, true);
-      L = a.Lx[s * N + (long)j * nx + i] + Ly;
+      L = a.Lx[s * N + idx] + Ly;
     }
-    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
+    X[s] = write_cell(a, a.out, idx, N, s, L);
   }
+  return true;
 }
 
 __global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
   (void)nbr;
-  fixup_cell(a, (long)blockIdx.x * blockDim.x + threadIdx.x, Y_WAVES);
+  long idx = 0;
+  double X[6];
+  const bool own = fixup_cell(a, (long)blockIdx.x * blockDim.x + threadIdx.x, Y_WAVES, idx, X);
+  if (a.Pn) {
+    double mx = 0.0, my = 0.0;
+    if (own) next_prims(a, idx, (long)a.nx * a.ny, X, mx, my);
+    block_max_out(mx, my, a.partn + 2 * ((long)a.fuse_off + blockIdx.x));
+  }
 }
 
 // Stand-alone flux limiter over the faces of one direction.
