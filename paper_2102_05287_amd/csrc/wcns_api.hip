@@ -570,7 +570,7 @@ static wcns_status launch_finalize(wcns_ctx* c, int nblk, int dt_mode, double dt
   f.dt_used = dt_used;
   f.damax = c->damax;
   ProfScope ps(c, PROF_FIN);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c->stream, (const double*)c->partial,
                      nblk, f);
   LAUNCH_CHECK();
   return WCNS_OK;
@@ -1015,12 +1015,30 @@ static size_t round32(size_t x) { return (x + 31) & ~(size_t)31; }
 
 // scratch doubles of one instance: P, U1, U2, (L), edge (for the smallest
 // y-tile), block maxima, step record
+// block-maxima pairs of the fused next-stage primitives of a 2D instance
+// (32-column y-tiles of yw face rows, then the fixup's blocks)
+static size_t fused_pairs(const wcns_grid& g, int yw) {
+  const size_t nbr = (size_t)(g.ny + 1 + yw - 1) / yw;
+  const size_t nyb = (size_t)((g.nx + 31) / 32) * nbr;
+  const size_t nfb = nbr > 1 ? ((nbr - 1) * (size_t)g.nx + 255) / 256 : 0;
+  return nyb + nfb;
+}
+
+// block-maxima pairs an instance's scratch holds: k_node's blocks, or (2D)
+// the fused ones at the smallest tile height
+static size_t inst_pairs(const wcns_grid& g) {
+  const size_t nblk = ((size_t)g.nx * g.ny + 255) / 256;
+  if (g.ndim != 2) return nblk;
+  const size_t f = fused_pairs(g, 2);
+  return f > nblk ? f : nblk;
+}
+
+// instance scratch: P, (2D) P2, U1, U2, block maxima, step record, (2D) L, edges
 static size_t inst_doubles(const wcns_grid& g, int nv) {
   const size_t N = (size_t)g.nx * g.ny;
-  size_t nblk = (N + 255) / 256;
   size_t nbr = (size_t)(g.ny + 1 + 1) / 2;
-  size_t d = round32(5 * N) + 2 * round32(nv * N) + round32(2 * nblk) + 32;
-  if (g.ndim == 2) d += round32(nv * N) + round32(nbr * 12 * g.nx);
+  size_t d = round32(5 * N) + 2 * round32(nv * N) + round32(2 * inst_pairs(g)) + 32;
+  if (g.ndim == 2) d += round32(5 * N) + round32(nv * N) + round32(nbr * 12 * g.nx);
   return d;
 }
 
@@ -1084,11 +1102,12 @@ static wcns_status batch_build(wcns_batch* b) {
     const long N = (long)g.nx * g.ny;
     double* base = b->arena + b->off[k];
     double* P = base;
-    double* U1 = P + round32(5 * N);
+    double* P2 = g.ndim == 2 ? P + round32(5 * N) : nullptr;   // fused next-stage primitives
+    double* U1 = (P2 ? P2 : P) + round32(5 * N);
     double* U2 = U1 + round32((size_t)b->nv * N);
     double* part = U2 + round32((size_t)b->nv * N);
     const int nblk = (int)((N + 255) / 256);
-    double* step = part + round32(2 * (size_t)nblk);
+    double* step = part + round32(2 * inst_pairs(g));
     double* L = step + 32;
     double* edge = L + round32((size_t)b->nv * N);
     const int nbr = (g.ny + 1 + yw - 1) / yw;
@@ -1130,6 +1149,18 @@ static wcns_status batch_build(wcns_batch* b) {
       } else {
         x.Wc[0] = Ws; x.Wc[1] = Ws + N; x.Wc[2] = Ws + 2 * N; x.Wc[3] = Ws;
         x.Wc[4] = Ws + 3 * N; x.Wc[5] = Ws + 4 * N;
+      }
+      if (s < 3 && P2) {
+        // stage 1 runs kb_node into P; the y-sweep and fixup of stages 1 and
+        // 2 leave the next stage's primitives in P2, then P, and the block
+        // maxima kb_finalize reduces
+        const double* Pc = s == 1 ? P2 : P;
+        x.P = Pc;
+        for (int q = 0; q < 5; ++q) x.Pc[q] = Pc + q * N;
+        x.Pn = s == 0 ? P2 : (s == 1 ? P : nullptr);
+        x.partn = part;
+        x.fuse_off = (int)((long)((g.nx + 31) / 32) * nbr);
+        if (s > 0) x.nblk = (int)fused_pairs(g, yw);
       }
       if (s < 3) {
         x.out = outs[s];
@@ -1210,9 +1241,10 @@ template <int YW>
 static void batch_stage_launches(wcns_batch* b, int s) {
   const KArgs* ka = b->d_ka + (size_t)s * b->n;
   const bool b32 = b->precision == WCNS_FP32_BULK;
-  if (b->ndim == 2)
+  // 2D stages 2 and 3 take their node primitives from the previous stage
+  if (b->ndim == 2 && (s == 0 || s == 3))
     hipLaunchKernelGGL(kb_node<true>, dim3(b->n_node), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_node);
-  else
+  else if (b->ndim != 2)
     hipLaunchKernelGGL(kb_node<false>, dim3(b->n_node), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_node);
   hipLaunchKernelGGL(kb_finalize, dim3(b->n), dim3(256), 0, b->stream, ka);
   const Task* tx = b->d_tasks + b->o_x;

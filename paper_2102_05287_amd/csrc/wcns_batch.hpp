@@ -66,7 +66,7 @@ __global__ __launch_bounds__(32 * YW) __attribute__((amdgpu_waves_per_eu(YW >= 4
   const Task task = t[blockIdx.x];
   const KArgs a = ka[task.inst];
   if (frozen(a)) return;
-  sweep_y_tile32<YW, false, B32>(a, task.a, task.b, tile);
+  sweep_y_tile32<YW, false, B32>(a, task.a, task.b, tile, (long)task.b * ((a.nx + 31) / 32) + task.a);
 }
 
 template <int YW>
@@ -74,9 +74,14 @@ __global__ __launch_bounds__(256) void kb_fixup(const KArgs* ka, const Task* t) 
   const Task task = t[blockIdx.x];
   const KArgs& a = ka[task.inst];
   if (frozen(a)) return;
-  long idx;
+  long idx = 0;
   double X[6];
-  (void)fixup_cell(a, (long)task.a * 256 + threadIdx.x, YW, idx, X);
+  const bool own = fixup_cell(a, (long)task.a * 256 + threadIdx.x, YW, idx, X);
+  if (a.Pn) {
+    double mx = 0.0, my = 0.0;
+    if (own) next_prims(a, idx, (long)a.nx * a.ny, X, mx, my);
+    block_max_out(mx, my, a.partn + 2 * ((long)a.fuse_off + task.a));
+  }
 }
 
 // end of a step: one step fewer for every live instance

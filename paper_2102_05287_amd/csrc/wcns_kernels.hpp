@@ -670,17 +670,18 @@ __global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partia
 
 // Global maxima -> dt, sigma and lambda in the device step record (one
 // block), so a whole step needs no host round trip.
-__global__ __launch_bounds__(256) void k_finalize(const double* partial, int nblk, FinArgs f) {
+// (1024 threads: up to 8192 block maxima arrive in one round of loads)
+__global__ __launch_bounds__(1024) void k_finalize(const double* partial, int nblk, FinArgs f) {
   double mx = 0.0, my = 0.0;
   partial_max(partial, nblk, mx, my);
   mx = wave_max(mx);
   my = wave_max(my);
-  __shared__ double red[2][4];
+  __shared__ double red[2][16];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   if (l == 0) { red[0][w] = mx; red[1][w] = my; }
   __syncthreads();
   if (threadIdx.x != 0) return;
-  for (int k = 0; k < 4; ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
   if (f.damax) { mx = fmax(mx, f.damax[0]); my = fmax(my, f.damax[1]); }
   double* step = f.step;
   double dt;
@@ -1147,8 +1148,9 @@ __device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by,
 // go to the edge buffer for the fixup.  Half the columns of the 64-column
 // tile at the same face rows: a quarter of the LDS per wave pair, so four
 // 4-wave blocks share a CU instead of two 8-wave ones.
+// (part: this block's slot for its block maxima when a.Pn is set)
 template <int FR, bool DIRI, bool B32>
-__device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, double* tile) {
+__device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, double* tile, long part) {
   constexpr int W = FR / 2;
   constexpr int ROWS = FR + 5;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1251,7 +1253,7 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
     }
     if (a.Pn) next_prims(a, idx, N, X, mx, my);
   }
-  if (a.Pn) block_max_out(mx, my, a.partn + 2 * ((long)blockIdx.y * gridDim.x + blockIdx.x));
+  if (a.Pn) block_max_out(mx, my, a.partn + 2 * part);
 }
 
 // y-tile columns of the single-grid y-sweep: 32 (sweep_y_tile32) or 64
@@ -1270,7 +1272,8 @@ template <bool DIRI, bool B32>
 __global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(WCNS_YWPE))) void k_sweep_y(KArgs a) {
   if constexpr (Y_CW == 32) {
     __shared__ double tile32[9 * (Y_WAVES + 5) * 32];
-    sweep_y_tile32<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile32);
+    sweep_y_tile32<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile32,
+                                       (long)blockIdx.y * gridDim.x + blockIdx.x);
   } else {
     __shared__ double tile[ytile_lds_doubles<Y_WAVES>()];
     sweep_y_tile_lds<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile);
