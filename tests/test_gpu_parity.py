@@ -357,6 +357,36 @@ def test_ssprk3_step_matches_oracle():
         assert_parity(host(Wd), ref, what=spec.name)
 
 
+def test_steps_after_the_state_changes_between_calls():
+    """Within a 2D step the later stages take node primitives left by the
+    previous stage's y-sweep and fixup; every step starts from primitives
+    of the state it is given.  Steps with the state replaced in between
+    (by another state, then by an in-place edit) and a step after an RHS
+    evaluation of a third state all match the oracle bit for bit (53 rows:
+    several y-tiles and a ragged last one)."""
+    spec_a = pb.random_smooth_state(70, 53, 41)
+    spec_b = pb.random_smooth_state(70, 53, 42)
+    s = oracle_setup(spec_a)
+    Wa = oracle_W(spec_a, s)
+    Wb = oracle_W(spec_b, oracle_setup(spec_b))
+    sol = solver_for(spec_a)
+    Wd = dev(Wa)
+    sol.step(Wd, 0.0)
+    ref, _, _ = orc.ssprk3_step(s, Wa)
+    assert np.array_equal(host(Wd), ref)
+    Wd.copy_(dev(Wb))                               # a different state, same buffer
+    sol.step(Wd, 0.0)
+    ref, _, _ = orc.ssprk3_step(s, Wb)
+    assert np.array_equal(host(Wd), ref)
+    W2 = ref.copy()
+    W2[:, 20:30, 10:40] = Wa[:, 20:30, 10:40]       # an edit in place
+    Wd.copy_(dev(W2))
+    sol.rhs(dev(Wa), dt=1e-9)                       # an RHS of another state in between
+    sol.step(Wd, 0.0)
+    ref, _, _ = orc.ssprk3_step(s, W2)
+    assert np.array_equal(host(Wd), ref)
+
+
 def test_water_air_tube_to_final_time():
     """1D water-air tube, 400 cells, CFL 0.5, t = 2.4e-4 s: relative L1 per
     variable <= 1e-9 against the oracle and no inadmissible cell after any
