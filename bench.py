@@ -405,10 +405,17 @@ def cpu_baseline(spec, target_s=12.0):
     for _ in range(calls):
         orc.rhs(s, W, dt)
     el = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": spec.nx * spec.ny * calls / el / 1e6, "unit": "Mcell-updates/s",
             "cores": 1, "kind": "oracle",
             "sample": f"{calls} full-grid RHS evaluations of the {spec.nx}x{spec.ny} "
-                      f"shock-bubble initial state (serial FP64 C++ oracle, 1 thread)"}
+                      f"shock-bubble initial state (serial FP64 C++ oracle, 1 thread)",
+            "host": {"cpu": cpu, "logical_cpus": os.cpu_count()}}
 
 
 def main():
