@@ -133,3 +133,36 @@ def test_batch_1d_window_x_sweep():
             W, dt, bad = orc.ssprk3_step(s, W)
         assert np.array_equal(host(states[k]), W), k
     b.close()
+
+
+def test_batch_full_size_512_instances_sampled():
+    """The batched workload at its full size (512 seeded instances, 37 M
+    cells, the bench's schedule space): two graph-replayed steps of the whole
+    batch; sampled instances of every side equal their single solves bit for
+    bit."""
+    specs = [pb.random_instance(i) for i in range(512)]
+    W0 = {}
+    conv = {}
+    for k, sp in enumerate(specs):
+        if sp.nx not in conv:
+            conv[sp.nx] = wcns.Solver.from_spec(sp)
+        W0[k] = conv[sp.nx].prim_to_cons(torch.from_numpy(sp.prim).cuda())
+        sp.prim = None
+    sides = sorted({sp.nx for sp in specs})
+    first_of_side = {min(k for k in range(512) if specs[k].nx == n) for n in sides}
+    sample = sorted({0, 1, 7, 100, 255, 300, 511} | first_of_side)
+    ref = {}
+    for k in sample:
+        sol = wcns.Solver.from_spec(specs[k])
+        Wd = W0[k].clone()
+        for _ in range(2):
+            sol.step(Wd, 0.0)
+        ref[k] = host(Wd)
+        sol.close()
+    states = [W0[k] for k in range(512)]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)
+    b.configure(8, 1)
+    b.step(2)
+    for k in sample:
+        assert np.array_equal(host(states[k]), ref[k]), k
+    b.close()
