@@ -1004,7 +1004,7 @@ struct wcns_batch {
   double* d_dt = nullptr;      // per-instance dt of the last step
   int32_t* d_live = nullptr;   // per-instance steps left (frozen at 0)
   int dt_cap = 0;
-  int ytile = 4, order = 2;
+  int ytile = 8, order = 2;
   bool x_lds = false;   // x-sweep with LDS windows (every instance has nx >= XLDS_MIN_NX)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;

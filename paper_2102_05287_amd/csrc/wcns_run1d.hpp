@@ -16,7 +16,7 @@
 
 namespace wcns {
 
-constexpr int RUN1D_THREADS = 512;   // 8 waves: 2 per SIMD at the sweeps' 168 VGPRs
+constexpr int RUN1D_THREADS = 512;   // 8 waves, 2 per SIMD (up to 256 VGPRs each)
 constexpr int RUN1D_MAX_CELLS = 4096;
 
 struct Run1D {

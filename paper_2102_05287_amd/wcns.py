@@ -496,7 +496,7 @@ class Batch:
         import torch
         torch.cuda.current_stream().wait_stream(self.stream)
 
-    def configure(self, ytile=4, order=2):
+    def configure(self, ytile=8, order=2):
         _check(lib().wcns_batch_configure(self._b, int(ytile), int(order)), "wcns_batch_configure")
 
     def reset(self, grids, states):
