@@ -66,7 +66,8 @@ def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=None, w_sqrt=None, fused=2.0 / 3
     """Algorithmic (issue-weighted) FP64 ops per launch of each kernel;
     w_div = w_sqrt = 1 gives the plain operation count.  `fused`: share of
     the y-sweep launches that also recover the next stage's node primitives
-    (stages 1 and 2 of an SSP-RK3 step, in place of k_node)."""
+    in place of k_node (2/3 for single-step calls; 1 - 1/(3K) for K steps
+    in one call)."""
     w_div = OP_WEIGHTS["div"] if w_div is None else w_div
     w_sqrt = OP_WEIGHTS["sqrt"] if w_sqrt is None else w_sqrt
     with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
@@ -108,16 +109,15 @@ def measured_traffic(kernel):
 
 
 def time_steps(sol, W0, steps, warmup):
-    """Seconds for `steps` device-CFL SSP-RK3 steps from W0 (after warmup)."""
+    """Seconds for `steps` device-CFL SSP-RK3 steps from W0 (after warmup),
+    enqueued as one multi-step call (wcns_ssprk3_steps)."""
     import torch
     W = W0.clone()
-    for _ in range(warmup):
-        sol.step(W, 0.0)
+    sol.steps(W, warmup, 0.0)
     W.copy_(W0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        sol.step(W, 0.0)
+    sol.steps(W, steps, 0.0)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, W
 
@@ -140,11 +140,10 @@ def precision_form(n, steps, warmup):
     # per-kernel device time of the FP32-bulk sweeps (same op model as FP64)
     W = W0.clone()
     s32.profile(True)
-    for _ in range(steps):
-        s32.step(W, 0.0)
+    s32.steps(W, steps, 0.0)
     prof = s32.profile_read(reset=True)
     s32.profile(False)
-    ops = kernel_ops(spec.nx, spec.ny)
+    ops = kernel_ops(spec.nx, spec.ny, fused=1.0 - 1.0 / (3 * steps))
     roof32 = {}
     for k in ("sweep_x", "sweep_y"):
         avg = prof[k][0] / 1e3 / prof[k][1]
@@ -267,8 +266,7 @@ def three_d_form(n=256, steps=10, warmup=2):
     cells = n ** 3
     W.copy_(W0)
     sol.profile(True)
-    for _ in range(steps):
-        sol.step(W, 0.0)
+    sol.steps(W, steps, 0.0)
     prof = sol.profile_read(reset=True)
     sol.profile(False)
     bad = sol.count_inadmissible(W)
@@ -475,14 +473,12 @@ def main():
     W0 = sol.prim_to_cons(V)
     W = W0.clone()
     print(f"# workload {spec.name} {spec.nx}x{spec.ny} fp64; warmup {args.warmup}", flush=True)
-    for _ in range(args.warmup):
-        sol.step(W, 0.0)
+    sol.steps(W, args.warmup, 0.0)
     torch.cuda.synchronize()
     W.copy_(W0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sol.step(W, 0.0)
+    sol.steps(W, args.steps, 0.0)       # K device-CFL steps, one call
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     cells = spec.nx * spec.ny
@@ -494,17 +490,17 @@ def main():
     # library's stream); the dominant kernel gives the roofline
     W.copy_(W0)
     sol.profile(True)
-    for _ in range(args.steps):
-        sol.step(W, 0.0)
+    sol.steps(W, args.steps, 0.0)
     prof = sol.profile_read(reset=True)
     sol.profile(False)
-    ops = kernel_ops(spec.nx, spec.ny)
+    fused = 1.0 - 1.0 / (3 * args.steps)   # y-sweeps that also recover the next primitives
+    ops = kernel_ops(spec.nx, spec.ny, fused=fused)
     dom = max((k for k in ops), key=lambda k: prof[k][0])
     ms, n = prof[dom]
     avg_s = ms / 1e3 / n
     achieved = ops[dom] / avg_s / 1e12
     peak = VALU_F64_SLOTS / 1e12
-    ops1 = kernel_ops(spec.nx, spec.ny, w_div=1, w_sqrt=1)
+    ops1 = kernel_ops(spec.nx, spec.ny, w_div=1, w_sqrt=1, fused=fused)
     roofline = {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(dom),
                 "frac_unweighted": ops1[dom] / avg_s / VALU_F64_SLOTS,

@@ -170,6 +170,16 @@ wcns_status wcns_max_wavespeed(wcns_ctx* ctx, const double* W, double* d_amax);
  * (may be NULL) receives the step taken.  Asynchronous; no host sync. */
 wcns_status wcns_ssprk3_step(wcns_ctx* ctx, double* W, double dt, double* dt_used);
 
+/* nsteps such steps (Sec. 5.3) in place on W, each with dt > 0 or, dt <= 0,
+ * its own device CFL step; dts: device array of >= nsteps doubles (may be
+ * NULL) receiving step k's dt at dts[k].  Bit for bit the same as nsteps
+ * calls of wcns_ssprk3_step.  In 2D the node primitives and wave-speed
+ * maxima of each step's first stage come from the previous step's last
+ * stage (W is not written by anyone else inside the call), which saves one
+ * primitive pass per step.  nsteps = 0 does nothing; WCNS_ERR_ARG for
+ * nsteps < 0.  Asynchronous; no host sync. */
+wcns_status wcns_ssprk3_steps(wcns_ctx* ctx, double* W, int32_t nsteps, double dt, double* dts);
+
 /* Count cells outside the admissible set G (Sec. 2): a1 < 0 or a1 > 1,
  * a_k r_k < 0, or rho e - pbar_inf <= 0 (NaN counts as outside).
  * Synchronises the stream; *n_bad is a host pointer. */

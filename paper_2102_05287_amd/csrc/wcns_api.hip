@@ -736,37 +736,52 @@ wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
   return launch_sweeps(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
 }
 
-wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used) {
-  if (!c || !W) return WCNS_ERR_ARG;
-  if (!isfinite(dt)) return WCNS_ERR_CFL;
-  // stage inputs / outputs of the Shu-Osher form
+// n SSP-RK3 steps of W in place (Shu-Osher form).  In 2D the node
+// primitives and block maxima of every stage but the first of the call come
+// from the previous stage's y-sweep and fixup (c->fuse): within one call no
+// one else writes W between steps.  Step k's dt goes to dts[k] (device).
+static wcns_status steps_impl(wcns_ctx* c, double* W, int n, double dt, double* dts) {
   const double* in[3] = {W, c->U1, c->U2};
   double* outs[3] = {c->U1, c->U2, W};
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
   const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
   double* Pcur = c->P;
   double* Pnext = c->P2;
-  for (int s = 0; s < 3; ++s) {
-    int mode = s == 0 ? (dt > 0.0 ? DT_GIVEN : DT_CFL) : DT_KEEP;
-    if (c->grid.ndim == 3) {
-      wcns_status st = launch_node_finalize3(c, in[s], mode, dt, s == 0 ? dt_used : nullptr);
+  for (int k = 0; k < n; ++k) {
+    double* dt_used = dts ? dts + k : nullptr;
+    for (int s = 0; s < 3; ++s) {
+      int mode = s == 0 ? (dt > 0.0 ? DT_GIVEN : DT_CFL) : DT_KEEP;
+      if (c->grid.ndim == 3) {
+        wcns_status st = launch_node_finalize3(c, in[s], mode, dt, s == 0 ? dt_used : nullptr);
+        if (st != WCNS_OK) return st;
+        st = launch_sweeps3(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
+        if (st != WCNS_OK) return st;
+        continue;
+      }
+      const bool first = k == 0 && s == 0, last = k == n - 1 && s == 2;
+      wcns_status st = !first && c->fuse
+                           ? launch_finalize(c, c->nfused, mode, dt, s == 0 ? dt_used : nullptr)
+                           : launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr, Pcur);
       if (st != WCNS_OK) return st;
-      st = launch_sweeps3(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
+      double* Pn = c->fuse && !last ? Pnext : nullptr;
+      st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s], Pcur, Pn);
       if (st != WCNS_OK) return st;
-      continue;
+      if (Pn) std::swap(Pcur, Pnext);
     }
-    // stages 2 and 3 take the node primitives and block maxima that the
-    // previous stage's y-sweep and fixup left (c->fuse)
-    wcns_status st = s > 0 && c->fuse
-                         ? launch_finalize(c, c->nfused, mode, dt, nullptr)
-                         : launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr, Pcur);
-    if (st != WCNS_OK) return st;
-    double* Pn = c->fuse && s < 2 ? Pnext : nullptr;
-    st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s], Pcur, Pn);
-    if (st != WCNS_OK) return st;
-    if (Pn) std::swap(Pcur, Pnext);
   }
   return WCNS_OK;
+}
+
+wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used) {
+  if (!c || !W) return WCNS_ERR_ARG;
+  if (!isfinite(dt)) return WCNS_ERR_CFL;
+  return steps_impl(c, W, 1, dt, dt_used);
+}
+
+wcns_status wcns_ssprk3_steps(wcns_ctx* c, double* W, int32_t nsteps, double dt, double* dts) {
+  if (!c || !W || nsteps < 0) return WCNS_ERR_ARG;
+  if (!isfinite(dt)) return WCNS_ERR_CFL;
+  return steps_impl(c, W, nsteps, dt, dts);
 }
 
 wcns_status wcns_run(wcns_ctx* c, double* W, double t0, double t_end, double dt_fixed,

@@ -60,7 +60,8 @@ _lib = None
 
 EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
            "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
-           "wcns_ssprk3_step", "wcns_check_admissible", "wcns_profile", "wcns_profile_read",
+           "wcns_ssprk3_step", "wcns_ssprk3_steps", "wcns_check_admissible", "wcns_profile",
+           "wcns_profile_read",
            "wcns_selftest_division", "wcns_selftest_division_by", "wcns_issue_probe", "wcns_run",
            "wcns_batch_create", "wcns_batch_reset",
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
@@ -91,6 +92,7 @@ def lib():
         L.wcns_limit.argtypes = [vp, C.c_int32, dp, dp, dp, dp, dp, C.c_double]
         L.wcns_max_wavespeed.argtypes = [vp, dp, dp]
         L.wcns_ssprk3_step.argtypes = [vp, dp, C.c_double, dp]
+        L.wcns_ssprk3_steps.argtypes = [vp, dp, C.c_int32, C.c_double, dp]
         L.wcns_check_admissible.argtypes = [vp, dp, C.POINTER(C.c_longlong)]
         L.wcns_profile.argtypes = [vp, C.c_int32]
         L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
@@ -221,6 +223,16 @@ class Solver:
         _check(lib().wcns_rhs(self._ctx, _ptr(W), _ptr(dWdt), float(dt)), "wcns_rhs")
         return dWdt
 
+    def steps(self, W, n, dt=0.0, dts=None):
+        """n SSP-RK3 steps in place on W (wcns_ssprk3_steps): the same bits
+        as n calls of step(); dts: optional device float64 tensor of >= n
+        elements receiving each step's dt."""
+        self._chk(W)
+        if dts is not None and dts.numel() < n:
+            raise ValueError("dts holds fewer than n values")
+        _check(lib().wcns_ssprk3_steps(self._ctx, _ptr(W), int(n), float(dt), _ptr(dts)),
+               "wcns_ssprk3_steps")
+
     def step(self, W, dt=0.0, dt_used=None):
         """One SSP-RK3 step in place on W; dt <= 0 selects the CFL step.
         dt_used: optional device float64 tensor of >= 1 element."""
@@ -252,8 +264,7 @@ class Solver:
         self.set_stream(s.cuda_stream)
         try:
             with torch.cuda.graph(g, stream=s):
-                for k in range(n):
-                    self.step(W, 0.0, dt_used=dt_used[k:k + 1])
+                self.steps(W, n, 0.0, dts=dt_used)
         finally:
             self.set_stream(old)
         return g
@@ -279,8 +290,7 @@ class Solver:
                         g = self.capture_steps(W, chunk, buf)
                     g.replay()
                 else:
-                    for k in range(chunk):
-                        self.step(W, 0.0, dt_used=buf[k:k + 1])
+                    self.steps(W, chunk, 0.0, dts=buf)
                 dts = buf.cpu().tolist()
                 for d in dts:
                     t += d

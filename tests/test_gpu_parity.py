@@ -413,3 +413,40 @@ def test_water_air_tube_to_final_time():
     for v in range(5):
         l1 = np.abs(got[v] - ref[v]).sum() / np.abs(ref[v]).sum()
         assert l1 <= 1e-9, (v, l1)
+
+
+@pytest.mark.parametrize("case", ["2d_fp64", "2d_fp32_bulk", "2d_dirichlet", "1d", "3d"])
+def test_multi_step_call_equals_single_steps(case):
+    """wcns_ssprk3_steps: n steps in one call (in 2D each step's first stage
+    takes the primitives the previous step's last stage left) give the same
+    bits and the same per-step dt as n calls of wcns_ssprk3_step."""
+    prec = wcns.FP32_BULK if case == "2d_fp32_bulk" else wcns.FP64
+    if case == "1d":
+        spec = pb.water_air_shock_tube(200)
+    elif case == "3d":
+        spec = pb.random_smooth_state_3d(40, 21, 19, seed=8)
+    else:
+        spec = pb.random_smooth_state(70, 45, 43)
+    if case == "2d_dirichlet":
+        spec.bc = (pb.BC_DIRICHLET, pb.BC_EXTRAP, pb.BC_REFLECT, pb.BC_DIRICHLET)
+        spec.dirichlet_prim = [spec.prim[:, :, 0].T.copy(), None, None, spec.prim[:, -1, :].T.copy()]
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    sol = wcns.Solver.from_spec(spec, precision=prec)
+    n = 5
+    Wa, Wb = dev(W0), dev(W0)
+    da = torch.zeros(n, dtype=torch.float64, device="cuda")
+    db = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for k in range(n):
+        sol.step(Wa, 0.0, dt_used=da[k:k + 1])
+    sol.steps(Wb, n, 0.0, dts=db)
+    assert torch.equal(Wa, Wb) and torch.equal(da, db)
+    if prec == wcns.FP64:
+        W = W0
+        for _ in range(n):
+            W, _, _ = orc.ssprk3_step(s, W)
+        assert np.array_equal(host(Wb), W)
+    sol.steps(Wb, 0, 0.0)                    # nothing
+    assert torch.equal(Wa, Wb)
+    with pytest.raises(wcns.WcnsError):
+        sol.steps(Wb, -1, 0.0)
