@@ -1010,7 +1010,7 @@ struct wcns_batch {
   std::vector<wcns_grid> grids;
   std::vector<double*> W;
   std::vector<size_t> off;     // arena offset of each instance's scratch
-  KArgs* d_ka = nullptr;       // [4][n]: stages 1-3 and the RHS-only set
+  KArgs* d_ka = nullptr;       // [5][n]: stages 1-3, the RHS-only set, stage 1 of a continuing step
   size_t ka_cap = 0;
   Task* d_tasks = nullptr;
   size_t tasks_cap = 0;
@@ -1021,8 +1021,10 @@ struct wcns_batch {
   int dt_cap = 0;
   int ytile = 8, order = 2;
   bool x_lds = false;   // x-sweep with LDS windows (every instance has nx >= XLDS_MIN_NX)
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;     // first step of a call (node primitives by kb_node)
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph2 = nullptr;    // later steps (2D: primitives from the previous step)
+  hipGraphExec_t exec2 = nullptr;
   bool dirty = true;
 };
 
@@ -1048,12 +1050,13 @@ static size_t inst_pairs(const wcns_grid& g) {
   return f > nblk ? f : nblk;
 }
 
-// instance scratch: P, (2D) P2, U1, U2, block maxima, step record, (2D) L, edges
+// instance scratch: P, (2D) P2, P3, U1, U2, block maxima, step record, (2D)
+// L, edges
 static size_t inst_doubles(const wcns_grid& g, int nv) {
   const size_t N = (size_t)g.nx * g.ny;
   size_t nbr = (size_t)(g.ny + 1 + 1) / 2;
   size_t d = round32(5 * N) + 2 * round32(nv * N) + round32(2 * inst_pairs(g)) + 32;
-  if (g.ndim == 2) d += round32(5 * N) + round32(nv * N) + round32(nbr * 12 * g.nx);
+  if (g.ndim == 2) d += 2 * round32(5 * N) + round32(nv * N) + round32(nbr * 12 * g.nx);
   return d;
 }
 
@@ -1079,8 +1082,12 @@ static wcns_status batch_check_grids(int n, const wcns_grid* grids, int ndim) {
 static void batch_drop_graph(wcns_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->exec2) (void)hipGraphExecDestroy(b->exec2);
+  if (b->graph2) (void)hipGraphDestroy(b->graph2);
   b->exec = nullptr;
   b->graph = nullptr;
+  b->exec2 = nullptr;
+  b->graph2 = nullptr;
   b->dirty = true;
 }
 
@@ -1103,7 +1110,7 @@ static void xcd_chunk(std::vector<Task>& t) {
 // (re)build the per-instance arguments and the task lists
 static wcns_status batch_build(wcns_batch* b) {
   const int n = b->n;
-  std::vector<KArgs> ka(4 * (size_t)n);
+  std::vector<KArgs> ka(5 * (size_t)n);
   std::vector<int> inst_order(n);
   for (int k = 0; k < n; ++k) inst_order[k] = k;
   if (b->order >= 1)
@@ -1117,8 +1124,11 @@ static wcns_status batch_build(wcns_batch* b) {
     const long N = (long)g.nx * g.ny;
     double* base = b->arena + b->off[k];
     double* P = base;
-    double* P2 = g.ndim == 2 ? P + round32(5 * N) : nullptr;   // fused next-stage primitives
-    double* U1 = (P2 ? P2 : P) + round32(5 * N);
+    // fused next-stage primitives (2D): stage 1 reads P, 2 reads P2, 3 reads
+    // P3, and stage 3 leaves the next step's in P
+    double* P2 = g.ndim == 2 ? P + round32(5 * N) : nullptr;
+    double* P3 = g.ndim == 2 ? P2 + round32(5 * N) : nullptr;
+    double* U1 = (P3 ? P3 : P) + round32(5 * N);
     double* U2 = U1 + round32((size_t)b->nv * N);
     double* part = U2 + round32((size_t)b->nv * N);
     const int nblk = (int)((N + 255) / 256);
@@ -1155,7 +1165,10 @@ static wcns_status batch_build(wcns_batch* b) {
     double* outs[3] = {U1, U2, b->W[k]};
     const double cA[3] = {0.0, 0.75, 1.0 / 3.0};
     const double cB[3] = {1.0, 0.25, 2.0 / 3.0};
-    for (int s = 0; s < 4; ++s) {
+    for (int set = 0; set < 5; ++set) {
+      // sets 0-2: stages 1-3; 3: RHS only; 4: stage 1 of a step that follows
+      // another in the same call
+      const int s = set == 4 ? 0 : set;
       KArgs x = a;
       const double* Ws = s < 3 ? in[s] : b->W[k];
       x.W = Ws;
@@ -1166,16 +1179,16 @@ static wcns_status batch_build(wcns_batch* b) {
         x.Wc[4] = Ws + 3 * N; x.Wc[5] = Ws + 4 * N;
       }
       if (s < 3 && P2) {
-        // stage 1 runs kb_node into P; the y-sweep and fixup of stages 1 and
-        // 2 leave the next stage's primitives in P2, then P, and the block
-        // maxima kb_finalize reduces
-        const double* Pc = s == 1 ? P2 : P;
+        // the first step of a call runs kb_node into P; the y-sweep and
+        // fixup of every stage leave the next stage's primitives (P2, P3,
+        // then P for the next step) and the block maxima kb_finalize reduces
+        const double* Pc = s == 0 ? P : (s == 1 ? P2 : P3);
         x.P = Pc;
         for (int q = 0; q < 5; ++q) x.Pc[q] = Pc + q * N;
-        x.Pn = s == 0 ? P2 : (s == 1 ? P : nullptr);
+        x.Pn = s == 0 ? P2 : (s == 1 ? P3 : P);
         x.partn = part;
         x.fuse_off = (int)((long)((g.nx + 31) / 32) * nbr);
-        if (s > 0) x.nblk = (int)fused_pairs(g, yw);
+        if (set != 0) x.nblk = (int)fused_pairs(g, yw);
       }
       if (s < 3) {
         x.out = outs[s];
@@ -1197,7 +1210,7 @@ static wcns_status batch_build(wcns_batch* b) {
         x.dt_used = nullptr;
         x.live = nullptr;
       }
-      ka[(size_t)s * n + k] = x;
+      ka[(size_t)set * n + k] = x;
     }
   }
   b->x_lds = true;
@@ -1251,13 +1264,15 @@ static wcns_status batch_build(wcns_batch* b) {
   return WCNS_OK;
 }
 
-// launches of one stage (set s of the per-instance arguments)
+// launches of stage s (3: RHS only); cont: stage 1 of a step that follows
+// another in the same call
 template <int YW>
-static void batch_stage_launches(wcns_batch* b, int s) {
-  const KArgs* ka = b->d_ka + (size_t)s * b->n;
+static void batch_stage_launches(wcns_batch* b, int s, bool cont) {
+  const KArgs* ka = b->d_ka + (size_t)(s == 0 && cont ? 4 : s) * b->n;
   const bool b32 = b->precision == WCNS_FP32_BULK;
-  // 2D stages 2 and 3 take their node primitives from the previous stage
-  if (b->ndim == 2 && (s == 0 || s == 3))
+  // 2D: only the first stage of a call (and the RHS) runs kb_node; the
+  // others take their node primitives from the previous stage
+  if (b->ndim == 2 && ((s == 0 && !cont) || s == 3))
     hipLaunchKernelGGL(kb_node<true>, dim3(b->n_node), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_node);
   else if (b->ndim != 2)
     hipLaunchKernelGGL(kb_node<false>, dim3(b->n_node), dim3(256), 0, b->stream, ka, b->d_tasks + b->o_node);
@@ -1284,10 +1299,10 @@ static void batch_stage_launches(wcns_batch* b, int s) {
   }
 }
 
-static void batch_stage(wcns_batch* b, int s) {
-  if (b->ytile == 2) batch_stage_launches<2>(b, s);
-  else if (b->ytile == 8) batch_stage_launches<8>(b, s);
-  else batch_stage_launches<4>(b, s);
+static void batch_stage(wcns_batch* b, int s, bool cont = false) {
+  if (b->ytile == 2) batch_stage_launches<2>(b, s, cont);
+  else if (b->ytile == 8) batch_stage_launches<8>(b, s, cont);
+  else batch_stage_launches<4>(b, s, cont);
   if (s == 2)
     hipLaunchKernelGGL(kb_tick, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->d_live, b->n);
 }
@@ -1428,15 +1443,20 @@ wcns_status wcns_batch_step(wcns_batch* b, int32_t nsteps) {
   if (!b || nsteps < 0) return WCNS_ERR_ARG;
   if (b->dirty) {
     batch_drop_graph(b);
-    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    for (int s = 0; s < 3; ++s) batch_stage(b, s);
-    hipError_t e1 = hipGetLastError();
-    hipError_t e2 = hipStreamEndCapture(b->stream, &b->graph);
-    if (e1 != hipSuccess || e2 != hipSuccess) { batch_drop_graph(b); return WCNS_ERR_HIP; }
-    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    for (int cont = 0; cont < 2; ++cont) {
+      HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      for (int s = 0; s < 3; ++s) batch_stage(b, s, cont == 1);
+      hipError_t e1 = hipGetLastError();
+      hipError_t e2 = hipStreamEndCapture(b->stream, cont ? &b->graph2 : &b->graph);
+      if (e1 != hipSuccess || e2 != hipSuccess) { batch_drop_graph(b); return WCNS_ERR_HIP; }
+      HIP_TRY(hipGraphInstantiate(cont ? &b->exec2 : &b->exec, cont ? b->graph2 : b->graph,
+                                  nullptr, nullptr, 0));
+    }
     b->dirty = false;
   }
-  for (int k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  // the first step of the call recovers the node primitives of the states
+  // as given; the later ones take them from the step before
+  for (int k = 0; k < nsteps; ++k) HIP_TRY(hipGraphLaunch(k == 0 ? b->exec : b->exec2, b->stream));
   return WCNS_OK;
 }
 

@@ -31,8 +31,8 @@ from . import wcns
 
 def footprint_bytes(ndim: int, nx: int, ny: int) -> int:
     """Device bytes one solve holds: its state plus its batch scratch
-    (primitives, two stage states, block maxima; in 2D a second primitive
-    buffer for the next stage, L and the y-tile edges)."""
+    (primitives, two stage states, block maxima; in 2D two more primitive
+    buffers for the next stages, L and the y-tile edges)."""
     nv = 5 if ndim == 1 else 6
     N = nx * ny
     pairs = (N + 255) // 256
@@ -40,8 +40,8 @@ def footprint_bytes(ndim: int, nx: int, ny: int) -> int:
         nbr = (ny + 2) // 2
         pairs = max(pairs, ((nx + 31) // 32) * nbr + ((nbr - 1) * nx + 255) // 256)
     d = nv * N + 5 * N + 2 * nv * N + 2 * pairs + 64
-    if ndim == 2:
-        d += 5 * N + nv * N + ((ny + 2) // 2) * 12 * nx
+    if ndim == 2:   # two more primitive buffers (next-stage primitives), L, edges
+        d += 2 * 5 * N + nv * N + ((ny + 2) // 2) * 12 * nx
     return 8 * d
 
 

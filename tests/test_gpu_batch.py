@@ -85,6 +85,39 @@ def test_batch_matches_oracle_and_reset():
     b.close()
 
 
+def test_batch_step_limits_and_states_changed_between_calls():
+    """Instances that run out of steps inside a multi-step call stop where
+    their limit says, and a later call starts from the states as they are
+    then (here one of them rewritten between the calls)."""
+    specs = instances(6)
+    W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
+
+    refs = []
+    for sp, w in zip(specs, W0):
+        sol = wcns.Solver.from_spec(sp)
+        Wd = dev(w)
+        seq = []
+        for _ in range(6):
+            sol.step(Wd, 0.0)
+            seq.append(host(Wd))
+        refs.append(seq)
+    states = [dev(w) for w in W0]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)
+    limits = [1, 2, 3, 4, 5, 5]
+    b.set_steps(limits)
+    b.step(5)
+    assert list(b.steps_left()) == [0] * 6
+    for k in range(6):
+        assert np.array_equal(host(states[k]), refs[k][limits[k] - 1]), k
+    states[2].copy_(dev(W0[2]))
+    b.set_steps([1, 1, 2, 1, 1, 1])
+    b.step(2)
+    for k in range(6):
+        want = refs[k][1] if k == 2 else refs[k][limits[k]]
+        assert np.array_equal(host(states[k]), want), k
+    b.close()
+
+
 def test_autotune_picks_a_schedule():
     specs = instances(6)
     states = [dev(oracle_W(sp, oracle_setup(sp))) for sp in specs]
