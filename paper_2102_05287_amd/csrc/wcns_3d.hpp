@@ -709,7 +709,7 @@ __global__ __launch_bounds__(64 * XW) void k3_sweep_xl(K3Args a) {
       }
     }
   }
-  __syncthreads();
+  wave_lds_sync();   // the window is this wave's own
   double Gm[7] = {0, 0, 0, 0, 0, 0, 0}, Gp[7] = {0, 0, 0, 0, 0, 0, 0};
   if (lane < t.nA + t.nB) {
     const LdsLoad3 ld{win + t.base(lane), 1, XWIN};

@@ -30,10 +30,10 @@ struct wcns_ctx {
   double dx, dy;
   KArgs base;
   double *P, *L, *U1, *U2, *partial, *step, *dirW, *dirP, *edge;
-  // 2D steps: the y-sweep and fixup of stages 1 and 2 write the next
-  // stage's node primitives into P2 (the two buffers alternate) and their
-  // block maxima into `partial` (nfused pairs), so only k_finalize runs
-  // before stages 2 and 3
+  // 2D steps: the y-sweep and fixup of every stage but the last of a call
+  // write the next stage's node primitives into the other buffer (P and P2
+  // alternate) and their block maxima into `partial` (nfused pairs), so
+  // only the first stage of a call runs k_node
   double* P2;
   int fuse, nfused;
   unsigned long long* count;

@@ -2,8 +2,10 @@
 // together.  Each phase of an SSP-RK3 stage (node primitives, dt/lambda,
 // x-sweep, y-sweep, y-tile fixup) is one launch over a device task list of
 // (instance, tile) pairs, reading per-instance arguments from a device array
-// prepared once per stage.  A whole step is therefore a fixed sequence of 15
-// launches that is captured once into a HIP graph and replayed.
+// prepared once per stage.  A whole step is therefore a fixed sequence of
+// launches, captured once into a HIP graph and replayed (in 2D a second
+// graph without the node launch serves the later steps of a call, whose
+// node primitives the previous step's last stage left).
 #pragma once
 #include "wcns_kernels.hpp"
 

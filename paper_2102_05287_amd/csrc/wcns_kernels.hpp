@@ -567,6 +567,31 @@ __device__ __forceinline__ double write_cell(const KArgs& a, double* dst, long i
   return v;
 }
 
+// The inputs of one finished cell's write_cell, loaded ahead of use: L_x
+// and (RK stage) U^n and W of component k, and dt
+struct CellIn {
+  double lx[6], un[6], w[6], dt;
+};
+__device__ __forceinline__ void load_cell_in(const KArgs& a, long idx, long N, CellIn& c) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) c.lx[k] = a.Lx[k * N + idx];
+  if (a.out_mode != OUT_STORE) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      c.un[k] = a.Un[k * N + idx];
+      c.w[k] = a.W[k * N + idx];
+    }
+    c.dt = a.step[0];
+  }
+}
+// write_cell on preloaded inputs (the same arithmetic)
+__device__ __forceinline__ double write_cell_in(const KArgs& a, double* dst, long idx, long N, int k,
+                                                double L, const CellIn& c) {
+  const double v = a.out_mode == OUT_STORE ? L : a.ca * c.un[k] + a.cb * (c.w[k] + c.dt * L);
+  dst[k * N + idx] = v;
+  return v;
+}
+
 // Node primitives of a finished cell of the next stage's state X (state
 // order) into a.Pn, and its wave speeds |u|+c, |v|+c into the running
 // maxima: k_node's arithmetic [Sec. 2, 3.3] on the values just written.
@@ -916,6 +941,14 @@ struct LdsLoadX {
   }
 };
 
+// LDS written by this wave is visible to all its lanes, without waiting
+// for the other waves of the block (for LDS only this wave uses)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Geometry of window tile `tile` over N cells in rows of nx (nx >= XLDS_MIN_NX)
 struct XWin {
   long c0;
@@ -952,7 +985,7 @@ __device__ __forceinline__ XWin x_window(int nx, long N, long tile) {
   return t;
 }
 
-// One tile per wave (`on` false: the wave only joins the block barrier).
+// One tile per wave (`on` false: the wave has no tile and writes nothing).
 template <bool HAS_T, bool DIRI, bool B32>
 __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool on, double* win) {
   const int lane = threadIdx.x & 63;
@@ -989,7 +1022,7 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
       }
     }
   }
-  __syncthreads();
+  wave_lds_sync();   // the window is this wave's own
   const bool active = lane < t.nA + t.nB;
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
@@ -1213,6 +1246,11 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
     }
     face_flux_core<1, true, B32>(a, ld, a.step[2], Gm, Gp);
   }
+  // the owned cell's L_x, U^n and W, loaded while the block exchanges G^-
+  const bool own = active && fr != FR - 1 && k < ny;
+  const long idx = (long)k * nx + i;
+  CellIn cin;
+  if (own) load_cell_in(a, idx, N, cin);
   double Gn[6];   // G^- of face row k + 1 when r == 0 (same wave, upper half)
 #pragma unroll
   for (int v = 0; v < 6; ++v) Gn[v] = __shfl(Gm[v], (lane + 32) & 63, 64);
@@ -1234,11 +1272,8 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
     }
   }
   __syncthreads();
-  const int j = k;
-  const bool own = active && fr != FR - 1 && j < ny;
   double mx = 0.0, my = 0.0;
   if (own) {
-    const long idx = (long)j * nx + i;
     double X[6];
 #pragma unroll
     for (int v = 0; v < 6; ++v) {
@@ -1247,9 +1282,9 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
       {
         const double up = r == 0 ? Gn[v] : sG[((w + 1) * 6 + v) * 32 + col];
         double Ly = hdiv(-(up - Gp[v]), a.dy, a.rdy);
-        L = a.Lx[s * N + idx] + Ly;
+        L = cin.lx[s] + Ly;
       }
-      X[s] = write_cell(a, a.out, idx, N, s, L);
+      X[s] = write_cell_in(a, a.out, idx, N, s, L, cin);
     }
     if (a.Pn) next_prims(a, idx, N, X, mx, my);
   }
@@ -1294,15 +1329,25 @@ __device__ __forceinline__ bool fixup_cell(const KArgs& a, long t, int yw, long&
   const double* lo = a.edge + (long)b * 12 * nx + 6 * nx;       // G^+ of face row j
   const double* hi = a.edge + (long)(b + 1) * 12 * nx;          // G^- of face row j+1
   idx = (long)j * nx + i;
+  // every input first: a store to a.out may alias a later load, so loads
+  // left between the stores would each wait for the one before
+  double gl[6], gh[6];
+#pragma unroll
+  for (int v = 0; v < 6; ++v) {
+    gl[v] = lo[v * nx + i];
+    gh[v] = hi[v * nx + i];
+  }
+  CellIn cin;
+  load_cell_in(a, idx, N, cin);
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
     const int s = state_index(1, v, true);
     double L;
     {
-      double Ly = hdiv(-(hi[v * nx + i] - lo[v * nx + i]), a.dy, a.rdy);
-      L = a.Lx[s * N + idx] + Ly;
+      double Ly = hdiv(-(gh[v] - gl[v]), a.dy, a.rdy);
+      L = cin.lx[s] + Ly;
     }
-    X[s] = write_cell(a, a.out, idx, N, s, L);
+    X[s] = write_cell_in(a, a.out, idx, N, s, L, cin);
   }
   return true;
 }
