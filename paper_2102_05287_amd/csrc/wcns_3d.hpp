@@ -570,6 +570,34 @@ __device__ __forceinline__ void write_cell3(const K3Args& a, long idx, long N, i
   }
 }
 
+// The inputs of one cell's final write, loaded ahead of the stores (a store
+// to a.out may alias a later load, so a load left between the stores waits
+// for the one before): the earlier passes' L and, in the last pass of an RK
+// stage, U^n, W and dt
+struct CellIn3 {
+  double lin[7], un[7], w[7], dt;
+};
+__device__ __forceinline__ void load_cell_in3(const K3Args& a, long idx, long N, CellIn3& c) {
+#pragma unroll
+  for (int k = 0; k < 7; ++k) c.lin[k] = a.Lin[k * N + idx];
+  if (a.last && a.out_mode != OUT_STORE) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      c.un[k] = a.Un[k * N + idx];
+      c.w[k] = a.W[k * N + idx];
+    }
+    c.dt = a.step[0];
+  }
+}
+// write_cell3 (or L alone before the last pass) on preloaded inputs
+__device__ __forceinline__ void write_cell3_in(const K3Args& a, long idx, long N, int k, double L,
+                                               const CellIn3& c) {
+  if (a.last && a.out_mode != OUT_STORE)
+    a.out[k * N + idx] = a.ca * c.un[k] + a.cb * (c.w[k] + c.dt * L);
+  else
+    a.out[k * N + idx] = L;
+}
+
 // ------------------------------------------------------------------ kernels
 __global__ __launch_bounds__(256) void k3_node(K3Args a, double* P, double* partial) {
   const long N = (long)a.nx * a.ny * a.nz;
@@ -883,6 +911,11 @@ __device__ __forceinline__ void sweep3_tile32(const K3Args& a, double* tile) {
                        ldc(a.Pc[4], o2), ldc(a.Pc[5], o2), ldc(a.Pc[4], o3), ldc(a.Pc[5], o3)};
     face_flux3_core<DIR>(a, ld, a.step[1 + DIR], Gm, Gp);
   }
+  // the owned cell's inputs, loaded while the block exchanges G^-
+  const bool own = active && fr != FR - 1 && k < nline;
+  const long idx = slab + (long)k * stride + col;
+  CellIn3 cin;
+  if (own) load_cell_in3(a, idx, N, cin);
   double Gn[7];   // G^- of face row k + 1 when r == 0 (same wave, upper half)
 #pragma unroll
   for (int v = 0; v < 7; ++v) Gn[v] = __shfl(Gm[v], (lane + 32) & 63, 64);
@@ -904,15 +937,13 @@ __device__ __forceinline__ void sweep3_tile32(const K3Args& a, double* tile) {
     }
   }
   __syncthreads();
-  if (!active || fr == FR - 1 || k >= nline) return;
-  const long idx = slab + (long)k * stride + col;
+  if (!own) return;
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const int s = state_index3(DIR, v);
     const double up = r == 0 ? Gn[v] : sG[((w + 1) * 7 + v) * 32 + cl];
-    const double L = a.Lin[s * N + idx] + hdiv(-(up - Gp[v]), h, rh);
-    if (a.last) write_cell3(a, idx, N, s, L);
-    else a.out[s * N + idx] = L;
+    const double L = cin.lin[s] + hdiv(-(up - Gp[v]), h, rh);
+    write_cell3_in(a, idx, N, s, L, cin);
   }
 }
 
@@ -949,12 +980,19 @@ __global__ __launch_bounds__(256) void k3_fixup(K3Args a) {
   const double* lo = a.edge + ((sl * a.nbr + b) * 14 + 7) * ncol;   // G^+ of face row j
   const double* hi = a.edge + ((sl * a.nbr + b + 1) * 14) * ncol;   // G^- of face row j+1
   const long idx = sl * plane + (long)j * stride + col;
+  double gl[7], gh[7];
+#pragma unroll
+  for (int v = 0; v < 7; ++v) {
+    gl[v] = lo[v * ncol + col];
+    gh[v] = hi[v * ncol + col];
+  }
+  CellIn3 cin;
+  load_cell_in3(a, idx, N, cin);
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const int s = state_index3(DIR, v);
-    const double L = a.Lin[s * N + idx] + hdiv(-(hi[v * ncol + col] - lo[v * ncol + col]), h, rh);
-    if (a.last) write_cell3(a, idx, N, s, L);
-    else a.out[s * N + idx] = L;
+    const double L = cin.lin[s] + hdiv(-(gh[v] - gl[v]), h, rh);
+    write_cell3_in(a, idx, N, s, L, cin);
   }
 }
 
