@@ -100,12 +100,24 @@ __global__ __launch_bounds__(RUN1D_THREADS) void k_run1d(Run1D* runs) {
       __syncthreads();
       // flux difference and the SSP-RK3 stage combination [Sec. 4.1, 5.3]
       for (int i = tid; i < n; i += RUN1D_THREADS) {
+        // every input first: a store to `out` may alias a later load, so
+        // loads left between the stores would each wait for the one before
+        double gr[6], gl[6], wn[6], wi[6];
 #pragma unroll
         for (int v = 0; v < 6; ++v) {
           if (v == 3) continue;
-          const double L = hdiv(-(Gm[v * (N + 1) + i + 1] - Gp[v * (N + 1) + i]), a0.dx, a0.rdx);
           const int k = state_index(0, v, false);
-          out[k * N + i] = ca[s] * W[k * N + i] + cb[s] * (in[k * N + i] + dt * L);
+          gr[v] = Gm[v * (N + 1) + i + 1];
+          gl[v] = Gp[v * (N + 1) + i];
+          wn[v] = W[k * N + i];
+          wi[v] = in[k * N + i];
+        }
+#pragma unroll
+        for (int v = 0; v < 6; ++v) {
+          if (v == 3) continue;
+          const double L = hdiv(-(gr[v] - gl[v]), a0.dx, a0.rdx);
+          const int k = state_index(0, v, false);
+          out[k * N + i] = ca[s] * wn[v] + cb[s] * (wi[v] + dt * L);
         }
       }
       __syncthreads();
