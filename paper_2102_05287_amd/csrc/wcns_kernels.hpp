@@ -547,13 +547,14 @@ __device__ __forceinline__ int state_index(int dir, int v, bool has_t) {
   return v;
 }
 
-// final write of one cell: L (store) or the SSP-RK3 combination
+// maximum over the 64 lanes of a wave
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
   return v;
 }
 
+// final write of one cell: L (store) or the SSP-RK3 combination [Sec. 4.1]
 __device__ __forceinline__ double write_cell(const KArgs& a, double* dst, long idx, long N, int k,
                                              double L) {
   double v;
@@ -568,16 +569,19 @@ __device__ __forceinline__ double write_cell(const KArgs& a, double* dst, long i
 }
 
 // The inputs of one finished cell's write_cell, loaded ahead of use: L_x
-// and (RK stage) U^n and W of component k, and dt
+// (2D) and (RK stage) U^n and W of the NC state components, and dt
 struct CellIn {
   double lx[6], un[6], w[6], dt;
 };
+template <int NC = 6, bool LX = true>
 __device__ __forceinline__ void load_cell_in(const KArgs& a, long idx, long N, CellIn& c) {
+  if (LX) {
 #pragma unroll
-  for (int k = 0; k < 6; ++k) c.lx[k] = a.Lx[k * N + idx];
+    for (int k = 0; k < NC; ++k) c.lx[k] = a.Lx[k * N + idx];
+  }
   if (a.out_mode != OUT_STORE) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < NC; ++k) {
       c.un[k] = a.Un[k * N + idx];
       c.w[k] = a.W[k * N + idx];
     }
@@ -1035,13 +1039,15 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
   if (!t.owner(lane)) return;
   const long c = t.cell(lane);
   double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;
+  CellIn cin;   // 1D: the stage's inputs, loaded before the first store
+  if (!HAS_T) load_cell_in<5, false>(a, c, N, cin);
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
     if (!HAS_T && v == 3) continue;
     const double L = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
     const int k = state_index(0, v, HAS_T);
     if (HAS_T) dst[k * N + c] = L;
-    else write_cell(a, a.out, c, N, k, L);
+    else write_cell_in(a, a.out, c, N, k, L, cin);
   }
 }
 
