@@ -253,8 +253,8 @@ wcns_status wcns_batch_create(int32_t n, const wcns_grid* grids, const wcns_eos*
  * stream; the captured graph is rebuilt on the next step. */
 wcns_status wcns_batch_reset(wcns_batch* b, int32_t n, const wcns_grid* grids, double* const* W);
 
-/* Schedule: ytile in {2, 4, 8} y-face rows per y-sweep block (32 columns,
- * two face rows per wave; default 8); order 0 = instances in the given
+/* Schedule: ytile in {2, 4, 8, 16} y-face rows per y-sweep block (32
+ * columns, two face rows per wave; default 16); order 0 = instances in the given
  * order, 1 = largest instance first, 2 = tiles of an instance kept on one
  * XCD (blocks are dealt round-robin to the 8 XCDs; default).  Takes effect
  * at the next step (the graph is re-captured). */

@@ -16,7 +16,7 @@
 //                stencil window in LDS: L_x (k3_sweep_x, global loads, for
 //                rows narrower than 61 cells)
 //   k3_sweep_l   y-lines (per z slab) or z-lines: one block over 32
-//                consecutive columns x 8 face rows (4 waves), stencil rows
+//                consecutive columns x 16 face rows (8 waves), stencil rows
 //                staged in LDS; the y pass adds L_y to L in place, the z
 //                pass finishes L = (L_x + L_y) + L_z and applies the SSP-RK3
 //                stage combination
@@ -28,15 +28,17 @@
 
 namespace wcns {
 
-// Strided-pass tiles: 32 columns x 8 face rows (4 waves, four blocks per
-// CU) or 64 columns x 4 face rows (one face row per wave; 6 rows measured
-// 1.5x slower: a 6-wave block cannot spread evenly over a CU's 4 SIMDs).
+// Strided-pass tiles: 32 columns x 16 face rows (8 waves, 59 KB of LDS, two
+// blocks per CU; against 8-row tiles the passes run ~1% slower but the
+// fixups have half the rows: 1.008x per RHS at 256^3) or 64 columns x 4
+// face rows (one face row per wave; 6 rows measured 1.5x slower: a 6-wave
+// block cannot spread evenly over a CU's 4 SIMDs).
 #ifndef WCNS_L3CW
 #define WCNS_L3CW 32
 #endif
 constexpr int L3_CW = WCNS_L3CW;
 #ifndef WCNS_YTILE3
-#define WCNS_YTILE3 (WCNS_L3CW == 32 ? 8 : 4)
+#define WCNS_YTILE3 (WCNS_L3CW == 32 ? 16 : 4)
 #endif
 constexpr int YW3 = WCNS_YTILE3;   // face rows per tile
 constexpr int L3_THREADS = L3_CW == 32 ? 32 * YW3 : 64 * YW3;
@@ -862,8 +864,8 @@ __device__ __forceinline__ void sweep3_tile64(const K3Args& a, double* tile) {
 // rho ctilde^2 of the two centre nodes from global memory into registers).
 // Cell row kb + 2w takes G^- of face row kb + 2w + 1 from lane + 32 of its
 // own wave; cell row kb + 2w + 1 takes it from wave w + 1 through LDS; the
-// tile's first G^- and last G^+ go to the edge buffer for k3_fixup.  The
-// tile is 36.6 KB: four 4-wave blocks per CU.
+// tile's first G^- and last G^+ go to the edge buffer for k3_fixup.  At 16
+// face rows the tile is 59 KB: two 8-wave blocks per CU.
 template <int DIR>
 __device__ __forceinline__ void sweep3_tile32(const K3Args& a, double* tile) {
   constexpr int FR = YW3, W = YW3 / 2, ROWS = YW3 + 5;

@@ -1019,7 +1019,7 @@ struct wcns_batch {
   double* d_dt = nullptr;      // per-instance dt of the last step
   int32_t* d_live = nullptr;   // per-instance steps left (frozen at 0)
   int dt_cap = 0;
-  int ytile = 8, order = 2;
+  int ytile = 16, order = 2;
   bool x_lds = false;   // x-sweep with LDS windows (every instance has nx >= XLDS_MIN_NX)
   hipGraph_t graph = nullptr;     // first step of a call (node primitives by kb_node)
   hipGraphExec_t exec = nullptr;
@@ -1302,6 +1302,7 @@ static void batch_stage_launches(wcns_batch* b, int s, bool cont) {
 static void batch_stage(wcns_batch* b, int s, bool cont = false) {
   if (b->ytile == 2) batch_stage_launches<2>(b, s, cont);
   else if (b->ytile == 8) batch_stage_launches<8>(b, s, cont);
+  else if (b->ytile == 16) batch_stage_launches<16>(b, s, cont);
   else batch_stage_launches<4>(b, s, cont);
   if (s == 2)
     hipLaunchKernelGGL(kb_tick, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->d_live, b->n);
@@ -1432,7 +1433,8 @@ wcns_status wcns_batch_reset(wcns_batch* b, int32_t n, const wcns_grid* grids, d
 }
 
 wcns_status wcns_batch_configure(wcns_batch* b, int32_t ytile, int32_t order) {
-  if (!b || (ytile != 2 && ytile != 4 && ytile != 8) || order < 0 || order > 2) return WCNS_ERR_ARG;
+  if (!b || (ytile != 2 && ytile != 4 && ytile != 8 && ytile != 16) || order < 0 || order > 2)
+    return WCNS_ERR_ARG;
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->ytile = ytile;
   b->order = order;

@@ -34,12 +34,14 @@ namespace wcns {
 
 enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 enum { OUT_STORE = 0, OUT_RK = 1 };
-// y-face rows per y-sweep block: 8 with the LDS-staged tile of 9 values
-// (two 8-wave blocks per CU, four waves per SIMD; half the straddling cell
-// rows of 4-row tiles), measured 1.03x (FP64) and 1.09x (FP32 bulk) faster
-// per y-sweep + fixup than 4-row tiles
+// y-face rows per y-sweep tile (single grid): 16 on 32 columns, 8 waves
+// and 48.6 KB of LDS per block, two blocks per CU.  Against 8-row tiles
+// (four 4-wave blocks per CU) the y-sweep itself runs 0.5-2% slower, but
+// the fixup has half the straddling cell rows: 1024^2 step 1.2%, 2048^2
+// FP64 1.1% and FP32 bulk 1.7% faster.  (Named Y_WAVES for the 64-column
+// tile, where a block has one wave per face row.)
 #ifndef WCNS_YTILE
-#define WCNS_YTILE 8
+#define WCNS_YTILE 16
 #endif
 constexpr int Y_WAVES = WCNS_YTILE;
 
@@ -1185,8 +1187,9 @@ __device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by,
 // kb + 2w + 1 from lane + 32 of its own wave (shuffle); cell row kb + 2w + 1
 // takes it from wave w + 1 through LDS; the tile's first G^- and last G^+
 // go to the edge buffer for the fixup.  Half the columns of the 64-column
-// tile at the same face rows: a quarter of the LDS per wave pair, so four
-// 4-wave blocks share a CU instead of two 8-wave ones.
+// tile: at 8 face rows a quarter of the LDS per wave pair (four 4-wave
+// blocks per CU); at 16 face rows, two 8-wave blocks per CU with half the
+// fixup rows.
 // (part: this block's slot for its block maxima when a.Pn is set)
 template <int FR, bool DIRI, bool B32>
 __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, double* tile, long part) {
@@ -1304,6 +1307,7 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
 constexpr int Y_CW = WCNS_YCW;
 // threads per y-sweep block
 constexpr int Y_THREADS = Y_CW == 32 ? 32 * Y_WAVES : 64 * Y_WAVES;
+static_assert(Y_THREADS <= 512, "y-tile block too large: 64-column tiles take at most 8 face rows");
 
 // waves per SIMD the y-sweep is compiled for (VGPR budget 512 / this)
 #ifndef WCNS_YWPE

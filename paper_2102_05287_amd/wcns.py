@@ -506,7 +506,7 @@ class Batch:
         import torch
         torch.cuda.current_stream().wait_stream(self.stream)
 
-    def configure(self, ytile=8, order=2):
+    def configure(self, ytile=16, order=2):
         _check(lib().wcns_batch_configure(self._b, int(ytile), int(order)), "wcns_batch_configure")
 
     def reset(self, grids, states):
@@ -564,7 +564,7 @@ def autotune(batch, trials=3, candidates=None):
     (best, {candidate: seconds})."""
     import time
     if candidates is None:
-        candidates = [(y, o) for y in (2, 4, 8) for o in (0, 1, 2)]
+        candidates = [(y, o) for y in (4, 8, 16) for o in (0, 1, 2)]
     times = {}
     for cand in candidates:
         batch.configure(*cand)

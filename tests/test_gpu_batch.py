@@ -49,7 +49,7 @@ def test_batch_equals_single_solves(precision):
         for _ in range(3):
             sol.step(Wd, 0.0)
         ref.append(host(Wd))
-    for ytile, order in ((4, 0), (2, 1), (8, 2)):
+    for ytile, order in ((4, 0), (2, 1), (8, 2), (16, 1)):
         states = [dev(w) for w in W0]
         b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states, precision=precision)
         b.configure(ytile, order)
