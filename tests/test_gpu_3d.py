@@ -24,7 +24,7 @@ def test_rhs_3d_random_states(shape, seed):
 
 @pytest.mark.parametrize("shape,bc", [
     ((61, 13, 8), (pb.BC_PERIODIC,) * 2 + (pb.BC_REFLECT, pb.BC_EXTRAP) + (pb.BC_EXTRAP, pb.BC_REFLECT)),
-    ((62, 7, 19), (pb.BC_REFLECT,) * 2 + (pb.BC_PERIODIC,) * 2 + (pb.BC_PERIODIC,) * 2),
+    ((62, 15, 31), (pb.BC_REFLECT,) * 2 + (pb.BC_PERIODIC,) * 2 + (pb.BC_PERIODIC,) * 2),
     ((97, 12, 6), (pb.BC_EXTRAP,) * 4 + (pb.BC_REFLECT,) * 2)])
 def test_rhs_3d_lds_windows_and_tiles(shape, bc):
     """x pass with LDS windows (rows of 61 cells and more, tiles crossing row

@@ -131,8 +131,11 @@ def test_rhs_1d_water_air_initial_and_midrun():
 
 
 @pytest.mark.parametrize("nx,ny,seed", [(70, 45, 1), (130, 67, 2), (64, 64, 3), (17, 9, 4),
-                                        (200, 3, 5), (3, 150, 6)])
+                                        (200, 3, 5), (3, 150, 6), (40, 47, 7)])
 def test_rhs_2d_random_states(nx, ny, seed):
+    """Several y-tiles of 16 face rows with ragged last ones (ny 45, 67, 150;
+    64: a one-row last tile), three full tiles (47), single tiles and thin
+    grids."""
     rhs_case(pb.random_smooth_state(nx, ny, seed))
 
 
