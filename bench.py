@@ -510,6 +510,12 @@ def main():
                             "and sqrt weighted by op_weights; peak = FP64 VALU issue rate "
                             "256 CU x 64 lanes x 2.4 GHz",
                 "op_weights": dict(OP_WEIGHTS)}
+    # both sweeps, each against the same peak (the dominant one is above)
+    roofline["kernels"] = {
+        k: {"avg_launch_ms": prof[k][0] / prof[k][1],
+            "achieved": ops[k] / (prof[k][0] / 1e3 / prof[k][1]) / 1e12,
+            "frac": ops[k] / (prof[k][0] / 1e3 / prof[k][1]) / VALU_F64_SLOTS}
+        for k in ("sweep_x", "sweep_y") if prof[k][1]}
     per_kernel = {k: {"ms_total": v[0], "launches": v[1]} for k, v in prof.items() if v[1]}
 
     # pure RHS rate (no stage combination) for reference
