@@ -44,6 +44,19 @@ class _Grid(C.Structure):
                 ("z0", C.c_double), ("z1", C.c_double)]
 
 
+def _state_ptrs(grids, states):
+    """Device pointers of the batch states, each checked against its grid:
+    contiguous device float64 of [nvar][ny][nx] (nvar 6 in 2D, 5 in 1D)."""
+    if len(states) != len(grids):
+        raise ValueError(f"{len(grids)} grids but {len(states)} states")
+    for k, (g, t) in enumerate(zip(grids, states)):
+        n = (6 if g.ndim == 2 else 5) * g.nx * max(g.ny, 1)
+        _dev_f64(t, n, f"state {k}")
+        if t.numel() != n:
+            raise ValueError(f"state {k}: {n} elements expected, got {t.numel()}")
+    return (C.c_void_p * len(states))(*[t.data_ptr() for t in states])
+
+
 class _Eos(C.Structure):
     _fields_ = [("gamma", C.c_double * 2), ("pinf", C.c_double * 2)]
 
@@ -142,6 +155,18 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _dev_f64(t, n, what):
+    """Check that t is a contiguous device float64 tensor of at least n
+    elements (the library writes or reads that many doubles through its
+    pointer); None passes."""
+    import torch
+    if t is None:
+        return
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and t.numel() >= n):
+        raise ValueError(f"{what}: a contiguous device float64 tensor of >= {n} elements is needed")
+
+
 class Solver:
     """One grid + fluids + options, bound to a device context.
 
@@ -204,9 +229,10 @@ class Solver:
         return torch.empty(shape, dtype=torch.float64, device="cuda")
 
     def _chk(self, t):
-        import torch
-        assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "device f64 contiguous"
-        assert t.numel() == self.nvar * self.nx * self.ny * self.nz, "shape [nvar]([nz])[ny][nx]"
+        n = self.nvar * self.nx * self.ny * self.nz
+        _dev_f64(t, n, "state")
+        if t.numel() != n:
+            raise ValueError(f"state: {n} elements ([nvar]([nz])[ny][nx]) expected, got {t.numel()}")
 
     # ----------------------------------------------------------- entry points
     def prim_to_cons(self, V, W=None):
@@ -228,8 +254,7 @@ class Solver:
         as n calls of step(); dts: optional device float64 tensor of >= n
         elements receiving each step's dt."""
         self._chk(W)
-        if dts is not None and dts.numel() < n:
-            raise ValueError("dts holds fewer than n values")
+        _dev_f64(dts, max(int(n), 0), "dts")
         _check(lib().wcns_ssprk3_steps(self._ctx, _ptr(W), int(n), float(dt), _ptr(dts)),
                "wcns_ssprk3_steps")
 
@@ -237,6 +262,7 @@ class Solver:
         """One SSP-RK3 step in place on W; dt <= 0 selects the CFL step.
         dt_used: optional device float64 tensor of >= 1 element."""
         self._chk(W)
+        _dev_f64(dt_used, 1, "dt_used")
         _check(lib().wcns_ssprk3_step(self._ctx, _ptr(W), float(dt), _ptr(dt_used)),
                "wcns_ssprk3_step")
         return W
@@ -317,6 +343,7 @@ class Solver:
         one device launch (wcns_run); W in place.  dts: optional device f64
         tensor receiving the dt of each step.  Returns (steps, t)."""
         self._chk(W)
+        _dev_f64(dts, 0, "dts")
         n = C.c_int64(0)
         tt = C.c_double(0.0)
         cap = 0 if dts is None else dts.numel()
@@ -329,6 +356,7 @@ class Solver:
         self._chk(W)
         if out is None:
             out = torch.zeros(3 if self.ndim == 3 else 2, dtype=torch.float64, device="cuda")
+        _dev_f64(out, 3 if self.ndim == 3 else 2, "out")
         _check(lib().wcns_max_wavespeed(self._ctx, _ptr(W), _ptr(out)), "wcns_max_wavespeed")
         return out
 
@@ -338,6 +366,10 @@ class Solver:
         nf = (self.nx + 1) * self.ny if direction == 0 else self.nx * (self.ny + 1)
         if G_out is None:
             G_out = torch.empty((2, self.nvar, nf), dtype=torch.float64, device="cuda")
+        _dev_f64(G_ho, (self.nvar + 1) * nf, "G_ho")
+        _dev_f64(G_lo, (self.nvar + 1) * nf, "G_lo")
+        _dev_f64(G_out, 2 * self.nvar * nf, "G_out")
+        _dev_f64(theta, nf, "theta")
         _check(lib().wcns_limit(self._ctx, int(direction), _ptr(W), _ptr(G_ho), _ptr(G_lo),
                                 _ptr(G_out), _ptr(theta), float(dt)), "wcns_limit")
         return G_out
@@ -362,6 +394,8 @@ class Solver:
 def selftest_division(a, b):
     """(IEEE quotient, kernels' division core) of device f64 tensors a, b."""
     import torch
+    _dev_f64(a, 0, "a")
+    _dev_f64(b, a.numel(), "b")
     qi = torch.empty_like(a)
     qc = torch.empty_like(a)
     _check(lib().wcns_selftest_division(_ptr(a), _ptr(b), _ptr(qi), _ptr(qc), a.numel(),
@@ -374,6 +408,7 @@ def selftest_division_by(a, b: float):
     """(IEEE quotient, kernels' constant-divisor path) of device tensor a and
     the scalar b; None when b does not take that path."""
     import torch
+    _dev_f64(a, 0, "a")
     qi = torch.empty_like(a)
     qc = torch.empty_like(a)
     rc = lib().wcns_selftest_division_by(_ptr(a), float(b), _ptr(qi), _ptr(qc), a.numel(),
@@ -487,7 +522,7 @@ class Batch:
         e.gamma[0], e.gamma[1] = gamma
         e.pinf[0], e.pinf[1] = pinf
         p = default_params(**params)
-        ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in states])
+        ptrs = _state_ptrs(grids, states)
         ctx = C.c_void_p()
         _check(lib().wcns_batch_create(n, G, C.byref(e), C.byref(p), int(precision), ptrs,
                                        int(capacity_cells), C.byref(ctx)), "wcns_batch_create")
@@ -512,7 +547,7 @@ class Batch:
     def reset(self, grids, states):
         n = len(grids)
         G = (_Grid * n)(*grids)
-        ptrs = (C.c_void_p * n)(*[t.data_ptr() for t in states])
+        ptrs = _state_ptrs(grids, states)
         self._enter()
         _check(lib().wcns_batch_reset(self._b, n, G, ptrs), "wcns_batch_reset")
         self.n = n

@@ -106,3 +106,22 @@ def test_issue_probe_rejects_bad_arguments():
     assert L.wcns_issue_probe(-1, 16, 0, C.byref(ms), None) == -1
     assert L.wcns_issue_probe(0, 0, 0, C.byref(ms), None) == -1      # iters < 1
     assert L.wcns_issue_probe(0, 16, 0, None, None) == -1            # no output
+
+
+def test_binding_rejects_tensors_the_library_cannot_use():
+    """Every tensor the binding hands to the library as a device pointer is
+    checked first: host tensors, other dtypes, non-contiguous views and too
+    few elements raise ValueError before any call (a host pointer or a short
+    buffer would otherwise be written by a kernel)."""
+    torch = pytest.importorskip("torch")
+    for bad in (torch.zeros(8, dtype=torch.float64),                  # host memory
+                torch.zeros(8, dtype=torch.float32),
+                torch.zeros(4, 4, dtype=torch.float64).t()):           # not contiguous
+        with pytest.raises(ValueError):
+            wcns._dev_f64(bad, 2, "t")
+    wcns._dev_f64(None, 2, "t")                                        # optional: passes
+    g = wcns.make_grid(2, 8, 4, 0.0, 1.0, 0.0, 1.0, (0, 0, 0, 0))
+    with pytest.raises(ValueError):
+        wcns._state_ptrs([g], [])                                      # count mismatch
+    with pytest.raises(ValueError):
+        wcns._state_ptrs([g], [torch.zeros(6 * 8 * 4, dtype=torch.float64)])   # host state
