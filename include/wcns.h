@@ -20,6 +20,10 @@
  *  - All kernels are enqueued on the context's stream (set at creation or
  *    by wcns_set_stream); calls are asynchronous unless stated otherwise.
  *    Calls on one context must not overlap (they share its scratch).
+ *  - Device pointers are checked for NULL only, not for residency or size
+ *    (that would cost a runtime query per call): a host pointer or a buffer
+ *    shorter than stated is the caller's error and faults the kernel that
+ *    touches it.  The Python binding checks every tensor it passes.
  */
 #ifndef WCNS_H_
 #define WCNS_H_
