@@ -234,6 +234,26 @@ def test_rhs_full_size_shock_bubble():
     rhs_case(spec)
 
 
+def test_steps_full_size_shock_bubble_in_one_call():
+    """The bench's launch configuration: the 1024^2 shock-bubble advanced by
+    several device-CFL steps in one wcns_ssprk3_steps call (node primitives
+    carried from each stage's y-sweep and fixup into the next, across the
+    steps) equals the oracle's steps bit for bit, with the same dt."""
+    spec = pb.shock_bubble(1024)
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    sol = solver_for(spec)
+    Wd = dev(W)
+    n = 2
+    dts = torch.zeros(n, dtype=torch.float64, device="cuda")
+    sol.steps(Wd, n, 0.0, dts=dts)
+    got, gdt = host(Wd), host(dts)
+    for k in range(n):
+        W, dt, bad = orc.ssprk3_step(s, W)
+        assert bad == 0 and gdt[k] == dt, (k, gdt[k], dt)
+    assert np.array_equal(got, W)
+
+
 def test_uniform_state_gives_zero_rhs_at_max_size():
     spec = pb.underwater_explosion(2048)
     spec.prim[:] = spec.prim[:, :1, :1]
