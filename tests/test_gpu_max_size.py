@@ -1,0 +1,64 @@
+"""The largest 2D grid the library accepts (nx * ny just under 2^29 cells,
+where the kernels' 32-bit byte offsets reach 2^32), checked exactly through
+periodicity: a small periodic random state tiled over the big periodic grid
+with the same spacing must give the tiled RHS and the tiled SSP-RK3 step of
+the small grid, bit for bit, since every stencil and both wave-speed maxima
+are the same.  The small grid's results come from the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import oracle_setup, oracle_W, orc, pb
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_2102_05287_amd import wcns  # noqa: E402
+
+PX, PY = 32, 43                  # the small periodic grid
+NX, NY = 32768, 16383            # 1024 x 381 tiles: 536 838 144 cells < 2^29
+
+
+def tiled_equal(big, small):
+    """big [nv][NY][NX] equals small [nv][PY][PX] tiled, element by element."""
+    nv = small.shape[0]
+    b = big.view(nv, NY // PY, PY, NX // PX, PX)
+    s = small.view(nv, 1, PY, 1, PX)
+    return not bool((b != s).any())
+
+
+def test_max_size_grid_equals_the_tiled_small_grid():
+    assert NX * NY < 1 << 29 and NX % PX == 0 and NY % PY == 0
+    free, _ = torch.cuda.mem_get_info()
+    if free < 200 * 2**30:
+        pytest.skip(f"needs about 180 GiB of device memory, {free / 2**30:.0f} GiB free")
+    spec = pb.random_smooth_state(PX, PY, 17)              # dx = dy = 1/32
+    spec.bc = (pb.BC_PERIODIC,) * 4
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    dt = orc.cfl_dt(s, W)
+    ref_rhs = orc.rhs(s, W, dt)
+    ref_step, dt_step, bad = orc.ssprk3_step(s, W)
+    assert bad == 0
+    print(f"  small grid {PX}x{PY} done; building {NX}x{NY}", flush=True)
+
+    h = spec.dx
+    sol = wcns.Solver(2, NX, NY, 0.0, NX * h, 0.0, NY * h, bc=spec.bc, gamma=spec.gamma,
+                      pinf=spec.pinf, cfl=spec.cfl)
+    Ws = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    Wb = Ws.repeat(1, NY // PY, NX // PX).contiguous()
+    del Ws
+    print("  big state on the device; RHS", flush=True)
+    L = sol.rhs(Wb, dt=dt)
+    assert tiled_equal(L, torch.from_numpy(ref_rhs).cuda())
+    del L
+    torch.cuda.empty_cache()
+    print("  RHS equal; one SSP-RK3 step", flush=True)
+    dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sol.step(Wb, 0.0, dt_used=dtu)
+    assert float(dtu.item()) == dt_step
+    assert tiled_equal(Wb, torch.from_numpy(ref_step).cuda())
+    print("  step equal", flush=True)
+    sol.close()
+    del Wb
+    torch.cuda.empty_cache()
