@@ -62,3 +62,55 @@ def test_max_size_grid_equals_the_tiled_small_grid():
     sol.close()
     del Wb
     torch.cuda.empty_cache()
+
+
+P3 = (32, 16, 23)                # small periodic 3D grid (x, y, z)
+N3 = (512, 512, 2047)            # 16 x 32 x 89 tiles: 536 608 768 cells < 2^29
+
+
+def tiled_equal_3d(big, small):
+    nv = small.shape[0]
+    (px, py, pz), (nx, ny, nz) = P3, N3
+    b = big.view(nv, nz // pz, pz, ny // py, py, nx // px, px)
+    s = small.view(nv, 1, pz, 1, py, 1, px)
+    return not bool((b != s).any())
+
+
+def test_max_size_3d_grid_equals_the_tiled_small_grid():
+    """The same check for the largest accepted 3D grid (z lines of 2047
+    cells: 128 full 16-row z tiles; y lines of 512: a one-row last tile)."""
+    (px, py, pz), (nx, ny, nz) = P3, N3
+    assert nx * ny * nz < 1 << 29 and nx % px == 0 and ny % py == 0 and nz % pz == 0
+    free, _ = torch.cuda.mem_get_info()
+    if free < 220 * 2**30:
+        pytest.skip(f"needs about 190 GiB of device memory, {free / 2**30:.0f} GiB free")
+    spec = pb.random_smooth_state_3d(px, py, pz, seed=18)  # dx = dy = dz = 1/32
+    spec.bc = (pb.BC_PERIODIC,) * 6
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    dt = orc.cfl_dt(s, W)
+    ref_rhs = orc.rhs(s, W, dt)
+    ref_step, dt_step, bad = orc.ssprk3_step(s, W)
+    assert bad == 0
+    print(f"  small grid {px}x{py}x{pz} done; building {nx}x{ny}x{nz}", flush=True)
+
+    h = spec.dx
+    sol = wcns.Solver(3, nx, ny, 0.0, nx * h, 0.0, ny * h, bc=spec.bc, gamma=spec.gamma,
+                      pinf=spec.pinf, cfl=spec.cfl, nz=nz, z0=0.0, z1=nz * h)
+    Ws = torch.from_numpy(np.ascontiguousarray(W)).cuda()
+    Wb = Ws.repeat(1, nz // pz, ny // py, nx // px).contiguous()
+    del Ws
+    print("  big state on the device; RHS", flush=True)
+    L = sol.rhs(Wb, dt=dt)
+    assert tiled_equal_3d(L, torch.from_numpy(ref_rhs).cuda())
+    del L
+    torch.cuda.empty_cache()
+    print("  RHS equal; one SSP-RK3 step", flush=True)
+    dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sol.step(Wb, 0.0, dt_used=dtu)
+    assert float(dtu.item()) == dt_step
+    assert tiled_equal_3d(Wb, torch.from_numpy(ref_step).cuda())
+    print("  step equal", flush=True)
+    sol.close()
+    del Wb
+    torch.cuda.empty_cache()
