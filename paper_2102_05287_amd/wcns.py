@@ -440,6 +440,8 @@ def issue_weights(iters: int = 2048) -> dict:
     slots/s."""
     for _ in range(4):                            # warm-up: code load, clocks up
         issue_probe("fma", iters)
+    for op in PROBE_OPS:                          # and once per op: the first measured
+        issue_probe(op, iters)                    # pass ran ~8% off the later ones
     t, w = {}, {}
     for op in PROBE_OPS:
         tf = issue_probe("fma", iters)
