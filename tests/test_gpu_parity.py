@@ -234,6 +234,13 @@ def test_rhs_full_size_shock_bubble():
     rhs_case(spec)
 
 
+def test_rhs_full_size_underwater_explosion_2048():
+    """The precision form's workload at full size, FP64 path: the 2048^2
+    underwater explosion near a wall (4.2 M cells), every cell against the
+    oracle."""
+    rhs_case(pb.underwater_explosion(2048))
+
+
 def test_steps_full_size_shock_bubble_in_one_call():
     """The bench's launch configuration: the 1024^2 shock-bubble advanced by
     several device-CFL steps in one wcns_ssprk3_steps call (node primitives
