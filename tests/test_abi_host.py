@@ -125,3 +125,36 @@ def test_binding_rejects_tensors_the_library_cannot_use():
         wcns._state_ptrs([g], [])                                      # count mismatch
     with pytest.raises(ValueError):
         wcns._state_ptrs([g], [torch.zeros(6 * 8 * 4, dtype=torch.float64)])   # host state
+
+
+def test_batch_create_rejects_bad_arguments():
+    """The batch's argument checks come before any device call (the state
+    pointers are never dereferenced here): no Dirichlet side, no 3D, one
+    ndim for all instances, the single-grid rules per instance."""
+    L = wcns.lib()
+    e = wcns._Eos()
+    e.gamma[0], e.gamma[1] = 6.12, 1.4
+    e.pinf[0], e.pinf[1] = 3.43e8, 0.0
+    p = wcns.default_params()
+    out = C.c_void_p()
+
+    def create(*grids, prm=p, eos=e):
+        G = (wcns._Grid * len(grids))(*grids)
+        W = (C.c_void_p * max(len(grids), 1))(*([8] * max(len(grids), 1)))
+        return L.wcns_batch_create(len(grids), G, C.byref(eos), C.byref(prm), 0, W, 0,
+                                   C.byref(out))
+
+    ok = wcns.make_grid(2, 16, 16, 0.0, 1.0, 0.0, 1.0, (1, 1, 1, 1))
+    assert create() == -1                                                       # n < 1
+    assert create(ok, wcns.make_grid(1, 16, 1, 0.0, 1.0)) == -1                 # mixed ndim
+    assert create(wcns.make_grid(3, 8, 8, 0.0, 1.0, 0.0, 1.0, (1,) * 6, nz=8)) == -1
+    assert create(wcns.make_grid(2, 16, 16, 0.0, 1.0, 0.0, 1.0, (3, 1, 1, 1))) == -1   # Dirichlet
+    assert create(ok, wcns.make_grid(2, 16, 16, 0.0, 1.0, 0.0, 1.0, (0, 1, 1, 1))) == -1
+    assert create(wcns.make_grid(2, 2, 16, 0.0, 1.0, 0.0, 1.0, (2, 2, 1, 1))) == -1
+    assert create(wcns.make_grid(2, 0, 16, 0.0, 1.0, 0.0, 1.0, (1,) * 4)) == -1
+    bad = wcns.default_params(cfl=0.7)
+    assert create(ok, prm=bad) == -1
+    e2 = wcns._Eos()
+    e2.gamma[0], e2.gamma[1] = 1.2, 1.67
+    assert create(ok, eos=e2) == -2
+    assert out.value is None
