@@ -92,10 +92,36 @@ def test_create_rejects_bad_arguments(kw, code):
 
 
 def test_null_arguments():
+    """Every entry point that takes a context or an output rejects NULL with
+    WCNS_ERR_ARG before touching the device."""
     L = wcns.lib()
+    out = C.c_void_p()
     assert L.wcns_rhs(None, None, None, 0.0) == -1
     assert L.wcns_ssprk3_step(None, None, 0.0, None) == -1
+    assert L.wcns_ssprk3_steps(None, None, 1, 0.0, None) == -1
     assert L.wcns_destroy(None) == -1
+    assert L.wcns_set_stream(None, None) == -1
+    assert L.wcns_prim_to_cons(None, None, None) == -1
+    assert L.wcns_limit(None, 0, None, None, None, None, None, 0.0) == -1
+    assert L.wcns_max_wavespeed(None, None, None) == -1
+    assert L.wcns_check_admissible(None, None, None) == -1
+    assert L.wcns_profile(None, 1) == -1
+    assert L.wcns_profile_read(None, None, None, 0) == -1
+    assert L.wcns_run(None, None, 0.0, 1.0, 0.0, 1, None, 0, None, None) == -1
+    assert L.wcns_params_default(None) == -1
+    assert L.wcns_create(None, None, None, 0, None, C.byref(out)) == -1
+    assert L.wcns_batch_step(None, 1) == -1
+    assert L.wcns_batch_rhs(None) == -1
+    assert L.wcns_batch_configure(None, 16, 2) == -1
+    assert L.wcns_batch_sync(None) == -1
+    assert L.wcns_batch_stream(None, C.byref(out)) == -1
+    assert L.wcns_batch_set_steps(None, None) == -1
+    assert L.wcns_batch_steps_left(None, None) == -1
+    assert L.wcns_batch_dt(None, None) == -1
+    assert L.wcns_batch_reset(None, 1, None, None) == -1
+    assert L.wcns_batch_destroy(None) == -1
+    assert L.wcns_prim_to_cons_n(None, 2, 1, None, None, None) == -1
+    assert L.wcns_selftest_division(None, None, None, None, 1, None) == -1
 
 
 def test_issue_probe_rejects_bad_arguments():
