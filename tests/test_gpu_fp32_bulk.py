@@ -121,3 +121,33 @@ def test_fp32_bulk_full_size_2048_against_fp64_gpu():
     e = [float((W32[v] - W64[v]).abs().sum() / W64[v].abs().sum()) for v in range(6)]
     print("  2048^2 rel L1 fp32-bulk vs fp64:", ["%.2e" % x for x in e], flush=True)
     assert max(e) < 1e-2, e
+
+
+def test_first_order_scheme_is_fp64_in_both_precisions():
+    """The first-order HLLC mode has no interpolation, midpoint flux or HCS,
+    the parts the precision form runs in FP32, so its FP32-bulk solve is
+    the FP64 one: steps of a random 2D state (periodic and Dirichlet sides,
+    several y-tiles) and of a 1D tube, bit for bit in both precisions and
+    against the oracle."""
+    cases = [pb.random_smooth_state(70, 45, 21), pb.water_air_shock_tube(200)]
+    dirichlet = pb.random_smooth_state(66, 37, 22)
+    dirichlet.bc = (pb.BC_DIRICHLET, pb.BC_EXTRAP, pb.BC_PERIODIC, pb.BC_PERIODIC)
+    dirichlet.dirichlet_prim = [dirichlet.prim[:, :, 0].T.copy(), None, None, None]
+    cases.append(dirichlet)
+    for spec in cases:
+        s = oracle_setup(spec, scheme=1)
+        W = oracle_W(spec, s)
+        ref = W
+        for _ in range(3):
+            ref, dt, bad = orc.ssprk3_step(s, ref)
+            assert bad == 0
+        out = []
+        for prec in (wcns.FP64, FP32):
+            sol = wcns.Solver.from_spec(spec, precision=prec, scheme=1)
+            Wd = dev(W)
+            sol.steps(Wd, 3, 0.0)
+            out.append(host(Wd))
+            sol.close()
+        print(f"  hllc1 {spec.name}: fp64 == fp32-bulk == oracle", flush=True)
+        assert np.array_equal(out[0], out[1]), spec.name
+        assert np.array_equal(out[0], ref), spec.name
