@@ -59,6 +59,28 @@ def test_batch_equals_single_solves(precision):
         b.close()
 
 
+@pytest.mark.parametrize("params", [dict(scheme=1), dict(interp_limiter=0, flux_limiter=0)])
+def test_batch_method_options_equal_single_solves(params):
+    """The method options reach every instance: the first-order scheme and
+    the unlimited scheme, batched, equal the single solves bit for bit."""
+    specs = instances(5)
+    W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
+    ref = []
+    for sp, w in zip(specs, W0):
+        sol = wcns.Solver.from_spec(sp, **params)
+        Wd = dev(w)
+        for _ in range(2):
+            sol.step(Wd, 0.0)
+        ref.append(host(Wd))
+        sol.close()
+    states = [dev(w) for w in W0]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states, **params)
+    b.step(2)
+    for k in range(len(specs)):
+        assert np.array_equal(host(states[k]), ref[k]), (params, k)
+    b.close()
+
+
 def test_batch_matches_oracle_and_reset():
     specs = instances(5)
     W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
