@@ -1,7 +1,8 @@
-"""The FP64 issue-cost probe that weights divides and square roots in the
-roofline: its timings scale with the work and its ratios fall in the range
-the instruction sequences allow (an IEEE divide is 11 VALU instructions on
-gfx950, one of them a quarter-rate reciprocal; a square root 19)."""
+"""The measurement aids behind the roofline: the FP64 issue-cost probe
+that weights divides and square roots (its timings scale with the work and
+its ratios fall in the range the instruction sequences allow: an IEEE
+divide is 11 VALU instructions on gfx950, one of them a quarter-rate
+reciprocal; a square root 19), and the per-class launch profile."""
 from __future__ import annotations
 
 import pytest
@@ -22,3 +23,28 @@ def test_issue_probe_scales_and_weights_are_plausible():
     assert 8.0 < w["div"] < 20.0
     assert 6.0 < w["div_core"] < w["div"] * 1.2
     assert 10.0 < w["sqrt"] < 30.0
+
+
+def test_profile_counts_the_launches_of_a_multi_step_call():
+    """The per-class launch counts the roofline reads (wcns_profile): n steps
+    in one 2D call run the node primitives once and, per stage, one
+    finalize, one x-sweep, one y-sweep and one fixup; an RHS evaluation
+    runs the node primitives again.  The times are positive."""
+    import numpy as np
+    from paper_2102_05287_amd import problems as pb
+    spec = pb.random_smooth_state(96, 70, 5)          # 71 face rows: 5 y-tile rows, a fixup
+    sol = wcns.Solver.from_spec(spec)
+    W = sol.prim_to_cons(torch.from_numpy(np.ascontiguousarray(spec.prim)).cuda())
+    sol.profile(True)
+    n = 4
+    sol.steps(W, n, 0.0)
+    prof = sol.profile_read(reset=True)
+    assert prof["node"][1] == 1
+    for k in ("finalize", "sweep_x", "sweep_y", "fixup_y"):
+        assert prof[k][1] == 3 * n, (k, prof[k])
+        assert prof[k][0] > 0.0
+    sol.rhs(W, dt=1e-9)
+    prof = sol.profile_read(reset=True)
+    assert prof["node"][1] == 1 and prof["sweep_y"][1] == 1 and prof["finalize"][1] == 1
+    sol.profile(False)
+    sol.close()
