@@ -251,6 +251,49 @@ def serving_form(n_req, rate, budget_gib, chunk):
     return summary
 
 
+HBM_PEAK = 8.0e12     # MI355X HBM3E, bytes/s
+
+
+def first_order_form(n=1024, steps=200, warmup=10):
+    """The first-order HLLC product mode on the default workload (n^2
+    shock-bubble, FP64, device-CFL steps in one call): Mcell-updates/s per
+    RHS and, since the mode skips the interpolation, limiter and midpoint
+    arithmetic, an HBM roofline of its sweeps: algorithmic bytes per launch
+    (x: W and the node primitives read, L_x written, 136 B per cell; y: W,
+    P, L_x and U^n read, the stage written, 232 B per cell, plus 40 B of
+    next-stage primitives in a share 1 - 1/(3K) of the launches) over the
+    mean launch time, against 8 TB/s."""
+    import torch
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import wcns
+    spec = pb.shock_bubble(n)
+    sol = wcns.Solver.from_spec(spec, scheme=1)
+    W0 = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+    el, W = time_steps(sol, W0, steps, warmup)
+    cells = spec.nx * spec.ny
+    W.copy_(W0)
+    sol.profile(True)
+    sol.steps(W, steps, 0.0)
+    prof = sol.profile_read(reset=True)
+    sol.profile(False)
+    bad = sol.count_inadmissible(W)
+    fused = 1.0 - 1.0 / (3 * steps)
+    nbytes = {"sweep_x": 136.0 * cells, "sweep_y": (232.0 + 40.0 * fused) * cells}
+    roof = {}
+    for k, b in nbytes.items():
+        t = prof[k][0] / 1e3 / prof[k][1]
+        roof[k] = {"avg_launch_ms": t * 1e3, "bytes_per_launch": b, "achieved": b / t / 1e9,
+                   "frac": b / t / HBM_PEAK}
+    del W, W0
+    sol.close()
+    return {"workload": f"2D shock-bubble {n}x{n}, first-order HLLC (scheme 1), FP64",
+            "steps": steps, "mcells_per_s": 3 * cells * steps / el / 1e6,
+            "ms_per_step": el / steps * 1e3, "inadmissible_after": bad,
+            "per_kernel_ms_per_launch": {k: v[0] / v[1] for k, v in prof.items() if v[1]},
+            "roofline": {"bound": "hbm", "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                         "kernels": roof}}
+
+
 def three_d_form(n=256, steps=10, warmup=2):
     """3D underwater explosion near a wall at n^3 (FP64, the direct 3D
     extension): Mcell-updates/s per RHS, per-kernel device time and the
@@ -426,7 +469,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision/batched/serving forms")
     ap.add_argument("--form", choices=("precision", "batched", "serving", "solutions", "rates",
-                                       "3d"),
+                                       "3d", "first_order"),
                     default=None,
                     help="run only this form and print its record")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -452,7 +495,8 @@ def main():
                "serving": lambda: serving_form(300, 200.0, 64, 20),
                "solutions": time_to_solution_form,
                "rates": serving_rate_sweep,
-               "3d": three_d_form}[args.form]
+               "3d": three_d_form,
+               "first_order": first_order_form}[args.form]
         print(json.dumps({"form": args.form, **run()}), flush=True)
         return
     if args.gpus != 1:
@@ -543,6 +587,8 @@ def main():
         forms["serving_rate_sweep"] = serving_rate_sweep()
         print("# 3D form ...", flush=True)
         forms["three_d"] = three_d_form()
+        print("# first-order mode ...", flush=True)
+        forms["first_order"] = first_order_form()
         print("# time to solution (paper runs) ...", flush=True)
         forms["time_to_solution"] = time_to_solution_form()
 

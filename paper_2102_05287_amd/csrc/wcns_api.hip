@@ -610,13 +610,17 @@ static bool diri(const wcns_ctx* c, int dir) {
 }
 
 // the x-sweep of arguments `a`: LDS windows for rows of >= XLDS_MIN_NX cells
-// (XG blocks), the flattened tiling otherwise
-#define XSWEEP(HT, DI, BF, XG)                                                               \
-  do {                                                                                       \
-    if (c->x_lds)                                                                            \
-      hipLaunchKernelGGL((k_sweep_xl<HT, DI, BF>), dim3(XG), dim3(64 * XW), 0, c->stream, a); \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_sweep_x<HT, DI, BF>), dim3(c->x_grid), dim3(64), 0, c->stream, a); \
+// (XG blocks; the first-order scheme takes its own instantiation, which runs
+// no FP32 code in either precision), the flattened tiling otherwise
+#define XSWEEP(HT, DI, BF, XG)                                                                 \
+  do {                                                                                         \
+    if (c->x_lds && c->params.scheme == WCNS_SCHEME_HLLC1)                                     \
+      hipLaunchKernelGGL((k_sweep_xl<HT, DI, false, true>), dim3(XG), dim3(64 * XW), 0,         \
+                         c->stream, a);                                                        \
+    else if (c->x_lds)                                                                         \
+      hipLaunchKernelGGL((k_sweep_xl<HT, DI, BF>), dim3(XG), dim3(64 * XW), 0, c->stream, a);   \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_sweep_x<HT, DI, BF>), dim3(c->x_grid), dim3(64), 0, c->stream, a);  \
   } while (0)
 
 #define XSWEEP_ALL(XG)                                \
@@ -635,7 +639,10 @@ static bool diri(const wcns_ctx* c, int dir) {
 static void ysweep(const wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
   dim3 gy((c->grid.nx + Y_CW - 1) / Y_CW, rows);
   const bool d = diri(c, 1);
-  if (b32) {
+  if (c->params.scheme == WCNS_SCHEME_HLLC1) {   // first order: no FP32 code in either precision
+    if (d) hipLaunchKernelGGL((k_sweep_y<true, false, true>), gy, dim3(Y_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((k_sweep_y<false, false, true>), gy, dim3(Y_THREADS), 0, s, a);
+  } else if (b32) {
     if (d) hipLaunchKernelGGL((k_sweep_y<true, true>), gy, dim3(Y_THREADS), 0, s, a);
     else hipLaunchKernelGGL((k_sweep_y<false, true>), gy, dim3(Y_THREADS), 0, s, a);
   } else {

@@ -239,8 +239,10 @@ struct LdsLoadY {
 // One face i+1/2 of a sweep: WCNS steps 1-9 [Sec. 4.2] with the
 // interpolation limiter [Sec. 5.1] and the flux limiter [Sec. 5.2].
 // Node data are re-read (from the cache or the LDS tile) in each phase
-// (phase_barrier) to keep the live register set small.
-template <int DIR, bool HAS_T, bool B32, class LD>
+// (phase_barrier) to keep the live register set small.  FO: compiled for
+// the first-order scheme only (the rest of the pipeline is dead code, so
+// the kernel keeps few registers).
+template <int DIR, bool HAS_T, bool B32, bool FO = false, class LD>
 __device__ __forceinline__ double face_flux_core(const KArgs& a, const LD& ld, double lam,
                                                  double Gm[6], double Gp[6]) {
   const EosC& e = a.eos;
@@ -258,7 +260,7 @@ __device__ __forceinline__ double face_flux_core(const KArgs& a, const LD& ld, d
     for (int v = 0; v < 5; ++v) { Hm[v] = h1.F[v]; Hp[v] = h1.F[v]; }
     Hm[5] = h1.fa - nl.w[5] * h1.ss;
     Hp[5] = h1.fa - nr.w[5] * h1.ss;
-    if (a.scheme == 1) {
+    if (FO || a.scheme == 1) {
 #pragma unroll
       for (int v = 0; v < 6; ++v) { Gm[v] = Hm[v]; Gp[v] = Hp[v]; }
       return 0.0;
@@ -992,7 +994,7 @@ __device__ __forceinline__ XWin x_window(int nx, long N, long tile) {
 }
 
 // One tile per wave (`on` false: the wave has no tile and writes nothing).
-template <bool HAS_T, bool DIRI, bool B32>
+template <bool HAS_T, bool DIRI, bool B32, bool FO = false>
 __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool on, double* win) {
   const int lane = threadIdx.x & 63;
   const int nx = a.nx;
@@ -1033,7 +1035,7 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
     const LdsLoadX<HAS_T> ld{win, t.base(lane)};
-    face_flux_core<0, HAS_T, B32>(a, ld, a.step[1], Gm, Gp);
+    face_flux_core<0, HAS_T, B32, FO>(a, ld, a.step[1], Gm, Gp);
   }
   double Gr[6];
 #pragma unroll
@@ -1057,13 +1059,16 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
 #ifndef WCNS_XWPE
 #define WCNS_XWPE 4
 #endif
-template <bool HAS_T, bool DIRI, bool B32>
-__global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(WCNS_XWPE))) void k_sweep_xl(KArgs a) {
+// (FO: the first-order scheme, memory-bound: six waves per SIMD, the most
+// the LDS windows allow)
+template <bool HAS_T, bool DIRI, bool B32, bool FO = false>
+__global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(FO ? 6 : WCNS_XWPE))) void k_sweep_xl(
+    KArgs a) {
   __shared__ double tile[XW][11 * XWIN];
   const int w = threadIdx.x >> 6;
   const long t = (long)blockIdx.x * XW + w;
   const long N = (long)a.nx * a.ny;
-  sweep_x_window<HAS_T, DIRI, B32>(a, t, t * XT < N, tile[w]);
+  sweep_x_window<HAS_T, DIRI, B32, FO>(a, t, t * XT < N, tile[w]);
 }
 
 // y-sweep tile: block = YW waves; wave w computes y-face row k = kb + w for
@@ -1191,7 +1196,7 @@ __device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by,
 // blocks per CU); at 16 face rows, two 8-wave blocks per CU with half the
 // fixup rows.
 // (part: this block's slot for its block maxima when a.Pn is set)
-template <int FR, bool DIRI, bool B32>
+template <int FR, bool DIRI, bool B32, bool FO = false>
 __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, double* tile, long part) {
   constexpr int W = FR / 2;
   constexpr int ROWS = FR + 5;
@@ -1253,7 +1258,7 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
       }
       if (q == 0) { ld.c2 = c; ld.h2 = h; } else { ld.c3 = c; ld.h3 = h; }
     }
-    face_flux_core<1, true, B32>(a, ld, a.step[2], Gm, Gp);
+    face_flux_core<1, true, B32, FO>(a, ld, a.step[2], Gm, Gp);
   }
   // the owned cell's L_x, U^n and W, loaded while the block exchanges G^-
   const bool own = active && fr != FR - 1 && k < ny;
@@ -1313,12 +1318,15 @@ static_assert(Y_THREADS <= 512, "y-tile block too large: 64-column tiles take at
 #ifndef WCNS_YWPE
 #define WCNS_YWPE (Y_WAVES >= 8 ? 4 : 3)
 #endif
-template <bool DIRI, bool B32>
-__global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(WCNS_YWPE))) void k_sweep_y(KArgs a) {
+// (FO: the first-order scheme, memory-bound: six waves per SIMD, three
+// 16-row tiles per CU)
+template <bool DIRI, bool B32, bool FO = false>
+__global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(FO ? 6 : WCNS_YWPE))) void k_sweep_y(
+    KArgs a) {
   if constexpr (Y_CW == 32) {
     __shared__ double tile32[9 * (Y_WAVES + 5) * 32];
-    sweep_y_tile32<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile32,
-                                       (long)blockIdx.y * gridDim.x + blockIdx.x);
+    sweep_y_tile32<Y_WAVES, DIRI, B32, FO>(a, blockIdx.x, blockIdx.y, tile32,
+                                           (long)blockIdx.y * gridDim.x + blockIdx.x);
   } else {
     __shared__ double tile[ytile_lds_doubles<Y_WAVES>()];
     sweep_y_tile_lds<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile);
