@@ -30,18 +30,9 @@ namespace wcns {
 
 // Strided-pass tiles: 32 columns x 16 face rows (8 waves, 59 KB of LDS, two
 // blocks per CU; against 8-row tiles the passes run ~1% slower but the
-// fixups have half the rows: 1.008x per RHS at 256^3) or 64 columns x 4
-// face rows (one face row per wave; 6 rows measured 1.5x slower: a 6-wave
-// block cannot spread evenly over a CU's 4 SIMDs).
-#ifndef WCNS_L3CW
-#define WCNS_L3CW 32
-#endif
-constexpr int L3_CW = WCNS_L3CW;
-#ifndef WCNS_YTILE3
-#define WCNS_YTILE3 (WCNS_L3CW == 32 ? 16 : 4)
-#endif
-constexpr int YW3 = WCNS_YTILE3;   // face rows per tile
-constexpr int L3_THREADS = L3_CW == 32 ? 32 * YW3 : 64 * YW3;
+// fixups have half the rows: 1.008x per RHS at 256^3).
+constexpr int YW3 = 16;   // face rows per tile
+constexpr int L3_THREADS = 32 * YW3;   // 8 waves: each covers two face rows
 
 struct K3Args {
   int32_t nx, ny, nz, tile_x;
@@ -755,109 +746,7 @@ __global__ __launch_bounds__(64 * XW) void k3_sweep_xl(K3Args a) {
 }
 
 // Strided pass of direction DIR (1: y-lines in z slab blockIdx.z; 2: z-lines
-// over the nx*ny columns).  The block first stages stencil rows kb-3 ..
-// kb+YW3+1 of its 64 consecutive columns in LDS (13 values per node in the
-// frame of DIR, ghost rows mapped while staging; wave w stages rows w,
-// w+YW3, ... with all loads of a row in flight together).  Wave w then
-// computes face row k = kb + w from LDS; cell row k (w < YW3-1) takes G^+ of
-// its own face and G^- of face row k+1 through LDS (the staged rows' space
-// reused); the tile's first G^- and last G^+ go to the edge buffer for
-// k3_fixup.
-// LDS: 0 every node loaded from global memory at its use instead; 1 all 13
-// values staged (60 KB per block, two blocks per CU); 2 11 values staged
-// (50.7 KB, three blocks per CU) and the sound speed and rho ctilde^2 of the
-// face's two centre nodes loaded from global memory into registers.
-// Measured at 256^3 (ms per y / z pass): 0: 2.62 / 2.99, 1: 2.12 / 2.45,
-// 2: 1.81 / 1.93.
-#ifndef WCNS_L3LDS_Y
-#define WCNS_L3LDS_Y 2
-#endif
-#ifndef WCNS_L3LDS_Z
-#define WCNS_L3LDS_Z 2
-#endif
-template <int DIR, int LDS>
-constexpr int tile3_doubles() { return LDS ? (LDS == 2 ? 11 : 13) * (YW3 + 5) * 64 : 7 * YW3 * 64; }
-
-template <int DIR, int LDS>
-__device__ __forceinline__ void sweep3_tile64(const K3Args& a, double* tile) {
-  constexpr int ROWS = YW3 + 5;
-  constexpr int NV = LDS == 2 ? 11 : 13;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const long plane = (long)a.nx * a.ny;
-  const long N = plane * a.nz;
-  const long ncol = DIR == 1 ? a.nx : plane;
-  const int nline = DIR == 1 ? a.ny : a.nz;
-  const long stride = DIR == 1 ? a.nx : plane;
-  const long slab = DIR == 1 ? (long)blockIdx.z * plane : 0;
-  const double h = DIR == 1 ? a.dy : a.dz;
-  const double rh = DIR == 1 ? a.rdy : a.rdz;
-  const long col = (long)blockIdx.x * 64 + lane;
-  const int by = blockIdx.y;
-  const int k = by * YW3 + w;
-  const bool active = col < ncol && k <= nline;
-  const int kb = by * YW3;
-#pragma unroll
-  for (int q = 0; q < (LDS ? (ROWS + YW3 - 1) / YW3 : 0); ++q) {
-    const int tr = w + q * YW3;
-    const int g = kb - 3 + tr;
-    // rows past nline + 2 are read by no active face and are left unset
-    if (tr < ROWS && g <= nline + 2 && col < ncol) {
-      bool flip;
-      const int s = ghost_src(g, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
-      double v[13];
-      node_values3<DIR>(a, (uint32_t)(slab + (long)s * stride + col) * 8u, flip, v);
-#pragma unroll
-      for (int c = 0; c < NV; ++c) tile[(c * ROWS + tr) * 64 + lane] = v[c];
-    }
-  }
-  if (LDS) __syncthreads();
-  double Gm[7] = {0, 0, 0, 0, 0, 0, 0}, Gp[7] = {0, 0, 0, 0, 0, 0, 0};
-  if (active) {
-    if (LDS == 1) {
-      const LdsLoad3 ld{tile + w * 64 + lane, 64, ROWS * 64};
-      face_flux3_core<DIR>(a, ld, a.step[1 + DIR], Gm, Gp);
-    } else if (LDS == 2) {
-      bool flip;
-      const int s2 = ghost_src(k - 1, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
-      const int s3 = ghost_src(k, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], flip);
-      const uint32_t o2 = (uint32_t)(slab + (long)s2 * stride + col) * 8u;
-      const uint32_t o3 = (uint32_t)(slab + (long)s3 * stride + col) * 8u;
-      const LdsLoad3C ld{tile + w * 64 + lane, 64, ROWS * 64,
-                         ldc(a.Pc[4], o2), ldc(a.Pc[5], o2), ldc(a.Pc[4], o3), ldc(a.Pc[5], o3)};
-      face_flux3_core<DIR>(a, ld, a.step[1 + DIR], Gm, Gp);
-    } else {
-      const Sten3 st = make_sten3(k - 3, nline, a.bc[2 * DIR], a.bc[2 * DIR + 1], slab + col, stride);
-      face_flux3<DIR>(a, st, a.step[1 + DIR], Gm, Gp);
-    }
-  }
-  if (LDS) __syncthreads();   // every face has read the tile: reuse it for G^-
-  double (*sGm)[7][64] = reinterpret_cast<double (*)[7][64]>(tile);
-#pragma unroll
-  for (int v = 0; v < 7; ++v) sGm[w][v][lane] = Gm[v];
-  if (active) {
-    double* e = a.edge + (((long)(DIR == 1 ? blockIdx.z : 0) * a.nbr + by) * 14) * ncol;
-    if (w == 0) {
-#pragma unroll
-      for (int v = 0; v < 7; ++v) e[v * ncol + col] = Gm[v];
-    }
-    if (w == YW3 - 1 || k == nline) {
-#pragma unroll
-      for (int v = 0; v < 7; ++v) e[(7 + v) * ncol + col] = Gp[v];
-    }
-  }
-  __syncthreads();
-  if (!active || w == YW3 - 1 || k >= nline) return;
-  const long idx = slab + (long)k * stride + col;
-#pragma unroll
-  for (int v = 0; v < 7; ++v) {
-    const int s = state_index3(DIR, v);
-    const double L = a.Lin[s * N + idx] + hdiv(-(sGm[w + 1][v][lane] - Gp[v]), h, rh);
-    if (a.last) write_cell3(a, idx, N, s, L);
-    else a.out[s * N + idx] = L;
-  }
-}
-
-// The strided tile on 32 columns: a block of YW3/2 waves covers 32
+// over the nx*ny columns) on tiles of 32 columns: a block of YW3/2 waves covers 32
 // consecutive columns x YW3 face rows; lane (r = lane / 32, col = lane % 32)
 // of wave w computes face row kb + 2w + r.  Stencil rows kb-3 .. kb+YW3+1
 // are staged first (11 values per node in the frame of DIR; c and
@@ -949,15 +838,14 @@ __device__ __forceinline__ void sweep3_tile32(const K3Args& a, double* tile) {
   }
 }
 
-template <int DIR, int LDS>
-__global__ __launch_bounds__(L3_THREADS) __attribute__((amdgpu_waves_per_eu(L3_CW == 32 ? 4 : 3))) void k3_sweep_l(K3Args a) {
-  if constexpr (L3_CW == 32) {
-    __shared__ double tile32[11 * (YW3 + 5) * 32];
-    sweep3_tile32<DIR>(a, tile32);
-  } else {
-    __shared__ double tile[tile3_doubles<DIR, LDS>()];
-    sweep3_tile64<DIR, LDS>(a, tile);
-  }
+// (measured at 256^3, ms per y / z pass: nodes loaded from global memory
+// at their use, 64-column tiles 2.62 / 2.99; all 13 values staged 2.12 /
+// 2.45; 11 values staged, c and rho ctilde^2 of the two centre nodes in
+// registers, 1.81 / 1.93; the same on 32 columns x 8 rows 1.78 / 1.81)
+template <int DIR>
+__global__ __launch_bounds__(L3_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k3_sweep_l(K3Args a) {
+  __shared__ double tile32[11 * (YW3 + 5) * 32];
+  sweep3_tile32<DIR>(a, tile32);
 }
 
 // the cell rows j = (b+1)*YW3 - 1 between tiles b and b+1 of a strided pass

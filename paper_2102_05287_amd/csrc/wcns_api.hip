@@ -19,6 +19,10 @@
 
 using namespace wcns;
 
+// k_node blocks at most (grid-stride beyond): its block maxima fit one
+// round of k_finalize's loads
+static constexpr long NODE_GRID_CAP = 2048;
+
 struct wcns_ctx {
   wcns_grid grid;
   wcns_eos eos;
@@ -254,11 +258,8 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   c->x_lds = g->nx >= XLDS_MIN_NX;
   c->xl_grid = (int)(((c->N + XT - 1) / XT + XW - 1) / XW);
   long ng = (c->N + 255) / 256;
-#ifndef WCNS_NODE_GRID_CAP
-#define WCNS_NODE_GRID_CAP 2048
-#endif
-  c->node_grid = (int)(ng < WCNS_NODE_GRID_CAP ? ng : WCNS_NODE_GRID_CAP);
-  c->nbr = (g->ny + 1 + Y_WAVES - 1) / Y_WAVES;
+  c->node_grid = (int)(ng < NODE_GRID_CAP ? ng : NODE_GRID_CAP);
+  c->nbr = (g->ny + 1 + Y_ROWS - 1) / Y_ROWS;
   a.nbr = c->nbr;
 
   wcns_status st = WCNS_OK;
@@ -273,11 +274,11 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
     alloc(&c->L, (size_t)c->nv * c->N);
     alloc(&c->edge, (size_t)c->nbr * 12 * g->nx);
   }
-  // fused node primitives: 2D with the 32-column y-tiles (whose epilogue
-  // and the fixup's write them)
-  c->fuse = g->ndim == 2 && Y_CW == 32;
+  // fused node primitives (2D): the y-tile epilogue and the fixup write
+  // the next stage's
+  c->fuse = g->ndim == 2;
   if (c->fuse) {
-    const long nyb = (long)((g->nx + Y_CW - 1) / Y_CW) * c->nbr;
+    const long nyb = (long)((g->nx + Y_COLS - 1) / Y_COLS) * c->nbr;
     const long nfb = c->nbr > 1 ? ((long)(c->nbr - 1) * g->nx + 255) / 256 : 0;
     c->nfused = (int)(nyb + nfb);
     alloc(&c->P2, 5 * (size_t)c->N);
@@ -436,7 +437,7 @@ static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_p
   c->x_lds = g->nx >= XLDS_MIN_NX;
   c->xl_grid = (int)(((N + XT - 1) / XT + XW - 1) / XW);
   const long ng = (N + 255) / 256;
-  c->node_grid = (int)(ng < WCNS_NODE_GRID_CAP ? ng : WCNS_NODE_GRID_CAP);
+  c->node_grid = (int)(ng < NODE_GRID_CAP ? ng : NODE_GRID_CAP);
   c->nbr_y3 = (g->ny + 1 + YW3 - 1) / YW3;
   c->nbr_z3 = (g->nz + 1 + YW3 - 1) / YW3;
   const size_t plane = (size_t)g->nx * g->ny;
@@ -519,7 +520,7 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   ay.nbr = c->nbr_y3;
   {
     ProfScope ps(c, PROF_Y);
-    hipLaunchKernelGGL((k3_sweep_l<1, WCNS_L3LDS_Y>), dim3((unsigned)((nx + L3_CW - 1) / L3_CW), c->nbr_y3, (unsigned)nz),
+    hipLaunchKernelGGL((k3_sweep_l<1>), dim3((unsigned)((nx + 31) / 32), c->nbr_y3, (unsigned)nz),
                        dim3(L3_THREADS), 0, c->stream, ay);
   }
   LAUNCH_CHECK();
@@ -537,7 +538,7 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   az.nbr = c->nbr_z3;
   {
     ProfScope ps(c, PROF_Z);
-    hipLaunchKernelGGL((k3_sweep_l<2, WCNS_L3LDS_Z>), dim3((unsigned)((nx * ny + L3_CW - 1) / L3_CW), c->nbr_z3, 1),
+    hipLaunchKernelGGL((k3_sweep_l<2>), dim3((unsigned)((nx * ny + 31) / 32), c->nbr_z3, 1),
                        dim3(L3_THREADS), 0, c->stream, az);
   }
   LAUNCH_CHECK();
@@ -637,7 +638,7 @@ static bool diri(const wcns_ctx* c, int dir) {
 
 // y-sweep of the first `rows` tile rows on stream s
 static void ysweep(const wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
-  dim3 gy((c->grid.nx + Y_CW - 1) / Y_CW, rows);
+  dim3 gy((c->grid.nx + Y_COLS - 1) / Y_COLS, rows);
   const bool d = diri(c, 1);
   if (c->params.scheme == WCNS_SCHEME_HLLC1) {   // first order: no FP32 code in either precision
     if (d) hipLaunchKernelGGL((k_sweep_y<true, false, true>), gy, dim3(Y_THREADS), 0, s, a);
@@ -690,7 +691,7 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   if (Pn) {
     a.Pn = Pn;
     a.partn = c->partial;
-    a.fuse_off = (int)((long)((c->grid.nx + Y_CW - 1) / Y_CW) * c->nbr);
+    a.fuse_off = (int)((long)((c->grid.nx + Y_COLS - 1) / Y_COLS) * c->nbr);
   }
   {
     ProfScope ps(c, PROF_X);

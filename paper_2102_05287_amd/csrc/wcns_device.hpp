@@ -43,22 +43,6 @@ struct NodeQ {
 };
 
 // ---------------------------------------------------------------- division
-// 1/b from the hardware reciprocal refined by two Newton steps (5 VALU
-// slots instead of the 11 of the IEEE divide; within ~1 ulp for the
-// normal-range operands used here).
-__device__ __forceinline__ double rcp_nr(double b) {
-#pragma clang fp contract(fast)
-  double r = __builtin_amdgcn_rcp(b);
-  double e = fma(-b, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-b, r, 1.0);
-  r = fma(r, e, r);
-  return r;
-}
-
-// a/b through the refined reciprocal (within ~2 ulp of the IEEE quotient).
-__device__ __forceinline__ double fdiv(double a, double b) { return a * rcp_nr(b); }
-
 // IEEE-754 double division without the range-scaling steps.  gfx950's
 // correctly rounded divide is: div_scale(den), rcp, div_scale(num), two
 // Newton steps (4 FMA), mul, residual FMA, div_fmas, div_fixup.  When
@@ -99,14 +83,6 @@ __device__ __forceinline__ double hdiv(double a, double h, double y) {
   return y != 0.0 ? cdiv(a, h, y) : ddiv(a, h);
 }
 
-// Division used by the face pipeline: the IEEE core, or the refined
-// reciprocal when FAST.
-template <bool FAST>
-__device__ __forceinline__ double qdiv(double a, double b) {
-  if (FAST) return fdiv(a, b);
-  return ddiv(a, b);
-}
-
 // ---------------------------------------------------------------- EOS
 __device__ __forceinline__ double mix_gamma(const EosC& e, double a1) {
 #pragma clang fp contract(off)
@@ -122,12 +98,12 @@ __device__ __forceinline__ double mix_pi(const EosC& e, double a1) {
 // Primitive recovery and mixture sound speed of one state [Sec. 2]:
 // p = (rho e - Pi)/Gamma, pbar_inf = Pi/(1+Gamma), gbar = 1 + 1/Gamma,
 // c^2 = gbar (p + pbar_inf)/rho, h = rho e - pbar_inf.
-template <bool HAS_T, bool FAST = false>
+template <bool HAS_T>
 __device__ __forceinline__ void recover(const EosC& e, const double X[6], double& un, double& ut,
                                         double& p, double& c, double& h) {
 #pragma clang fp contract(off)
   double rho = X[0] + X[1];
-  double irho = qdiv<FAST>(1.0, rho);
+  double irho = ddiv(1.0, rho);
   un = X[2] * irho;
   double ke;
   if (HAS_T) {
@@ -140,9 +116,9 @@ __device__ __forceinline__ void recover(const EosC& e, const double X[6], double
   double rhoe = X[4] - 0.5 * ke;
   double Gam = mix_gamma(e, X[5]);
   double Pi = mix_pi(e, X[5]);
-  p = qdiv<FAST>(rhoe - Pi, Gam);
-  double pinf_bar = qdiv<FAST>(Pi, 1.0 + Gam);
-  double gbar = 1.0 + qdiv<FAST>(1.0, Gam);
+  p = ddiv(rhoe - Pi, Gam);
+  double pinf_bar = ddiv(Pi, 1.0 + Gam);
+  double gbar = 1.0 + ddiv(1.0, Gam);
   double c2 = gbar * (p + pinf_bar) * irho;
   c = sqrt(c2);
   h = rhoe - pinf_bar;

@@ -34,16 +34,14 @@ namespace wcns {
 
 enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 enum { OUT_STORE = 0, OUT_RK = 1 };
-// y-face rows per y-sweep tile (single grid): 16 on 32 columns, 8 waves
-// and 48.6 KB of LDS per block, two blocks per CU.  Against 8-row tiles
-// (four 4-wave blocks per CU) the y-sweep itself runs 0.5-2% slower, but
-// the fixup has half the straddling cell rows: 1024^2 step 1.2%, 2048^2
-// FP64 1.1% and FP32 bulk 1.7% faster.  (Named Y_WAVES for the 64-column
-// tile, where a block has one wave per face row.)
-#ifndef WCNS_YTILE
-#define WCNS_YTILE 16
-#endif
-constexpr int Y_WAVES = WCNS_YTILE;
+// y-sweep tiles (single grid): 32 columns x 16 y-face rows, 8 waves and
+// 48.6 KB of LDS per block, two blocks per CU.  Against 8-row tiles (four
+// 4-wave blocks per CU) the y-sweep itself runs 0.5-2% slower, but the
+// fixup has half the straddling cell rows: 1024^2 step 1.2%, 2048^2 FP64
+// 1.1% and FP32 bulk 1.7% faster.
+constexpr int Y_ROWS = 16;
+constexpr int Y_COLS = 32;
+constexpr int Y_THREADS = Y_COLS * Y_ROWS;   // 8 waves: each covers two face rows
 
 struct KArgs {
   int32_t nx, ny, nv, tile_x;     // tile_x: cells per x-sweep wave
@@ -172,21 +170,6 @@ __device__ __forceinline__ void load_node(const KArgs& a, const Sten& st, int m,
 }
 
 // ------------------------------------------------------------------ face
-// Characteristic field f of node q with the face's projection constants
-// [App. A, R^{-1}]: U1 = u - p/(rho c), U2 = a1r1 - a1 p/(rho c^2),
-// U3 = a2r2 - a2 p/(rho c^2), U4 = u_t, U5 = a1, U6 = u + p/(rho c).
-__device__ __forceinline__ double char_field(int f, const NodeQ& q, double fa1, double fa2,
-                                             double k1, double k2) {
-  switch (f) {
-    case 0: return q.un - q.p * k1;
-    case 1: return q.w[0] - fa1 * q.p * k2;
-    case 2: return q.w[1] - fa2 * q.p * k2;
-    case 3: return q.ut;
-    case 4: return q.w[5];
-    default: return q.un + q.p * k1;
-  }
-}
-
 // Node loaders of the face pipeline: ld(m, q) fills node m (0..5 = i-2 ..
 // i+3) of the face in the sweep's rotated frame.
 // From global memory through the face's stencil offsets:
@@ -200,23 +183,20 @@ struct GlobalLoad {
   }
 };
 
-// From a y-tile staged in LDS: value c (0..5 state, 6..10 node primitives)
-// of tile row r, column `lane` at tile[(c * rows + r) * 64 + lane]; node m of
-// the face of wave w is tile row w + m.  Ghost rows are staged already
-// mapped (reflective ones with the wall-normal momentum and velocity
-// negated), so the node comes out as load_node would give it.
-// With CH the tile holds values 0..8 only: the sound speed and rho ctilde^2,
-// which the face pipeline reads only at the two nodes next to the face
-// (m = 2, 3), come from registers.
-// (CW: columns of the tile; w: the face's row in the tile, lane: its column.)
-template <bool CH = false, int CW = 64>
+// From a y-tile staged in LDS: value c (0..5 state, 6..8 u, v, p) of tile
+// row r, column `col` at tile[(c * rows + r) * Y_COLS + col]; node m of the
+// face of row w is tile row w + m.  Ghost rows are staged already mapped
+// (reflective ones with the wall-normal momentum and velocity negated), so
+// the node comes out as load_node would give it.  The sound speed and
+// rho ctilde^2, which the face pipeline reads only at the two nodes next to
+// the face (m = 2, 3), come from registers.
 struct LdsLoadY {
   const double* tile;
   int rows, w, lane;
   double c2 = 0.0, h2 = 0.0, c3 = 0.0, h3 = 0.0;
   __device__ __forceinline__ void operator()(int m, NodeQ& q) const {
-    const double* t = tile + (w + m) * CW + lane;
-    const int cs = rows * CW;
+    const double* t = tile + (w + m) * Y_COLS + lane;
+    const int cs = rows * Y_COLS;
     q.w[0] = t[0];
     q.w[1] = t[cs];
     q.w[2] = t[3 * cs];        // rho v: normal momentum of the y frame
@@ -226,13 +206,8 @@ struct LdsLoadY {
     q.ut = t[6 * cs];
     q.un = t[7 * cs];
     q.p = t[8 * cs];
-    if (CH) {
-      q.c = m == 2 ? c2 : (m == 3 ? c3 : 0.0);
-      q.h = m == 2 ? h2 : (m == 3 ? h3 : 0.0);
-    } else {
-      q.c = t[9 * cs];
-      q.h = t[10 * cs];
-    }
+    q.c = m == 2 ? c2 : (m == 3 ? c3 : 0.0);
+    q.h = m == 2 ? h2 : (m == 3 ? h3 : 0.0);
   }
 };
 
@@ -277,10 +252,6 @@ __device__ __forceinline__ double face_flux_core(const KArgs& a, const LD& ld, d
   double UL[6], UR[6];
   float ULf[6], URf[6];
   const float eps32 = fmaxf((float)a.tol.weno_eps, 1e-30f);
-#ifndef WCNS_PREFETCH
-#define WCNS_PREFETCH 1
-#endif
-#if WCNS_PREFETCH
   // Fields in three groups that share their node data: (u_n, p) -> fields 0
   // and 5, (a1r1, a2r2, p) -> fields 1 and 2, (u_t, a1) -> fields 3 and 4.
   // The next group's node values are loaded before the current group's
@@ -355,31 +326,6 @@ __device__ __forceinline__ double face_flux_core(const KArgs& a, const LD& ld, d
     }
     weno_pair(4, nw);
   }
-#else
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    if (!HAS_T && f == 3) { UL[3] = 0.0; UR[3] = 0.0; ULf[3] = 0.0f; URf[3] = 0.0f; continue; }
-    phase_barrier();
-    double u[6];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      NodeQ q;
-      ld(m, q);
-      u[m] = char_field(f, q, fa1, fa2, k1, k2);
-    }
-    if constexpr (B32) {
-      float v[6];
-#pragma unroll
-      for (int m = 0; m < 6; ++m) v[m] = (float)u[m];
-      ULf[f] = weno_is_f(v[0], v[1], v[2], v[3], v[4], eps32);
-      URf[f] = weno_is_f(v[5], v[4], v[3], v[2], v[1], eps32);
-    } else {
-      UL[f] = weno_is(u[0], u[1], u[2], u[3], u[4], a.tol.weno_eps);
-      phase_barrier();
-      UR[f] = weno_is(u[5], u[4], u[3], u[2], u[1], a.tol.weno_eps);
-    }
-  }
-#endif
   phase_barrier();
   if constexpr (B32) {
     // back-projection V = R U in FP32 [App. A]
@@ -1055,133 +1001,19 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
   }
 }
 
-// waves per SIMD the windowed x-sweep is compiled for (VGPR budget 512 / this)
-#ifndef WCNS_XWPE
-#define WCNS_XWPE 4
-#endif
+// waves per SIMD the windowed x-sweep is compiled for (VGPR budget 512 / this):
+// 4 (112 VGPRs, no spills; compiled for 5 it spills and runs 2% slower)
+constexpr int XL_WPE = 4;
 // (FO: the first-order scheme, memory-bound: six waves per SIMD, the most
 // the LDS windows allow)
 template <bool HAS_T, bool DIRI, bool B32, bool FO = false>
-__global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(FO ? 6 : WCNS_XWPE))) void k_sweep_xl(
+__global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(FO ? 6 : XL_WPE))) void k_sweep_xl(
     KArgs a) {
   __shared__ double tile[XW][11 * XWIN];
   const int w = threadIdx.x >> 6;
   const long t = (long)blockIdx.x * XW + w;
   const long N = (long)a.nx * a.ny;
   sweep_x_window<HAS_T, DIRI, B32, FO>(a, t, t * XT < N, tile[w]);
-}
-
-// y-sweep tile: block = YW waves; wave w computes y-face row k = kb + w for
-// 64 columns.  The block first stages stencil rows kb-3 .. kb+YW+1 (YW+5
-// rows) x 64 columns in LDS, ghost rows mapped while staging, and the face
-// pipeline reads every node from LDS (measured 111 against 127 us per
-// 1024^2 launch for per-node global loads).  Cell row kb + w (w < YW-1)
-// uses G^+ of its own face and G^- of face row kb + w + 1 through the
-// reused tile; the last face row of the tile leaves G^+ in the edge buffer
-// and the first one G^-; the fixup finishes the cell row in between.
-// 1: the y-tile stages 9 values per node and keeps the sound speed and
-// rho ctilde^2 of the face's two centre nodes in registers (LdsLoadY<true>)
-#ifndef WCNS_YCH
-#define WCNS_YCH 1
-#endif
-constexpr bool Y_CH = WCNS_YCH != 0;
-
-template <int YW, bool CH = Y_CH>
-constexpr int ytile_lds_doubles() { return (CH ? 9 : 11) * (YW + 5) * 64; }
-
-template <int YW, bool DIRI, bool B32, bool CH = Y_CH>
-__device__ __forceinline__ void sweep_y_tile_lds(const KArgs& a, int bx, int by, double* tile) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = bx * 64 + lane;
-  const int kb = by * YW;
-  const int k = kb + w;
-  const int nx = a.nx, ny = a.ny;
-  const long N = (long)nx * ny;
-  constexpr int ROWS = YW + 5;
-  // stage: tile row tr holds global row g = kb - 3 + tr; wave w stages rows
-  // w, w + YW, ... with all eleven loads of a row in flight together (rows
-  // past ny + 2 are read by no active face and are left unset)
-#pragma unroll
-  for (int q = 0; q < (ROWS + YW - 1) / YW; ++q) {
-    const int tr = w + q * YW;
-    const int g = kb - 3 + tr;
-    if (tr < ROWS && g <= ny + 2 && i < nx) {
-      bool flip;
-      const int s = ghost_src(g, ny, a.bc[2], a.bc[3], flip);
-      double v[11];
-      if (DIRI && s < 0) {
-        const int r = a.dir_off[g < 0 ? 2 : 3] + i;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] = a.dirW[r * 6 + c];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) v[6 + c] = a.dirP[r * 5 + c];
-      } else {
-        const uint32_t o = ((uint32_t)s * (uint32_t)nx + (uint32_t)i) * 8u;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] = ldc(a.Wc[c], o);
-#pragma unroll
-        for (int c = 0; c < 5; ++c) v[6 + c] = ldc(a.Pc[c], o);
-      }
-      if (flip) { v[3] = -v[3]; v[7] = -v[7]; }   // rho v and v change sign at the wall
-#pragma unroll
-      for (int c = 0; c < (CH ? 9 : 11); ++c) tile[(c * ROWS + tr) * 64 + lane] = v[c];
-    }
-  }
-  __syncthreads();
-  const bool active = i < nx && k <= ny;
-  double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
-  if (active) {
-    LdsLoadY<CH> ld{tile, ROWS, w, lane};
-    if (CH) {
-      // c and rho ctilde^2 of cell rows k-1 and k (ghost rows mapped)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int g = k - 1 + q;
-        bool flip;
-        const int s = ghost_src(g, ny, a.bc[2], a.bc[3], flip);
-        double c, h;
-        if (DIRI && s < 0) {
-          const int r = a.dir_off[g < 0 ? 2 : 3] + i;
-          c = a.dirP[r * 5 + 3];
-          h = a.dirP[r * 5 + 4];
-        } else {
-          const uint32_t o = ((uint32_t)s * (uint32_t)nx + (uint32_t)i) * 8u;
-          c = ldc(a.Pc[3], o);
-          h = ldc(a.Pc[4], o);
-        }
-        if (q == 0) { ld.c2 = c; ld.h2 = h; } else { ld.c3 = c; ld.h3 = h; }
-      }
-    }
-    face_flux_core<1, true, B32>(a, ld, a.step[2], Gm, Gp);
-  }
-  __syncthreads();   // every face has read the tile: reuse it for G^-
-  double (*sGm)[6][64] = reinterpret_cast<double (*)[6][64]>(tile);
-#pragma unroll
-  for (int v = 0; v < 6; ++v) sGm[w][v][lane] = Gm[v];
-  if (active) {
-    double* e = a.edge + (long)by * 12 * nx;
-    if (w == 0) {
-#pragma unroll
-      for (int v = 0; v < 6; ++v) e[v * nx + i] = Gm[v];
-    }
-    if (w == YW - 1 || k == ny) {
-#pragma unroll
-      for (int v = 0; v < 6; ++v) e[(6 + v) * nx + i] = Gp[v];
-    }
-  }
-  __syncthreads();
-  const int j = k;
-  if (!active || w == YW - 1 || j >= ny) return;
-#pragma unroll
-  for (int v = 0; v < 6; ++v) {
-    double L;
-    {
-      double Ly = hdiv(-(sGm[w + 1][v][lane] - Gp[v]), a.dy, a.rdy);
-      const int s = state_index(1, v, true);
-      L = a.Lx[s * N + (long)j * nx + i] + Ly;
-    }
-    write_cell(a, a.out, (long)j * nx + i, N, state_index(1, v, true), L);
-  }
 }
 
 // The y-tile on 32 columns: a block of FR/2 waves covers 32 columns x FR
@@ -1240,7 +1072,7 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
   const bool active = i < nx && k <= ny;
   double Gm[6] = {0, 0, 0, 0, 0, 0}, Gp[6] = {0, 0, 0, 0, 0, 0};
   if (active) {
-    LdsLoadY<true, 32> ld{tile, ROWS, fr, col};
+    LdsLoadY ld{tile, ROWS, fr, col};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {   // c and rho ctilde^2 of cell rows k-1 and k
       const int g = k - 1 + q;
@@ -1305,32 +1137,14 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
   if (a.Pn) block_max_out(mx, my, a.partn + 2 * part);
 }
 
-// y-tile columns of the single-grid y-sweep: 32 (sweep_y_tile32) or 64
-#ifndef WCNS_YCW
-#define WCNS_YCW 32
-#endif
-constexpr int Y_CW = WCNS_YCW;
-// threads per y-sweep block
-constexpr int Y_THREADS = Y_CW == 32 ? 32 * Y_WAVES : 64 * Y_WAVES;
-static_assert(Y_THREADS <= 512, "y-tile block too large: 64-column tiles take at most 8 face rows");
-
-// waves per SIMD the y-sweep is compiled for (VGPR budget 512 / this)
-#ifndef WCNS_YWPE
-#define WCNS_YWPE (Y_WAVES >= 8 ? 4 : 3)
-#endif
 // (FO: the first-order scheme, memory-bound: six waves per SIMD, three
 // 16-row tiles per CU)
 template <bool DIRI, bool B32, bool FO = false>
-__global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(FO ? 6 : WCNS_YWPE))) void k_sweep_y(
+__global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(FO ? 6 : 4))) void k_sweep_y(
     KArgs a) {
-  if constexpr (Y_CW == 32) {
-    __shared__ double tile32[9 * (Y_WAVES + 5) * 32];
-    sweep_y_tile32<Y_WAVES, DIRI, B32, FO>(a, blockIdx.x, blockIdx.y, tile32,
-                                           (long)blockIdx.y * gridDim.x + blockIdx.x);
-  } else {
-    __shared__ double tile[ytile_lds_doubles<Y_WAVES>()];
-    sweep_y_tile_lds<Y_WAVES, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile);
-  }
+  __shared__ double tile32[9 * (Y_ROWS + 5) * Y_COLS];
+  sweep_y_tile32<Y_ROWS, DIRI, B32, FO>(a, blockIdx.x, blockIdx.y, tile32,
+                                        (long)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // cell rows j = (b+1)*YW - 1 between y-tile b and b+1 (t: flat index over
@@ -1374,7 +1188,7 @@ __global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
   (void)nbr;
   long idx = 0;
   double X[6];
-  const bool own = fixup_cell(a, (long)blockIdx.x * blockDim.x + threadIdx.x, Y_WAVES, idx, X);
+  const bool own = fixup_cell(a, (long)blockIdx.x * blockDim.x + threadIdx.x, Y_ROWS, idx, X);
   if (a.Pn) {
     double mx = 0.0, my = 0.0;
     if (own) next_prims(a, idx, (long)a.nx * a.ny, X, mx, my);

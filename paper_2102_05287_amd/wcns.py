@@ -17,8 +17,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# WCNS_LIB may point at another build of the same library (variant timing)
-LIB_PATH = os.environ.get("WCNS_LIB", os.path.join(_HERE, "libwcns.so"))
+LIB_PATH = os.path.join(_HERE, "libwcns.so")
 
 WCNS_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "fluids violate Lemma 1", -3: "out of memory",
