@@ -354,15 +354,7 @@ def time_to_solution_form():
         W = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if spec.dt_fixed > 0:
-            t, n = 0.0, 0
-            while t < spec.t_end:
-                dt = spec.dt_fixed if t + spec.dt_fixed <= spec.t_end else spec.t_end - t
-                sol.step(W, dt)
-                t += dt
-                n += 1
-        else:
-            n, t = sol.advance(W, spec.t_end, chunk=64 if spec.ndim == 2 else 32)
+        n, t = sol.advance(W, spec.t_end, chunk=64 if spec.ndim == 2 else 32, dt=spec.dt_fixed)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         a1 = W[-1]

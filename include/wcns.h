@@ -24,6 +24,17 @@
  *    (that would cost a runtime query per call): a host pointer or a buffer
  *    shorter than stated is the caller's error and faults the kernel that
  *    touches it.  The Python binding checks every tensor it passes.
+ *  - Admissibility is reported lazily (the admissible set G of Sec. 2:
+ *    0 <= a1 <= 1, a_k r_k >= 0, rho e - pbar_inf > 0; the limiters of
+ *    Sec. 5 exist to keep every stage result inside it).  The kernels count,
+ *    with no host synchronisation, every input cell of a call's first stage
+ *    and every stage result (cell states after an SSP-RK3 stage) that lies
+ *    outside G.  Once a count has been made visible to the host, every later
+ *    call that enqueues work on the context (wcns_rhs, wcns_limit,
+ *    wcns_max_wavespeed, wcns_ssprk3_step[s], wcns_ssprk3_advance, wcns_run)
+ *    returns WCNS_ERR_INADMISSIBLE without enqueuing anything, until
+ *    wcns_violations reads and clears the count.  Work already enqueued runs
+ *    on (the states it writes are then no longer meaningful).
  */
 #ifndef WCNS_H_
 #define WCNS_H_
@@ -90,7 +101,11 @@ typedef struct {
   double eps_arho, eps_alpha, eps_rhoc2;  /* limiter tolerances, Sec. 5.1: 1e-10, 1e-10, 1e-8 */
   double hs_arho, hs_alpha, hs_rhoc2;     /* hard-switch tolerances: 1e-11, 1e-11, 1e-9       */
   double weno_eps;                        /* epsilon of the IS weights (Sec. 4.3); the paper  */
-                                          /* gives none; default 1e-40                        */
+                                          /* gives none; default 1e-40; accepted in           */
+                                          /* [1e-200, 1e200] (WCNS_ERR_ARG otherwise), where  */
+                                          /* every IS-weight quotient tau_5/(beta + eps) has  */
+                                          /* the normal-range operands the kernels' division  */
+                                          /* core rounds exactly                              */
   double cfl;                             /* CFL number, <= 0.5 (Sec. 3.3, 5.3); default 0.5  */
   int32_t interp_limiter;                 /* 1: apply Algorithms 1-3 (Sec. 5.1)               */
   int32_t flux_limiter;                   /* 1: apply Algorithms 4-6 (Sec. 5.2)               */
@@ -105,7 +120,8 @@ wcns_status wcns_params_default(wcns_params* p);
 
 /* Create a context for one grid.  Validates the fluids against Lemma 1
  * (WCNS_ERR_EOS), the grid (nx, ny >= 1, ndim in {1,2}, bc kinds, reflective
- * sides need >= 3 cells) and the parameters (WCNS_ERR_ARG), checks the
+ * sides need >= 3 cells) and the parameters (cfl in (0, 0.5], weno_eps in
+ * [1e-200, 1e200], scheme, precision; WCNS_ERR_ARG), checks the
  * Dirichlet ghost states (finite, partial densities >= 0 with a positive sum,
  * 0 <= a1 <= 1; else WCNS_ERR_INADMISSIBLE), then allocates all device
  * scratch once (WCNS_ERR_NOMEM).  stream: hipStream_t or NULL for
@@ -183,6 +199,30 @@ wcns_status wcns_ssprk3_step(wcns_ctx* ctx, double* W, double dt, double* dt_use
  * primitive pass per step.  nsteps = 0 does nothing; WCNS_ERR_ARG for
  * nsteps < 0.  Asynchronous; no host sync. */
 wcns_status wcns_ssprk3_steps(wcns_ctx* ctx, double* W, int32_t nsteps, double dt, double* dts);
+
+/* Time loop of the paper's runs on the device: up to nsteps SSP-RK3 steps
+ * (Sec. 5.3) of W in place, each of size dt > 0 or, dt <= 0, the CFL step
+ * of Sec. 3.3 from the state at its start, the last one shortened to end
+ * at t_end; the time is kept on the device.  t: device double, the time at
+ * the start (in) and after the steps taken (out); steps_taken: device int64
+ * (may be NULL), incremented by one per step taken; dts: device array of
+ * >= nsteps doubles (may be NULL), the dt of each step slot (0 for a
+ * skipped one).  Each step clips its dt to t_end - t when t + dt > t_end; a
+ * step that would start at t >= t_end is skipped (its kernels return at
+ * once), and so is every later step of the call.  A caller therefore
+ * enqueues chunks without reading t in between, and stops once a chunk
+ * took fewer steps than it enqueued; the chunks can be captured in a HIP
+ * graph.  The steps taken are the arithmetic of wcns_ssprk3_steps.
+ * Asynchronous; no host sync.  WCNS_ERR_CFL for a non-finite dt or t_end. */
+wcns_status wcns_ssprk3_advance(wcns_ctx* ctx, double* W, double dt, double t_end, int32_t nsteps,
+                                double* t, int64_t* steps_taken, double* dts);
+
+/* Lazy admissibility report (see the conventions above): synchronises the
+ * context's stream and returns in *n_bad (host) the number of cells the
+ * kernels found outside G since creation or the last clear; clear = 1 then
+ * resets the count and lets later calls run again.  Returns
+ * WCNS_ERR_INADMISSIBLE when *n_bad > 0, WCNS_OK otherwise. */
+wcns_status wcns_violations(wcns_ctx* ctx, int64_t* n_bad, int32_t clear);
 
 /* Count cells outside the admissible set G (Sec. 2): a1 < 0 or a1 > 1,
  * a_k r_k < 0, or rho e - pbar_inf <= 0 (NaN counts as outside).
@@ -289,6 +329,14 @@ wcns_status wcns_batch_steps_left(wcns_batch* b, int32_t* steps);
  * enqueued on `stream` (hipStream_t or NULL). */
 wcns_status wcns_prim_to_cons_n(const wcns_eos* eos, int32_t ndim, int64_t ncell, const double* V,
                                 double* W, void* stream);
+
+/* Per-instance admissibility report of the batched form: synchronises the
+ * batch stream and writes counts[k] (host int64[n]), the number of cells of
+ * instance k found outside G (its input at the first stage of a step call,
+ * every stage result) since the instance was bound or the last clear;
+ * clear = 1 resets the counts.  Batched calls never refuse work: a server
+ * reads these after each tick and retires the instances that failed. */
+wcns_status wcns_batch_violations(wcns_batch* b, int64_t* counts, int32_t clear);
 
 /* Host copy of every instance's last time step, dt[n] (synchronises). */
 wcns_status wcns_batch_dt(wcns_batch* b, double* dt);

@@ -53,6 +53,12 @@ struct K3Args {
   const double* Un;           // state at the start of the step
   double* edge;               // strided-pass tile edges [nslab][nbr][14][ncol]
   double ca, cb;              // RK: out = ca*Un + cb*(W + dt*L)
+  // lazy admissibility report, as in KArgs: stage results (and k3_node's
+  // input with check_in) outside G counted into *viol, flag *vflag raised;
+  // node_skip: a k3_node launch inside a step (returns when it is skipped)
+  unsigned long long* viol;
+  int32_t* vflag;
+  int32_t check_in, node_skip;
 };
 
 struct NodeQ3 {
@@ -582,18 +588,27 @@ __device__ __forceinline__ void load_cell_in3(const K3Args& a, long idx, long N,
     c.dt = a.step[0];
   }
 }
-// write_cell3 (or L alone before the last pass) on preloaded inputs
-__device__ __forceinline__ void write_cell3_in(const K3Args& a, long idx, long N, int k, double L,
-                                               const CellIn3& c) {
-  if (a.last && a.out_mode != OUT_STORE)
-    a.out[k * N + idx] = a.ca * c.un[k] + a.cb * (c.w[k] + c.dt * L);
-  else
-    a.out[k * N + idx] = L;
+// write_cell3 (or L alone before the last pass) on preloaded inputs;
+// returns the value written
+__device__ __forceinline__ double write_cell3_in(const K3Args& a, long idx, long N, int k, double L,
+                                                 const CellIn3& c) {
+  const double v = (a.last && a.out_mode != OUT_STORE) ? a.ca * c.un[k] + a.cb * (c.w[k] + c.dt * L) : L;
+  a.out[k * N + idx] = v;
+  return v;
+}
+
+// Stage-result check of a cell the last pass of an RK stage finished (X in
+// state order): counted when outside G (the lanes that get here vote).
+__device__ __forceinline__ void stage_check3(const K3Args& a, const double X[7]) {
+  if (!(a.viol && a.last && a.out_mode != OUT_STORE)) return;
+  report_bad(a.viol, a.vflag, !admissible(X[0], X[1], X[6], rhoc2_tilde3(a.eos, X)));
 }
 
 // ------------------------------------------------------------------ kernels
 __global__ __launch_bounds__(256) void k3_node(K3Args a, double* P, double* partial) {
+  if (a.node_skip && a.step[STEP_SKIP] != 0.0) return;
   const long N = (long)a.nx * a.ny * a.nz;
+  const bool check = a.viol && a.check_in;
   double m[3] = {0.0, 0.0, 0.0};
   for (long o = (long)blockIdx.x * blockDim.x + threadIdx.x; o < N;
        o += (long)gridDim.x * blockDim.x) {
@@ -607,6 +622,7 @@ __global__ __launch_bounds__(256) void k3_node(K3Args a, double* P, double* part
     m[0] = fmax(m[0], fabs(u) + c);
     m[1] = fmax(m[1], fabs(v) + c);
     m[2] = fmax(m[2], fabs(w) + c);
+    if (check) report_bad(a.viol, a.vflag, !admissible(X[0], X[1], X[6], h));
   }
   __shared__ double red[3][4];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -627,9 +643,12 @@ __global__ __launch_bounds__(256) void k3_node(K3Args a, double* P, double* part
 // Time step and three-way split [Sec. 3.3]: tau_d = max(|u_d|+c)/h_d,
 // dt = CFL/(tau_x + tau_y + tau_z), sigma_d = tau_d/(tau_x + tau_y + tau_z),
 // lambda_d = dt/(h_d sigma_d).
+// clock, nsteps, t_end: the time loop to t_end as in k_finalize (clock null:
+// none)
 __global__ __launch_bounds__(256) void k3_finalize(const double* partial, int nblk, int dt_mode,
                                                    double dt_in, double cfl, double dx, double dy,
-                                                   double dz, double* step, double* dt_used) {
+                                                   double dz, double* step, double* dt_used,
+                                                   double* clock, int64_t* nsteps, double t_end) {
   double m[3] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nblk; b += blockDim.x)
 #pragma unroll
@@ -645,10 +664,19 @@ __global__ __launch_bounds__(256) void k3_finalize(const double* partial, int nb
   if (threadIdx.x != 0) return;
   for (int d = 0; d < 3; ++d)
     for (int k = 1; k < 4; ++k) m[d] = fmax(m[d], red[d][k]);
+  if (dt_mode == DT_KEEP && step[STEP_SKIP] != 0.0) return;   // inside a skipped step
   double dt;
   if (dt_mode == DT_GIVEN) dt = dt_in;
   else if (dt_mode == DT_KEEP) dt = step[0];
   else dt = cfl / (m[0] / dx + m[1] / dy + m[2] / dz);
+  if (dt_mode != DT_KEEP) {
+    const bool run = !clock || clock_step(clock, nsteps, t_end, dt);
+    step[STEP_SKIP] = run ? 0.0 : 1.0;
+    if (!run) {
+      if (dt_used) *dt_used = 0.0;
+      return;
+    }
+  }
   const double h[3] = {dx, dy, dz};
   const double t[3] = {m[0] / dx, m[1] / dy, m[2] / dz};
   const double tot = t[0] + t[1] + t[2];
@@ -663,6 +691,7 @@ __global__ __launch_bounds__(256) void k3_finalize(const double* partial, int nb
 // x pass: one wave per tile of tile_x flattened cells (rows of nx); lanes
 // past the tile own the right faces of its row segments (as in 2D)
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k3_sweep_x(K3Args a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   const int lane = threadIdx.x;
   const int nx = a.nx;
   const long N = (long)nx * a.ny * a.nz;
@@ -706,6 +735,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k3
 // XLDS_MIN_NX cells): flattened tiles of XT cells over the ny*nz rows with
 // the window geometry of the 2D sweep, 13 values per slot in the x frame.
 __global__ __launch_bounds__(64 * XW) void k3_sweep_xl(K3Args a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   __shared__ double tile[XW][13 * XWIN];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nx = a.nx;
@@ -829,13 +859,15 @@ __device__ __forceinline__ void sweep3_tile32(const K3Args& a, double* tile) {
   }
   __syncthreads();
   if (!own) return;
+  double X[7];
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const int s = state_index3(DIR, v);
     const double up = r == 0 ? Gn[v] : sG[((w + 1) * 7 + v) * 32 + cl];
     const double L = cin.lin[s] + hdiv(-(up - Gp[v]), h, rh);
-    write_cell3_in(a, idx, N, s, L, cin);
+    X[s] = write_cell3_in(a, idx, N, s, L, cin);
   }
+  stage_check3(a, X);
 }
 
 // (measured at 256^3, ms per y / z pass: nodes loaded from global memory
@@ -844,6 +876,7 @@ __device__ __forceinline__ void sweep3_tile32(const K3Args& a, double* tile) {
 // registers, 1.81 / 1.93; the same on 32 columns x 8 rows 1.78 / 1.81)
 template <int DIR>
 __global__ __launch_bounds__(L3_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k3_sweep_l(K3Args a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   __shared__ double tile32[11 * (YW3 + 5) * 32];
   sweep3_tile32<DIR>(a, tile32);
 }
@@ -851,6 +884,7 @@ __global__ __launch_bounds__(L3_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 // the cell rows j = (b+1)*YW3 - 1 between tiles b and b+1 of a strided pass
 template <int DIR>
 __global__ __launch_bounds__(256) void k3_fixup(K3Args a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   const long plane = (long)a.nx * a.ny;
   const long N = plane * a.nz;
   const long ncol = DIR == 1 ? a.nx : plane;
@@ -878,12 +912,14 @@ __global__ __launch_bounds__(256) void k3_fixup(K3Args a) {
   }
   CellIn3 cin;
   load_cell_in3(a, idx, N, cin);
+  double X[7];
 #pragma unroll
   for (int v = 0; v < 7; ++v) {
     const int s = state_index3(DIR, v);
     const double L = cin.lin[s] + hdiv(-(gh[v] - gl[v]), h, rh);
-    write_cell3_in(a, idx, N, s, L, cin);
+    X[s] = write_cell3_in(a, idx, N, s, L, cin);
   }
+  stage_check3(a, X);
 }
 
 // V (a1r1, a2r2, u, v, w, p, a1) -> W [Sec. 2 mixture EOS]

@@ -40,7 +40,11 @@ struct wcns_ctx {
   // only the first stage of a call runs k_node
   double* P2;
   int fuse, nfused;
-  unsigned long long* count;
+  // count[0]: wcns_check_admissible's; count[1]: the cells the kernels found
+  // outside G since creation or the last wcns_violations clear (viol)
+  unsigned long long *count, *viol;
+  int32_t* hflag;   // host-mapped pinned flag raised with viol (lazy error)
+  int32_t* dflag;   // its device address
   double* damax;  // Dirichlet ghost wave-speed maxima [2] (inside dirP), or null
   // 3D: arguments shared by its kernels, strided-pass edge buffer, tile rows
   K3Args base3;
@@ -180,6 +184,7 @@ wcns_status wcns_destroy(wcns_ctx* c) {
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->count) (void)hipFree(c->count);
+  if (c->hflag) (void)hipHostFree(c->hflag);
   if (c->edge3) (void)hipFree(c->edge3);
   if (c->run_G) (void)hipFree(c->run_G);
   if (c->run_dev) (void)hipFree(c->run_dev);
@@ -190,11 +195,35 @@ wcns_status wcns_destroy(wcns_ctx* c) {
 static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
                            int32_t precision, void* stream, wcns_ctx** out);
 
-wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
-                        int32_t precision, void* stream, wcns_ctx** out) {
-  if (!g || !eos || !prm || !out) return WCNS_ERR_ARG;
-  *out = nullptr;
-  if (g->ndim == 3) return create3(g, eos, prm, precision, stream, out);
+// The admissible-count pair (zeroed) and the host-mapped violation flag.
+static wcns_status alloc_report(wcns_ctx* c) {
+  if (hipMalloc((void**)&c->count, 2 * sizeof(unsigned long long)) != hipSuccess) return WCNS_ERR_NOMEM;
+  c->viol = c->count + 1;
+  const unsigned long long z[2] = {0ull, 0ull};
+  if (hipMemcpy(c->count, z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return WCNS_ERR_HIP;
+  if (hipHostMalloc((void**)&c->hflag, sizeof(int32_t), hipHostMallocMapped) != hipSuccess) {
+    c->hflag = nullptr;
+    return WCNS_ERR_NOMEM;
+  }
+  *c->hflag = 0;
+  if (hipHostGetDevicePointer((void**)&c->dflag, c->hflag, 0) != hipSuccess) return WCNS_ERR_HIP;
+  return WCNS_OK;
+}
+
+// weno_eps range: every IS-weight quotient tau_5/(beta + eps) then has a
+// normal divisor at least eps and, for |tau_5| < 1e100, a normal quotient,
+// the operand range on which the kernels' division core is the IEEE divide
+static bool weno_eps_ok(double e) { return e >= 1e-200 && e <= 1e200; }
+
+// A violation seen by earlier work on this context (lazy report): the
+// entry points that enqueue work refuse to run until wcns_violations clears it.
+static bool flagged(const wcns_ctx* c) {
+  return c->hflag && __atomic_load_n(c->hflag, __ATOMIC_ACQUIRE) != 0;
+}
+
+// Validation of a 1D/2D grid, the fluids (Lemma 1) and the options.
+static wcns_status check_setup(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
+                               int32_t precision) {
   if (g->ndim != 1 && g->ndim != 2) return WCNS_ERR_ARG;
   if (g->nx < 1 || g->ny < 1 || (g->ndim == 1 && g->ny != 1)) return WCNS_ERR_ARG;
   // node loads use 32-bit byte offsets within one component array
@@ -210,12 +239,16 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   }
   if (!eos_ok(eos)) return WCNS_ERR_EOS;
   if (!(prm->cfl > 0.0 && prm->cfl <= 0.5)) return WCNS_ERR_ARG;
-  if (!(prm->weno_eps > 0.0)) return WCNS_ERR_ARG;
+  if (!weno_eps_ok(prm->weno_eps)) return WCNS_ERR_ARG;
   if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
   if (precision != WCNS_FP64 && precision != WCNS_FP32_BULK) return WCNS_ERR_ARG;
+  return WCNS_OK;
+}
 
-  wcns_ctx* c = (wcns_ctx*)calloc(1, sizeof(wcns_ctx));
-  if (!c) return WCNS_ERR_NOMEM;
+// Everything of a 1D/2D context but its device buffers: sizes, launch
+// geometry and the kernel arguments (c zero-filled by the caller).
+static void ctx_setup(wcns_ctx* c, const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
+                      int32_t precision, void* stream) {
   c->grid = *g;
   c->eos = *eos;
   c->params = *prm;
@@ -261,6 +294,20 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   c->node_grid = (int)(ng < NODE_GRID_CAP ? ng : NODE_GRID_CAP);
   c->nbr = (g->ny + 1 + Y_ROWS - 1) / Y_ROWS;
   a.nbr = c->nbr;
+}
+
+wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
+                        int32_t precision, void* stream, wcns_ctx** out) {
+  if (!g || !eos || !prm || !out) return WCNS_ERR_ARG;
+  *out = nullptr;
+  if (g->ndim == 3) return create3(g, eos, prm, precision, stream, out);
+  wcns_status chk = check_setup(g, eos, prm, precision);
+  if (chk != WCNS_OK) return chk;
+
+  wcns_ctx* c = (wcns_ctx*)calloc(1, sizeof(wcns_ctx));
+  if (!c) return WCNS_ERR_NOMEM;
+  ctx_setup(c, g, eos, prm, precision, stream);
+  KArgs& a = c->base;
 
   wcns_status st = WCNS_OK;
   auto alloc = [&](double** p, size_t n) {
@@ -294,9 +341,10 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   const int R = 2 * g->ny + 2 * g->nx;
   alloc(&c->dirW, 6 * (size_t)R);
   alloc(&c->dirP, 5 * (size_t)R + 2);
-  if (st == WCNS_OK && hipMalloc((void**)&c->count, sizeof(unsigned long long)) != hipSuccess)
-    st = WCNS_ERR_NOMEM;
+  if (st == WCNS_OK) st = alloc_report(c);
   if (st != WCNS_OK) { wcns_destroy(c); return st; }
+  a.viol = c->viol;
+  a.vflag = c->dflag;
 
   // Dirichlet ghost rows: primitive states from the grid (per row, or one
   // state for the whole side), converted on the device like any state
@@ -390,7 +438,7 @@ static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_p
   }
   if (!eos_ok(eos)) return WCNS_ERR_EOS;
   if (!(prm->cfl > 0.0 && prm->cfl <= 0.5)) return WCNS_ERR_ARG;
-  if (!(prm->weno_eps > 0.0)) return WCNS_ERR_ARG;
+  if (!weno_eps_ok(prm->weno_eps)) return WCNS_ERR_ARG;
   if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
   if (precision != WCNS_FP64) return WCNS_ERR_ARG;
 
@@ -455,9 +503,10 @@ static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_p
   alloc(&c->edge3, ey > ez ? ey : ez);
   alloc(&c->partial, 3 * (size_t)c->node_grid);
   alloc(&c->step, 8);
-  if (st == WCNS_OK && hipMalloc((void**)&c->count, sizeof(unsigned long long)) != hipSuccess)
-    st = WCNS_ERR_NOMEM;
+  if (st == WCNS_OK) st = alloc_report(c);
   if (st != WCNS_OK) { wcns_destroy(c); return st; }
+  a.viol = c->viol;
+  a.vflag = c->dflag;
   double zero8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (hipMemcpy(c->step, zero8, sizeof(zero8), hipMemcpyHostToDevice) != hipSuccess) {
     wcns_destroy(c);
@@ -469,15 +518,30 @@ static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_p
   return WCNS_OK;
 }
 
+// Time loop to t_end kept on the device (wcns_ssprk3_advance): the clock
+// and step counter the first stage's finalize advances.
+struct Clock {
+  double* t;
+  int64_t* n;
+  double t_end;
+};
+
 static void set_bases3(const wcns_ctx* c, K3Args& a, const double* W) {
   a.W = W;
   for (int k = 0; k < 7; ++k) a.Wc[k] = W + (size_t)k * c->N;
 }
 
+// node primitives and maxima of W, then dt/lambda.  in_step: a stage after
+// the first of a step (its k3_node returns when the step is skipped);
+// check_in: k3_node also counts inadmissible input cells (the first stage
+// of a call: later inputs are stage results, checked where they are made)
 static wcns_status launch_node_finalize3(wcns_ctx* c, const double* W, int dt_mode, double dt,
-                                         double* dt_used) {
+                                         double* dt_used, bool in_step = false,
+                                         bool check_in = true, const Clock* clk = nullptr) {
   K3Args a = c->base3;
   set_bases3(c, a, W);
+  a.node_skip = in_step ? 1 : 0;
+  a.check_in = check_in ? 1 : 0;
   {
     ProfScope ps(c, PROF_NODE);
     hipLaunchKernelGGL(k3_node, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
@@ -487,7 +551,8 @@ static wcns_status launch_node_finalize3(wcns_ctx* c, const double* W, int dt_mo
     ProfScope ps(c, PROF_FIN);
     hipLaunchKernelGGL(k3_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
                        c->node_grid, dt_mode, dt, c->params.cfl, a.dx, a.dy, a.dz, c->step,
-                       dt_used);
+                       dt_used, clk ? clk->t : nullptr, clk ? clk->n : nullptr,
+                       clk ? clk->t_end : 0.0);
   }
   LAUNCH_CHECK();
   return WCNS_OK;
@@ -559,7 +624,8 @@ wcns_status wcns_set_stream(wcns_ctx* c, void* stream) {
 }
 
 // dt/lambda from the nblk block-maxima pairs in c->partial
-static wcns_status launch_finalize(wcns_ctx* c, int nblk, int dt_mode, double dt, double* dt_used) {
+static wcns_status launch_finalize(wcns_ctx* c, int nblk, int dt_mode, double dt, double* dt_used,
+                                   const Clock* clk = nullptr) {
   FinArgs f;
   f.ndim = c->grid.ndim;
   f.dt_mode = dt_mode;
@@ -570,6 +636,9 @@ static wcns_status launch_finalize(wcns_ctx* c, int nblk, int dt_mode, double dt
   f.step = c->step;
   f.dt_used = dt_used;
   f.damax = c->damax;
+  f.clock = clk ? clk->t : nullptr;
+  f.nsteps = clk ? clk->n : nullptr;
+  f.t_end = clk ? clk->t_end : 0.0;
   ProfScope ps(c, PROF_FIN);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c->stream, (const double*)c->partial,
                      nblk, f);
@@ -578,11 +647,15 @@ static wcns_status launch_finalize(wcns_ctx* c, int nblk, int dt_mode, double dt
 }
 
 // node primitives of state W into P + wave-speed maxima, then dt/lambda
+// (in_step, check_in: as for launch_node_finalize3)
 static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mode, double dt,
-                                        double* dt_used, double* P = nullptr) {
+                                        double* dt_used, double* P = nullptr, bool in_step = false,
+                                        bool check_in = true, const Clock* clk = nullptr) {
   if (!P) P = c->P;
   KArgs a = c->base;
   a.W = W;
+  a.node_skip = in_step ? 1 : 0;
+  a.check_in = check_in ? 1 : 0;
   {
     ProfScope ps(c, PROF_NODE);
     if (c->grid.ndim == 2)
@@ -591,7 +664,7 @@ static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mod
       hipLaunchKernelGGL(k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, P, c->partial);
   }
   LAUNCH_CHECK();
-  return launch_finalize(c, c->node_grid, dt_mode, dt, dt_used);
+  return launch_finalize(c, c->node_grid, dt_mode, dt, dt_used, clk);
 }
 
 // per-component base pointers of a state and of the node primitives
@@ -706,8 +779,7 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   if (c->nbr > 1) {
     long nt = (long)(c->nbr - 1) * c->grid.nx;
     ProfScope ps(c, PROF_FIX);
-    hipLaunchKernelGGL(k_fixup_y, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, a,
-                       c->nbr);
+    hipLaunchKernelGGL(k_fixup_y, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, a);
     LAUNCH_CHECK();
   }
   return WCNS_OK;
@@ -734,6 +806,7 @@ wcns_status wcns_prim_to_cons(wcns_ctx* c, const double* V, double* W) {
 wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
   if (!c || !W || !dWdt || W == dWdt) return WCNS_ERR_ARG;
   if (!(dt >= 0.0) || !isfinite(dt)) return WCNS_ERR_CFL;
+  if (flagged(c)) return WCNS_ERR_INADMISSIBLE;
   if (c->grid.ndim == 3) {
     wcns_status s = launch_node_finalize3(c, W, DT_GIVEN, dt, nullptr);
     if (s != WCNS_OK) return s;
@@ -748,7 +821,11 @@ wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
 // primitives and block maxima of every stage but the first of the call come
 // from the previous stage's y-sweep and fixup (c->fuse): within one call no
 // one else writes W between steps.  Step k's dt goes to dts[k] (device).
-static wcns_status steps_impl(wcns_ctx* c, double* W, int n, double dt, double* dts) {
+// clk: the time loop to t_end on the device (each step's first finalize
+// clips dt or marks the step skipped; a skipped step's kernels return at
+// once, and so do all later ones of the call, since the clock stays put).
+static wcns_status steps_impl(wcns_ctx* c, double* W, int n, double dt, double* dts,
+                              const Clock* clk = nullptr) {
   const double* in[3] = {W, c->U1, c->U2};
   double* outs[3] = {c->U1, c->U2, W};
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
@@ -758,18 +835,21 @@ static wcns_status steps_impl(wcns_ctx* c, double* W, int n, double dt, double* 
   for (int k = 0; k < n; ++k) {
     double* dt_used = dts ? dts + k : nullptr;
     for (int s = 0; s < 3; ++s) {
-      int mode = s == 0 ? (dt > 0.0 ? DT_GIVEN : DT_CFL) : DT_KEEP;
+      const int mode = s == 0 ? (dt > 0.0 ? DT_GIVEN : DT_CFL) : DT_KEEP;
+      const bool first = k == 0 && s == 0, last = k == n - 1 && s == 2;
+      const Clock* ck = s == 0 ? clk : nullptr;
       if (c->grid.ndim == 3) {
-        wcns_status st = launch_node_finalize3(c, in[s], mode, dt, s == 0 ? dt_used : nullptr);
+        wcns_status st = launch_node_finalize3(c, in[s], mode, dt, s == 0 ? dt_used : nullptr,
+                                               s > 0, first, ck);
         if (st != WCNS_OK) return st;
         st = launch_sweeps3(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s]);
         if (st != WCNS_OK) return st;
         continue;
       }
-      const bool first = k == 0 && s == 0, last = k == n - 1 && s == 2;
       wcns_status st = !first && c->fuse
-                           ? launch_finalize(c, c->nfused, mode, dt, s == 0 ? dt_used : nullptr)
-                           : launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr, Pcur);
+                           ? launch_finalize(c, c->nfused, mode, dt, s == 0 ? dt_used : nullptr, ck)
+                           : launch_node_finalize(c, in[s], mode, dt, s == 0 ? dt_used : nullptr,
+                                                  Pcur, s > 0, first, ck);
       if (st != WCNS_OK) return st;
       double* Pn = c->fuse && !last ? Pnext : nullptr;
       st = launch_sweeps(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s], Pcur, Pn);
@@ -783,13 +863,39 @@ static wcns_status steps_impl(wcns_ctx* c, double* W, int n, double dt, double* 
 wcns_status wcns_ssprk3_step(wcns_ctx* c, double* W, double dt, double* dt_used) {
   if (!c || !W) return WCNS_ERR_ARG;
   if (!isfinite(dt)) return WCNS_ERR_CFL;
+  if (flagged(c)) return WCNS_ERR_INADMISSIBLE;
   return steps_impl(c, W, 1, dt, dt_used);
 }
 
 wcns_status wcns_ssprk3_steps(wcns_ctx* c, double* W, int32_t nsteps, double dt, double* dts) {
   if (!c || !W || nsteps < 0) return WCNS_ERR_ARG;
   if (!isfinite(dt)) return WCNS_ERR_CFL;
+  if (flagged(c)) return WCNS_ERR_INADMISSIBLE;
   return steps_impl(c, W, nsteps, dt, dts);
+}
+
+wcns_status wcns_ssprk3_advance(wcns_ctx* c, double* W, double dt, double t_end, int32_t nsteps,
+                                double* t, int64_t* steps_taken, double* dts) {
+  if (!c || !W || !t || nsteps < 0) return WCNS_ERR_ARG;
+  if (!isfinite(t_end) || !isfinite(dt)) return WCNS_ERR_CFL;
+  if (flagged(c)) return WCNS_ERR_INADMISSIBLE;
+  const Clock clk{t, steps_taken, t_end};
+  return steps_impl(c, W, nsteps, dt, dts, &clk);
+}
+
+wcns_status wcns_violations(wcns_ctx* c, int64_t* n_bad, int32_t clear) {
+  if (!c || !n_bad) return WCNS_ERR_ARG;
+  unsigned long long h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, c->viol, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  *n_bad = (int64_t)h;
+  if (clear) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, c->stream, c->viol, 1);
+    LAUNCH_CHECK();
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    __atomic_store_n(c->hflag, 0, __ATOMIC_RELEASE);
+  }
+  return h ? WCNS_ERR_INADMISSIBLE : WCNS_OK;
 }
 
 wcns_status wcns_run(wcns_ctx* c, double* W, double t0, double t_end, double dt_fixed,
@@ -800,6 +906,7 @@ wcns_status wcns_run(wcns_ctx* c, double* W, double t0, double t_end, double dt_
   if (!c->run_dev) return WCNS_ERR_ARG;   // 1D grids of at most RUN1D_MAX_CELLS cells only
   if (!isfinite(t0) || !isfinite(t_end) || !(dt_fixed >= 0.0) || !isfinite(dt_fixed))
     return WCNS_ERR_CFL;
+  if (flagged(c)) return WCNS_ERR_INADMISSIBLE;
   Run1D r;
   memset(&r, 0, sizeof(r));
   r.a = c->base;
@@ -839,6 +946,7 @@ wcns_status wcns_run(wcns_ctx* c, double* W, double t0, double t_end, double dt_
 
 wcns_status wcns_max_wavespeed(wcns_ctx* c, const double* W, double* d_amax) {
   if (!c || !W || !d_amax) return WCNS_ERR_ARG;
+  if (flagged(c)) return WCNS_ERR_INADMISSIBLE;
   if (c->grid.ndim == 3) {
     wcns_status s = launch_node_finalize3(c, W, DT_GIVEN, 0.0, nullptr);
     if (s != WCNS_OK) return s;
@@ -861,6 +969,7 @@ wcns_status wcns_limit(wcns_ctx* c, int32_t dir, const double* W, const double* 
   if (c->grid.ndim == 3) return WCNS_ERR_ARG;
   if (dir != 0 && !(dir == 1 && c->grid.ndim == 2)) return WCNS_ERR_ARG;
   if (!(dt >= 0.0) || !isfinite(dt)) return WCNS_ERR_CFL;
+  if (flagged(c)) return WCNS_ERR_INADMISSIBLE;
   wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr);
   if (s != WCNS_OK) return s;
   KArgs a = c->base;
@@ -1026,6 +1135,7 @@ struct wcns_batch {
   size_t o_node = 0, o_x = 0, o_y = 0, o_fix = 0;
   double* d_dt = nullptr;      // per-instance dt of the last step
   int32_t* d_live = nullptr;   // per-instance steps left (frozen at 0)
+  unsigned long long* d_viol = nullptr;   // per-instance cells found outside G
   int dt_cap = 0;
   int ytile = 16, order = 2;
   bool x_lds = false;   // x-sweep with LDS windows (every instance has nx >= XLDS_MIN_NX)
@@ -1169,6 +1279,7 @@ static wcns_status batch_build(wcns_batch* b) {
     a.cfl = b->params.cfl;
     a.dt_used = b->d_dt + k;
     a.live = b->d_live + k;
+    a.viol = b->d_viol + k;
     const double* in[3] = {b->W[k], U1, U2};
     double* outs[3] = {U1, U2, b->W[k]};
     const double cA[3] = {0.0, 0.75, 1.0 / 3.0};
@@ -1178,6 +1289,10 @@ static wcns_status batch_build(wcns_batch* b) {
       // another in the same call
       const int s = set == 4 ? 0 : set;
       KArgs x = a;
+      // the node pass checks its input only where no stage made it (the
+      // first stage of a call, the RHS); stage results are checked where
+      // they are written
+      x.check_in = (set == 0 || set == 3) ? 1 : 0;
       const double* Ws = s < 3 ? in[s] : b->W[k];
       x.W = Ws;
       if (g.ndim == 2) {
@@ -1331,15 +1446,21 @@ static wcns_status batch_layout(wcns_batch* b, int n, const wcns_grid* grids, do
   if (n > b->dt_cap) {
     if (b->d_dt) (void)hipFree(b->d_dt);
     if (b->d_live) (void)hipFree(b->d_live);
+    if (b->d_viol) (void)hipFree(b->d_viol);
     b->d_dt = nullptr;
     b->d_live = nullptr;
+    b->d_viol = nullptr;
     if (hipMalloc((void**)&b->d_dt, sizeof(double) * n) != hipSuccess) return WCNS_ERR_NOMEM;
     if (hipMalloc((void**)&b->d_live, sizeof(int32_t) * n) != hipSuccess) return WCNS_ERR_NOMEM;
+    if (hipMalloc((void**)&b->d_viol, sizeof(unsigned long long) * n) != hipSuccess)
+      return WCNS_ERR_NOMEM;
     b->dt_cap = n;
   }
-  // every instance live for ever until told otherwise
+  // every instance live for ever until told otherwise, no violation yet
   std::vector<int32_t> live(n, 0x7fffffff);
   HIP_TRY(hipMemcpy(b->d_live, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  std::vector<unsigned long long> zero(n, 0ull);
+  HIP_TRY(hipMemcpy(b->d_viol, zero.data(), sizeof(unsigned long long) * n, hipMemcpyHostToDevice));
   return batch_build(b);
 }
 
@@ -1354,6 +1475,7 @@ wcns_status wcns_batch_destroy(wcns_batch* b) {
   if (b->d_tasks) (void)hipFree(b->d_tasks);
   if (b->d_dt) (void)hipFree(b->d_dt);
   if (b->d_live) (void)hipFree(b->d_live);
+  if (b->d_viol) (void)hipFree(b->d_viol);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return WCNS_OK;
@@ -1372,7 +1494,7 @@ wcns_status wcns_batch_create(int32_t n, const wcns_grid* grids, const wcns_eos*
   wcns_status st = batch_check_grids(n, grids, ndim);
   if (st != WCNS_OK) return st;
   if (!eos_ok(eos)) return WCNS_ERR_EOS;
-  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5) || !(prm->weno_eps > 0.0)) return WCNS_ERR_ARG;
+  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5) || !weno_eps_ok(prm->weno_eps)) return WCNS_ERR_ARG;
   if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
   if (precision != WCNS_FP64 && precision != WCNS_FP32_BULK) return WCNS_ERR_ARG;
   if (capacity_cells < 0) return WCNS_ERR_ARG;
@@ -1524,6 +1646,21 @@ wcns_status wcns_prim_to_cons_n(const wcns_eos* eos, int32_t ndim, int64_t ncell
   else
     hipLaunchKernelGGL(k_prim_to_cons<false>, dim3(g), dim3(256), 0, (hipStream_t)stream, a, V, W);
   LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+wcns_status wcns_batch_violations(wcns_batch* b, int64_t* counts, int32_t clear) {
+  if (!b || !counts) return WCNS_ERR_ARG;
+  std::vector<unsigned long long> h(b->n);
+  HIP_TRY(hipMemcpyAsync(h.data(), b->d_viol, sizeof(unsigned long long) * b->n,
+                         hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int k = 0; k < b->n; ++k) counts[k] = (int64_t)h[k];
+  if (clear) {
+    hipLaunchKernelGGL(k_zero_u64, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->d_viol, b->n);
+    LAUNCH_CHECK();
+    HIP_TRY(hipStreamSynchronize(b->stream));
+  }
   return WCNS_OK;
 }
 

@@ -79,11 +79,7 @@ __global__ __launch_bounds__(256) void kb_fixup(const KArgs* ka, const Task* t) 
   long idx = 0;
   double X[6];
   const bool own = fixup_cell(a, (long)task.a * 256 + threadIdx.x, YW, idx, X);
-  if (a.Pn) {
-    double mx = 0.0, my = 0.0;
-    if (own) next_prims(a, idx, (long)a.nx * a.ny, X, mx, my);
-    block_max_out(mx, my, a.partn + 2 * ((long)a.fuse_off + task.a));
-  }
+  fixup_finish(a, own, idx, X, task.a);
 }
 
 // end of a step: one step fewer for every live instance

@@ -34,6 +34,11 @@ namespace wcns {
 
 enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 enum { OUT_STORE = 0, OUT_RK = 1 };
+// Step record (device, one per solve): [0] dt, [1] lambda_x, [2] lambda_y,
+// [3] max(|u|+c), [4] max(|v|+c) (3D: [1..3] lambda, [4..6] maxima), and at
+// STEP_SKIP a flag set when a step of a time loop bounded by t_end would
+// start at or after t_end: every kernel of that step then returns at once.
+enum { STEP_SKIP = 7 };
 // y-sweep tiles (single grid): 32 columns x 16 y-face rows, 8 waves and
 // 48.6 KB of LDS per block, two blocks per CU.  Against 8-row tiles (four
 // 4-wave blocks per CU) the y-sweep itself runs 0.5-2% slower, but the
@@ -82,6 +87,14 @@ struct KArgs {
   double* Pn;
   double* partn;
   int32_t fuse_off, pad5;
+  // Lazy admissibility report [Sec. 2]: stage results outside G (and, with
+  // check_in, k_node's input cells) are counted into *viol (null: not
+  // counted) and raise the host-mapped flag *vflag (null: none).
+  // node_skip: a k_node launch inside a step (not its first stage), which
+  // returns at once when the step is skipped.
+  unsigned long long* viol;
+  int32_t* vflag;
+  int32_t check_in, node_skip;
 };
 
 // ------------------------------------------------------------------ nodes
@@ -504,6 +517,24 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// A state in the admissible set G [Sec. 2]: 0 <= a1 <= 1, a_k r_k >= 0 and
+// h = rho e - pbar_inf > 0 (NaN fails every test).
+__device__ __forceinline__ bool admissible(double a1r1, double a2r2, double a1, double h) {
+  return a1 >= 0.0 && a1 <= 1.0 && a1r1 >= 0.0 && a2r2 >= 0.0 && h > 0.0;
+}
+
+// Lazy admissibility report: the cells of this wave with `bad` set are added
+// to *viol and the host-visible flag is raised, by one lane and only when
+// the wave has such a cell.
+__device__ __forceinline__ void report_bad(unsigned long long* viol, int32_t* vflag, bool bad) {
+  const unsigned long long m = __ballot(bad);
+  if (m == 0ull) return;
+  if ((int)(threadIdx.x & 63) == __ffsll((long long)m) - 1) {
+    atomicAdd(viol, (unsigned long long)__popcll(m));
+    if (vflag) __hip_atomic_store(vflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
 // final write of one cell: L (store) or the SSP-RK3 combination [Sec. 4.1]
 __device__ __forceinline__ double write_cell(const KArgs& a, double* dst, long idx, long N, int k,
                                              double L) {
@@ -549,7 +580,8 @@ __device__ __forceinline__ double write_cell_in(const KArgs& a, double* dst, lon
 // Node primitives of a finished cell of the next stage's state X (state
 // order) into a.Pn, and its wave speeds |u|+c, |v|+c into the running
 // maxima: k_node's arithmetic [Sec. 2, 3.3] on the values just written.
-__device__ __forceinline__ void next_prims(const KArgs& a, long idx, long N, const double X[6],
+// Returns whether X is admissible.
+__device__ __forceinline__ bool next_prims(const KArgs& a, long idx, long N, const double X[6],
                                            double& mx, double& my) {
   double un, ut, p, c, h;
   recover<true>(a.eos, X, un, ut, p, c, h);
@@ -557,6 +589,13 @@ __device__ __forceinline__ void next_prims(const KArgs& a, long idx, long N, con
   P[idx] = un; P[N + idx] = ut; P[2 * N + idx] = p; P[3 * N + idx] = c; P[4 * N + idx] = h;
   mx = fmax(mx, fabs(un) + c);
   my = fmax(my, fabs(ut) + c);
+  return admissible(X[0], X[1], X[5], h);
+}
+
+// Stage-result check of one finished 2D cell X (state order) when it is
+// not made by next_prims: false if X lies outside G.
+__device__ __forceinline__ bool stage_ok(const KArgs& a, const double X[6]) {
+  return admissible(X[0], X[1], X[5], rhoc2_tilde<true>(a.eos, X));
 }
 
 // Block maxima of (mx, my) to out2[0], out2[1]; every thread of the block
@@ -584,10 +623,29 @@ enum { DT_GIVEN = 0, DT_CFL = 1, DT_KEEP = 2 };
 struct FinArgs {
   int32_t ndim, dt_mode;
   double dx, dy, cfl, dt_in;
-  double* step;       // [0] dt, [1] lam_x, [2] lam_y, [3] amax_x, [4] amax_y
-  double* dt_used;    // optional copy of dt
+  double* step;       // step record (STEP_SKIP and the layout above)
+  double* dt_used;    // optional copy of dt (0 for a skipped step)
   const double* damax;  // Dirichlet ghost maxima [2] or null
+  // time loop to t_end (clock null: none): *clock is the time at the start
+  // of the step, *nsteps (may be null) counts the steps taken
+  double* clock;
+  int64_t* nsteps;
+  double t_end;
 };
+
+// The time loop's last step [Sec. 3.3 CFL step, shortened to land on
+// t_end]: a step that would start at or after t_end is skipped; otherwise
+// dt is clipped to t_end - t and the clock advanced.  Returns false for a
+// skipped step.  (The order of the operations is that of the serial time
+// loop.)
+__device__ __forceinline__ bool clock_step(double* clock, int64_t* nsteps, double t_end, double& dt) {
+  const double t = *clock;
+  if (!(t < t_end)) return false;
+  if (t + dt > t_end) dt = t_end - t;
+  *clock = t + dt;
+  if (nsteps) *nsteps += 1;
+  return true;
+}
 
 // Maxima over the per-block pairs (partial[2b], partial[2b+1]), b < nblk, of
 // this thread's share: eight pairs per round with all loads issued together
@@ -615,7 +673,9 @@ __device__ __forceinline__ void partial_max(const double* partial, int nblk, dou
 // block's writes visible across the XCDs' separate L2s.)
 template <bool HAS_T>
 __global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partial) {
+  if (a.node_skip && a.step[STEP_SKIP] != 0.0) return;
   const long N = (long)a.nx * a.ny;
+  const bool check = a.viol && a.check_in;
   double mx = 0.0, my = 0.0;
   for (long o = (long)blockIdx.x * blockDim.x + threadIdx.x; o < N;
        o += (long)gridDim.x * blockDim.x) {
@@ -632,6 +692,7 @@ __global__ __launch_bounds__(256) void k_node(KArgs a, double* P, double* partia
     P[o] = un; P[N + o] = ut; P[2 * N + o] = p; P[3 * N + o] = c; P[4 * N + o] = h;
     mx = fmax(mx, fabs(un) + c);
     my = fmax(my, fabs(ut) + c);
+    if (check) report_bad(a.viol, a.vflag, !admissible(X[0], X[1], X[5], h));
   }
   mx = wave_max(mx);
   my = wave_max(my);
@@ -663,10 +724,19 @@ __global__ __launch_bounds__(1024) void k_finalize(const double* partial, int nb
   for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { mx = fmax(mx, red[0][k]); my = fmax(my, red[1][k]); }
   if (f.damax) { mx = fmax(mx, f.damax[0]); my = fmax(my, f.damax[1]); }
   double* step = f.step;
+  if (f.dt_mode == DT_KEEP && step[STEP_SKIP] != 0.0) return;   // inside a skipped step
   double dt;
   if (f.dt_mode == DT_GIVEN) dt = f.dt_in;
   else if (f.dt_mode == DT_KEEP) dt = step[0];
   else dt = f.ndim == 1 ? f.cfl * f.dx / mx : f.cfl / (mx / f.dx + my / f.dy);
+  if (f.dt_mode != DT_KEEP) {
+    const bool run = !f.clock || clock_step(f.clock, f.nsteps, f.t_end, dt);
+    step[STEP_SKIP] = run ? 0.0 : 1.0;
+    if (!run) {
+      if (f.dt_used) *f.dt_used = 0.0;
+      return;
+    }
+  }
   step[0] = dt;
   if (f.ndim == 1) {
     step[1] = dt / f.dx;
@@ -734,6 +804,7 @@ __device__ __forceinline__ void node_block(const KArgs& a, int blk) {
   const long N = (long)a.nx * a.ny;
   const long o = (long)blk * blockDim.x + threadIdx.x;
   double mx = 0.0, my = 0.0;
+  bool bad = false;
   if (o < N) {
     double X[6];
     if (HAS_T) {
@@ -749,7 +820,9 @@ __device__ __forceinline__ void node_block(const KArgs& a, int blk) {
     P[o] = un; P[N + o] = ut; P[2 * N + o] = p; P[3 * N + o] = c; P[4 * N + o] = h;
     mx = fabs(un) + c;
     my = fabs(ut) + c;
+    bad = !admissible(X[0], X[1], X[5], h);
   }
+  if (a.viol && a.check_in) report_bad(a.viol, a.vflag, bad);
   mx = wave_max(mx);
   my = wave_max(my);
   __shared__ double red[2][4];
@@ -838,26 +911,25 @@ __device__ __forceinline__ void sweep_x_tile(const KArgs& a, long tile) {
   for (int v = 0; v < 6; ++v) Gr[v] = __shfl(Gm[v], src, 64);
   if (!owns_cell) return;
   double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;
-  const int nvs = HAS_T ? 6 : 5;
+  double X[6] = {0, 0, 0, 0, 0, 0};   // 1D: the stage result, in the rotated order
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
     if (!HAS_T && v == 3) continue;
-    double L;
-    {
-      L = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
-    }
+    const double L = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
     const int k = state_index(0, v, HAS_T);
     if (HAS_T) {
       dst[k * N + c] = L;   // L_x; the y-sweep finishes the cell
     } else {
-      write_cell(a, a.out, c, N, k, L);
+      X[v] = write_cell(a, a.out, c, N, k, L);
     }
   }
-  (void)nvs;
+  if (!HAS_T && a.viol && a.out_mode == OUT_RK)
+    report_bad(a.viol, a.vflag, !admissible(X[0], X[1], X[5], rhoc2_tilde<false>(a.eos, X)));
 }
 
 template <bool HAS_T, bool DIRI, bool B32>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_sweep_x(KArgs a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   sweep_x_tile<HAS_T, DIRI, B32>(a, blockIdx.x);
 }
 
@@ -991,14 +1063,17 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
   double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;
   CellIn cin;   // 1D: the stage's inputs, loaded before the first store
   if (!HAS_T) load_cell_in<5, false>(a, c, N, cin);
+  double X[6] = {0, 0, 0, 0, 0, 0};   // 1D: the stage result, in the rotated order
 #pragma unroll
   for (int v = 0; v < 6; ++v) {
     if (!HAS_T && v == 3) continue;
     const double L = hdiv(-(Gr[v] - Gp[v]), a.dx, a.rdx);
     const int k = state_index(0, v, HAS_T);
     if (HAS_T) dst[k * N + c] = L;
-    else write_cell_in(a, a.out, c, N, k, L, cin);
+    else X[v] = write_cell_in(a, a.out, c, N, k, L, cin);
   }
+  if (!HAS_T && a.viol && a.out_mode == OUT_RK)
+    report_bad(a.viol, a.vflag, !admissible(X[0], X[1], X[5], rhoc2_tilde<false>(a.eos, X)));
 }
 
 // waves per SIMD the windowed x-sweep is compiled for (VGPR budget 512 / this):
@@ -1009,6 +1084,7 @@ constexpr int XL_WPE = 4;
 template <bool HAS_T, bool DIRI, bool B32, bool FO = false>
 __global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(FO ? 6 : XL_WPE))) void k_sweep_xl(
     KArgs a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   __shared__ double tile[XW][11 * XWIN];
   const int w = threadIdx.x >> 6;
   const long t = (long)blockIdx.x * XW + w;
@@ -1119,6 +1195,7 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
   }
   __syncthreads();
   double mx = 0.0, my = 0.0;
+  bool bad = false;
   if (own) {
     double X[6];
 #pragma unroll
@@ -1132,8 +1209,10 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
       }
       X[s] = write_cell_in(a, a.out, idx, N, s, L, cin);
     }
-    if (a.Pn) next_prims(a, idx, N, X, mx, my);
+    if (a.Pn) bad = !next_prims(a, idx, N, X, mx, my);
+    else if (a.viol && a.out_mode == OUT_RK) bad = !stage_ok(a, X);
   }
+  if (a.viol && a.out_mode == OUT_RK) report_bad(a.viol, a.vflag, bad);
   if (a.Pn) block_max_out(mx, my, a.partn + 2 * part);
 }
 
@@ -1142,6 +1221,7 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
 template <bool DIRI, bool B32, bool FO = false>
 __global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(FO ? 6 : 4))) void k_sweep_y(
     KArgs a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   __shared__ double tile32[9 * (Y_ROWS + 5) * Y_COLS];
   sweep_y_tile32<Y_ROWS, DIRI, B32, FO>(a, blockIdx.x, blockIdx.y, tile32,
                                         (long)blockIdx.y * gridDim.x + blockIdx.x);
@@ -1184,16 +1264,26 @@ __device__ __forceinline__ bool fixup_cell(const KArgs& a, long t, int yw, long&
   return true;
 }
 
-__global__ __launch_bounds__(256) void k_fixup_y(KArgs a, int nbr) {
-  (void)nbr;
+// the fixup's stage-result check and next-stage primitives (blk: this
+// block's slot after fuse_off for its block maxima)
+__device__ __forceinline__ void fixup_finish(const KArgs& a, bool own, long idx, const double X[6],
+                                             long blk) {
+  double mx = 0.0, my = 0.0;
+  bool bad = false;
+  if (own) {
+    if (a.Pn) bad = !next_prims(a, idx, (long)a.nx * a.ny, X, mx, my);
+    else if (a.viol && a.out_mode == OUT_RK) bad = !stage_ok(a, X);
+  }
+  if (a.viol && a.out_mode == OUT_RK) report_bad(a.viol, a.vflag, bad);
+  if (a.Pn) block_max_out(mx, my, a.partn + 2 * ((long)a.fuse_off + blk));
+}
+
+__global__ __launch_bounds__(256) void k_fixup_y(KArgs a) {
+  if (a.step[STEP_SKIP] != 0.0) return;
   long idx = 0;
   double X[6];
   const bool own = fixup_cell(a, (long)blockIdx.x * blockDim.x + threadIdx.x, Y_ROWS, idx, X);
-  if (a.Pn) {
-    double mx = 0.0, my = 0.0;
-    if (own) next_prims(a, idx, (long)a.nx * a.ny, X, mx, my);
-    block_max_out(mx, my, a.partn + 2 * ((long)a.fuse_off + blockIdx.x));
-  }
+  fixup_finish(a, own, idx, X, blockIdx.x);
 }
 
 // Stand-alone flux limiter over the faces of one direction.
@@ -1312,7 +1402,7 @@ __global__ __launch_bounds__(256) void k_selftest_cdiv(const double* a, double b
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
-  int t = threadIdx.x;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) p[t] = 0ull;
 }
 

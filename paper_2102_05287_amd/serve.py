@@ -13,7 +13,10 @@ arrive over time.  The server
     same ticks;
   * between ticks retires finished solves and admits newly arrived ones
     (membership changes rebind the batch inside its existing scratch, which
-    grows by doubling only when needed).
+    grows by doubling only when needed);
+  * retires, marked failed, a solve whose kernels found a cell outside the
+    admissible set (the batch's per-instance report, read once per tick), so
+    it neither runs on nor disturbs the others.
 
 Every solve in a batch runs exactly the arithmetic it runs alone (the batched
 kernels are the single-solve kernels per tile), so a result does not depend
@@ -57,6 +60,8 @@ class Solve:
     admitted: float = -1.0
     done: float = -1.0
     result: object = None  # host copy of the final state (when kept)
+    failed: bool = False   # retired after a cell left the admissible set
+    bad_cells: int = 0
 
 
 @dataclass
@@ -174,12 +179,15 @@ class Server:
             tdone = now()
             for g in live:
                 left = g.batch.steps_left()
+                viol = g.batch.violations()
                 keep = []
-                for m, l in zip(g.members, left):
+                for m, l, nb in zip(g.members, left, viol):
                     before = m.steps - m.taken
                     m.taken = m.steps - int(l)
                     work += 3.0 * m.spec.nx * m.spec.ny * (before - int(l))
-                    if l == 0:
+                    if nb:
+                        m.failed, m.bad_cells = True, int(nb)
+                    if l == 0 or nb:
                         self._retire(g, m, tdone)
                         finished.append(m)
                     else:
@@ -195,6 +203,7 @@ class Server:
             np.array([s.done for s in finished])
         summary = {
             "requests": len(finished),
+            "failed": sum(1 for s in finished if s.failed),
             "makespan_s": makespan,
             "solves_per_s": len(finished) / makespan,
             "latency_p50_s": float(np.percentile(lat, 50)),

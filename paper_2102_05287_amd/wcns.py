@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libwcns.so")
 WCNS_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "fluids violate Lemma 1", -3: "out of memory",
           -4: "HIP error", -5: "inadmissible state", -6: "invalid time step"}
+WCNS_ERR_INADMISSIBLE = -5
 BC_PERIODIC, BC_EXTRAP, BC_REFLECT, BC_DIRICHLET = 0, 1, 2, 3
 FP64, FP32_BULK = 0, 1
 SCHEME_PPWCNSIS, SCHEME_HLLC1 = 0, 1
@@ -72,13 +73,15 @@ _lib = None
 
 EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_stream",
            "wcns_prim_to_cons", "wcns_rhs", "wcns_limit", "wcns_max_wavespeed",
-           "wcns_ssprk3_step", "wcns_ssprk3_steps", "wcns_check_admissible", "wcns_profile",
+           "wcns_ssprk3_step", "wcns_ssprk3_steps", "wcns_ssprk3_advance", "wcns_violations",
+           "wcns_check_admissible", "wcns_profile",
            "wcns_profile_read",
            "wcns_selftest_division", "wcns_selftest_division_by", "wcns_issue_probe", "wcns_run",
            "wcns_batch_create", "wcns_batch_reset",
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
            "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
-           "wcns_batch_steps_left", "wcns_prim_to_cons_n", "wcns_status_str"]
+           "wcns_batch_steps_left", "wcns_batch_violations", "wcns_prim_to_cons_n",
+           "wcns_status_str"]
 PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other", "sweep_z"]
 
 
@@ -105,6 +108,8 @@ def lib():
         L.wcns_max_wavespeed.argtypes = [vp, dp, dp]
         L.wcns_ssprk3_step.argtypes = [vp, dp, C.c_double, dp]
         L.wcns_ssprk3_steps.argtypes = [vp, dp, C.c_int32, C.c_double, dp]
+        L.wcns_ssprk3_advance.argtypes = [vp, dp, C.c_double, C.c_double, C.c_int32, dp, dp, dp]
+        L.wcns_violations.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32]
         L.wcns_check_admissible.argtypes = [vp, dp, C.POINTER(C.c_longlong)]
         L.wcns_profile.argtypes = [vp, C.c_int32]
         L.wcns_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
@@ -125,6 +130,7 @@ def lib():
         L.wcns_batch_destroy.argtypes = [vp]
         L.wcns_batch_set_steps.argtypes = [vp, C.POINTER(C.c_int32)]
         L.wcns_batch_steps_left.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.wcns_batch_violations.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32]
         L.wcns_prim_to_cons_n.argtypes = [C.POINTER(_Eos), C.c_int32, C.c_int64, dp, dp, vp]
         L.wcns_status_str.argtypes = [C.c_int]
         L.wcns_status_str.restype = C.c_char_p
@@ -266,21 +272,10 @@ class Solver:
                "wcns_ssprk3_step")
         return W
 
-    def cfl_dt(self, amax) -> float:
-        """The CFL step of the device for wave-speed maxima amax (Sec. 3.3),
-        in the same floating-point operations."""
-        cfl = self.params.cfl
-        if self.ndim == 1:
-            return cfl * self.dx / amax[0]
-        if self.ndim == 3:
-            return cfl / (amax[0] / self.dx + amax[1] / self.dy + amax[2] / self.dz)
-        return cfl / (amax[0] / self.dx + amax[1] / self.dy)
-
-    def capture_steps(self, W, n, dt_used):
-        """A HIP graph of n device-CFL SSP-RK3 steps of W in place, step k
-        writing its dt to dt_used[k]; replay() runs them on the current torch
-        stream.  (The library only enqueues kernels inside a step, so the
-        captured graph holds kernel nodes only.)"""
+    def _capture(self, enqueue):
+        """A HIP graph of the library work `enqueue()` puts on this solver's
+        stream (kernel nodes only: the entry points used here only launch
+        kernels); replay() runs it on the current torch stream."""
         import torch
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -289,53 +284,78 @@ class Solver:
         self.set_stream(s.cuda_stream)
         try:
             with torch.cuda.graph(g, stream=s):
-                self.steps(W, n, 0.0, dts=dt_used)
+                enqueue()
         finally:
             self.set_stream(old)
         return g
 
-    def advance(self, W, t_end, t=0.0, chunk=64, margin=8.0, max_steps=1 << 40, graph=False):
-        """March W in place from time t to t_end with CFL steps, the last one
-        shortened to land on t_end (the time loop of the paper's runs).
-        Far from t_end the device picks every dt itself and the host reads
-        the chunk's time steps once per `chunk` steps (the chunk replayed as
-        one HIP graph when `graph`: measured no faster than eager launches
-        for the 400-cell tube, 78 vs 70 us per step, so off by default);
-        once t_end is within margin * chunk * (largest recent dt) it takes
-        one step at a time from the device's wave-speed maxima.  Returns
-        (steps, t)."""
+    def capture_steps(self, W, n, dt_used):
+        """A HIP graph of n device-CFL SSP-RK3 steps of W in place, step k
+        writing its dt to dt_used[k]."""
+        return self._capture(lambda: self.steps(W, n, 0.0, dts=dt_used))
+
+    def capture_advance(self, W, t_end, n, clock, steps_taken):
+        """A HIP graph of n steps of the device time loop toward t_end
+        (advance_steps); replays continue from the device clock."""
+        return self._capture(lambda: self.advance_steps(W, t_end, n, clock, steps_taken))
+
+    def advance_steps(self, W, t_end, n, clock, steps_taken=None, dts=None, dt=0.0):
+        """Enqueue up to n SSP-RK3 steps of the device time loop toward t_end
+        (wcns_ssprk3_advance), each of size dt > 0 or the CFL step (dt <= 0):
+        clock is a device float64 tensor holding the time (updated on the
+        device), steps_taken an optional device int64 tensor counting the
+        steps taken, dts an optional device tensor of >= n elements
+        receiving each step slot's dt (0 when skipped)."""
         import torch
-        buf = torch.zeros(chunk, dtype=torch.float64, device="cuda")
-        steps, dt_last, g = 0, None, None
-        while t < t_end and steps < max_steps:
-            if dt_last is not None and t_end - t > margin * chunk * dt_last \
-                    and steps + chunk <= max_steps:
-                if graph:
-                    if g is None:
-                        g = self.capture_steps(W, chunk, buf)
-                    g.replay()
-                else:
-                    self.steps(W, chunk, 0.0, dts=buf)
-                dts = buf.cpu().tolist()
-                for d in dts:
-                    t += d
-                steps += chunk
-                dt_last = max(dts)
-                if not all(d > 0.0 for d in dts):
-                    raise WcnsError(-6, "advance: non-positive or non-finite time step")
-                if t > t_end:
-                    raise WcnsError(-6, "advance: a chunk passed t_end (raise margin)")
-            else:
-                dt = self.cfl_dt(self.max_wavespeed(W).cpu().tolist())
-                if not dt > 0.0:
-                    raise WcnsError(-6, "advance: non-positive or non-finite time step")
-                if t + dt > t_end:
-                    dt = t_end - t
-                self.step(W, dt)
-                t += dt
-                steps += 1
-                dt_last = dt
-        return steps, t
+        self._chk(W)
+        _dev_f64(clock, 1, "clock")
+        _dev_f64(dts, max(int(n), 0), "dts")
+        if steps_taken is not None and not (isinstance(steps_taken, torch.Tensor) and steps_taken.is_cuda
+                                            and steps_taken.dtype == torch.int64
+                                            and steps_taken.numel() >= 1):
+            raise ValueError("steps_taken: a device int64 tensor is needed")
+        _check(lib().wcns_ssprk3_advance(self._ctx, _ptr(W), float(dt), float(t_end), int(n),
+                                         _ptr(clock), _ptr(steps_taken), _ptr(dts)),
+               "wcns_ssprk3_advance")
+
+    def advance(self, W, t_end, t=0.0, chunk=64, max_steps=1 << 40, dt=0.0):
+        """March W in place from time t to t_end (the time loop of the
+        paper's runs): the library takes steps of size dt > 0 or, by default,
+        picks every CFL step, and shortens the last one to land on t_end,
+        keeping the time on the device; the host only
+        enqueues chunks of `chunk` steps and reads the step count once per
+        chunk, stopping when a chunk took fewer steps than it enqueued.
+        Raises WcnsError (inadmissible state) if the kernels found a cell
+        outside the admissible set on the way.  Returns (steps, t)."""
+        import torch
+        clock = torch.full((1,), float(t), dtype=torch.float64, device="cuda")
+        taken = torch.zeros(1, dtype=torch.int64, device="cuda")
+        done = 0
+        while done < max_steps:
+            n = int(min(chunk, max_steps - done))
+            self.advance_steps(W, t_end, n, clock, taken, dt=dt)
+            now = int(taken.item())
+            if now - done < n:
+                done = now
+                break
+            done = now
+        self.check_violations()
+        return done, float(clock.item())
+
+    def violations(self, clear=False) -> int:
+        """Cells the kernels found outside the admissible set since creation
+        or the last clear (wcns_violations; synchronises)."""
+        n = C.c_int64(0)
+        rc = lib().wcns_violations(self._ctx, C.byref(n), int(bool(clear)))
+        if rc not in (WCNS_OK, -5):
+            _check(rc, "wcns_violations")
+        return int(n.value)
+
+    def check_violations(self):
+        """Raise WcnsError(-5) if the kernels found an inadmissible cell."""
+        n = self.violations()
+        if n:
+            raise WcnsError(-5, f"{n} cells outside the admissible set")
 
     def run(self, W, t_end, t=0.0, dt_fixed=0.0, max_steps=1 << 40, dts=None):
         """1D grids of at most 4096 cells: the whole time loop to t_end in
@@ -575,6 +595,13 @@ class Batch:
     def steps_left(self):
         arr = (C.c_int32 * self.n)()
         _check(lib().wcns_batch_steps_left(self._b, arr), "wcns_batch_steps_left")
+        return np.array(arr[:], dtype=np.int64)
+
+    def violations(self, clear=False):
+        """Per-instance count of cells found outside the admissible set
+        (wcns_batch_violations; synchronises the batch stream)."""
+        arr = (C.c_int64 * self.n)()
+        _check(lib().wcns_batch_violations(self._b, arr, int(bool(clear))), "wcns_batch_violations")
         return np.array(arr[:], dtype=np.int64)
 
     def dt(self):

@@ -42,6 +42,17 @@ def test_status_strings():
         assert wcns.lib().wcns_status_str(code)
 
 
+def test_binding_has_no_method_arithmetic():
+    """The binding marshals arguments only: the time loop (CFL step, the
+    last step clipped to t_end) lives in the library, so no CFL or wave-speed
+    formula appears in the Python package."""
+    pkg = os.path.join(ROOT, "paper_2102_05287_amd")
+    for f in ("wcns.py", "serve.py"):
+        text = open(os.path.join(pkg, f)).read()
+        for pat in (r"def cfl_dt", r"cfl\s*\*\s*self\.dx", r"cfl\s*/\s*\(", r"amax\[0\]\s*/"):
+            assert not re.search(pat, text), (f, pat)
+
+
 def _create(**kw):
     g = wcns._Grid()
     g.ndim, g.nx, g.ny = kw.get("ndim", 2), kw.get("nx", 8), kw.get("ny", 8)
@@ -85,6 +96,12 @@ def _create(**kw):
     (dict(cfl=0.0), -1),
     (dict(scheme=5), -1),
     (dict(weno_eps=0.0), -1),
+    (dict(weno_eps=4.9e-324), -1),              # subnormal: outside the division core's range
+    (dict(weno_eps=1e-310), -1),
+    (dict(weno_eps=1e-201), -1),                # below the accepted [1e-200, 1e200]
+    (dict(weno_eps=1e201), -1),
+    (dict(weno_eps=float("nan")), -1),
+    (dict(ndim=3, nz=4, weno_eps=1e-310), -1),
     (dict(precision=9), -1),
 ])
 def test_create_rejects_bad_arguments(kw, code):
@@ -118,6 +135,9 @@ def test_null_arguments():
     assert L.wcns_batch_set_steps(None, None) == -1
     assert L.wcns_batch_steps_left(None, None) == -1
     assert L.wcns_batch_dt(None, None) == -1
+    assert L.wcns_ssprk3_advance(None, None, 0.0, 1.0, 1, None, None, None) == -1
+    assert L.wcns_violations(None, None, 0) == -1
+    assert L.wcns_batch_violations(None, None, 0) == -1
     assert L.wcns_batch_reset(None, 1, None, None) == -1
     assert L.wcns_batch_destroy(None) == -1
     assert L.wcns_prim_to_cons_n(None, 2, 1, None, None, None) == -1

@@ -4,9 +4,6 @@ oracle.  Accuracy is stated as relative L1 per variable; positivity and
 boundedness must hold exactly (no inadmissible cell after any step)."""
 from __future__ import annotations
 
-import json
-import os
-
 import numpy as np
 import pytest
 
@@ -47,9 +44,7 @@ def step_error(spec, s, W, dt, got, ref):
 
 def test_fp32_bulk_rhs_close_to_oracle_on_smooth_data():
     """Smooth data (no limiter activity): one FP32-bulk RHS is within FP32
-    round-off of the oracle.  (At material interfaces the limiters divide by
-    differences of ~1e-8, so FP32 rounding moves their theta at O(1); there
-    the meaningful comparison is the final-time L1 below.)"""
+    round-off of the oracle."""
     specs = [pb.random_smooth_state(96, 70, 3, with_bubble=False, with_shock=False),
              pb.convergence_advection(64)]
     for spec in specs:
@@ -64,63 +59,97 @@ def test_fp32_bulk_rhs_close_to_oracle_on_smooth_data():
         assert max(errs) < 1e-6, errs
 
 
-def run_gpu(sol, W0, t_end, cfl, dx, dy):
-    Wd = dev(W0)
-    t, n = 0.0, 0
-    while t < t_end:
-        a = host(sol.max_wavespeed(Wd))
-        dt = cfl / (a[0] / dx + a[1] / dy)
-        if t + dt > t_end:
-            dt = t_end - t
-        sol.step(Wd, dt)
-        t += dt
-        n += 1
-        assert sol.count_inadmissible(Wd) == 0, n
-    return host(Wd), n
+# Per-step relative error bounds of one FP32-bulk RHS at material interfaces
+# (the shock-bubble and underwater-explosion initial states at 128^2), per
+# variable in state order.  At an interface the absent phase's partial
+# density is ~1e-8 against O(1) interpolated characteristic values, so the
+# limiters' theta = (q(A) - eps)/(q(A) - q(B)) divides by differences of
+# ~1e-8: FP32 rounding of the interpolation (~1e-7 relative) moves theta at
+# O(1) there and the interface fluxes of the partial densities by their own
+# size.  The bounds are a few times the measured errors (stated with them in
+# the design notes); the Euler step with the FP32-bulk RHS must still be
+# admissible, since the limiters run in FP64 on the FP32 fluxes.
+INTERFACE_BOUND = {"shock_bubble": [1e-4, 5e-2, 1e-3, 1e-3, 1e-4, 1e-4],
+                   "underwater_explosion": [1e-4, 5e-2, 1e-3, 1e-3, 1e-4, 1e-4]}
+
+
+@pytest.mark.parametrize("name", ["shock_bubble", "underwater_explosion"])
+def test_fp32_bulk_rhs_at_material_interfaces(name):
+    """One FP32-bulk RHS of a state with sharp material interfaces against
+    the oracle: the per-variable per-step error is bounded as stated above
+    (the partial densities carry the O(1) theta changes of the limiters),
+    and W + dt L stays in the admissible set."""
+    spec = pb.shock_bubble(128) if name == "shock_bubble" else pb.underwater_explosion(128)
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    dt = orc.cfl_dt(s, W)
+    ref = orc.rhs(s, W, dt)
+    sol = wcns.Solver.from_spec(spec, precision=FP32)
+    got = host(sol.rhs(dev(W), dt=dt))
+    errs = step_error(spec, s, W, dt, got, ref)
+    print(f"  fp32 rhs {name} 128^2: per-step relative error {['%.2e' % e for e in errs]}", flush=True)
+    for v, (e, bound) in enumerate(zip(errs, INTERFACE_BOUND[name])):
+        assert e < bound, (v, e, bound)
+    assert orc.count_inadmissible(s, W + dt * got) == 0
 
 
 def test_fp32_bulk_underwater_explosion_256_l1():
-    """Underwater explosion at 256^2 to t = 2e-4 s: FP32-bulk GPU against the
-    FP64 oracle (and the FP64 GPU path), relative L1 per variable."""
+    """Underwater explosion at 256^2 to t = 2e-4 s, each precision through
+    the library's own time loop: FP32-bulk GPU against the FP64 oracle (and
+    the FP64 GPU path), relative L1 per variable, no stage result outside
+    the admissible set."""
     spec = pb.underwater_explosion(256)
     s = oracle_setup(spec)
     W0 = oracle_W(spec, s)
     ref, steps, _ = orc.run(s, W0, spec.t_end)
-    sol32 = wcns.Solver.from_spec(spec, precision=FP32)
-    got32, n32 = run_gpu(sol32, W0, spec.t_end, spec.cfl, spec.dx, spec.dy)
-    sol64 = wcns.Solver.from_spec(spec)
-    got64, n64 = run_gpu(sol64, W0, spec.t_end, spec.cfl, spec.dx, spec.dy)
+    out = {}
+    for prec in (FP32, wcns.FP64):
+        sol = wcns.Solver.from_spec(spec, precision=prec)
+        Wd = dev(W0)
+        n, t = sol.advance(Wd, spec.t_end, chunk=64)
+        assert t == spec.t_end and sol.violations() == 0
+        out[prec] = (host(Wd), n)
+    (got32, n32), (got64, n64) = out[FP32], out[wcns.FP64]
     e32 = rel_l1(got32, ref)
     e64 = rel_l1(got64, ref)
     print("  underwater 256 steps oracle/fp64/fp32:", steps, n64, n32, flush=True)
     print("  rel L1 fp32 vs oracle:", ["%.2e" % e for e in e32], flush=True)
     print("  rel L1 fp64 vs oracle:", ["%.2e" % e for e in e64], flush=True)
-    assert max(e64) <= 1e-9
+    assert n64 == steps and max(e64) <= 1e-9
     assert max(e32) < 2e-3, e32
 
 
-def test_fp32_bulk_full_size_2048_against_fp64_gpu():
-    """The precision form at its full size (2048^2 underwater explosion, the
-    bench's launch configuration): 10 steps of the FP32-bulk path against
-    the FP64 path on the same GPU, both with the FP64 path's CFL time step,
-    relative L1 per variable below 1e-2 (measured 1e-7 .. 4e-3, largest for
-    the momenta, which start at zero) and no inadmissible cell."""
+# relative L1 bound of the FP32-bulk solve against the FP64 one at the full
+# size and final time, per variable (a few times the measured values,
+# stated with them in the design notes)
+FULL_SIZE_BOUND = [1e-2] * 6
+
+
+def test_fp32_bulk_full_size_2048_to_final_time():
+    """The precision form at its full size: the 2048^2 underwater explosion
+    to t = 2e-4 s, FP32 bulk and FP64 each through the library's time loop
+    on the same GPU (each picks its own CFL steps), relative L1 per variable
+    of the final states within the stated bound, no stage result of either
+    outside the admissible set."""
     spec = pb.underwater_explosion(2048)
     V = torch.from_numpy(spec.prim).cuda()
     spec.prim = None
-    sol64 = wcns.Solver.from_spec(spec)
-    sol32 = wcns.Solver.from_spec(spec, precision=FP32)
-    W64 = sol64.prim_to_cons(V)
-    W32 = W64.clone()
+    res = {}
+    for prec in (wcns.FP64, FP32):
+        sol = wcns.Solver.from_spec(spec, precision=prec)
+        W = sol.prim_to_cons(V)
+        n, t = sol.advance(W, spec.t_end, chunk=100)
+        assert t == spec.t_end and sol.violations() == 0
+        assert sol.count_inadmissible(W) == 0
+        res[prec] = (W, n)
+        sol.close()
     del V
-    dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
-    for _ in range(10):
-        sol64.step(W64, 0.0, dt_used=dtu)
-        sol32.step(W32, float(dtu.item()))
-    assert sol32.count_inadmissible(W32) == 0 and sol64.count_inadmissible(W64) == 0
+    (W64, n64), (W32, n32) = res[wcns.FP64], res[FP32]
     e = [float((W32[v] - W64[v]).abs().sum() / W64[v].abs().sum()) for v in range(6)]
-    print("  2048^2 rel L1 fp32-bulk vs fp64:", ["%.2e" % x for x in e], flush=True)
-    assert max(e) < 1e-2, e
+    print(f"  2048^2 to t = {spec.t_end}: steps fp64 {n64}, fp32-bulk {n32}; rel L1 fp32-bulk vs fp64:",
+          ["%.2e" % x for x in e], flush=True)
+    for v in range(6):
+        assert e[v] < FULL_SIZE_BOUND[v], (v, e[v])
 
 
 def test_first_order_scheme_is_fp64_in_both_precisions():

@@ -1,0 +1,120 @@
+"""Lazy admissibility report (the admissible set G of Sec. 2, which the
+limiters of Sec. 5 keep every stage result inside): the kernels count the
+input cells of a call's first stage and every stage result outside G with no
+host synchronisation, the next call that would enqueue work refuses to run
+(WCNS_ERR_INADMISSIBLE), and wcns_violations reads and clears the count.
+Failures are planted in the input state (on the host) only."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from helpers import oracle_setup, oracle_W, orc, pb
+from test_gpu_parity import assert_parity, dev, host, solver_for
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from paper_2102_05287_amd import wcns  # noqa: E402
+
+INADM = wcns.WCNS_ERR_INADMISSIBLE
+
+
+def _cases():
+    s2 = pb.random_smooth_state(70, 45, seed=5)
+    s1 = pb.water_air_shock_tube(200)
+    s3 = pb.random_smooth_state_3d(24, 21, 19, seed=6)
+    return [("2d", s2, (5, 20, 30)), ("1d", s1, (4, 50)), ("3d", s3, (6, 7, 8, 9))]
+
+
+@pytest.mark.parametrize("case", ["2d", "1d", "3d"])
+def test_injected_alpha_above_one_is_reported_by_the_step_path(case):
+    """A cell with a1 = 1.5 in the state handed to a multi-step call: the
+    call itself returns (nothing synchronises), the next step call on the
+    context is refused with WCNS_ERR_INADMISSIBLE, wcns_violations reports
+    at least that cell, and after clearing the context runs again."""
+    name, spec, cell = next(c for c in _cases() if c[0] == case)
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    W[cell] = 1.5
+    assert orc.count_inadmissible(s, W) == 1
+    sol = solver_for(spec)
+    Wd = dev(W)
+    sol.steps(Wd, 2, 0.0)          # lazy: no error at the call itself
+    torch.cuda.synchronize()
+    with pytest.raises(wcns.WcnsError) as e:
+        sol.step(Wd, 0.0)
+    assert e.value.code == INADM
+    with pytest.raises(wcns.WcnsError) as e:
+        sol.rhs(Wd, dt=1e-9)
+    assert e.value.code == INADM
+    n = sol.violations()
+    print(f"  {name}: a1 = 1.5 at {cell}: {n} inadmissible cells reported", flush=True)
+    assert n >= 1
+    assert sol.violations(clear=True) == n
+    assert sol.violations() == 0
+    ok = dev(oracle_W(spec, s))
+    sol.step(ok, 0.0)              # cleared: runs again
+    assert sol.violations() == 0
+
+
+@pytest.mark.parametrize("case", ["2d", "1d", "3d"])
+def test_violation_count_equals_the_oracle(case):
+    """A slightly negative partial density (a2r2 = -1e-3 in one cell) keeps
+    every value finite, so the solve stays bit for bit the oracle's: one
+    step call reports exactly the oracle's count (the bad input cell plus
+    the stage results outside G after each of the three stages)."""
+    name, spec, cell = next(c for c in _cases() if c[0] == case)
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    idx = (1,) + tuple(cell[1:])
+    W[idx] = -1e-3
+    n_in = orc.count_inadmissible(s, W)
+    ref, dt, bad = orc.ssprk3_step(s, W)
+    sol = solver_for(spec)
+    Wd = dev(W)
+    dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sol.step(Wd, 0.0, dt_used=dtu)
+    n = sol.violations(clear=True)
+    print(f"  {name}: a2r2 = -1e-3: {n} reported; oracle {n_in} input + {bad} stage results",
+          flush=True)
+    assert float(dtu.item()) == dt
+    assert_parity(host(Wd), ref, what=f"{name} inadmissible input step")
+    assert n == n_in + bad
+
+
+def test_rhs_reports_an_inadmissible_input():
+    """wcns_rhs checks its input state (its output is L, not a state)."""
+    spec = pb.random_smooth_state(64, 40, seed=9)
+    s = oracle_setup(spec)
+    W = oracle_W(spec, s)
+    sol = solver_for(spec)
+    sol.rhs(dev(W), dt=1e-9)
+    assert sol.violations() == 0
+    W[0, 3, 3] = -5.0
+    W[5, 10, 11] = -0.25
+    sol.rhs(dev(W), dt=1e-9)
+    assert sol.violations(clear=True) == 2
+
+
+def test_batch_reports_the_failing_instance_only():
+    """Batched form: per-instance counts; the other instances of the batch
+    are untouched by a failing one (bit for bit their solo solves)."""
+    specs = [pb.random_instance(i) for i in (3, 4, 5)]
+    specs = [sp for sp in specs]
+    W0 = [orc.prim_to_cons(oracle_setup(sp), sp.prim) for sp in specs]
+    W0[1][5, 7, 9] = 1.5
+    states = [dev(w) for w in W0]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)
+    b.step(3)
+    b.sync()
+    v = b.violations()
+    print(f"  batch violations per instance: {v.tolist()}", flush=True)
+    assert v[0] == 0 and v[2] == 0 and v[1] >= 1
+    for k in (0, 2):
+        sol = solver_for(specs[k])
+        Wd = dev(W0[k])
+        sol.steps(Wd, 3, 0.0)
+        assert torch.equal(Wd, states[k]), k
+    assert b.violations(clear=True)[1] == v[1]
+    assert b.violations().tolist() == [0, 0, 0]
+    b.close()

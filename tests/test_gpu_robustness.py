@@ -22,6 +22,7 @@ from test_gpu_parity import assert_parity, dev, host, rhs_case, solver_for
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
+from paper_2102_05287_amd import wcns  # noqa: E402
 
 
 def _random_rows(rng, n, nvar):
@@ -139,8 +140,10 @@ def test_mach10_cylinder_full_size():
 
 
 def test_sedov_blast_to_final_time():
-    """Sec. 6.4: 4000 fixed steps to t = 1e-3; every step admissible on
-    the oracle side, the GPU final state equal to it."""
+    """Sec. 6.4: 4000 fixed steps to t = 1e-3 through the library's time
+    loop (fixed dt, the last step shortened on the device); every step
+    admissible on the oracle side, no stage result outside G on the GPU, the
+    final state equal to the oracle's."""
     spec = pb.sedov_multimaterial(401)
     s = oracle_setup(spec)
     W0 = oracle_W(spec, s)
@@ -148,17 +151,9 @@ def test_sedov_blast_to_final_time():
     assert steps == 4000
     sol = solver_for(spec)
     Wd = dev(W0)
-    # the oracle's time loop: fixed steps, the last one shortened to t_end
-    tt, n = 0.0, 0
-    while tt < spec.t_end:
-        dt = spec.dt_fixed
-        if tt + dt > spec.t_end:
-            dt = spec.t_end - tt
-        sol.step(Wd, dt)
-        tt += dt
-        n += 1
+    n, tt = sol.advance(Wd, spec.t_end, chunk=250, dt=spec.dt_fixed)
     assert n == steps and tt == t
-    assert sol.count_inadmissible(Wd) == 0
+    assert sol.violations() == 0 and sol.count_inadmissible(Wd) == 0
     got = host(Wd)
     assert_parity(got, ref, what="sedov t_end")
     for v in range(5):
@@ -168,42 +163,43 @@ def test_sedov_blast_to_final_time():
 
 def test_sedov_without_limiters_fails():
     """Negative control (Sec. 5 motivation): with both limiters off the same
-    Sedov run leaves the admissible set on the GPU too."""
+    Sedov run leaves the admissible set on the GPU too, and the library
+    reports it by itself: the kernels count the inadmissible stage results,
+    the next call refuses to run (WCNS_ERR_INADMISSIBLE) with no host check
+    in between, and wcns_violations gives the count."""
     spec = pb.sedov_multimaterial(401)
     s = oracle_setup(spec)
     sol = solver_for(spec, interp_limiter=False, flux_limiter=False)
     Wd = dev(oracle_W(spec, s))
-    bad = 0
+    refused_at = None
     for k in range(4000):
-        sol.step(Wd, spec.dt_fixed)
-        if (k + 1) % 500 == 0:
-            bad = sol.count_inadmissible(Wd)
-            if bad:
-                break
-    print(f"  limiters off: {bad} inadmissible cells after {k + 1} steps", flush=True)
-    assert bad > 0
+        try:
+            sol.step(Wd, spec.dt_fixed)
+        except wcns.WcnsError as e:
+            assert e.code == wcns.WCNS_ERR_INADMISSIBLE
+            refused_at = k
+            break
+    nviol = sol.violations(clear=True)
+    bad = sol.count_inadmissible(Wd)
+    print(f"  limiters off: call {refused_at} refused; {nviol} stage results outside G; "
+          f"{bad} inadmissible cells now", flush=True)
+    assert refused_at is not None and nviol > 0 and bad > 0
+    sol.step(Wd, spec.dt_fixed)   # cleared: calls run again
 
 
 def test_hllc1_water_air_tube_to_final_time():
     """First-order HLLC (the paper's comparison scheme) as a product mode:
-    the 1D water-air tube to t = 2.4e-4 s against the oracle."""
+    the 1D water-air tube to t = 2.4e-4 s against the oracle (the library's
+    time loop)."""
     spec = pb.water_air_shock_tube(400)
     s = oracle_setup(spec, scheme=1)
     W0 = oracle_W(spec, s)
     ref, steps, t_ref = orc.run(s, W0, spec.t_end)
     sol = solver_for(spec, scheme=1)
     Wd = dev(W0)
-    t, n = 0.0, 0
-    while t < spec.t_end:
-        a = host(sol.max_wavespeed(Wd))
-        dt = spec.cfl * spec.dx / a[0]
-        if t + dt > spec.t_end:
-            dt = spec.t_end - t
-        sol.step(Wd, dt)
-        t += dt
-        n += 1
+    n, t = sol.advance(Wd, spec.t_end, chunk=64)
     assert n == steps and t == t_ref
-    assert sol.count_inadmissible(Wd) == 0
+    assert sol.violations() == 0 and sol.count_inadmissible(Wd) == 0
     got = host(Wd)
     for v in range(5):
         l1 = np.abs(got[v] - ref[v]).sum() / np.abs(ref[v]).sum()
@@ -217,8 +213,9 @@ def test_hllc1_mach10_cylinder_rhs():
 
 @pytest.mark.parametrize("case", ["tube_1d", "shock_bubble_2d"])
 def test_advance_matches_the_oracle_time_loop(case):
-    """Solver.advance (device time steps, host reads once per chunk, exact
-    steps near the end) lands on t_end with the oracle's step sequence."""
+    """Solver.advance (the device time loop: CFL steps, the last one
+    shortened on the device to land on t_end; the host reads the step count
+    once per chunk) takes the oracle's step sequence and ends at its time."""
     if case == "tube_1d":
         spec, chunk = pb.water_air_shock_tube(400), 16
         t_end = spec.t_end
@@ -259,14 +256,33 @@ def test_captured_steps_replay_like_eager_steps():
             assert sol.count_inadmissible(Wg) == 0
 
 
-def test_advance_with_and_without_graphs_agree():
+def test_advance_chunks_replayed_as_a_graph():
+    """The device time loop needs no host arithmetic, so a chunk of it can
+    be captured: one graph of 32 advance steps, replayed (with a read of the
+    step count and a synchronisation between replays) until a replay takes
+    fewer steps than it holds, gives the oracle's run to t_end bit for bit;
+    its skipped steps leave the state and the clock alone."""
     spec = pb.water_air_shock_tube(400)
     s = oracle_setup(spec)
     W0 = oracle_W(spec, s)
     ref, steps, t_ref = orc.run(s, W0, spec.t_end)
     sol = solver_for(spec)
-    for graph in (True, False):
-        Wd = dev(W0)
-        n, t = sol.advance(Wd, spec.t_end, chunk=32, graph=graph)
-        assert n == steps and t == t_ref, graph
-        assert_parity(host(Wd), ref, what=f"advance graph={graph}")
+    Wd = dev(W0)
+    clock = torch.zeros(1, dtype=torch.float64, device="cuda")
+    taken = torch.zeros(1, dtype=torch.int64, device="cuda")
+    g = sol.capture_advance(Wd, spec.t_end, 32, clock, taken)
+    done, replays = 0, 0
+    while True:
+        g.replay()
+        replays += 1
+        now = int(taken.item())
+        if now - done < 32:
+            break
+        done = now
+    print(f"  {replays} replays, {now} steps to t = {clock.item()!r} (oracle {steps})", flush=True)
+    assert now == steps and float(clock.item()) == t_ref
+    assert_parity(host(Wd), ref, what="advance graph")
+    W_end = host(Wd)
+    g.replay()   # past t_end: every step skipped
+    assert int(taken.item()) == steps and float(clock.item()) == t_ref
+    assert np.array_equal(host(Wd), W_end)
