@@ -40,7 +40,13 @@ VALU_F64_SLOTS = 256 * 64 * 2.4e9
 # available, the kernels' division core (8 instructions, one a quarter-rate
 # reciprocal: 11 issue units); the compiler's IEEE divide (11 instructions,
 # 14 issue units) is reported beside it.  Until measured: the issue units.
-OP_WEIGHTS = {"div": 11.0, "sqrt": 19.0, "source": "issue units of the instruction sequences"}
+# FP32 (the precision form's bulk): a non-packed operation issues like an
+# FP64 one; its quotient is a quarter-rate reciprocal and a product.
+OP_WEIGHTS = {"div": 11.0, "sqrt": 19.0, "f32": 1.0, "div_f32": 5.0, "sqrt_f32": 5.0,
+              "source": "issue units of the instruction sequences"}
+# steps of the face pipeline the precision form runs in FP32 (the others,
+# and the per-cell difference and RK combination, stay FP64)
+FP32_PHASES = ("weno", "back_v", "mid_hllc", "hcs")
 
 
 def measure_weights():
@@ -48,10 +54,13 @@ def measure_weights():
     from paper_2102_05287_amd import wcns
     runs = [wcns.issue_weights(4096) for _ in range(3)]
     med = {op: round(statistics.median(r["weights"][op] for r in runs), 2)
-           for op in ("div_core", "div", "sqrt")}
+           for op in ("div_core", "div", "sqrt", "fma_f32", "div_f32", "sqrt_f32")}
     OP_WEIGHTS["div"] = med["div_core"]
     OP_WEIGHTS["sqrt"] = med["sqrt"]
     OP_WEIGHTS["div_ieee_sequence"] = med["div"]
+    OP_WEIGHTS["f32"] = med["fma_f32"]
+    OP_WEIGHTS["div_f32"] = med["div_f32"]
+    OP_WEIGHTS["sqrt_f32"] = med["sqrt_f32"]
     OP_WEIGHTS["source"] = "issue probe (wcns_issue_probe), median of 3; div = division core"
     OP_WEIGHTS["fma_slots_per_s"] = statistics.median(r["fma_slots_per_s"] for r in runs)
 
@@ -62,17 +71,37 @@ def weighted(c, w_div=None, w_sqrt=None):
     return c["add"] + c["mul"] + c["cmp"] + w_div * c["div"] + w_sqrt * c["sqrt"]
 
 
-def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=None, w_sqrt=None, fused=2.0 / 3.0):
-    """Algorithmic (issue-weighted) FP64 ops per launch of each kernel;
-    w_div = w_sqrt = 1 gives the plain operation count.  `fused`: share of
-    the y-sweep launches that also recover the next stage's node primitives
-    in place of k_node (2/3 for single-step calls; 1 - 1/(3K) for K steps
-    in one call)."""
+def weighted_f32(c, unit=False):
+    """FP32 operations in FP64 FMA issue slots (unit: every operation 1)."""
+    if unit:
+        return c["add"] + c["mul"] + c["cmp"] + c["div"] + c["sqrt"]
+    return (OP_WEIGHTS["f32"] * (c["add"] + c["mul"] + c["cmp"]) + OP_WEIGHTS["div_f32"] * c["div"]
+            + OP_WEIGHTS["sqrt_f32"] * c["sqrt"])
+
+
+def face_weighted(oc, fp32_bulk=False, w_div=None, w_sqrt=None):
+    """Weighted algorithmic operations of one face: FP64 throughout, or the
+    precision form's split (FP32_PHASES priced as FP32, the rest as FP64)."""
+    if not fp32_bulk:
+        return weighted(oc["face"], w_div, w_sqrt)
+    unit = w_div == 1 and w_sqrt == 1
+    return sum(weighted_f32(c, unit) if k in FP32_PHASES else weighted(c, w_div, w_sqrt)
+               for k, c in oc["face_phases"].items())
+
+
+def kernel_ops(nx, ny, scheme="ppwcnsis", w_div=None, w_sqrt=None, fused=2.0 / 3.0,
+               fp32_bulk=False):
+    """Algorithmic (issue-weighted) ops per launch of each kernel, in FP64
+    FMA issue slots; w_div = w_sqrt = 1 gives the plain operation count.
+    `fused`: share of the y-sweep launches that also recover the next
+    stage's node primitives in place of k_node (2/3 for single-step calls;
+    1 - 1/(3K) for K steps in one call).  fp32_bulk: the precision form's
+    split of the face work by precision."""
     w_div = OP_WEIGHTS["div"] if w_div is None else w_div
     w_sqrt = OP_WEIGHTS["sqrt"] if w_sqrt is None else w_sqrt
     with open(os.path.join(ROOT, "tests", "golden", "opcount.json")) as f:
         oc = json.load(f)["counts"][scheme]
-    face = weighted(oc["face"], w_div, w_sqrt)
+    face = face_weighted(oc, fp32_bulk, w_div, w_sqrt)
     node = weighted(oc["node"], w_div, w_sqrt)
     cells = nx * ny
     diff = 6 * (1 + w_div)                 # -(G^- - G^+)/dx per component
@@ -122,54 +151,81 @@ def time_steps(sol, W0, steps, warmup):
     return time.perf_counter() - t0, W
 
 
-def precision_form(n, steps, warmup):
-    """Underwater explosion at n^2: FP32-bulk and FP64 paths on the same
-    device, Mcell-updates/s per RHS each, and the relative L1 per variable of
-    the FP32-bulk state against the FP64 one after the same steps (both with
-    the FP64 path's time steps, so the runs are step-aligned)."""
+def precision_form(n=2048, prof_steps=20):
+    """Underwater explosion at n^2 (2048^2: the precision form's workload)
+    to its final time t = 2e-4 s, FP64 and FP32 bulk each through the
+    library's time loop on the same device (each takes its own CFL steps):
+    time to solution and Mcell-updates/s per RHS of each, the relative L1
+    per variable of the FP32-bulk final state against the FP64 one, the
+    relative L1 per variable of one FP32-bulk RHS of the initial state (its
+    sharp material interfaces) against the FP64 RHS, and the ALU roofline of
+    the FP32-bulk sweeps with each step of the face pipeline priced at its
+    own precision (the FP64 path equals the oracle bit for bit, so the FP64
+    runs stand for it at this size)."""
     import torch
     from paper_2102_05287_amd import problems as pb
     from paper_2102_05287_amd import wcns
     spec = pb.underwater_explosion(n)
-    s64 = wcns.Solver.from_spec(spec)
-    s32 = wcns.Solver.from_spec(spec, precision=wcns.FP32_BULK)
-    W0 = s64.prim_to_cons(torch.from_numpy(spec.prim).cuda())
-    t64, W64 = time_steps(s64, W0, steps, warmup)
-    t32, W32 = time_steps(s32, W0, steps, warmup)
+    V = torch.from_numpy(spec.prim).cuda()
+    spec.prim = None
     cells = spec.nx * spec.ny
-    # per-kernel device time of the FP32-bulk sweeps (same op model as FP64)
-    W = W0.clone()
-    s32.profile(True)
-    s32.steps(W, steps, 0.0)
-    prof = s32.profile_read(reset=True)
-    s32.profile(False)
-    ops = kernel_ops(spec.nx, spec.ny, fused=1.0 - 1.0 / (3 * steps))
+    out = {"workload": f"2D underwater explosion near a wall, {n}x{n}, to t = {spec.t_end} s"}
+    finals = {}
+    W0 = None
+    for name, prec in (("fp64", wcns.FP64), ("fp32_bulk", wcns.FP32_BULK)):
+        sol = wcns.Solver.from_spec(spec, precision=prec)
+        if W0 is None:
+            W0 = sol.prim_to_cons(V)
+        W = W0.clone()
+        sol.steps(W, 3, 0.0)               # warm-up
+        W.copy_(W0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, t = sol.advance(W, spec.t_end, chunk=128)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"{name}_steps"] = steps
+        out[f"{name}_wall_s"] = el
+        out[f"{name}_mcells_per_s"] = 3 * cells * steps / el / 1e6
+        out[f"{name}_violations"] = sol.violations()
+        out[f"{name}_inadmissible_at_end"] = sol.count_inadmissible(W)
+        finals[name] = W
+        # one RHS of the initial state (material interfaces)
+        finals[name + "_rhs"] = sol.rhs(W0, dt=1e-8).clone()
+        if prec == wcns.FP32_BULK:
+            Wp = W0.clone()
+            sol.profile(True)
+            sol.steps(Wp, prof_steps, 0.0)
+            prof = sol.profile_read(reset=True)
+            sol.profile(False)
+            del Wp
+        sol.close()
+    A, B = finals["fp64"], finals["fp32_bulk"]
+    out["rel_l1_fp32_vs_fp64_final_per_variable"] = [
+        float((B[v] - A[v]).abs().sum() / A[v].abs().sum()) for v in range(6)]
+    La, Lb = finals["fp64_rhs"], finals["fp32_bulk_rhs"]
+    out["rel_l1_rhs_fp32_vs_fp64_initial_per_variable"] = [
+        float((Lb[v] - La[v]).abs().sum() / La[v].abs().sum().clamp_min(1e-300)) for v in range(6)]
+    out["speedup_fp32_bulk"] = out["fp32_bulk_mcells_per_s"] / out["fp64_mcells_per_s"]
+    ops = kernel_ops(spec.nx, spec.ny, fused=1.0 - 1.0 / (3 * prof_steps), fp32_bulk=True)
+    ops1 = kernel_ops(spec.nx, spec.ny, w_div=1, w_sqrt=1, fused=1.0 - 1.0 / (3 * prof_steps),
+                      fp32_bulk=True)
     roof32 = {}
     for k in ("sweep_x", "sweep_y"):
         avg = prof[k][0] / 1e3 / prof[k][1]
-        roof32[k] = {"avg_launch_ms": avg * 1e3, "achieved": ops[k] / avg / 1e12,
-                     "frac": ops[k] / avg / VALU_F64_SLOTS}
-    del W
-    # step-aligned accuracy: same dt sequence (from the FP64 state)
-    A, B = W0.clone(), W0.clone()
-    dtu = torch.zeros(1, dtype=torch.float64, device="cuda")
-    for _ in range(steps):
-        s64.step(A, 0.0, dt_used=dtu)
-        s32.step(B, float(dtu.item()))
-    l1 = ((B - A).abs().sum(dim=(1, 2)) / A.abs().sum(dim=(1, 2)).clamp_min(1e-300)).tolist()
-    bad = s32.count_inadmissible(B)
-    return {"workload": f"2D underwater explosion near a wall, {n}x{n}",
-            "steps": steps,
-            "fp64_mcells_per_s": 3 * cells * steps / t64 / 1e6,
-            "fp32_bulk_mcells_per_s": 3 * cells * steps / t32 / 1e6,
-            "speedup_fp32_bulk": t64 / t32,
-            "roofline_fp32_bulk": {"bound": "alu", "peak": VALU_F64_SLOTS / 1e12, "unit": "TFLOP/s",
-                                   "kernels": roof32,
-                                   "note": "FP64 op model and FP64 issue peak; the FP32 "
-                                           "interpolation issues at the same per-wave rate "
-                                           "(no packed math is generated)"},
-            "rel_l1_fp32_vs_fp64_per_variable": l1,
-            "inadmissible_fp32": bad}
+        roof32[k] = {"avg_launch_ms": avg * 1e3, "ops_per_launch": ops[k],
+                     "achieved": ops[k] / avg / 1e12, "frac": ops[k] / avg / VALU_F64_SLOTS,
+                     "frac_unweighted": ops1[k] / avg / VALU_F64_SLOTS}
+    out["roofline_fp32_bulk"] = {
+        "bound": "alu", "peak": VALU_F64_SLOTS / 1e12, "unit": "TFLOP/s", "kernels": roof32,
+        "op_model": "oracle op count per face filed by pipeline step (tests/golden/opcount.json "
+                    "face_phases); " + ", ".join(FP32_PHASES) + " priced as FP32 (f32, div_f32, "
+                    "sqrt_f32 of op_weights), the rest and the per-cell work as FP64; peak = "
+                    "the FP64 / non-packed FP32 VALU issue rate 256 CU x 64 lanes x 2.4 GHz",
+        "op_weights": dict(OP_WEIGHTS)}
+    del A, B, La, Lb, W0, V, finals
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched_form(n_inst, steps, seq_steps):
@@ -233,10 +289,13 @@ def batched_form(n_inst, steps, seq_steps):
     return out
 
 
-def serving_form(n_req, rate, budget_gib, chunk):
-    """Poisson request stream (seed 4) at `rate` req/s replayed in real time
-    through the continuous-batching server; mixed 1D (200-20000 cells) and 2D
-    (64^2-1024^2) water/air solves of 100-2000 steps, FP64 or FP32-bulk."""
+def serving_form(n_req=2000, rate=200.0, budget_gib=64, chunk=20):
+    """The Poisson request stream (seed 4) at `rate` req/s replayed in real
+    time through the continuous-batching server: the whole 2000-request
+    trace of mixed 1D (200-20000 cells) and 2D (64^2-1024^2) water/air
+    solves of 100-2000 steps, FP64 or FP32 bulk.  Offered over capacity, so
+    latency there is mostly queueing: the rate sweep gives the sustainable
+    rate."""
     from paper_2102_05287_amd import problems as pb
     from paper_2102_05287_amd import serve
     reqs = pb.serving_trace(n_req, rate, seed=4)
@@ -244,11 +303,44 @@ def serving_form(n_req, rate, budget_gib, chunk):
     srv = serve.Server(hbm_budget=budget_gib << 30, chunk=chunk)
     done, summary = srv.run(solves, realtime=True)
     offered = sum(3.0 * s.spec.nx * s.spec.ny * s.steps for s in solves) / (reqs[-1].arrival or 1.0)
-    summary.update({"workload": f"first {n_req} requests of the seed-4 trace at {rate} req/s "
-                                f"(Poisson), mixed 1D/2D, FP64/FP32-bulk",
+    summary.update({"workload": f"the seed-4 trace, {n_req} requests at {rate} req/s (Poisson), "
+                                f"mixed 1D/2D, FP64/FP32-bulk",
                     "offered_mcell_updates_per_s": offered / 1e6,
                     "hbm_budget_gib": budget_gib, "peak_hbm_used_gib": srv.peak_used / 2**30})
     return summary
+
+
+def serving_rate_sweep(n_req=300, rates=(8.0, 12.0, 16.0, 20.0, 28.0), budget_gib=64, chunk=20):
+    """The first n_req requests of the seed-4 trace (the same solves at every
+    rate) replayed at several Poisson arrival rates: completion rate and
+    latency against offered rate.  A rate is sustained when the server
+    completes at least 95% of it and its p99 latency stays within 3x the p99
+    at the lowest rate (latency bounded, not growing with a queue); the
+    sustainable rate is the highest such rate."""
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import serve
+    rows = []
+    for r in rates:
+        reqs = pb.serving_trace(2000, r, seed=4)[:n_req]
+        solves = [serve.Solve(q.rid, q.arrival, pb.request_problem(q), q.steps, q.fp32) for q in reqs]
+        srv = serve.Server(hbm_budget=budget_gib << 30, chunk=chunk)
+        _, sm = srv.run(solves, realtime=True)
+        offered = n_req / reqs[-1].arrival
+        rows.append({"rate_req_per_s": r, "offered_req_per_s": offered,
+                     "solves_per_s": sm["solves_per_s"],
+                     "latency_p50_s": sm["latency_p50_s"], "latency_p99_s": sm["latency_p99_s"],
+                     "makespan_s": sm["makespan_s"],
+                     "mcell_updates_per_s": sm["mcell_updates_per_s"]})
+        print(f"#   rate {r}: {sm['solves_per_s']:.1f} solves/s, p50 {sm['latency_p50_s']:.2f} s, "
+              f"p99 {sm['latency_p99_s']:.2f} s", flush=True)
+    base = rows[0]["latency_p99_s"]
+    for row in rows:
+        row["sustained"] = bool(row["solves_per_s"] >= 0.95 * row["offered_req_per_s"]
+                                and row["latency_p99_s"] <= 3.0 * base)
+    ok = [row["rate_req_per_s"] for row in rows if row["sustained"]]
+    return {"requests_per_rate": n_req, "rates": rows,
+            "sustainable_rate_req_per_s": max(ok) if ok else None,
+            "rule": "completes >= 95% of the offered rate and p99 <= 3x the p99 at the lowest rate"}
 
 
 HBM_PEAK = 8.0e12     # MI355X HBM3E, bytes/s
@@ -257,12 +349,12 @@ HBM_PEAK = 8.0e12     # MI355X HBM3E, bytes/s
 def first_order_form(n=1024, steps=200, warmup=10):
     """The first-order HLLC product mode on the default workload (n^2
     shock-bubble, FP64, device-CFL steps in one call): Mcell-updates/s per
-    RHS and, since the mode skips the interpolation, limiter and midpoint
-    arithmetic, an HBM roofline of its sweeps: algorithmic bytes per launch
-    (x: W and the node primitives read, L_x written, 136 B per cell; y: W,
-    P, L_x and U^n read, the stage written, 232 B per cell, plus 40 B of
-    next-stage primitives in a share 1 - 1/(3K) of the launches) over the
-    mean launch time, against 8 TB/s."""
+    RHS and, since the mode has no interpolation, limiter or midpoint
+    arithmetic, an HBM roofline of its RK stages against their algorithmic
+    bytes: a stage reads U^(s) and (stages 2, 3) U^n and writes U^(s+1),
+    96 + 144 + 144 B per cell per step of 6 FP64 components.  `achieved` is
+    those bytes over the device time of all the stage's kernels per step
+    (HIP events around each launch)."""
     import torch
     from paper_2102_05287_amd import problems as pb
     from paper_2102_05287_amd import wcns
@@ -277,21 +369,20 @@ def first_order_form(n=1024, steps=200, warmup=10):
     prof = sol.profile_read(reset=True)
     sol.profile(False)
     bad = sol.count_inadmissible(W)
-    fused = 1.0 - 1.0 / (3 * steps)
-    nbytes = {"sweep_x": 136.0 * cells, "sweep_y": (232.0 + 40.0 * fused) * cells}
-    roof = {}
-    for k, b in nbytes.items():
-        t = prof[k][0] / 1e3 / prof[k][1]
-        roof[k] = {"avg_launch_ms": t * 1e3, "bytes_per_launch": b, "achieved": b / t / 1e9,
-                   "frac": b / t / HBM_PEAK}
+    alg_bytes = (96.0 + 144.0 + 144.0) * cells        # per step
+    dev_s = sum(v[0] for v in prof.values()) / 1e3 / steps
+    roof = {"bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK / 1e9, "kernel": "rk_stage (all kernels)",
+            "bytes_per_step": alg_bytes, "device_ms_per_step": dev_s * 1e3,
+            "achieved": alg_bytes / dev_s / 1e9, "frac": alg_bytes / dev_s / HBM_PEAK,
+            "frac_wall": alg_bytes / (el / steps) / HBM_PEAK}
     del W, W0
     sol.close()
     return {"workload": f"2D shock-bubble {n}x{n}, first-order HLLC (scheme 1), FP64",
             "steps": steps, "mcells_per_s": 3 * cells * steps / el / 1e6,
             "ms_per_step": el / steps * 1e3, "inadmissible_after": bad,
             "per_kernel_ms_per_launch": {k: v[0] / v[1] for k, v in prof.items() if v[1]},
-            "roofline": {"bound": "hbm", "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                         "kernels": roof}}
+            "launches_per_step": {k: v[1] / steps for k, v in prof.items() if v[1]},
+            "roofline": roof}
 
 
 def three_d_form(n=256, steps=10, warmup=2):
@@ -404,51 +495,43 @@ def time_to_solution_form():
     return out
 
 
-def serving_rate_sweep(n_req=60, rates=(10.0, 20.0, 40.0, 200.0), budget_gib=64, chunk=20):
-    """The same first n_req requests of the seed-4 trace replayed at several
-    arrival rates: latency against offered load; the completion rate at the
-    highest (over-capacity) rate is the server's capacity."""
-    from paper_2102_05287_amd import problems as pb
-    from paper_2102_05287_amd import serve
-    rows = []
-    for r in rates:
-        reqs = pb.serving_trace(n_req, r, seed=4)
-        solves = [serve.Solve(q.rid, q.arrival, pb.request_problem(q), q.steps, q.fp32) for q in reqs]
-        srv = serve.Server(hbm_budget=budget_gib << 30, chunk=chunk)
-        _, sm = srv.run(solves, realtime=True)
-        rows.append({"rate_req_per_s": r, "solves_per_s": sm["solves_per_s"],
-                     "latency_p50_s": sm["latency_p50_s"], "latency_p99_s": sm["latency_p99_s"],
-                     "makespan_s": sm["makespan_s"]})
-        print(f"#   rate {r}: {sm['solves_per_s']:.1f} solves/s, p99 {sm['latency_p99_s']:.2f} s",
-              flush=True)
-    return {"requests_per_rate": n_req, "rates": rows,
-            "capacity_solves_per_s": rows[-1]["solves_per_s"]}
-
-
-def cpu_baseline(spec, target_s=12.0):
+def cpu_baseline(spec, target_s=10.0):
+    """The oracle on the same initial state, timed on this host: as many
+    full-grid RHS evaluations as fit in about target_s seconds, serially (1
+    thread) and with the OpenMP build of the same source over all host
+    cores (bit-identical results); `value` is the all-cores rate."""
     from oracle import oracle as orc
     s = orc.Setup(ndim=spec.ndim, nx=spec.nx, ny=spec.ny, dx=spec.dx, dy=spec.dy, bc=spec.bc)
     W = orc.prim_to_cons(s, spec.prim)
     dt = orc.cfl_dt(s, W)
-    t0 = time.perf_counter()
-    orc.rhs(s, W, dt)
-    one = time.perf_counter() - t0
-    calls = max(1, int(target_s / max(one, 1e-3)) - 1)
-    t0 = time.perf_counter()
-    for _ in range(calls):
-        orc.rhs(s, W, dt)
-    el = time.perf_counter() - t0
+
+    def rate(fn):
+        t0 = time.perf_counter()
+        fn(s, W, dt)
+        one = time.perf_counter() - t0
+        calls = max(1, int(target_s / max(one, 1e-3)) - 1)
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            fn(s, W, dt)
+        el = time.perf_counter() - t0
+        return spec.nx * spec.ny * calls / el / 1e6, calls
+
+    serial, n1 = rate(orc.rhs)
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    allc, nall = rate(orc.rhs_parallel)
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as f:
             cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), cpu)
     except OSError:
         pass
-    return {"value": spec.nx * spec.ny * calls / el / 1e6, "unit": "Mcell-updates/s",
-            "cores": 1, "kind": "oracle",
-            "sample": f"{calls} full-grid RHS evaluations of the {spec.nx}x{spec.ny} "
-                      f"shock-bubble initial state (serial FP64 C++ oracle, 1 thread)",
-            "host": {"cpu": cpu, "logical_cpus": os.cpu_count()}}
+    return {"value": allc, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nall} full-grid RHS evaluations of the {spec.nx}x{spec.ny} shock-bubble "
+                      f"initial state, FP64 C++ oracle built with OpenMP over grid rows "
+                      f"({threads} threads; bit-identical to the serial build)",
+            "serial": {"value": serial, "cores": 1,
+                       "sample": f"{n1} RHS evaluations, the serial build, 1 thread"},
+            "host": {"cpu": cpu, "logical_cpus": os.cpu_count(), "nproc": len(os.sched_getaffinity(0))}}
 
 
 def main():
@@ -482,9 +565,9 @@ def main():
         import torch
         torch.cuda.set_device(0)
         measure_weights()
-        run = {"precision": lambda: precision_form(2048, 20, 3),
+        run = {"precision": precision_form,
                "batched": lambda: batched_form(512, 200, 20),
-               "serving": lambda: serving_form(300, 200.0, 64, 20),
+               "serving": serving_form,
                "solutions": time_to_solution_form,
                "rates": serving_rate_sweep,
                "3d": three_d_form,
@@ -570,11 +653,11 @@ def main():
     forms = {}
     if not args.no_forms:
         print("# precision form (2048^2 underwater explosion) ...", flush=True)
-        forms["precision_fp32_bulk"] = precision_form(2048, 20, 3)
+        forms["precision_fp32_bulk"] = precision_form()
         print("# batched form (512 instances) ...", flush=True)
         forms["batched"] = batched_form(512, 200, 20)
         print("# serving form ...", flush=True)
-        forms["serving"] = serving_form(300, 200.0, 64, 20)
+        forms["serving"] = serving_form()
         print("# serving rate sweep ...", flush=True)
         forms["serving_rate_sweep"] = serving_rate_sweep()
         print("# 3D form ...", flush=True)

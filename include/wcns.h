@@ -251,13 +251,14 @@ wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int3
 wcns_status wcns_selftest_division(const double* a, const double* b, double* q_ieee,
                                    double* q_core, int64_t n, void* stream);
 
-/* Measurement aid: issue cost of one FP64 operation on this GPU.  Runs
+/* Measurement aid: issue cost of one FP64 or FP32 operation on this GPU.  Runs
  * `iters` rounds of 8 independent chains of operation `op` per lane over a
  * grid that keeps 8 waves on every SIMD of the device (blocks of 256
  * threads; `blocks` <= 0 picks 32 per compute unit), synchronises, and
  * returns the kernel's device time in *ms (host).  op: 0 FMA, 1 add, 2 mul,
  * 3 IEEE divide (the compiler's sequence), 4 IEEE square root, 5 the
- * kernels' division core.  The ratio of two ops' times at equal iters is
+ * kernels' division core; FP32 (the precision form's bulk): 6 FMA, 7 the
+ * kernels' quotient (hardware reciprocal and a product), 8 square root.  The ratio of two ops' times at equal iters is
  * their relative issue cost (the roofline of the sweeps weights divides and
  * square roots in FMA slots).  Allocates and frees its own 8-byte-per-thread
  * output; WCNS_ERR_ARG for an unknown op or iters < 1. */

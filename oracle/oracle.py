@@ -26,12 +26,17 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 BC_PERIODIC, BC_EXTRAP, BC_REFLECT, BC_DIRICHLET = 0, 1, 2, 3
 
 
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_FLAGS = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+
+
 def build() -> str:
-    """Compile the oracle (always; a few seconds)."""
-    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
-           "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp"]
-    subprocess.check_call(cmd)
+    """Compile the oracle (always; a few seconds): the serial library and
+    the same source with OpenMP over grid rows (the all-cores baseline)."""
+    subprocess.check_call(_FLAGS + ["-Wno-unknown-pragmas", _SRC, "-o", _LIB + ".tmp"])
     os.replace(_LIB + ".tmp", _LIB)
+    subprocess.check_call(_FLAGS + ["-fopenmp", _SRC, "-o", _LIB_OMP + ".tmp"])
+    os.replace(_LIB_OMP + ".tmp", _LIB_OMP)
     return _LIB
 
 
@@ -138,7 +143,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if any(not os.path.exists(f) or os.path.getmtime(f) < os.path.getmtime(_SRC)
+               for f in (_LIB, _LIB_OMP)):
             build()
         L = C.CDLL(_LIB)
         P = C.POINTER(_Problem)
@@ -174,6 +180,8 @@ def lib():
         L.oracle_run.restype = C.c_long
         L.oracle_opcount_face.argtypes = [P, dp, C.c_double, C.POINTER(C.c_longlong)]
         L.oracle_opcount_face3.argtypes = [P, dp, C.c_double, C.POINTER(C.c_longlong)]
+        L.oracle_opcount_phases.argtypes = [C.POINTER(C.c_longlong)]
+        L.oracle_opcount_phases.restype = C.c_int
         _lib = L
     return _lib
 
@@ -219,6 +227,27 @@ def rhs(s: Setup, W: np.ndarray, dt: float) -> np.ndarray:
     if rc != 0:
         raise ValueError(f"oracle_rhs failed: {rc}")
     return L
+
+
+_lib_omp = None
+
+
+def rhs_parallel(s: Setup, W: np.ndarray, dt: float) -> np.ndarray:
+    """rhs() from the OpenMP build of the same source (rows over the threads
+    of OMP_NUM_THREADS): the same bits, on all cores."""
+    global _lib_omp
+    lib()   # builds both libraries when the source is newer
+    if _lib_omp is None:
+        L = C.CDLL(_LIB_OMP)
+        L.oracle_rhs.argtypes = [C.POINTER(_Problem), C.POINTER(C.c_double),
+                                 C.POINTER(C.c_double), C.c_double]
+        _lib_omp = L
+    W = _arr(W)
+    out = np.empty_like(W)
+    rc = _lib_omp.oracle_rhs(C.byref(s.c()), _dp(W), _dp(out), float(dt))
+    if rc != 0:
+        raise ValueError(f"oracle_rhs failed: {rc}")
+    return out
 
 
 def rhs_cells(s: Setup, W: np.ndarray, dt: float, cells: np.ndarray) -> np.ndarray:
@@ -367,4 +396,15 @@ def opcount_face(s: Setup, stencil, lam: float) -> dict:
         assert st.size == 36
         lib().oracle_opcount_face(C.byref(s.c()), _dp(st), float(lam), out)
     keys = ["add", "mul", "div", "sqrt", "cmp"]
-    return {"node": dict(zip(keys, out[0:5])), "face": dict(zip(keys, out[5:10]))}
+    res = {"node": dict(zip(keys, out[0:5])), "face": dict(zip(keys, out[5:10]))}
+    if st.size == 36:
+        ph = (C.c_longlong * (5 * len(PHASES)))()
+        assert lib().oracle_opcount_phases(ph) == len(PHASES)
+        res["face_phases"] = {name: dict(zip(keys, ph[5 * k:5 * k + 5]))
+                              for k, name in enumerate(PHASES)}
+    return res
+
+
+# steps of the face pipeline the op count is filed under (the oracle's PH_ order)
+PHASES = ["first_order", "project", "weno", "back_v", "to_w", "interp_limit", "mid_recover",
+          "mid_hllc", "hcs", "split_limit"]

@@ -72,20 +72,46 @@ enum { BC_PERIODIC = 0, BC_EXTRAP = 1, BC_REFLECT = 2, BC_DIRICHLET = 3 };
 struct OpCounts { long long add, mul, div, sqrt, cmp; };
 static OpCounts g_ops;
 
+// The counts are also filed by step of the face pipeline (the phase set by
+// count_phase; bookkeeping only, no arithmetic): the precision form runs
+// some steps in FP32, so its roofline prices each step at its own precision.
+enum {
+  PH_FIRST_ORDER,   // first-order HLLC flux at the face [Sec. 3.2]
+  PH_PROJECT,       // face averages and U = R^{-1} V [Sec. 4.2, App. A]
+  PH_WENO,          // IS-WENO interpolation [Sec. 4.3]
+  PH_BACK_V,        // V = R U [App. A]
+  PH_TO_W,          // V -> W [Sec. 2]
+  PH_INTERP_LIMIT,  // Algorithms 1-3 [Sec. 5.1]
+  PH_MID_RECOVER,   // primitives of the limited midpoint states [Sec. 2]
+  PH_MID_HLLC,      // midpoint HLLC flux [Sec. 3.1-3.2]
+  PH_HCS,           // HCS flux and velocity [Sec. 4.1]
+  PH_SPLIT_LIMIT,   // split fluxes G^{+-} and Algorithms 4-6 [Sec. 3.2, 5.2]
+  NPHASE
+};
+static OpCounts g_phase_ops[NPHASE];
+static int g_phase = 0;
+
 struct Cnt {
   double v;
   Cnt() : v(0) {}
   Cnt(double x) : v(x) {}
 };
-inline Cnt operator+(Cnt a, Cnt b) { g_ops.add++; return Cnt(a.v + b.v); }
-inline Cnt operator-(Cnt a, Cnt b) { g_ops.add++; return Cnt(a.v - b.v); }
+inline void tick(long long OpCounts::*f) {
+  g_ops.*f += 1;
+  g_phase_ops[g_phase].*f += 1;
+}
+inline Cnt operator+(Cnt a, Cnt b) { tick(&OpCounts::add); return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { tick(&OpCounts::add); return Cnt(a.v - b.v); }
 inline Cnt operator-(Cnt a) { return Cnt(-a.v); }  // sign flip: free
-inline Cnt operator*(Cnt a, Cnt b) { g_ops.mul++; return Cnt(a.v * b.v); }
-inline Cnt operator/(Cnt a, Cnt b) { g_ops.div++; return Cnt(a.v / b.v); }
-inline bool operator<(Cnt a, Cnt b) { g_ops.cmp++; return a.v < b.v; }
-inline bool operator>(Cnt a, Cnt b) { g_ops.cmp++; return a.v > b.v; }
-inline bool operator==(Cnt a, Cnt b) { g_ops.cmp++; return a.v == b.v; }
-inline Cnt sqrt(Cnt a) { g_ops.sqrt++; return Cnt(std::sqrt(a.v)); }
+inline Cnt operator*(Cnt a, Cnt b) { tick(&OpCounts::mul); return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { tick(&OpCounts::div); return Cnt(a.v / b.v); }
+inline bool operator<(Cnt a, Cnt b) { tick(&OpCounts::cmp); return a.v < b.v; }
+inline bool operator>(Cnt a, Cnt b) { tick(&OpCounts::cmp); return a.v > b.v; }
+inline bool operator==(Cnt a, Cnt b) { tick(&OpCounts::cmp); return a.v == b.v; }
+inline Cnt sqrt(Cnt a) { tick(&OpCounts::sqrt); return Cnt(std::sqrt(a.v)); }
+// the step the next operations belong to (counting scalar only)
+inline void count_phase(const Cnt&, int ph) { g_phase = ph; }
+inline void count_phase(const double&, int) {}
 inline double val(Cnt a) { return a.v; }
 inline double val(double a) { return a; }
 using std::sqrt;
@@ -420,6 +446,7 @@ inline void back_project_to_w(const Eos& e, const FaceAvg<T>& f, const T* U, T* 
   T us = NR == 7 ? U[4] : T(0.0);
   T p = T(0.5) * f.rho * f.c * (Uplus - U[0]);
   T a1 = U[NR - 2];
+  count_phase(a1, PH_TO_W);
   T rho = a1r1 + a2r2;
   X[0] = a1r1;
   X[1] = a2r2;
@@ -454,6 +481,7 @@ inline T face_flux(const Eos& e, const Problem& P, const Node<T, NR> nd[6], T la
   const Node<T, NR>& nl = nd[2];
   const Node<T, NR>& nr = nd[3];
   // first-order HLLC at the face from W_i, W_{i+1}  [Sec. 3.2]
+  count_phase(lam, PH_FIRST_ORDER);
   T Fh[NR - 1], fah, ush;
   hllc(nl, nr, Fh, fah, ush);
   T Hm[NR], Hp[NR];
@@ -465,10 +493,12 @@ inline T face_flux(const Eos& e, const Problem& P, const Node<T, NR> nd[6], T la
     return T(0.0);
   }
   // step 2: characteristic projection of the stencil nodes
+  count_phase(lam, PH_PROJECT);
   FaceAvg<T> fa = face_avg(nl, nr);
   T U[6][NR];
   for (int m = 0; m < 6; ++m) project(fa, nd[m], U[m]);
   // step 3: left- and right-biased IS-WENO interpolation per field
+  count_phase(lam, PH_WENO);
   T UL[NR], UR[NR];
   for (int k = 0; k < NR; ++k) {
     UL[k] = weno_is(U[0][k], U[1][k], U[2][k], U[3][k], U[4][k], P.weno_eps);
@@ -476,27 +506,34 @@ inline T face_flux(const Eos& e, const Problem& P, const Node<T, NR> nd[6], T la
   }
   // steps 4-5: back to primitive, then conservative
   T WL[NR], WR[NR];
+  count_phase(lam, PH_BACK_V);
   back_project_to_w<NR>(e, fa, UL, WL);
+  count_phase(lam, PH_BACK_V);
   back_project_to_w<NR>(e, fa, UR, WR);
   // interpolation limiter toward W_i (left) and W_{i+1} (right)
+  count_phase(lam, PH_INTERP_LIMIT);
   if (P.interp_limiter) {
     interp_limit<NR>(e, P, nl.w, WL);
     interp_limit<NR>(e, P, nr.w, WR);
   }
   // step 6: high-order midpoint flux and velocity from the Riemann solver
+  count_phase(lam, PH_MID_RECOVER);
   Node<T, NR> tl = node_from_w<NR>(e, WL);
   Node<T, NR> tr = node_from_w<NR>(e, WR);
+  count_phase(lam, PH_MID_HLLC);
   T Ft[NR - 1], fat, ust;
   hllc(tl, tr, Ft, fat, ust);
   T gt[NR];
   for (int v = 0; v < NR - 1; ++v) gt[v] = Ft[v];
   gt[IA] = fat;
   // steps 7-8: node fluxes and HCS reconstruction of the flux and velocity
+  count_phase(lam, PH_HCS);
   T Gh[NR];
   for (int v = 0; v < NR; ++v)
     Gh[v] = hcs(gt[v], nd[0].g[v], nd[1].g[v], nd[2].g[v], nd[3].g[v], nd[4].g[v], nd[5].g[v]);
   T uh = hcs(ust, nd[0].un, nd[1].un, nd[2].un, nd[3].un, nd[4].un, nd[5].un);
   // step 9: non-conservative split fluxes G^{+-}
+  count_phase(lam, PH_SPLIT_LIMIT);
   for (int v = 0; v < NR - 1; ++v) { Gm[v] = Gh[v]; Gp[v] = Gh[v]; }
   Gm[IA] = Gh[IA] - nl.w[IA] * uh;
   Gp[IA] = Gh[IA] - nr.w[IA] * uh;
@@ -653,8 +690,12 @@ void rhs(const Problem& P, const double* W, double* L, double dt) {
   double lam[2];
   stage_lambda(P, W, dt, lam);
   std::vector<double> Lx((size_t)ncell * 6, 0.0);
-  std::vector<double> Gm, Gp;
+  // Rows (and below, columns) are independent: the OpenMP build of this file
+  // (the all-cores CPU baseline) splits them over threads, each writing its
+  // own rows, so its results are those of the serial build bit for bit.
+#pragma omp parallel for schedule(dynamic, 2)
   for (int j = 0; j < P.ny; ++j) {
+    std::vector<double> Gm, Gp;
     sweep_line(P, W, 0, j, lam[0], Gm, Gp, nullptr);
     for (int i = 0; i < P.nx; ++i) {
       double Rm[6], Rp[6], Xm[6], Xp[6];
@@ -665,7 +706,9 @@ void rhs(const Problem& P, const double* W, double* L, double dt) {
   }
   std::vector<double> Ly((size_t)ncell * 6, 0.0);
   if (P.ndim == 2) {
+#pragma omp parallel for schedule(dynamic, 2)
     for (int i = 0; i < P.nx; ++i) {
+      std::vector<double> Gm, Gp;
       sweep_line(P, W, 1, i, lam[1], Gm, Gp, nullptr);
       for (int j = 0; j < P.ny; ++j) {
         double Rm[6], Rp[6], Xm[6], Xp[6];
@@ -1225,12 +1268,26 @@ void oracle_opcount_face(const Problem* P, const double* stencil /* [6][6] */, d
   }
   OpCounts six = g_ops;
   g_ops = OpCounts{0, 0, 0, 0, 0};
+  for (int k = 0; k < NPHASE; ++k) g_phase_ops[k] = OpCounts{0, 0, 0, 0, 0};
   Cnt Gm[6], Gp[6];
   face_flux(e, *P, nd, Cnt(lam), Gm, Gp);
   OpCounts f = g_ops;
+  g_phase = 0;
   out[0] = six.add / 6; out[1] = six.mul / 6; out[2] = six.div / 6;
   out[3] = six.sqrt / 6; out[4] = six.cmp / 6;
   out[5] = f.add; out[6] = f.mul; out[7] = f.div; out[8] = f.sqrt; out[9] = f.cmp;
+}
+
+// The face part of the last oracle_opcount_face by step of the pipeline:
+// out[5 k .. 5 k + 4] = (add, mul, div, sqrt, cmp) of phase k < NPHASE
+// (the PH_ order above); returns NPHASE.
+int oracle_opcount_phases(long long* out) {
+  for (int k = 0; k < NPHASE; ++k) {
+    const OpCounts& c = g_phase_ops[k];
+    out[5 * k] = c.add; out[5 * k + 1] = c.mul; out[5 * k + 2] = c.div;
+    out[5 * k + 3] = c.sqrt; out[5 * k + 4] = c.cmp;
+  }
+  return NPHASE;
 }
 
 // The same for a 3D face (rotated frame, 6 nodes x 7 components).

@@ -1036,7 +1036,7 @@ wcns_status wcns_selftest_division_by(const double* a, double b, double* q_ieee,
 }
 
 wcns_status wcns_issue_probe(int32_t op, int32_t iters, int32_t blocks, double* ms, void* stream) {
-  if (op < PROBE_FMA || op > PROBE_DIV_CORE || iters < 1 || !ms) return WCNS_ERR_ARG;
+  if (op < PROBE_FMA || op > PROBE_SQRT_F32 || iters < 1 || !ms) return WCNS_ERR_ARG;
   hipStream_t s = (hipStream_t)stream;
   int dev = 0, ncu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -1057,7 +1057,10 @@ wcns_status wcns_issue_probe(int32_t op, int32_t iters, int32_t blocks, double* 
       case PROBE_MUL: hipLaunchKernelGGL(k_issue_probe<PROBE_MUL>, dim3(blocks), dim3(256), 0, s, out, iters, c, d); break;
       case PROBE_DIV: hipLaunchKernelGGL(k_issue_probe<PROBE_DIV>, dim3(blocks), dim3(256), 0, s, out, iters, c, 1.5); break;
       case PROBE_SQRT: hipLaunchKernelGGL(k_issue_probe<PROBE_SQRT>, dim3(blocks), dim3(256), 0, s, out, iters, c, d); break;
-      default: hipLaunchKernelGGL(k_issue_probe<PROBE_DIV_CORE>, dim3(blocks), dim3(256), 0, s, out, iters, c, 1.5); break;
+      case PROBE_DIV_CORE: hipLaunchKernelGGL(k_issue_probe<PROBE_DIV_CORE>, dim3(blocks), dim3(256), 0, s, out, iters, c, 1.5); break;
+      case PROBE_FMA_F32: hipLaunchKernelGGL(k_issue_probe_f32<PROBE_FMA_F32>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f); break;
+      case PROBE_DIV_F32: hipLaunchKernelGGL(k_issue_probe_f32<PROBE_DIV_F32>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1.5f); break;
+      default: hipLaunchKernelGGL(k_issue_probe_f32<PROBE_SQRT_F32>, dim3(blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f); break;
     }
     if (hipGetLastError() != hipSuccess) st = WCNS_ERR_HIP;
     (void)hipEventRecord(e1, s);

@@ -438,12 +438,14 @@ def selftest_division_by(a, b: float):
     return qi, qc
 
 
-PROBE_OPS = {"fma": 0, "add": 1, "mul": 2, "div": 3, "sqrt": 4, "div_core": 5}
+PROBE_OPS = {"fma": 0, "add": 1, "mul": 2, "div": 3, "sqrt": 4, "div_core": 5,
+             "fma_f32": 6, "div_f32": 7, "sqrt_f32": 8}
 
 
 def issue_probe(op: str, iters: int, blocks: int = 0) -> float:
     """Device time (ms) of `iters` rounds of 8 independent chains of one FP64
-    operation per lane over a grid that fills every SIMD (wcns_issue_probe)."""
+    or FP32 operation per lane over a grid that fills every SIMD
+    (wcns_issue_probe)."""
     import torch
     ms = C.c_double(0.0)
     _check(lib().wcns_issue_probe(PROBE_OPS[op], int(iters), int(blocks), C.byref(ms),
@@ -453,8 +455,8 @@ def issue_probe(op: str, iters: int, blocks: int = 0) -> float:
 
 
 def issue_weights(iters: int = 2048) -> dict:
-    """Issue cost of each probed FP64 operation in FMA slots: its time over
-    the time of an FMA probe of equal work run just before it (so clock
+    """Issue cost of each probed operation in FP64 FMA slots: its time over
+    the time of an FP64 FMA probe of equal work run just before it (so clock
     changes between probes cancel), plus the measured FMA issue rate in
     slots/s."""
     for _ in range(4):                            # warm-up: code load, clocks up

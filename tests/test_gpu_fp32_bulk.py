@@ -70,7 +70,7 @@ def test_fp32_bulk_rhs_close_to_oracle_on_smooth_data():
 # the design notes); the Euler step with the FP32-bulk RHS must still be
 # admissible, since the limiters run in FP64 on the FP32 fluxes.
 INTERFACE_BOUND = {"shock_bubble": [1e-4, 5e-2, 1e-3, 1e-3, 1e-4, 1e-4],
-                   "underwater_explosion": [1e-4, 5e-2, 1e-3, 1e-3, 1e-4, 1e-4]}
+                   "underwater_explosion": [1e-12, 1e-1, 5e-5, 5e-5, 2e-3, 2e-4]}
 
 
 @pytest.mark.parametrize("name", ["shock_bubble", "underwater_explosion"])

@@ -23,6 +23,11 @@ def test_issue_probe_scales_and_weights_are_plausible():
     assert 8.0 < w["div"] < 20.0
     assert 6.0 < w["div_core"] < w["div"] * 1.2
     assert 10.0 < w["sqrt"] < 30.0
+    # FP32 without packed math issues at the FP64 rate; the quotient is a
+    # quarter-rate reciprocal and a product
+    assert 0.8 < w["fma_f32"] < 1.25
+    assert 2.0 < w["div_f32"] < 8.0
+    assert 1.0 < w["sqrt_f32"] < 20.0
 
 
 def test_profile_counts_the_launches_of_a_multi_step_call():

@@ -23,7 +23,7 @@ def _cases():
     s2 = pb.random_smooth_state(70, 45, seed=5)
     s1 = pb.water_air_shock_tube(200)
     s3 = pb.random_smooth_state_3d(24, 21, 19, seed=6)
-    return [("2d", s2, (5, 20, 30)), ("1d", s1, (4, 50)), ("3d", s3, (6, 7, 8, 9))]
+    return [("2d", s2, (5, 20, 30)), ("1d", s1, (4, 0, 50)), ("3d", s3, (6, 7, 8, 9))]
 
 
 @pytest.mark.parametrize("case", ["2d", "1d", "3d"])

@@ -676,3 +676,18 @@ def test_dirichlet_ghosts_enter_the_cfl_maxima():
     a = orc.max_wavespeed(s, orc.prim_to_cons(s, V))
     assert 1.5e5 + 1440.0 < a[0] < 1.5e5 + 1460.0, a
     assert 370.0 < a[1] < 380.0, a
+
+
+def test_openmp_build_of_the_oracle_is_bitwise_identical():
+    """The all-cores CPU baseline: the same oracle source built with OpenMP
+    over grid rows gives the serial build's RHS bit for bit (2D with every
+    side kind, 1D, a limiter-active state)."""
+    cases = [pb.random_smooth_state(96, 70, seed=41), pb.water_air_shock_tube(400),
+             pb.shock_bubble(64)]
+    for spec in cases:
+        s = oracle_setup(spec)
+        W = oracle_W(spec, s)
+        dt = orc.cfl_dt(s, W)
+        a = orc.rhs(s, W, dt)
+        b = orc.rhs_parallel(s, W, dt)
+        assert np.array_equal(a, b), spec.name
