@@ -148,7 +148,7 @@ def test_issue_probe_rejects_bad_arguments():
     """Argument checks of the issue probe come before any device call."""
     L = wcns.lib()
     ms = C.c_double(0.0)
-    assert L.wcns_issue_probe(6, 16, 0, C.byref(ms), None) == -1     # unknown op
+    assert L.wcns_issue_probe(9, 16, 0, C.byref(ms), None) == -1     # unknown op
     assert L.wcns_issue_probe(-1, 16, 0, C.byref(ms), None) == -1
     assert L.wcns_issue_probe(0, 0, 0, C.byref(ms), None) == -1      # iters < 1
     assert L.wcns_issue_probe(0, 16, 0, None, None) == -1            # no output
