@@ -54,7 +54,9 @@ typedef enum {
   WCNS_ERR_NOMEM = -3,        /* device allocation failed                      */
   WCNS_ERR_HIP = -4,          /* a HIP runtime call failed                     */
   WCNS_ERR_INADMISSIBLE = -5, /* a state lies outside the admissible set G     */
-  WCNS_ERR_CFL = -6           /* non-finite or non-positive time step          */
+  WCNS_ERR_CFL = -6,          /* non-finite or non-positive time step          */
+  WCNS_ERR_TOO_LARGE = -7     /* grid needs more than the allocation-free      */
+                              /* entry point's static scratch                  */
 } wcns_status;
 
 typedef enum {
@@ -343,6 +345,31 @@ wcns_status wcns_batch_violations(wcns_batch* b, int64_t* counts, int32_t clear)
 wcns_status wcns_batch_dt(wcns_batch* b, double* dt);
 
 wcns_status wcns_batch_destroy(wcns_batch* b);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free right-hand side, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The arithmetic and kernels of wcns_rhs (same results,
+ * bit for bit) without a context: grid, fluids, options and precision are
+ * validated as by wcns_create and the scratch (node primitives, y-tile edge
+ * fluxes, block maxima, step record) lives in a static device array of
+ * WCNS_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load until the
+ * process ends.  It needs 8 (5 N + 12 nx ceil((ny+1)/16)) bytes plus
+ * ~16 KiB for N = nx*ny cells, i.e. up to ~1.45 M cells (1024^2 fits);
+ * larger grids return WCNS_ERR_TOO_LARGE.  1D and 2D grids without
+ * Dirichlet sides (WCNS_ERR_ARG otherwise).  W, dWdt: device [nvar][ny][nx],
+ * caller-owned, must not alias; dt as in wcns_rhs.  Calls no allocating
+ * routine: the first call on a device looks up the array's address once.
+ * Every call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (every value a call reads is written by that call first), so
+ * calls that overlap on one GPU (other streams, other threads) race.
+ * Asynchronous on `stream` (hipStream_t or NULL).  No admissibility report
+ * (there is no context to hold one).
+ * ---------------------------------------------------------------------- */
+#define WCNS_NOALLOC_SCRATCH_BYTES (64u << 20)
+wcns_status wcns_rhs_noalloc(const wcns_grid* grid, const wcns_eos* eos, const wcns_params* params,
+                             int32_t precision, void* stream, const double* W, double* dWdt,
+                             double dt);
 
 /* Human-readable status. */
 const char* wcns_status_str(wcns_status s);

@@ -112,6 +112,7 @@ const char* wcns_status_str(wcns_status s) {
     case WCNS_ERR_HIP: return "HIP runtime error";
     case WCNS_ERR_INADMISSIBLE: return "state outside the admissible set";
     case WCNS_ERR_CFL: return "invalid time step";
+    case WCNS_ERR_TOO_LARGE: return "grid too large for the allocation-free scratch";
   }
   return "unknown status";
 }
@@ -1675,3 +1676,6 @@ wcns_status wcns_batch_dt(wcns_batch* b, double* dt) {
 }
 
 }  // extern "C"
+
+// the allocation-free right-hand side (uses the set-up and launch sequences above)
+#include "wcns_noalloc.hpp"

@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libwcns.so")
 
 WCNS_OK = 0
 STATUS = {0: "ok", -1: "invalid argument", -2: "fluids violate Lemma 1", -3: "out of memory",
-          -4: "HIP error", -5: "inadmissible state", -6: "invalid time step"}
+          -4: "HIP error", -5: "inadmissible state", -6: "invalid time step",
+          -7: "grid too large for the allocation-free scratch"}
 WCNS_ERR_INADMISSIBLE = -5
 BC_PERIODIC, BC_EXTRAP, BC_REFLECT, BC_DIRICHLET = 0, 1, 2, 3
 FP64, FP32_BULK = 0, 1
@@ -81,7 +82,7 @@ EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_strea
            "wcns_batch_configure", "wcns_batch_step", "wcns_batch_rhs", "wcns_batch_sync",
            "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
            "wcns_batch_steps_left", "wcns_batch_violations", "wcns_prim_to_cons_n",
-           "wcns_status_str"]
+           "wcns_rhs_noalloc", "wcns_status_str"]
 PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other", "sweep_z"]
 
 
@@ -132,6 +133,8 @@ def lib():
         L.wcns_batch_steps_left.argtypes = [vp, C.POINTER(C.c_int32)]
         L.wcns_batch_violations.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32]
         L.wcns_prim_to_cons_n.argtypes = [C.POINTER(_Eos), C.c_int32, C.c_int64, dp, dp, vp]
+        L.wcns_rhs_noalloc.argtypes = [C.POINTER(_Grid), C.POINTER(_Eos), C.POINTER(_Params),
+                                       C.c_int32, vp, dp, dp, C.c_double]
         L.wcns_status_str.argtypes = [C.c_int]
         L.wcns_status_str.restype = C.c_char_p
         for name in EXPORTS:

@@ -38,8 +38,36 @@ def test_params_default_matches_paper():
 
 
 def test_status_strings():
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert wcns.lib().wcns_status_str(code)
+
+
+def test_noalloc_rhs_refuses_before_any_device_work():
+    """The allocation-free RHS validates like wcns_create and refuses a grid
+    past its static scratch (WCNS_ERR_TOO_LARGE) or with a Dirichlet side
+    before it touches a device."""
+    L = wcns.lib()
+    g = wcns._Grid()
+    g.ndim, g.nx, g.ny = 2, 2048, 2048
+    g.x0, g.x1, g.y0, g.y1 = 0.0, 1.0, 0.0, 1.0
+    for k in range(4):
+        g.bc[k] = 1
+    e = wcns._Eos()
+    e.gamma[0], e.gamma[1] = 6.12, 1.4
+    e.pinf[0], e.pinf[1] = 3.43e8, 0.0
+    p = wcns.default_params()
+    fake = C.c_void_p(0x1000)
+    assert L.wcns_rhs_noalloc(C.byref(g), C.byref(e), C.byref(p), 0, None, fake,
+                              C.c_void_p(0x2000), 0.0) == -7
+    g.nx, g.ny = 64, 64
+    g.bc[0] = 3
+    assert L.wcns_rhs_noalloc(C.byref(g), C.byref(e), C.byref(p), 0, None, fake,
+                              C.c_void_p(0x2000), 0.0) == -1
+    g.bc[0] = 1
+    e.gamma[0] = 1.2
+    assert L.wcns_rhs_noalloc(C.byref(g), C.byref(e), C.byref(p), 0, None, fake,
+                              C.c_void_p(0x2000), 0.0) == -2
+    assert L.wcns_rhs_noalloc(None, C.byref(e), C.byref(p), 0, None, fake, fake, 0.0) == -1
 
 
 def test_binding_has_no_method_arithmetic():
