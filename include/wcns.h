@@ -235,12 +235,13 @@ wcns_status wcns_check_admissible(wcns_ctx* ctx, const double* W, long long* n_b
  * the context launches is bracketed by a pair of HIP events recorded on the
  * context's stream; wcns_profile_read synchronises the stream and returns,
  * per kernel class, the summed device time in milliseconds and the number of
- * launches since the last reset.  Classes (WCNS_NPROF = 7): 0 node
+ * launches since the last reset.  Classes (WCNS_NPROF = 8): 0 node
  * primitives + wave-speed maxima, 1 dt/lambda finalize, 2 x-sweep,
- * 3 y-sweep, 4 tile fixups, 5 other, 6 z-sweep (3D).  `ms` and `launches`
+ * 3 y-sweep, 4 tile fixups, 5 other, 6 z-sweep (3D), 7 one-pass stage of the
+ * first-order scheme (2D).  `ms` and `launches`
  * hold WCNS_NPROF entries.  Enabling allocates the event pool (so it is not
  * graph-capturable); disabling releases it. */
-#define WCNS_NPROF 7
+#define WCNS_NPROF 8
 wcns_status wcns_profile(wcns_ctx* ctx, int32_t enable);
 wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
 

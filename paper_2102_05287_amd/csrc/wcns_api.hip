@@ -13,6 +13,7 @@
 #include "wcns_3d.hpp"
 #include "wcns_run1d.hpp"
 #include "wcns_probe.hpp"
+#include "wcns_fo.hpp"
 
 #include <algorithm>
 #include <vector>
@@ -54,6 +55,8 @@ struct wcns_ctx {
   double* run_G;
   Run1D* run_dev;
   int node_grid, tile_x, x_grid, nbr;
+  // first-order scheme in 2D: one pass per stage over (strip, row block) wave tasks
+  int fo, fo_nstrip, fo_ntask, fo_grid;
   int x_lds, xl_grid;   // x-sweep with LDS windows (rows of >= XLDS_MIN_NX cells), its grid
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
@@ -92,7 +95,8 @@ struct ProfScope {
     if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
   }
 };
-enum { PROF_NODE = 0, PROF_FIN = 1, PROF_X = 2, PROF_Y = 3, PROF_FIX = 4, PROF_OTHER = 5, PROF_Z = 6 };
+enum { PROF_NODE = 0, PROF_FIN = 1, PROF_X = 2, PROF_Y = 3, PROF_FIX = 4, PROF_OTHER = 5, PROF_Z = 6,
+       PROF_FO = 7 };
 
 #define HIP_TRY(x)                                   \
   do {                                               \
@@ -295,6 +299,13 @@ static void ctx_setup(wcns_ctx* c, const wcns_grid* g, const wcns_eos* eos, cons
   c->node_grid = (int)(ng < NODE_GRID_CAP ? ng : NODE_GRID_CAP);
   c->nbr = (g->ny + 1 + Y_ROWS - 1) / Y_ROWS;
   a.nbr = c->nbr;
+  c->fo = g->ndim == 2 && prm->scheme == WCNS_SCHEME_HLLC1;
+  if (c->fo) {
+    c->fo_nstrip = (g->nx + FO_LANES - 1) / FO_LANES;
+    c->fo_ntask = c->fo_nstrip * ((g->ny + FO_ROWS - 1) / FO_ROWS);
+    const int blocks = (c->fo_ntask + FO_WAVES - 1) / FO_WAVES;
+    c->fo_grid = (blocks + 7) / 8 * 8;   // the task deal needs a multiple of 8 blocks
+  }
 }
 
 wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_params* prm,
@@ -331,7 +342,8 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
     c->nfused = (int)(nyb + nfb);
     alloc(&c->P2, 5 * (size_t)c->N);
   }
-  alloc(&c->partial, 2 * (size_t)(c->nfused > c->node_grid ? c->nfused : c->node_grid));
+  const int npart = std::max(std::max(c->nfused, c->node_grid), c->fo_ntask);
+  alloc(&c->partial, 2 * (size_t)npart);
   alloc(&c->step, 8);
   if (g->ndim == 1 && g->nx <= RUN1D_MAX_CELLS) {
     alloc(&c->run_G, 12 * ((size_t)g->nx + 1));
@@ -804,6 +816,9 @@ wcns_status wcns_prim_to_cons(wcns_ctx* c, const double* V, double* W) {
   return WCNS_OK;
 }
 
+static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode, const double* Un,
+                             double ca, double cb, bool maxima);
+
 wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
   if (!c || !W || !dWdt || W == dWdt) return WCNS_ERR_ARG;
   if (!(dt >= 0.0) || !isfinite(dt)) return WCNS_ERR_CFL;
@@ -815,7 +830,56 @@ wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
   }
   wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr);
   if (s != WCNS_OK) return s;
+  if (c->fo) return launch_fo(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0, false);
   return launch_sweeps(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
+}
+
+// one pass of the first-order scheme over state W into `out` (mode STORE:
+// L; RK: next stage); maxima: the stage result's wave-speed maxima to
+// c->partial (fo_ntask pairs) for the next step's finalize
+static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode, const double* Un,
+                             double ca, double cb, bool maxima) {
+  KArgs a = c->base;
+  a.W = W;
+  a.out = out;
+  a.Un = Un;
+  a.ca = ca;
+  a.cb = cb;
+  a.out_mode = mode;
+  set_bases(c, a, W, c->P);
+  a.partn = maxima ? c->partial : nullptr;
+  ProfScope ps(c, PROF_FO);
+  if (diri(c, 0) || diri(c, 1))
+    hipLaunchKernelGGL(k_fo_stage<true>, dim3(c->fo_grid), dim3(64 * FO_WAVES), 0, c->stream, a,
+                       c->fo_nstrip, c->fo_ntask);
+  else
+    hipLaunchKernelGGL(k_fo_stage<false>, dim3(c->fo_grid), dim3(64 * FO_WAVES), 0, c->stream, a,
+                       c->fo_nstrip, c->fo_ntask);
+  LAUNCH_CHECK();
+  return WCNS_OK;
+}
+
+// n steps of the first-order scheme in 2D: per step one finalize (dt from
+// the maxima of U^n: k_node's for the first step of a call, then those the
+// previous step's last stage reduced; the scheme uses no lambda, so stages
+// 2 and 3 keep the step record) and one pass per stage.
+static wcns_status steps_fo(wcns_ctx* c, double* W, int n, double dt, double* dts, const Clock* clk) {
+  const double* in[3] = {W, c->U1, c->U2};
+  double* outs[3] = {c->U1, c->U2, W};
+  const double ca[3] = {0.0, 0.75, 1.0 / 3.0};
+  const double cb[3] = {1.0, 0.25, 2.0 / 3.0};
+  const int mode = dt > 0.0 ? DT_GIVEN : DT_CFL;
+  for (int k = 0; k < n; ++k) {
+    double* dt_used = dts ? dts + k : nullptr;
+    wcns_status st = k == 0 ? launch_node_finalize(c, W, mode, dt, dt_used, c->P, false, true, clk)
+                            : launch_finalize(c, c->fo_ntask, mode, dt, dt_used, clk);
+    if (st != WCNS_OK) return st;
+    for (int s = 0; s < 3; ++s) {
+      st = launch_fo(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s], s == 2 && k < n - 1);
+      if (st != WCNS_OK) return st;
+    }
+  }
+  return WCNS_OK;
 }
 
 // n SSP-RK3 steps of W in place (Shu-Osher form).  In 2D the node
@@ -827,6 +891,7 @@ wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
 // once, and so do all later ones of the call, since the clock stays put).
 static wcns_status steps_impl(wcns_ctx* c, double* W, int n, double dt, double* dts,
                               const Clock* clk = nullptr) {
+  if (c->fo) return steps_fo(c, W, n, dt, dts, clk);
   const double* in[3] = {W, c->U1, c->U2};
   double* outs[3] = {c->U1, c->U2, W};
   const double ca[3] = {0.0, 0.75, 1.0 / 3.0};

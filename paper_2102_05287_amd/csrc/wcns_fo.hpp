@@ -1,0 +1,209 @@
+// First-order HLLC scheme (the paper's comparison scheme, Sec. 3; theta = 0
+// in both limiters) as one pass per SSP-RK3 stage in 2D.
+//
+// The mode needs only the face HLLC flux of the two cells next to a face,
+// so a stage is memory-bound: it reads U^(s) (and U^n) and writes U^(s+1),
+// 96 or 144 B per cell.  One wave owns a strip of 62 columns (lanes 1..62;
+// lanes 0 and 63 hold the halo columns) and marches down R rows of it plus
+// a halo row above and below, keeping two rows of node values in registers:
+// per row it loads the six state components, recovers the primitives
+// (Sec. 2), computes the x-face fluxes of the row (the right neighbour's
+// node by a lane shuffle) and the y-face flux between the previous row and
+// this one, which finishes the previous row's cells: L = L_x + L_y and the
+// stage combination, the same arithmetic in the same order as the two-pass
+// kernels (x-sweep L_x, y-sweep L_x + L_y), so the results are those of the
+// oracle bit for bit.  Nothing but the stage result goes to memory: no node
+// primitives, no L_x, no tile edges.  At the last stage of a step that is
+// followed by another, each wave also reduces the wave speeds |u|+c, |v|+c
+// of its finished cells (Sec. 3.3) for the next step's time step.
+//
+// Wave tasks are dealt so that the row blocks of a strip run on one XCD
+// (block b runs on XCD b % 8): a block's halo rows are its neighbours' edge
+// rows and are then found in that XCD's L2.
+#pragma once
+#include "wcns_kernels.hpp"
+
+#pragma clang fp contract(off)
+
+namespace wcns {
+
+constexpr int FO_LANES = 62;     // owned columns per wave
+constexpr int FO_WAVES = 4;      // waves per block
+constexpr int FO_ROWS = 8;       // rows per wave task
+// (three waves per SIMD: 156 VGPRs without spills; a four-wave budget of
+// 128 spills 108-224 B per lane)
+
+// Node of (column c in -1..nx, row g in -1..ny): its state (ghosts mapped
+// as in the sweeps, reflective ones with the wall-normal momentum negated;
+// corner ghosts, which no face uses, are clamped) and primitives.
+template <bool DIRI>
+__device__ __forceinline__ void fo_node(const KArgs& a, int c, int g, NodeQ& q) {
+  bool fx, fy;
+  int sx = ghost_src(c, a.nx, a.bc[0], a.bc[1], fx);
+  int sy = ghost_src(g, a.ny, a.bc[2], a.bc[3], fy);
+  double X[6];
+  if (DIRI && sx < 0 && sy >= 0) {
+    const double* d = a.dirW + (a.dir_off[c < 0 ? 0 : 1] + sy) * 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = d[k];
+  } else if (DIRI && sy < 0 && sx >= 0) {
+    const double* d = a.dirW + (a.dir_off[g < 0 ? 2 : 3] + sx) * 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = d[k];
+  } else {
+    if (sx < 0) sx = c < 0 ? 0 : a.nx - 1;   // corner ghost of a Dirichlet side: unused
+    if (sy < 0) sy = g < 0 ? 0 : a.ny - 1;
+    const uint32_t o = ((uint32_t)sy * (uint32_t)a.nx + (uint32_t)sx) * 8u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[k] = ldc(a.Wc[k], o);
+  }
+  if (fx) X[2] = -X[2];
+  if (fy) X[3] = -X[3];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) q.w[k] = X[k];
+  recover<true>(a.eos, X, q.un, q.ut, q.p, q.c, q.h);
+}
+
+// the node in the y frame (normal momentum rho v)
+__device__ __forceinline__ NodeQ fo_yframe(const NodeQ& q) {
+  NodeQ r = q;
+  r.w[2] = q.w[3];
+  r.w[3] = q.w[2];
+  r.un = q.ut;
+  r.ut = q.un;
+  return r;
+}
+
+// split first-order HLLC fluxes H^- (alpha of the left cell), H^+ [Sec. 3.2]
+__device__ __forceinline__ void fo_face(const NodeQ& l, const NodeQ& r, double Hm[6], double Hp[6]) {
+  HllcOut h;
+  hllc<true>(l, r, h);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) { Hm[v] = h.F[v]; Hp[v] = h.F[v]; }
+  Hm[5] = h.fa - l.w[5] * h.ss;
+  Hp[5] = h.fa - r.w[5] * h.ss;
+}
+
+__device__ __forceinline__ NodeQ shfl_node(const NodeQ& q, int src) {
+  NodeQ r;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) r.w[k] = __shfl(q.w[k], src, 64);
+  r.un = __shfl(q.un, src, 64);
+  r.ut = __shfl(q.ut, src, 64);
+  r.p = __shfl(q.p, src, 64);
+  r.c = __shfl(q.c, src, 64);
+  r.h = 0.0;
+  return r;
+}
+
+// Cells of a wave outside G (nbad per lane) added to *viol, flag raised.
+__device__ __forceinline__ void report_count(unsigned long long* viol, int32_t* vflag, int nbad) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) nbad += __shfl_xor(nbad, off, 64);
+  if ((threadIdx.x & 63) == 0 && nbad > 0) {
+    atomicAdd(viol, (unsigned long long)nbad);
+    if (vflag) __hip_atomic_store(vflag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+// One RK stage (or, out_mode OUT_STORE, the RHS) of the first-order scheme
+// over waves of (strip, row block) tasks: strip = t % nstrip, rows
+// FO_ROWS * (t / nstrip) onward.  The grid is a multiple of 8 blocks.  With
+// a.partn set, the stage result's wave-speed maxima of wave t go to
+// a.partn[2t], [2t+1].
+template <bool DIRI>
+__global__ __launch_bounds__(64 * FO_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_fo_stage(KArgs a, int nstrip, int ntask) {
+  if (a.step[STEP_SKIP] != 0.0) return;
+  const int R = FO_ROWS;
+  const int lane = threadIdx.x & 63;
+  // task of this wave: block b runs on XCD b % 8, so block rank
+  // (b % 8) * per + b / 8 gives each XCD a contiguous range of tasks
+  const int per = (int)gridDim.x / 8;
+  const int b = blockIdx.x;
+  const int bq = (b % 8) * per + b / 8;
+  const int t = bq * FO_WAVES + (int)(threadIdx.x >> 6);
+  const bool on = t < ntask;
+  const int strip = on ? t % nstrip : 0;
+  const int rb = on ? t / nstrip : 0;
+  const int nx = a.nx, ny = a.ny;
+  const long N = (long)nx * ny;
+  const int c = strip * FO_LANES - 1 + lane;          // column of this lane (-1 .. )
+  const int cc = c <= nx ? c : nx;                    // lanes past the halo repeat it
+  const int j0 = rb * R;
+  const int g1 = on ? (j0 + R < ny ? j0 + R : ny) : j0 - 1;   // last node row
+  const bool owner = on && lane >= 1 && lane <= FO_LANES && c < nx;
+  const double dt = a.step[0];
+  const bool rk = a.out_mode == OUT_RK;
+  const bool check = a.viol && rk;
+  double mx = 0.0, my = 0.0;
+  int nbad = 0;
+
+  // per lane, kept in LDS between rows (fewer live registers): L_x of the
+  // previous row and G^+ of its lower y-face
+  __shared__ double keep[FO_WAVES][2][6][64];
+  double (*Lx_prev)[64] = keep[threadIdx.x >> 6][0];
+  double (*Gp_prev)[64] = keep[threadIdx.x >> 6][1];
+  NodeQ prev;
+  fo_node<DIRI>(a, cc, j0 - 1, prev);
+  for (int g = j0; g <= g1; ++g) {
+    NodeQ cur;
+    fo_node<DIRI>(a, cc, g, cur);
+    // y-face between rows g-1 and g: its G^- finishes the cells of row g-1
+    double Gm[6], Gp[6];
+    fo_face(fo_yframe(prev), fo_yframe(cur), Gm, Gp);
+    if (owner && g - 1 >= j0) {
+      const long idx = (long)(g - 1) * nx + c;
+      double un[6];
+      if (rk) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) un[k] = a.Un[k * N + idx];
+      }
+      double X[6];
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        const int s = state_index(1, v, true);
+        const double Ly = hdiv(-(Gm[v] - Gp_prev[v][lane]), a.dy, a.rdy);
+        const double L = Lx_prev[s][lane] + Ly;
+        X[s] = rk ? a.ca * un[s] + a.cb * (prev.w[s] + dt * L) : L;
+      }
+#pragma unroll
+      for (int s = 0; s < 6; ++s) a.out[s * N + idx] = X[s];
+      if (a.partn) {
+        double u, v, p, cs, h;
+        recover<true>(a.eos, X, u, v, p, cs, h);
+        mx = fmax(mx, fabs(u) + cs);
+        my = fmax(my, fabs(v) + cs);
+        nbad += admissible(X[0], X[1], X[5], h) ? 0 : 1;
+      } else if (check) {
+        nbad += stage_ok(a, X) ? 0 : 1;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 6; ++v) Gp_prev[v][lane] = Gp[v];
+    // x-faces of row g (an interior row of this block): lane L holds face
+    // c + 1/2 (right neighbour by shuffle); cell c takes G^+ of face c - 1/2
+    // from lane L - 1
+    if (g < j0 + R && g < ny) {
+      const NodeQ right = shfl_node(cur, (lane + 1) & 63);
+      double Hm[6], Hp[6];
+      fo_face(cur, right, Hm, Hp);
+#pragma unroll
+      for (int v = 0; v < 6; ++v) {
+        const double gl = __shfl(Hp[v], (lane + 63) & 63, 64);
+        Lx_prev[v][lane] = hdiv(-(Hm[v] - gl), a.dx, a.rdx);   // x frame = state order
+      }
+    }
+    prev = cur;
+  }
+  if (check) report_count(a.viol, a.vflag, nbad);
+  if (a.partn) {
+    mx = wave_max(mx);
+    my = wave_max(my);
+    if (on && lane == 0) {
+      a.partn[2 * t] = mx;
+      a.partn[2 * t + 1] = my;
+    }
+  }
+}
+
+}  // namespace wcns
