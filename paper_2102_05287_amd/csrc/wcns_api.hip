@@ -56,7 +56,7 @@ struct wcns_ctx {
   Run1D* run_dev;
   int node_grid, tile_x, x_grid, nbr;
   // first-order scheme in 2D: one pass per stage over (strip, row block) wave tasks
-  int fo, fo_nstrip, fo_ntask, fo_grid;
+  int fo, fo_nstrip, fo_nrb, fo_ntask, fo_grid;
   int x_lds, xl_grid;   // x-sweep with LDS windows (rows of >= XLDS_MIN_NX cells), its grid
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
@@ -301,8 +301,17 @@ static void ctx_setup(wcns_ctx* c, const wcns_grid* g, const wcns_eos* eos, cons
   a.nbr = c->nbr;
   c->fo = g->ndim == 2 && prm->scheme == WCNS_SCHEME_HLLC1;
   if (c->fo) {
+    // as many (strip, row block) waves as the GPU holds at once
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+      ncu = 256;
+    const long slots = 4L * FO_WPE * ncu;
     c->fo_nstrip = (g->nx + FO_LANES - 1) / FO_LANES;
-    c->fo_ntask = c->fo_nstrip * ((g->ny + FO_ROWS - 1) / FO_ROWS);
+    const long nrb = slots / c->fo_nstrip;   // never past the slots: a partial second round
+                                             // of waves would double the pass
+    c->fo_nrb = (int)std::max(1L, std::min(nrb, (long)g->ny));
+    c->fo_ntask = c->fo_nstrip * c->fo_nrb;
     const int blocks = (c->fo_ntask + FO_WAVES - 1) / FO_WAVES;
     c->fo_grid = (blocks + 7) / 8 * 8;   // the task deal needs a multiple of 8 blocks
   }
@@ -817,7 +826,7 @@ wcns_status wcns_prim_to_cons(wcns_ctx* c, const double* V, double* W) {
 }
 
 static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode, const double* Un,
-                             double ca, double cb, bool maxima);
+                             double ca, double cb, bool maxima, bool check_out);
 
 wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
   if (!c || !W || !dWdt || W == dWdt) return WCNS_ERR_ARG;
@@ -828,18 +837,22 @@ wcns_status wcns_rhs(wcns_ctx* c, const double* W, double* dWdt, double dt) {
     if (s != WCNS_OK) return s;
     return launch_sweeps3(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
   }
-  wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr);
+  // (the first-order pass checks its input itself)
+  wcns_status s = launch_node_finalize(c, W, DT_GIVEN, dt, nullptr, nullptr, false, !c->fo);
   if (s != WCNS_OK) return s;
-  if (c->fo) return launch_fo(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0, false);
+  if (c->fo) return launch_fo(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0, false, false);
   return launch_sweeps(c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
 }
 
 // one pass of the first-order scheme over state W into `out` (mode STORE:
 // L; RK: next stage); maxima: the stage result's wave-speed maxima to
-// c->partial (fo_ntask pairs) for the next step's finalize
+// c->partial (fo_ntask pairs) for the next step's finalize; the pass checks
+// its input cells and, with check_out (the last stage of a call), its result
 static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode, const double* Un,
-                             double ca, double cb, bool maxima) {
+                             double ca, double cb, bool maxima, bool check_out) {
   KArgs a = c->base;
+  a.check_in = 1;
+  a.check_out = check_out ? 1 : 0;
   a.W = W;
   a.out = out;
   a.Un = Un;
@@ -851,10 +864,10 @@ static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode
   ProfScope ps(c, PROF_FO);
   if (diri(c, 0) || diri(c, 1))
     hipLaunchKernelGGL(k_fo_stage<true>, dim3(c->fo_grid), dim3(64 * FO_WAVES), 0, c->stream, a,
-                       c->fo_nstrip, c->fo_ntask);
+                       c->fo_nstrip, c->fo_nrb, c->fo_ntask);
   else
     hipLaunchKernelGGL(k_fo_stage<false>, dim3(c->fo_grid), dim3(64 * FO_WAVES), 0, c->stream, a,
-                       c->fo_nstrip, c->fo_ntask);
+                       c->fo_nstrip, c->fo_nrb, c->fo_ntask);
   LAUNCH_CHECK();
   return WCNS_OK;
 }
@@ -871,11 +884,12 @@ static wcns_status steps_fo(wcns_ctx* c, double* W, int n, double dt, double* dt
   const int mode = dt > 0.0 ? DT_GIVEN : DT_CFL;
   for (int k = 0; k < n; ++k) {
     double* dt_used = dts ? dts + k : nullptr;
-    wcns_status st = k == 0 ? launch_node_finalize(c, W, mode, dt, dt_used, c->P, false, true, clk)
+    wcns_status st = k == 0 ? launch_node_finalize(c, W, mode, dt, dt_used, c->P, false, false, clk)
                             : launch_finalize(c, c->fo_ntask, mode, dt, dt_used, clk);
     if (st != WCNS_OK) return st;
     for (int s = 0; s < 3; ++s) {
-      st = launch_fo(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s], s == 2 && k < n - 1);
+      const bool last = k == n - 1 && s == 2;
+      st = launch_fo(c, in[s], outs[s], OUT_RK, W, ca[s], cb[s], s == 2 && !last, last);
       if (st != WCNS_OK) return st;
     }
   }

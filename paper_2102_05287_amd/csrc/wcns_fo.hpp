@@ -4,9 +4,10 @@
 // The mode needs only the face HLLC flux of the two cells next to a face,
 // so a stage is memory-bound: it reads U^(s) (and U^n) and writes U^(s+1),
 // 96 or 144 B per cell.  One wave owns a strip of 62 columns (lanes 1..62;
-// lanes 0 and 63 hold the halo columns) and marches down R rows of it plus
-// a halo row above and below, keeping two rows of node values in registers:
-// per row it loads the six state components, recovers the primitives
+// lanes 0 and 63 hold the halo columns) and marches down a block of rows of
+// it plus a halo row above and below, keeping two rows of node values in
+// registers and the next row's state in flight: per row it recovers the
+// primitives
 // (Sec. 2), computes the x-face fluxes of the row (the right neighbour's
 // node by a lane shuffle) and the y-face flux between the previous row and
 // this one, which finishes the previous row's cells: L = L_x + L_y and the
@@ -17,9 +18,11 @@
 // followed by another, each wave also reduces the wave speeds |u|+c, |v|+c
 // of its finished cells (Sec. 3.3) for the next step's time step.
 //
-// Wave tasks are dealt so that the row blocks of a strip run on one XCD
-// (block b runs on XCD b % 8): a block's halo rows are its neighbours' edge
-// rows and are then found in that XCD's L2.
+// The rows of a strip are split into nrb near-equal blocks so that the grid
+// has about as many waves as the GPU holds at once (three per SIMD): one
+// round, no tail.  Wave tasks are dealt so that the row blocks of a strip
+// run on one XCD (block b runs on XCD b % 8): a block's halo rows are its
+// neighbours' edge rows and are then found in that XCD's L2.
 #pragma once
 #include "wcns_kernels.hpp"
 
@@ -29,21 +32,27 @@ namespace wcns {
 
 constexpr int FO_LANES = 62;     // owned columns per wave
 constexpr int FO_WAVES = 4;      // waves per block
-constexpr int FO_ROWS = 8;       // rows per wave task
-// (three waves per SIMD: 156 VGPRs without spills; a four-wave budget of
-// 128 spills 108-224 B per lane)
+constexpr int FO_WPE = 3;        // waves per SIMD the kernel is compiled for
+// (a four-wave budget of 128 VGPRs spills 108-224 B per lane)
 
-// Node of (column c in -1..nx, row g in -1..ny): its state (ghosts mapped
-// as in the sweeps, reflective ones with the wall-normal momentum negated;
-// corner ghosts, which no face uses, are clamped) and primitives.
+// Column of a lane: its source column sx after the x ghost mapping (-1: an
+// x-side Dirichlet ghost) and whether the wall-normal momentum flips.
+struct FoCol {
+  int c, sx;
+  bool fx;
+};
+
+// State of node (column col.c in -1..nx, row g in -1..ny): ghosts mapped as
+// in the sweeps, reflective ones with the wall-normal momentum negated;
+// corner ghosts, which no face uses, are clamped.  (Only rows -1 and ny
+// need the y mapping.)
 template <bool DIRI>
-__device__ __forceinline__ void fo_node(const KArgs& a, int c, int g, NodeQ& q) {
-  bool fx, fy;
-  int sx = ghost_src(c, a.nx, a.bc[0], a.bc[1], fx);
-  int sy = ghost_src(g, a.ny, a.bc[2], a.bc[3], fy);
-  double X[6];
+__device__ __forceinline__ void fo_load(const KArgs& a, const FoCol& col, int g, double X[6]) {
+  int sx = col.sx, sy = g;
+  bool fy = false;
+  if (g < 0 || g >= a.ny) sy = ghost_src(g, a.ny, a.bc[2], a.bc[3], fy);
   if (DIRI && sx < 0 && sy >= 0) {
-    const double* d = a.dirW + (a.dir_off[c < 0 ? 0 : 1] + sy) * 6;
+    const double* d = a.dirW + (a.dir_off[col.c < 0 ? 0 : 1] + sy) * 6;
 #pragma unroll
     for (int k = 0; k < 6; ++k) X[k] = d[k];
   } else if (DIRI && sy < 0 && sx >= 0) {
@@ -51,14 +60,18 @@ __device__ __forceinline__ void fo_node(const KArgs& a, int c, int g, NodeQ& q) 
 #pragma unroll
     for (int k = 0; k < 6; ++k) X[k] = d[k];
   } else {
-    if (sx < 0) sx = c < 0 ? 0 : a.nx - 1;   // corner ghost of a Dirichlet side: unused
+    if (sx < 0) sx = col.c < 0 ? 0 : a.nx - 1;   // corner ghost of a Dirichlet side: unused
     if (sy < 0) sy = g < 0 ? 0 : a.ny - 1;
     const uint32_t o = ((uint32_t)sy * (uint32_t)a.nx + (uint32_t)sx) * 8u;
 #pragma unroll
     for (int k = 0; k < 6; ++k) X[k] = ldc(a.Wc[k], o);
   }
-  if (fx) X[2] = -X[2];
+  if (col.fx) X[2] = -X[2];
   if (fy) X[3] = -X[3];
+}
+
+// the node of a loaded state: the state and its primitives [Sec. 2]
+__device__ __forceinline__ void fo_node(const KArgs& a, const double X[6], NodeQ& q) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) q.w[k] = X[k];
   recover<true>(a.eos, X, q.un, q.ut, q.p, q.c, q.h);
@@ -107,14 +120,14 @@ __device__ __forceinline__ void report_count(unsigned long long* viol, int32_t* 
 }
 
 // One RK stage (or, out_mode OUT_STORE, the RHS) of the first-order scheme
-// over waves of (strip, row block) tasks: strip = t % nstrip, rows
-// FO_ROWS * (t / nstrip) onward.  The grid is a multiple of 8 blocks.  With
-// a.partn set, the stage result's wave-speed maxima of wave t go to
-// a.partn[2t], [2t+1].
+// over waves of (strip, row block) tasks: strip = t % nstrip, row block
+// rb = t / nstrip of nrb covering rows [rb ny / nrb, (rb + 1) ny / nrb).
+// The grid is a multiple of 8 blocks.  With a.partn set, the stage result's
+// wave-speed maxima of wave t go to a.partn[2t], [2t+1].
 template <bool DIRI>
-__global__ __launch_bounds__(64 * FO_WAVES) __attribute__((amdgpu_waves_per_eu(3))) void k_fo_stage(KArgs a, int nstrip, int ntask) {
+__global__ __launch_bounds__(64 * FO_WAVES) __attribute__((amdgpu_waves_per_eu(FO_WPE))) void k_fo_stage(
+    KArgs a, int nstrip, int nrb, int ntask) {
   if (a.step[STEP_SKIP] != 0.0) return;
-  const int R = FO_ROWS;
   const int lane = threadIdx.x & 63;
   // task of this wave: block b runs on XCD b % 8, so block rank
   // (b % 8) * per + b / 8 gives each XCD a contiguous range of tasks
@@ -129,12 +142,17 @@ __global__ __launch_bounds__(64 * FO_WAVES) __attribute__((amdgpu_waves_per_eu(3
   const long N = (long)nx * ny;
   const int c = strip * FO_LANES - 1 + lane;          // column of this lane (-1 .. )
   const int cc = c <= nx ? c : nx;                    // lanes past the halo repeat it
-  const int j0 = rb * R;
-  const int g1 = on ? (j0 + R < ny ? j0 + R : ny) : j0 - 1;   // last node row
+  const int j0 = (int)((long)rb * ny / nrb);
+  const int j1 = (int)((long)(rb + 1) * ny / nrb);    // first row of the next block
+  const int g1 = on ? j1 : j0 - 1;                    // last node row
   const bool owner = on && lane >= 1 && lane <= FO_LANES && c < nx;
   const double dt = a.step[0];
   const bool rk = a.out_mode == OUT_RK;
-  const bool check = a.viol && rk;
+  const bool use_un = rk && a.ca != 0.0;   // stage 1 (ca = 0) needs no U^n: U^(1) = U^n + dt L
+  // admissibility: the stage's input cells (every stage result of a call
+  // is the next stage's input) and, with check_out, its result
+  const bool check_in = a.viol && a.check_in;
+  const bool check_out = a.viol && a.check_out && rk;
   double mx = 0.0, my = 0.0;
   int nbad = 0;
 
@@ -143,28 +161,39 @@ __global__ __launch_bounds__(64 * FO_WAVES) __attribute__((amdgpu_waves_per_eu(3
   __shared__ double keep[FO_WAVES][2][6][64];
   double (*Lx_prev)[64] = keep[threadIdx.x >> 6][0];
   double (*Gp_prev)[64] = keep[threadIdx.x >> 6][1];
+  FoCol col;
+  col.c = cc;
+  col.sx = ghost_src(cc, nx, a.bc[0], a.bc[1], col.fx);
   NodeQ prev;
-  fo_node<DIRI>(a, cc, j0 - 1, prev);
+  double X0[6], Xn[6];
+  fo_load<DIRI>(a, col, j0 - 1, X0);
+  fo_load<DIRI>(a, col, j0, Xn);
+  fo_node(a, X0, prev);
   for (int g = j0; g <= g1; ++g) {
     NodeQ cur;
-    fo_node<DIRI>(a, cc, g, cur);
+    fo_node(a, Xn, cur);
+    // the next row's state and the finished row's U^n are loaded while
+    // this row's primitives and y-face are computed
+    if (g < g1) fo_load<DIRI>(a, col, g + 1, Xn);
+    const bool fin = owner && g - 1 >= j0;
+    const long idx = (long)(g - 1) * nx + c;
+    double un[6];
+    if (use_un && fin) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) un[k] = a.Un[k * N + idx];
+    }
     // y-face between rows g-1 and g: its G^- finishes the cells of row g-1
     double Gm[6], Gp[6];
     fo_face(fo_yframe(prev), fo_yframe(cur), Gm, Gp);
-    if (owner && g - 1 >= j0) {
-      const long idx = (long)(g - 1) * nx + c;
-      double un[6];
-      if (rk) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) un[k] = a.Un[k * N + idx];
-      }
+    if (fin) {
       double X[6];
 #pragma unroll
       for (int v = 0; v < 6; ++v) {
         const int s = state_index(1, v, true);
         const double Ly = hdiv(-(Gm[v] - Gp_prev[v][lane]), a.dy, a.rdy);
         const double L = Lx_prev[s][lane] + Ly;
-        X[s] = rk ? a.ca * un[s] + a.cb * (prev.w[s] + dt * L) : L;
+        X[s] = !rk ? L : (use_un ? a.ca * un[s] + a.cb * (prev.w[s] + dt * L)
+                                 : a.cb * (prev.w[s] + dt * L));
       }
 #pragma unroll
       for (int s = 0; s < 6; ++s) a.out[s * N + idx] = X[s];
@@ -173,17 +202,16 @@ __global__ __launch_bounds__(64 * FO_WAVES) __attribute__((amdgpu_waves_per_eu(3
         recover<true>(a.eos, X, u, v, p, cs, h);
         mx = fmax(mx, fabs(u) + cs);
         my = fmax(my, fabs(v) + cs);
-        nbad += admissible(X[0], X[1], X[5], h) ? 0 : 1;
-      } else if (check) {
-        nbad += stage_ok(a, X) ? 0 : 1;
       }
+      if (check_out) nbad += stage_ok(a, X) ? 0 : 1;
     }
 #pragma unroll
     for (int v = 0; v < 6; ++v) Gp_prev[v][lane] = Gp[v];
     // x-faces of row g (an interior row of this block): lane L holds face
     // c + 1/2 (right neighbour by shuffle); cell c takes G^+ of face c - 1/2
     // from lane L - 1
-    if (g < j0 + R && g < ny) {
+    if (g < j1) {
+      if (check_in && owner) nbad += admissible(cur.w[0], cur.w[1], cur.w[5], cur.h) ? 0 : 1;
       const NodeQ right = shfl_node(cur, (lane + 1) & 63);
       double Hm[6], Hp[6];
       fo_face(cur, right, Hm, Hp);
@@ -195,7 +223,7 @@ __global__ __launch_bounds__(64 * FO_WAVES) __attribute__((amdgpu_waves_per_eu(3
     }
     prev = cur;
   }
-  if (check) report_count(a.viol, a.vflag, nbad);
+  if (check_in || check_out) report_count(a.viol, a.vflag, nbad);
   if (a.partn) {
     mx = wave_max(mx);
     my = wave_max(my);

@@ -86,7 +86,8 @@ struct KArgs {
   // (y-sweep blocks first, the fixup's from fuse_off on)
   double* Pn;
   double* partn;
-  int32_t fuse_off, pad5;
+  int32_t fuse_off;
+  int32_t check_out;     // one-pass first-order stage: also check its result
   // Lazy admissibility report [Sec. 2]: stage results outside G (and, with
   // check_in, k_node's input cells) are counted into *viol (null: not
   // counted) and raise the host-mapped flag *vflag (null: none).

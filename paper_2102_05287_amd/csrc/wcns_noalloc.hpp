@@ -61,7 +61,7 @@ extern "C" wcns_status wcns_rhs_noalloc(const wcns_grid* g, const wcns_eos* eos,
   c.base.step = c.step;
   st = launch_node_finalize(&c, W, DT_GIVEN, dt, nullptr);
   if (st != WCNS_OK) return st;
-  if (c.fo) return launch_fo(&c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0, false);
+  if (c.fo) return launch_fo(&c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0, false, false);
   return launch_sweeps(&c, W, dWdt, OUT_STORE, nullptr, 0.0, 0.0);
 }
 

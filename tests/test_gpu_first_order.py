@@ -1,6 +1,6 @@
 """The first-order HLLC scheme (the paper's comparison scheme, Sec. 3) in 2D
 runs as one pass per SSP-RK3 stage (k_fo_stage: 62-column strips marching
-down 8-row blocks).  Its results must be the oracle's bit for bit: grids
+down row blocks sized so the grid fills the GPU once).  Its results must be the oracle's bit for bit: grids
 whose width and height leave ragged last strips and row blocks, single
 rows and columns, every side kind (periodic, extrapolated, reflective,
 per-row Dirichlet), RHS calls, multi-step calls (the wave-speed maxima of a
@@ -48,10 +48,16 @@ def _cases():
     diri.bc = (pb.BC_DIRICHLET, pb.BC_EXTRAP, pb.BC_REFLECT, pb.BC_DIRICHLET)
     diri.dirichlet_prim = [_rows(rng, 27), None, None, _rows(rng, 93)]
     out.append(diri)
+    # several rows per wave task (the row blocks are sized to the GPU)
+    out.append(pb.random_smooth_state(600, 700, 13))
+    big = pb.random_smooth_state(1000, 500, 14)
+    big.bc = (pb.BC_DIRICHLET, pb.BC_EXTRAP, pb.BC_REFLECT, pb.BC_REFLECT)
+    big.dirichlet_prim = [_rows(rng, 500), None, None, None]
+    out.append(big)
     return out
 
 
-@pytest.mark.parametrize("k", range(11))
+@pytest.mark.parametrize("k", range(13))
 def test_first_order_pass_rhs_and_steps_equal_the_oracle(k):
     spec = _cases()[k]
     print(f"  first order {spec.nx}x{spec.ny} bc {spec.bc}", flush=True)
