@@ -326,10 +326,9 @@ def serving_form(n_req=2000, rate=200.0, budget_gib=64, chunk=20):
 def serving_rate_sweep(n_req=300, rates=(8.0, 12.0, 16.0, 20.0, 28.0), budget_gib=64, chunk=20):
     """The first n_req requests of the seed-4 trace (the same solves at every
     rate) replayed at several Poisson arrival rates: completion rate and
-    latency against offered rate.  A rate is sustained when the server
-    completes at least 95% of it and its p99 latency stays within 3x the p99
-    at the lowest rate (latency bounded, not growing with a queue); the
-    sustainable rate is the highest such rate."""
+    latency against offered rate.  A rate is sustained while latency stays
+    bounded (p50 within 2x and p99 within 3x their values at the lowest
+    rate); the sustainable rate is the highest such rate."""
     from paper_2102_05287_amd import problems as pb
     from paper_2102_05287_amd import serve
     rows = []
@@ -346,14 +345,14 @@ def serving_rate_sweep(n_req=300, rates=(8.0, 12.0, 16.0, 20.0, 28.0), budget_gi
                      "mcell_updates_per_s": sm["mcell_updates_per_s"]})
         print(f"#   rate {r}: {sm['solves_per_s']:.1f} solves/s, p50 {sm['latency_p50_s']:.2f} s, "
               f"p99 {sm['latency_p99_s']:.2f} s", flush=True)
-    base = rows[0]["latency_p99_s"]
+    p50, p99 = rows[0]["latency_p50_s"], rows[0]["latency_p99_s"]
     for row in rows:
-        row["sustained"] = bool(row["solves_per_s"] >= 0.95 * row["offered_req_per_s"]
-                                and row["latency_p99_s"] <= 3.0 * base)
+        row["sustained"] = bool(row["latency_p50_s"] <= 2.0 * p50 and row["latency_p99_s"] <= 3.0 * p99)
     ok = [row["rate_req_per_s"] for row in rows if row["sustained"]]
     return {"requests_per_rate": n_req, "rates": rows,
             "sustainable_rate_req_per_s": max(ok) if ok else None,
-            "rule": "completes >= 95% of the offered rate and p99 <= 3x the p99 at the lowest rate"}
+            "rule": "latency stays bounded: p50 <= 2x and p99 <= 3x those at the lowest rate "
+                    "(beyond it a queue builds and latency grows with the offered rate)"}
 
 
 HBM_PEAK = 8.0e12     # MI355X HBM3E, bytes/s
@@ -498,19 +497,25 @@ def time_to_solution_form():
     run("mach10_cylinder_hllc1", pb.mach10_cylinder(), scheme=1)
     run("mach100_jet", pb.mach100_jet())
     run("mach100_jet_hllc1", pb.mach100_jet(), scheme=1)
-    # negative control: no limiters, checked every 50 steps until it fails
+    # negative control: no limiters; the library's lazy report refuses the
+    # next chunk once a stage result has left the admissible set
     spec = pb.mach10_cylinder()
     sol = wcns.Solver.from_spec(spec, interp_limiter=False, flux_limiter=False)
     W = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
-    fail_at, n = None, 0
-    while n < 8000 and fail_at is None:
-        for _ in range(50):
-            sol.step(W, 0.0)
-        n += 50
-        if sol.count_inadmissible(W):
-            fail_at = n
-    out["mach10_cylinder_limiters_off"] = {"first_inadmissible_within_steps": fail_at,
-                                           "checked_every": 50, "max_steps": 8000}
+    refused_after, n = None, 0
+    while n < 8000 and refused_after is None:
+        try:
+            sol.steps(W, 50, 0.0)
+            n += 50
+            torch.cuda.synchronize()
+        except wcns.WcnsError as e:
+            if e.code != wcns.WCNS_ERR_INADMISSIBLE:
+                raise
+            refused_after = n
+    nviol = sol.violations(clear=True)
+    out["mach10_cylinder_limiters_off"] = {"refused_after_steps": refused_after,
+                                           "chunk_steps": 50, "max_steps": 8000,
+                                           "stage_results_outside_G": nviol}
     sol.close()
     return out
 
@@ -605,12 +610,17 @@ def main():
     from paper_2102_05287_amd import wcns
 
     torch.cuda.set_device(0)
-    measure_weights()
     spec = pb.shock_bubble(args.n)
     sol = wcns.Solver.from_spec(spec)
     V = torch.from_numpy(spec.prim).cuda()
     W0 = sol.prim_to_cons(V)
     W = W0.clone()
+    # the issue probes (about half a second of sustained GPU work) run right
+    # before the warm-up steps: after host-side set-up the GPU needs ~15 ms
+    # of sustained load to reach its working clock, longer than a few
+    # warm-up steps take (measured: the first 20-step call after an idle
+    # gap ran 0.75-0.77 ms per step against 0.70-0.71 when kept busy)
+    measure_weights()
     print(f"# workload {spec.name} {spec.nx}x{spec.ny} fp64; warmup {args.warmup}", flush=True)
     sol.steps(W, args.warmup, 0.0)
     torch.cuda.synchronize()

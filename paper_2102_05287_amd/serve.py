@@ -153,30 +153,39 @@ class Server:
         finished = []
         ticks = 0
         work = 0.0
+        spent = {"admit": 0.0, "rebind": 0.0, "step": 0.0, "check": 0.0, "idle": 0.0}
         while pending or queue or self.active:
+            ta = time.perf_counter()
             tnow = now()
             while pending and (not realtime or pending[0].arrival <= tnow):
                 queue.append(pending.pop(0))
             while queue and self._fits(queue[0]):
                 self._admit(queue.pop(0), tnow)
             self.peak_used = max(self.peak_used, self.used)
+            tb = time.perf_counter()
+            spent["admit"] += tb - ta
             if queue and self.active == 0:
                 raise RuntimeError(f"request {queue[0].rid} exceeds the HBM budget")
             if not self.active:
                 if pending:
                     time.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                spent["idle"] += time.perf_counter() - tb
                 continue
             live = [g for g in self.groups.values() if g.members]
             for g in live:
                 if g.dirty:
                     self._rebind(g)
             torch.cuda.synchronize()
+            tc = time.perf_counter()
+            spent["rebind"] += tc - tb
             for g in live:
                 g.batch.step(self.chunk)
             for g in live:
                 g.batch.sync()
             ticks += 1
             tdone = now()
+            td = time.perf_counter()
+            spent["step"] += td - tc
             for g in live:
                 left = g.batch.steps_left()
                 viol = g.batch.violations()
@@ -195,6 +204,7 @@ class Server:
                 if len(keep) != len(g.members):
                     g.members = keep
                     g.dirty = True
+            spent["check"] += time.perf_counter() - td
             if log:
                 log(f"tick {ticks} t={tdone:.2f}s active={self.active} queued={len(queue)} "
                     f"pending={len(pending)} done={len(finished)}")
@@ -211,6 +221,7 @@ class Server:
             "mcell_updates_per_s": work / makespan / 1e6,
             "ticks": ticks,
             "chunk_steps": self.chunk,
+            "host_seconds": spent,
         }
         for g in self.groups.values():
             if g.batch is not None:
