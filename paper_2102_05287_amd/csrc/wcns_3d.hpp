@@ -766,9 +766,9 @@ __global__ __launch_bounds__(64 * XW) void k3_sweep_xl(K3Args a) {
     const LdsLoad3 ld{win + t.base(lane), 1, XWIN};
     face_flux3_core<0>(a, ld, a.step[1], Gm, Gp);
   }
-  double Gr[7];
+  double Gr[7];   // (lane 63 owns no cell)
 #pragma unroll
-  for (int v = 0; v < 7; ++v) Gr[v] = __shfl(Gm[v], (lane + 1) & 63, 64);
+  for (int v = 0; v < 7; ++v) Gr[v] = from_next_lane(Gm[v]);
   if (!t.owner(lane)) return;
   const long c = t.cell(lane);
 #pragma unroll

@@ -35,6 +35,7 @@ struct wcns_ctx {
   double dx, dy;
   KArgs base;
   double *P, *L, *U1, *U2, *partial, *step, *dirW, *dirP, *edge;
+  double* sink;   // first-order pass: stores of lanes that finish no cell (FO_SINK_SLOTS x 8)
   // 2D steps: the y-sweep and fixup of every stage but the last of a call
   // write the next stage's node primitives into the other buffer (P and P2
   // alternate) and their block maxima into `partial` (nfused pairs), so
@@ -185,7 +186,8 @@ wcns_status wcns_destroy(wcns_ctx* c) {
   if (!c) return WCNS_ERR_ARG;
   prof_release(c);
   (void)hipStreamSynchronize(c->stream);
-  double* bufs[] = {c->P, c->P2, c->L, c->U1, c->U2, c->partial, c->step, c->dirW, c->dirP, c->edge};
+  double* bufs[] = {c->P, c->P2, c->L, c->U1, c->U2, c->partial, c->step, c->dirW, c->dirP, c->edge,
+                    c->sink};
   for (double* b : bufs)
     if (b) (void)hipFree(b);
   if (c->count) (void)hipFree(c->count);
@@ -353,6 +355,7 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   }
   const int npart = std::max(std::max(c->nfused, c->node_grid), c->fo_ntask);
   alloc(&c->partial, 2 * (size_t)npart);
+  if (c->fo) alloc(&c->sink, 8 * (size_t)FO_SINK_SLOTS);
   alloc(&c->step, 8);
   if (g->ndim == 1 && g->nx <= RUN1D_MAX_CELLS) {
     alloc(&c->run_G, 12 * ((size_t)g->nx + 1));
@@ -861,13 +864,14 @@ static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode
   a.out_mode = mode;
   set_bases(c, a, W, c->P);
   a.partn = maxima ? c->partial : nullptr;
+  a.sink = c->sink;
   ProfScope ps(c, PROF_FO);
-  if (diri(c, 0) || diri(c, 1))
-    hipLaunchKernelGGL(k_fo_stage<true>, dim3(c->fo_grid), dim3(64 * FO_WAVES), 0, c->stream, a,
-                       c->fo_nstrip, c->fo_nrb, c->fo_ntask);
-  else
-    hipLaunchKernelGGL(k_fo_stage<false>, dim3(c->fo_grid), dim3(64 * FO_WAVES), 0, c->stream, a,
-                       c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  const bool d = diri(c, 0) || diri(c, 1), un = mode == OUT_RK && ca != 0.0;
+  const dim3 grid(c->fo_grid), block(64 * FO_WAVES);
+  if (d && un) hipLaunchKernelGGL((k_fo_stage<true, true>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  else if (d) hipLaunchKernelGGL((k_fo_stage<true, false>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  else if (un) hipLaunchKernelGGL((k_fo_stage<false, true>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  else hipLaunchKernelGGL((k_fo_stage<false, false>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
   LAUNCH_CHECK();
   return WCNS_OK;
 }

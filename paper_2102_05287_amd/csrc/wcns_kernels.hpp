@@ -96,6 +96,7 @@ struct KArgs {
   unsigned long long* viol;
   int32_t* vflag;
   int32_t check_in, node_skip;
+  double* sink;          // one-pass first-order stage: where lanes that finish no cell write
 };
 
 // ------------------------------------------------------------------ nodes
@@ -510,6 +511,20 @@ __device__ __forceinline__ int state_index(int dir, int v, bool has_t) {
   if (dir == 1 && (v == 2 || v == 3)) return 5 - v;
   return v;
 }
+
+// Neighbour lanes by DPP whole-wave shifts (a VALU move, no LDS round
+// trip): from_next_lane gives lane L the value of lane L + 1 (lane 63 keeps
+// its own), from_prev_lane the value of lane L - 1 (lane 0 keeps its own).
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  int lo = (int)(unsigned)u, hi = (int)(unsigned)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double from_next_lane(double x) { return dpp_shift<0x130>(x); }   // wave_shl:1
+__device__ __forceinline__ double from_prev_lane(double x) { return dpp_shift<0x138>(x); }   // wave_shr:1
 
 // maximum over the 64 lanes of a wave
 __device__ __forceinline__ double wave_max(double v) {
@@ -1056,9 +1071,9 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
     const LdsLoadX<HAS_T> ld{win, t.base(lane)};
     face_flux_core<0, HAS_T, B32, FO>(a, ld, a.step[1], Gm, Gp);
   }
-  double Gr[6];
+  double Gr[6];   // (lane 63 owns no cell)
 #pragma unroll
-  for (int v = 0; v < 6; ++v) Gr[v] = __shfl(Gm[v], (lane + 1) & 63, 64);
+  for (int v = 0; v < 6; ++v) Gr[v] = from_next_lane(Gm[v]);
   if (!t.owner(lane)) return;
   const long c = t.cell(lane);
   double* dst = (!HAS_T || a.Lout == nullptr) ? a.out : a.Lout;

@@ -5,7 +5,8 @@
 
 // ---------------------------------------------------------------- no allocation
 // The allocation-free right-hand side keeps its scratch (node primitives,
-// y-tile edge fluxes, block maxima, step record) in this file-scope device
+// y-tile edge fluxes, block maxima, step record, the first-order pass's
+// sink) in this file-scope device
 // array: every GPU the library runs on holds its own copy until the process
 // ends, and every call on that GPU shares it.  Its device address is taken
 // once per device with hipGetSymbolAddress; the host-side name is only a
@@ -45,11 +46,13 @@ extern "C" wcns_status wcns_rhs_noalloc(const wcns_grid* g, const wcns_eos* eos,
   wcns_ctx c;
   memset(&c, 0, sizeof(c));
   ctx_setup(&c, g, eos, prm, precision, stream);
-  // scratch: P [5][N], (2D) edges [nbr][12][nx], block maxima, step record
+  // scratch: P [5][N], (2D) edges [nbr][12][nx], block maxima, step record,
+  // (first-order scheme) the sink of the one-pass stage
   const size_t nP = round32d(5 * (size_t)c.N);
   const size_t nE = g->ndim == 2 ? round32d((size_t)c.nbr * 12 * g->nx) : 0;
   const size_t nB = round32d(2 * (size_t)c.node_grid);
-  if ((nP + nE + nB + 32) * sizeof(double) > WCNS_NOALLOC_SCRATCH_BYTES) return WCNS_ERR_TOO_LARGE;
+  const size_t nS = c.fo ? 8 * (size_t)FO_SINK_SLOTS : 0;
+  if ((nP + nE + nB + 32 + nS) * sizeof(double) > WCNS_NOALLOC_SCRATCH_BYTES) return WCNS_ERR_TOO_LARGE;
   double* base = nullptr;
   wcns_status st = noalloc_scratch(&base);
   if (st != WCNS_OK) return st;
@@ -57,6 +60,7 @@ extern "C" wcns_status wcns_rhs_noalloc(const wcns_grid* g, const wcns_eos* eos,
   c.edge = g->ndim == 2 ? base + nP : nullptr;
   c.partial = base + nP + nE;
   c.step = base + nP + nE + nB;
+  c.sink = c.fo ? base + nP + nE + nB + 32 : nullptr;
   c.base.edge = c.edge;
   c.base.step = c.step;
   st = launch_node_finalize(&c, W, DT_GIVEN, dt, nullptr);
