@@ -367,7 +367,9 @@ def first_order_form(n=1024, steps=200, warmup=10):
     96 + 144 + 144 B per cell per step.  In 2D each stage is one launch of
     the one-pass kernel, so `achieved` is those bytes per launch (the
     three-stage mean, 128 B per cell) over its mean launch time (HIP events
-    around each launch); `step` prices the whole step, finalize included."""
+    around each launch); `stages` splits it into stage 1 (96 B per cell) and
+    stages 2 and 3 (144 B); `step` prices the whole step, finalize
+    included."""
     import torch
     from paper_2102_05287_amd import problems as pb
     from paper_2102_05287_amd import wcns
@@ -384,13 +386,19 @@ def first_order_form(n=1024, steps=200, warmup=10):
     bad = sol.count_inadmissible(W)
     step_bytes = (96.0 + 144.0 + 144.0) * cells
     launch_bytes = step_bytes / 3.0
-    ms, nl = prof["fo_stage"]
-    t_launch = ms / 1e3 / nl
+    # stage 1 (class fo_stage: no U^n) and stages 2, 3 (fo_stage_un)
+    (ms1, n1), (ms23, n23) = prof["fo_stage"], prof["fo_stage_un"]
+    t_launch = (ms1 + ms23) / 1e3 / (n1 + n23)
     dev_step = sum(v[0] for v in prof.values()) / 1e3 / steps
+    stages = {}
+    for name, ms, nl, b in (("stage1", ms1, n1, 96.0), ("stages23", ms23, n23, 144.0)):
+        t = ms / 1e3 / nl
+        stages[name] = {"bytes_per_cell": b, "avg_launch_ms": t * 1e3, "achieved": b * cells / t / 1e9,
+                        "frac": b * cells / t / HBM_PEAK}
     roof = {"bound": "hbm", "kernel": "fo_stage", "unit": "GB/s", "peak": HBM_PEAK / 1e9,
             "bytes_per_launch": launch_bytes, "avg_launch_ms": t_launch * 1e3,
             "achieved": launch_bytes / t_launch / 1e9, "frac": launch_bytes / t_launch / HBM_PEAK,
-            "traffic": measured_traffic("fo_stage"),
+            "traffic": measured_traffic("fo_stage"), "stages": stages,
             "step": {"bytes": step_bytes, "device_ms": dev_step * 1e3,
                      "frac": step_bytes / dev_step / HBM_PEAK,
                      "frac_wall": step_bytes / (el / steps) / HBM_PEAK}}

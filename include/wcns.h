@@ -235,13 +235,14 @@ wcns_status wcns_check_admissible(wcns_ctx* ctx, const double* W, long long* n_b
  * the context launches is bracketed by a pair of HIP events recorded on the
  * context's stream; wcns_profile_read synchronises the stream and returns,
  * per kernel class, the summed device time in milliseconds and the number of
- * launches since the last reset.  Classes (WCNS_NPROF = 8): 0 node
+ * launches since the last reset.  Classes (WCNS_NPROF = 9): 0 node
  * primitives + wave-speed maxima, 1 dt/lambda finalize, 2 x-sweep,
  * 3 y-sweep, 4 tile fixups, 5 other, 6 z-sweep (3D), 7 one-pass stage of the
- * first-order scheme (2D).  `ms` and `launches`
+ * first-order scheme (2D) that reads no U^n (an RHS, the first RK stage),
+ * 8 one that combines with U^n (RK stages 2 and 3).  `ms` and `launches`
  * hold WCNS_NPROF entries.  Enabling allocates the event pool (so it is not
  * graph-capturable); disabling releases it. */
-#define WCNS_NPROF 8
+#define WCNS_NPROF 9
 wcns_status wcns_profile(wcns_ctx* ctx, int32_t enable);
 wcns_status wcns_profile_read(wcns_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
 

@@ -97,7 +97,7 @@ struct ProfScope {
   }
 };
 enum { PROF_NODE = 0, PROF_FIN = 1, PROF_X = 2, PROF_Y = 3, PROF_FIX = 4, PROF_OTHER = 5, PROF_Z = 6,
-       PROF_FO = 7 };
+       PROF_FO = 7, PROF_FO_UN = 8 };
 
 #define HIP_TRY(x)                                   \
   do {                                               \
@@ -865,8 +865,8 @@ static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode
   set_bases(c, a, W, c->P);
   a.partn = maxima ? c->partial : nullptr;
   a.sink = c->sink;
-  ProfScope ps(c, PROF_FO);
   const bool d = diri(c, 0) || diri(c, 1), un = mode == OUT_RK && ca != 0.0;
+  ProfScope ps(c, un ? PROF_FO_UN : PROF_FO);
   const dim3 grid(c->fo_grid), block(64 * FO_WAVES);
   if (d && un) hipLaunchKernelGGL((k_fo_stage<true, true>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
   else if (d) hipLaunchKernelGGL((k_fo_stage<true, false>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);

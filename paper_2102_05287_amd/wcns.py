@@ -83,7 +83,8 @@ EXPORTS = ["wcns_params_default", "wcns_create", "wcns_destroy", "wcns_set_strea
            "wcns_batch_stream", "wcns_batch_dt", "wcns_batch_destroy", "wcns_batch_set_steps",
            "wcns_batch_steps_left", "wcns_batch_violations", "wcns_prim_to_cons_n",
            "wcns_rhs_noalloc", "wcns_status_str"]
-PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other", "sweep_z", "fo_stage"]
+PROF_CLASSES = ["node", "finalize", "sweep_x", "sweep_y", "fixup_y", "other", "sweep_z", "fo_stage",
+                "fo_stage_un"]
 
 
 def lib():
