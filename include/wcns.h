@@ -232,8 +232,11 @@ wcns_status wcns_violations(wcns_ctx* ctx, int64_t* n_bad, int32_t clear);
 wcns_status wcns_check_admissible(wcns_ctx* ctx, const double* W, long long* n_bad);
 
 /* Measurement aid (not needed for the method).  While enabled, every kernel
- * the context launches is bracketed by a pair of HIP events recorded on the
- * context's stream; wcns_profile_read synchronises the stream and returns,
+ * the context launches is timed by a pair of HIP events on the context's
+ * stream that the launch itself stamps with the kernel's start and end
+ * (hipExtLaunchKernelGGL), so the time excludes the dispatch; a skipped
+ * step's kernels count with the time they took to return.
+ * wcns_profile_read synchronises the stream and returns,
  * per kernel class, the summed device time in milliseconds and the number of
  * launches since the last reset.  Classes (WCNS_NPROF = 9): 0 node
  * primitives + wave-speed maxima, 1 dt/lambda finalize, 2 x-sweep,

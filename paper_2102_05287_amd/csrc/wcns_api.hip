@@ -3,6 +3,7 @@
 // RHS, the stand-alone flux limiter, the wave-speed reduction and the SSP-RK3
 // step.  No allocation happens after wcns_create.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <utility>
 #include <math.h>
 #include <stdlib.h>
@@ -61,6 +62,7 @@ struct wcns_ctx {
   int x_lds, xl_grid;   // x-sweep with LDS windows (rows of >= XLDS_MIN_NX cells), its grid
   // measurement aid: event pairs around launches (wcns_profile)
   int prof_on, prof_n, prof_cap;
+  int prof_pend;   // 1 + slot of the open ProfScope whose event pair the next launch takes (0: none)
   hipEvent_t* ev;
   int* ev_cls;
   double prof_ms[WCNS_NPROF];
@@ -72,6 +74,7 @@ static wcns_status prof_fold(wcns_ctx* c) {
   if (!c->prof_on || c->prof_n == 0) return WCNS_OK;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return WCNS_ERR_HIP;
   for (int k = 0; k < c->prof_n; ++k) {
+    if (c->ev_cls[k] < 0) continue;   // a scope that launched nothing
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) != hipSuccess) return WCNS_ERR_HIP;
     c->prof_ms[c->ev_cls[k]] += ms;
@@ -81,7 +84,10 @@ static wcns_status prof_fold(wcns_ctx* c) {
   return WCNS_OK;
 }
 
-// RAII bracket of one launch when profiling is on
+// One launch timed when profiling is on: the scope opens an event pair that
+// the launch inside it (KLAUNCH) hands to hipExtLaunchKernelGGL, which
+// stamps the pair with the kernel's own start and end, so the time excludes
+// the dispatch that events recorded around the launch would include.
 struct ProfScope {
   wcns_ctx* c;
   int slot;
@@ -90,12 +96,31 @@ struct ProfScope {
     if (c->prof_n == c->prof_cap) (void)prof_fold(c);
     slot = c->prof_n++;
     c->ev_cls[slot] = cls;
-    (void)hipEventRecord(c->ev[2 * slot], c->stream);
+    c->prof_pend = slot + 1;
   }
   ~ProfScope() {
-    if (slot >= 0) (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+    if (slot < 0 || c->prof_pend != slot + 1) return;
+    // nothing was launched: keep the pair valid, count no launch
+    (void)hipEventRecord(c->ev[2 * slot], c->stream);
+    (void)hipEventRecord(c->ev[2 * slot + 1], c->stream);
+    c->ev_cls[slot] = -1;
+    c->prof_pend = 0;
   }
 };
+
+// hipLaunchKernelGGL, or, inside an open ProfScope of context C, the same
+// launch stamping that scope's event pair
+#define KLAUNCH(C, K, G, B, SHM, ST, ...)                                                      \
+  do {                                                                                         \
+    if ((C)->prof_pend > 0) {                                                                  \
+      const int slot_ = (C)->prof_pend - 1;                                                    \
+      (C)->prof_pend = 0;                                                                      \
+      hipExtLaunchKernelGGL(K, G, B, SHM, ST, (C)->ev[2 * slot_], (C)->ev[2 * slot_ + 1], 0,  \
+                            __VA_ARGS__);                                                      \
+    } else {                                                                                   \
+      hipLaunchKernelGGL(K, G, B, SHM, ST, __VA_ARGS__);                                       \
+    }                                                                                          \
+  } while (0)
 enum { PROF_NODE = 0, PROF_FIN = 1, PROF_X = 2, PROF_Y = 3, PROF_FIX = 4, PROF_OTHER = 5, PROF_Z = 6,
        PROF_FO = 7, PROF_FO_UN = 8 };
 
@@ -569,12 +594,12 @@ static wcns_status launch_node_finalize3(wcns_ctx* c, const double* W, int dt_mo
   a.check_in = check_in ? 1 : 0;
   {
     ProfScope ps(c, PROF_NODE);
-    hipLaunchKernelGGL(k3_node, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
+    KLAUNCH(c, k3_node, dim3(c->node_grid), dim3(256), 0, c->stream, a, c->P, c->partial);
   }
   LAUNCH_CHECK();
   {
     ProfScope ps(c, PROF_FIN);
-    hipLaunchKernelGGL(k3_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
+    KLAUNCH(c, k3_finalize, dim3(1), dim3(256), 0, c->stream, (const double*)c->partial,
                        c->node_grid, dt_mode, dt, c->params.cfl, a.dx, a.dy, a.dz, c->step,
                        dt_used, clk ? clk->t : nullptr, clk ? clk->n : nullptr,
                        clk ? clk->t_end : 0.0);
@@ -598,9 +623,9 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   {
     ProfScope ps(c, PROF_X);
     if (c->x_lds)
-      hipLaunchKernelGGL(k3_sweep_xl, dim3(c->xl_grid), dim3(64 * XW), 0, c->stream, a);
+      KLAUNCH(c, k3_sweep_xl, dim3(c->xl_grid), dim3(64 * XW), 0, c->stream, a);
     else
-      hipLaunchKernelGGL(k3_sweep_x, dim3(c->x_grid), dim3(64), 0, c->stream, a);
+      KLAUNCH(c, k3_sweep_x, dim3(c->x_grid), dim3(64), 0, c->stream, a);
   }
   LAUNCH_CHECK();
   K3Args ay = a;   // y pass: L = L_x + L_y in place
@@ -610,14 +635,14 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   ay.nbr = c->nbr_y3;
   {
     ProfScope ps(c, PROF_Y);
-    hipLaunchKernelGGL((k3_sweep_l<1>), dim3((unsigned)((nx + 31) / 32), c->nbr_y3, (unsigned)nz),
+    KLAUNCH(c, (k3_sweep_l<1>), dim3((unsigned)((nx + 31) / 32), c->nbr_y3, (unsigned)nz),
                        dim3(L3_THREADS), 0, c->stream, ay);
   }
   LAUNCH_CHECK();
   if (c->nbr_y3 > 1) {
     const long nt = (long)(c->nbr_y3 - 1) * nx * nz;
     ProfScope ps(c, PROF_FIX);
-    hipLaunchKernelGGL((k3_fixup<1>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+    KLAUNCH(c, (k3_fixup<1>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
                        ay);
     LAUNCH_CHECK();
   }
@@ -628,14 +653,14 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
   az.nbr = c->nbr_z3;
   {
     ProfScope ps(c, PROF_Z);
-    hipLaunchKernelGGL((k3_sweep_l<2>), dim3((unsigned)((nx * ny + 31) / 32), c->nbr_z3, 1),
+    KLAUNCH(c, (k3_sweep_l<2>), dim3((unsigned)((nx * ny + 31) / 32), c->nbr_z3, 1),
                        dim3(L3_THREADS), 0, c->stream, az);
   }
   LAUNCH_CHECK();
   if (c->nbr_z3 > 1) {
     const long nt = (long)(c->nbr_z3 - 1) * nx * ny;
     ProfScope ps(c, PROF_FIX);
-    hipLaunchKernelGGL((k3_fixup<2>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
+    KLAUNCH(c, (k3_fixup<2>), dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream,
                        az);
     LAUNCH_CHECK();
   }
@@ -665,7 +690,7 @@ static wcns_status launch_finalize(wcns_ctx* c, int nblk, int dt_mode, double dt
   f.nsteps = clk ? clk->n : nullptr;
   f.t_end = clk ? clk->t_end : 0.0;
   ProfScope ps(c, PROF_FIN);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, c->stream, (const double*)c->partial,
+  KLAUNCH(c, k_finalize, dim3(1), dim3(1024), 0, c->stream, (const double*)c->partial,
                      nblk, f);
   LAUNCH_CHECK();
   return WCNS_OK;
@@ -684,9 +709,9 @@ static wcns_status launch_node_finalize(wcns_ctx* c, const double* W, int dt_mod
   {
     ProfScope ps(c, PROF_NODE);
     if (c->grid.ndim == 2)
-      hipLaunchKernelGGL(k_node<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, P, c->partial);
+      KLAUNCH(c, k_node<true>, dim3(c->node_grid), dim3(256), 0, c->stream, a, P, c->partial);
     else
-      hipLaunchKernelGGL(k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, P, c->partial);
+      KLAUNCH(c, k_node<false>, dim3(c->node_grid), dim3(256), 0, c->stream, a, P, c->partial);
   }
   LAUNCH_CHECK();
   return launch_finalize(c, c->node_grid, dt_mode, dt, dt_used, clk);
@@ -714,12 +739,12 @@ static bool diri(const wcns_ctx* c, int dir) {
 #define XSWEEP(HT, DI, BF, XG)                                                                 \
   do {                                                                                         \
     if (c->x_lds && c->params.scheme == WCNS_SCHEME_HLLC1)                                     \
-      hipLaunchKernelGGL((k_sweep_xl<HT, DI, false, true>), dim3(XG), dim3(64 * XW), 0,         \
+      KLAUNCH(c, (k_sweep_xl<HT, DI, false, true>), dim3(XG), dim3(64 * XW), 0,         \
                          c->stream, a);                                                        \
     else if (c->x_lds)                                                                         \
-      hipLaunchKernelGGL((k_sweep_xl<HT, DI, BF>), dim3(XG), dim3(64 * XW), 0, c->stream, a);   \
+      KLAUNCH(c, (k_sweep_xl<HT, DI, BF>), dim3(XG), dim3(64 * XW), 0, c->stream, a);   \
     else                                                                                       \
-      hipLaunchKernelGGL((k_sweep_x<HT, DI, BF>), dim3(c->x_grid), dim3(64), 0, c->stream, a);  \
+      KLAUNCH(c, (k_sweep_x<HT, DI, BF>), dim3(c->x_grid), dim3(64), 0, c->stream, a);  \
   } while (0)
 
 #define XSWEEP_ALL(XG)                                \
@@ -735,18 +760,18 @@ static bool diri(const wcns_ctx* c, int dir) {
   } while (0)
 
 // y-sweep of the first `rows` tile rows on stream s
-static void ysweep(const wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
+static void ysweep(wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
   dim3 gy((c->grid.nx + Y_COLS - 1) / Y_COLS, rows);
   const bool d = diri(c, 1);
   if (c->params.scheme == WCNS_SCHEME_HLLC1) {   // first order: no FP32 code in either precision
-    if (d) hipLaunchKernelGGL((k_sweep_y<true, false, true>), gy, dim3(Y_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_sweep_y<false, false, true>), gy, dim3(Y_THREADS), 0, s, a);
+    if (d) KLAUNCH(c, (k_sweep_y<true, false, true>), gy, dim3(Y_THREADS), 0, s, a);
+    else KLAUNCH(c, (k_sweep_y<false, false, true>), gy, dim3(Y_THREADS), 0, s, a);
   } else if (b32) {
-    if (d) hipLaunchKernelGGL((k_sweep_y<true, true>), gy, dim3(Y_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_sweep_y<false, true>), gy, dim3(Y_THREADS), 0, s, a);
+    if (d) KLAUNCH(c, (k_sweep_y<true, true>), gy, dim3(Y_THREADS), 0, s, a);
+    else KLAUNCH(c, (k_sweep_y<false, true>), gy, dim3(Y_THREADS), 0, s, a);
   } else {
-    if (d) hipLaunchKernelGGL((k_sweep_y<true, false>), gy, dim3(Y_THREADS), 0, s, a);
-    else hipLaunchKernelGGL((k_sweep_y<false, false>), gy, dim3(Y_THREADS), 0, s, a);
+    if (d) KLAUNCH(c, (k_sweep_y<true, false>), gy, dim3(Y_THREADS), 0, s, a);
+    else KLAUNCH(c, (k_sweep_y<false, false>), gy, dim3(Y_THREADS), 0, s, a);
   }
 }
 
@@ -804,7 +829,7 @@ static wcns_status launch_sweeps(wcns_ctx* c, const double* W, double* out, int 
   if (c->nbr > 1) {
     long nt = (long)(c->nbr - 1) * c->grid.nx;
     ProfScope ps(c, PROF_FIX);
-    hipLaunchKernelGGL(k_fixup_y, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, a);
+    KLAUNCH(c, k_fixup_y, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, c->stream, a);
     LAUNCH_CHECK();
   }
   return WCNS_OK;
@@ -868,10 +893,10 @@ static wcns_status launch_fo(wcns_ctx* c, const double* W, double* out, int mode
   const bool d = diri(c, 0) || diri(c, 1), un = mode == OUT_RK && ca != 0.0;
   ProfScope ps(c, un ? PROF_FO_UN : PROF_FO);
   const dim3 grid(c->fo_grid), block(64 * FO_WAVES);
-  if (d && un) hipLaunchKernelGGL((k_fo_stage<true, true>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
-  else if (d) hipLaunchKernelGGL((k_fo_stage<true, false>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
-  else if (un) hipLaunchKernelGGL((k_fo_stage<false, true>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
-  else hipLaunchKernelGGL((k_fo_stage<false, false>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  if (d && un) KLAUNCH(c, (k_fo_stage<true, true>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  else if (d) KLAUNCH(c, (k_fo_stage<true, false>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  else if (un) KLAUNCH(c, (k_fo_stage<false, true>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
+  else KLAUNCH(c, (k_fo_stage<false, false>), grid, block, 0, c->stream, a, c->fo_nstrip, c->fo_nrb, c->fo_ntask);
   LAUNCH_CHECK();
   return WCNS_OK;
 }
@@ -1013,11 +1038,11 @@ wcns_status wcns_run(wcns_ctx* c, double* W, double t0, double t_end, double dt_
   {
     ProfScope ps(c, PROF_OTHER);
     if (b32) {
-      if (d) hipLaunchKernelGGL((k_run1d<true, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
-      else hipLaunchKernelGGL((k_run1d<false, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+      if (d) KLAUNCH(c, (k_run1d<true, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+      else KLAUNCH(c, (k_run1d<false, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
     } else {
-      if (d) hipLaunchKernelGGL((k_run1d<true, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
-      else hipLaunchKernelGGL((k_run1d<false, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+      if (d) KLAUNCH(c, (k_run1d<true, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+      else KLAUNCH(c, (k_run1d<false, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
     }
   }
   LAUNCH_CHECK();
