@@ -404,8 +404,8 @@ inline T flux_limit(const Eos& e, const Problem& P, const T* Wl, const T* Wr,
 }
 
 // Characteristic projection built from face averages [App. A, R_A and
-// R_A^{-1}; Sec. 4.2: arithmetic averages of partial densities, mixture
-// density and speed of sound].
+// R_A^{-1}; Sec. 4.2]: the plain means of the two nodes' partial
+// densities, total density and sound speed.
 template <class T> struct FaceAvg { T a1, a2, rho, c, k1, k2; };
 
 template <class T, int NR>
