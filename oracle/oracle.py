@@ -232,16 +232,24 @@ def rhs(s: Setup, W: np.ndarray, dt: float) -> np.ndarray:
 _lib_omp = None
 
 
-def rhs_parallel(s: Setup, W: np.ndarray, dt: float) -> np.ndarray:
-    """rhs() from the OpenMP build of the same source (rows over the threads
-    of OMP_NUM_THREADS): the same bits, on all cores."""
+def _omp():
     global _lib_omp
     lib()   # builds both libraries when the source is newer
     if _lib_omp is None:
         L = C.CDLL(_LIB_OMP)
         L.oracle_rhs.argtypes = [C.POINTER(_Problem), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.c_double]
+        L.oracle_run.restype = C.c_long
+        L.oracle_run.argtypes = [C.POINTER(_Problem), C.POINTER(C.c_double), C.c_double,
+                                 C.c_double, C.c_long, C.POINTER(C.c_double)]
         _lib_omp = L
+    return _lib_omp
+
+
+def rhs_parallel(s: Setup, W: np.ndarray, dt: float) -> np.ndarray:
+    """rhs() from the OpenMP build of the same source (rows over the threads
+    of OMP_NUM_THREADS): the same bits, on all cores."""
+    _omp()
     W = _arr(W)
     out = np.empty_like(W)
     rc = _lib_omp.oracle_rhs(C.byref(s.c()), _dp(W), _dp(out), float(dt))
@@ -322,6 +330,21 @@ def run(s: Setup, W: np.ndarray, t_end: float, dt_fixed: float = 0.0, max_steps:
     t = C.c_double(0.0)
     steps = lib().oracle_run(C.byref(s.c()), _dp(W), float(t_end), float(dt_fixed),
                              int(max_steps), C.byref(t))
+    if steps == -5:
+        raise FloatingPointError(f"inadmissible state at t={t.value}")
+    if steps < 0:
+        raise ValueError(f"oracle_run failed: {steps}")
+    return W, int(steps), t.value
+
+
+def run_parallel(s: Setup, W: np.ndarray, t_end: float, dt_fixed: float = 0.0,
+                 max_steps: int = 10**9):
+    """run() from the OpenMP build (its RHS rows over the threads): the same
+    bits, on all cores, for the long runs that pin whole solves."""
+    W = _arr(W).copy()
+    t = C.c_double(0.0)
+    steps = _omp().oracle_run(C.byref(s.c()), _dp(W), float(t_end), float(dt_fixed),
+                              int(max_steps), C.byref(t))
     if steps == -5:
         raise FloatingPointError(f"inadmissible state at t={t.value}")
     if steps < 0:

@@ -763,10 +763,7 @@ static bool diri(const wcns_ctx* c, int dir) {
 static void ysweep(wcns_ctx* c, const KArgs& a, bool b32, int rows, hipStream_t s) {
   dim3 gy((c->grid.nx + Y_COLS - 1) / Y_COLS, rows);
   const bool d = diri(c, 1);
-  if (c->params.scheme == WCNS_SCHEME_HLLC1) {   // first order: no FP32 code in either precision
-    if (d) KLAUNCH(c, (k_sweep_y<true, false, true>), gy, dim3(Y_THREADS), 0, s, a);
-    else KLAUNCH(c, (k_sweep_y<false, false, true>), gy, dim3(Y_THREADS), 0, s, a);
-  } else if (b32) {
+  if (b32) {
     if (d) KLAUNCH(c, (k_sweep_y<true, true>), gy, dim3(Y_THREADS), 0, s, a);
     else KLAUNCH(c, (k_sweep_y<false, true>), gy, dim3(Y_THREADS), 0, s, a);
   } else {

@@ -1120,7 +1120,7 @@ __global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(FO ? 6 
 // blocks per CU); at 16 face rows, two 8-wave blocks per CU with half the
 // fixup rows.
 // (part: this block's slot for its block maxima when a.Pn is set)
-template <int FR, bool DIRI, bool B32, bool FO = false>
+template <int FR, bool DIRI, bool B32>
 __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, double* tile, long part) {
   constexpr int W = FR / 2;
   constexpr int ROWS = FR + 5;
@@ -1182,7 +1182,7 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
       }
       if (q == 0) { ld.c2 = c; ld.h2 = h; } else { ld.c3 = c; ld.h3 = h; }
     }
-    face_flux_core<1, true, B32, FO>(a, ld, a.step[2], Gm, Gp);
+    face_flux_core<1, true, B32>(a, ld, a.step[2], Gm, Gp);
   }
   // the owned cell's L_x, U^n and W, loaded while the block exchanges G^-
   const bool own = active && fr != FR - 1 && k < ny;
@@ -1232,14 +1232,13 @@ __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, d
   if (a.Pn) block_max_out(mx, my, a.partn + 2 * part);
 }
 
-// (FO: the first-order scheme, memory-bound: six waves per SIMD, three
-// 16-row tiles per CU)
-template <bool DIRI, bool B32, bool FO = false>
-__global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(FO ? 6 : 4))) void k_sweep_y(
+// (the first-order scheme in 2D runs k_fo_stage instead)
+template <bool DIRI, bool B32>
+__global__ __launch_bounds__(Y_THREADS) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_y(
     KArgs a) {
   if (a.step[STEP_SKIP] != 0.0) return;
   __shared__ double tile32[9 * (Y_ROWS + 5) * Y_COLS];
-  sweep_y_tile32<Y_ROWS, DIRI, B32, FO>(a, blockIdx.x, blockIdx.y, tile32,
+  sweep_y_tile32<Y_ROWS, DIRI, B32>(a, blockIdx.x, blockIdx.y, tile32,
                                         (long)blockIdx.y * gridDim.x + blockIdx.x);
 }
 
