@@ -5,11 +5,14 @@ to the oracle bit for bit without the oracle's hours of CPU time:
 
   * the shock-bubble interaction at 1024^2, 1000 CFL-0.5 SSP-RK3 steps;
   * the underwater explosion near a wall at 2048^2 (FP64) to its final time
-    t = 2e-4 s, the last step shortened to land on it.
+    t = 2e-4 s, the last step shortened to land on it;
+  * the Mach 100 water jet at 1024 x 512 (per-row Dirichlet inflow) to its
+    final time 4e-6 s.
 
 Calls only the oracle (its OpenMP build, bit-identical to the serial one;
-about 25 minutes on 8 cores).  Run from the repository root:
-    python tests/golden/write_full_runs.py
+about 14, 50 and 20 minutes on 8 cores).  Run from the repository root,
+naming the runs to (re)compute (default: all); the others are kept:
+    python tests/golden/write_full_runs.py [shock_bubble underwater jet]
 """
 from __future__ import annotations
 
@@ -47,30 +50,38 @@ def record(name, spec, W, steps, t, secs):
     }
 
 
-def main():
+def main(which):
+    path = os.path.join(HERE, "full_runs.json")
     out = {"note": "final states of whole oracle solves (oracle/oracle.py run_parallel), "
                    "written by tests/golden/write_full_runs.py; sha256 of the state as "
-                   "[6][ny][nx] little-endian float64",
+                   "[nvar][ny][nx] little-endian float64",
            "runs": {}}
-    sb = pb.shock_bubble(1024)
-    s = oracle_setup(sb)
-    t0 = time.time()
-    W, steps, t = orc.run_parallel(s, oracle_W(sb, s), float("inf"), 0.0, 1000)
-    out["runs"]["shock_bubble_1024_1000_steps"] = record(
-        "2D shock-bubble 1024x1024, 1000 SSP-RK3 steps at CFL 0.5", sb, W, steps, t, time.time() - t0)
-    print(json.dumps(out["runs"]["shock_bubble_1024_1000_steps"]), flush=True)
-    del W
-    ue = pb.underwater_explosion(2048)
-    s = oracle_setup(ue)
-    t0 = time.time()
-    W, steps, t = orc.run_parallel(s, oracle_W(ue, s), ue.t_end)
-    out["runs"]["underwater_explosion_2048_to_t_end"] = record(
-        f"2D underwater explosion near a wall 2048x2048, FP64, to t = {ue.t_end} s", ue, W, steps, t,
-        time.time() - t0)
-    print(json.dumps(out["runs"]["underwater_explosion_2048_to_t_end"]), flush=True)
-    with open(os.path.join(HERE, "full_runs.json"), "w") as f:
-        json.dump(out, f, indent=1)
+    if os.path.exists(path):
+        with open(path) as f:
+            out["runs"] = json.load(f)["runs"]
+
+    def solve(key, name, spec, t_end, max_steps=10**9):
+        s = oracle_setup(spec)
+        t0 = time.time()
+        W, steps, t = orc.run_parallel(s, oracle_W(spec, s), t_end, 0.0, max_steps)
+        out["runs"][key] = record(name, spec, W, steps, t, time.time() - t0)
+        print(json.dumps(out["runs"][key]), flush=True)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+
+    if "shock_bubble" in which:
+        solve("shock_bubble_1024_1000_steps", "2D shock-bubble 1024x1024, 1000 SSP-RK3 steps at CFL 0.5",
+              pb.shock_bubble(1024), float("inf"), 1000)
+    if "underwater" in which:
+        ue = pb.underwater_explosion(2048)
+        solve("underwater_explosion_2048_to_t_end",
+              f"2D underwater explosion near a wall 2048x2048, FP64, to t = {ue.t_end} s", ue, ue.t_end)
+    if "jet" in which:
+        jet = pb.mach100_jet()
+        solve("mach100_jet_to_t_end",
+              f"2D Mach 100 water jet 1024x512 (per-row Dirichlet inflow) to t = {jet.t_end} s", jet,
+              jet.t_end)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:] or ["shock_bubble", "underwater", "jet"])

@@ -61,6 +61,22 @@ def test_noalloc_rhs_equals_rhs_twice_second_smaller(precision):
             assert np.array_equal(got.cpu().numpy(), orc.rhs(s, oracle_W(spec, s), dt))
 
 
+def test_noalloc_rhs_first_order_pass_twice_second_smaller():
+    """The first-order scheme in 2D (its one-pass stage, whose idle lanes
+    store to a sink carved from the scratch): two grids in a row, the second
+    smaller, equal to the context path and to the oracle."""
+    for spec in (pb.random_smooth_state(200, 130, seed=35), pb.random_smooth_state(63, 17, seed=36)):
+        s = oracle_setup(spec, scheme=1)
+        Wh = oracle_W(spec, s)
+        W = dev(Wh)
+        dt = orc.cfl_dt(s, Wh)
+        print(f"  noalloc first order {spec.nx}x{spec.ny}", flush=True)
+        rc, got = noalloc_rhs(spec, W, dt, scheme=1)
+        assert rc == 0, rc
+        assert torch.equal(got, context_rhs(spec, W, dt, scheme=1))
+        assert np.array_equal(got.cpu().numpy(), orc.rhs(s, Wh, dt))
+
+
 def test_noalloc_rhs_full_size_shock_bubble():
     """The 1024^2 shock-bubble (the largest grid class the scratch holds)
     twice in a row, then a smaller random state with an air bubble and a
