@@ -32,7 +32,8 @@ _FLAGS = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math", "-s
 
 def build() -> str:
     """Compile the oracle (always; a few seconds): the serial library and
-    the same source with OpenMP over grid rows (the all-cores baseline)."""
+    the same source with OpenMP over grid rows and lines (the all-cores
+    baseline)."""
     subprocess.check_call(_FLAGS + ["-Wno-unknown-pragmas", _SRC, "-o", _LIB + ".tmp"])
     os.replace(_LIB + ".tmp", _LIB)
     subprocess.check_call(_FLAGS + ["-fopenmp", _SRC, "-o", _LIB_OMP + ".tmp"])
@@ -247,8 +248,8 @@ def _omp():
 
 
 def rhs_parallel(s: Setup, W: np.ndarray, dt: float) -> np.ndarray:
-    """rhs() from the OpenMP build of the same source (rows over the threads
-    of OMP_NUM_THREADS): the same bits, on all cores."""
+    """rhs() from the OpenMP build of the same source (rows, in 3D lines,
+    over the threads of OMP_NUM_THREADS): the same bits, on all cores."""
     _omp()
     W = _arr(W)
     out = np.empty_like(W)
@@ -339,7 +340,7 @@ def run(s: Setup, W: np.ndarray, t_end: float, dt_fixed: float = 0.0, max_steps:
 
 def run_parallel(s: Setup, W: np.ndarray, t_end: float, dt_fixed: float = 0.0,
                  max_steps: int = 10**9):
-    """run() from the OpenMP build (its RHS rows over the threads): the same
+    """run() from the OpenMP build (its RHS rows or lines over the threads): the same
     bits, on all cores, for the long runs that pin whole solves."""
     W = _arr(W).copy()
     t = C.c_double(0.0)

@@ -912,21 +912,24 @@ void rhs3(const Problem& P, const double* W, double* L, double dt) {
   double lam[3];
   stage_lambda3(P, W, dt, lam);
   std::vector<double> Ld[3];
-  std::vector<double> Gm, Gp;
   for (int d = 0; d < 3; ++d) {
     Ld[d].assign((size_t)n * 7, 0.0);
     const int na = d == 0 ? P.ny : P.nx, nb = d == 2 ? P.ny : P.nz;
-    for (int b = 0; b < nb; ++b)
-      for (int a = 0; a < na; ++a) {
-        sweep_line3(P, W, d, a, b, lam[d], Gm, Gp, nullptr);
-        for (int pos = 0; pos < len3(P, d); ++pos) {
-          double Xm[7], Xp[7];
-          unrotate3(d, &Gm[(size_t)(pos + 1) * 7], Xm);
-          unrotate3(d, &Gp[(size_t)pos * 7], Xp);
-          const long o = line_cell3(P, d, a, b, pos);
-          for (int v = 0; v < 7; ++v) Ld[d][(size_t)o * 7 + v] = -(Xm[v] - Xp[v]) / h3(P, d);
-        }
+    // Lines are independent (each cell lies on one line per direction): the
+    // OpenMP build splits them over threads, the same bits as the serial one.
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long l = 0; l < (long)na * nb; ++l) {
+      const int b = (int)(l / na), a = (int)(l % na);
+      std::vector<double> Gm, Gp;
+      sweep_line3(P, W, d, a, b, lam[d], Gm, Gp, nullptr);
+      for (int pos = 0; pos < len3(P, d); ++pos) {
+        double Xm[7], Xp[7];
+        unrotate3(d, &Gm[(size_t)(pos + 1) * 7], Xm);
+        unrotate3(d, &Gp[(size_t)pos * 7], Xp);
+        const long o = line_cell3(P, d, a, b, pos);
+        for (int v = 0; v < 7; ++v) Ld[d][(size_t)o * 7 + v] = -(Xm[v] - Xp[v]) / h3(P, d);
       }
+    }
   }
   for (long o = 0; o < n; ++o)
     for (int v = 0; v < 7; ++v)

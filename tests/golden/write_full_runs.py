@@ -7,12 +7,13 @@ to the oracle bit for bit without the oracle's hours of CPU time:
   * the underwater explosion near a wall at 2048^2 (FP64) to its final time
     t = 2e-4 s, the last step shortened to land on it;
   * the Mach 100 water jet at 1024 x 512 (per-row Dirichlet inflow) to its
-    final time 4e-6 s.
+    final time 4e-6 s;
+  * the 3D underwater explosion near a wall at 256^3, 20 CFL steps.
 
 Calls only the oracle (its OpenMP build, bit-identical to the serial one;
-about 14, 50 and 20 minutes on 8 cores).  Run from the repository root,
+about 14, 60, 20 and 10 minutes on 8 cores).  Run from the repository root,
 naming the runs to (re)compute (default: all); the others are kept:
-    python tests/golden/write_full_runs.py [shock_bubble underwater jet]
+    python tests/golden/write_full_runs.py [shock_bubble underwater jet 3d]
 """
 from __future__ import annotations
 
@@ -38,13 +39,13 @@ def record(name, spec, W, steps, t, secs):
     s = oracle_setup(spec)
     return {
         "workload": name,
-        "grid": [spec.nx, spec.ny],
+        "grid": [spec.nx, spec.ny] + ([spec.nz] if spec.ndim == 3 else []),
         "steps": steps,
         "t": t,
         "t_hex": float(t).hex(),
         "sha256": digest(W),
         "component_sums": [float(np.sum(W[k])) for k in range(W.shape[0])],
-        "alpha1_min_max": [float(W[5].min()), float(W[5].max())],
+        "alpha1_min_max": [float(W[-1].min()), float(W[-1].max())],
         "inadmissible": orc.count_inadmissible(s, W),
         "oracle_seconds": round(secs, 1),
     }
@@ -81,7 +82,11 @@ def main(which):
         solve("mach100_jet_to_t_end",
               f"2D Mach 100 water jet 1024x512 (per-row Dirichlet inflow) to t = {jet.t_end} s", jet,
               jet.t_end)
+    if "3d" in which:
+        solve("underwater_explosion_3d_256_20_steps",
+              "3D underwater explosion near a wall 256^3, 20 SSP-RK3 steps at CFL 0.5",
+              pb.underwater_explosion_3d(256), float("inf"), 20)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1:] or ["shock_bubble", "underwater", "jet"])
+    main(sys.argv[1:] or ["shock_bubble", "underwater", "jet", "3d"])

@@ -680,10 +680,10 @@ def test_dirichlet_ghosts_enter_the_cfl_maxima():
 
 def test_openmp_build_of_the_oracle_is_bitwise_identical():
     """The all-cores CPU baseline: the same oracle source built with OpenMP
-    over grid rows gives the serial build's RHS bit for bit (2D with every
-    side kind, 1D, a limiter-active state)."""
+    over grid rows (3D: grid lines) gives the serial build's RHS bit for bit
+    (2D with every side kind, 1D, a limiter-active state, 3D)."""
     cases = [pb.random_smooth_state(96, 70, seed=41), pb.water_air_shock_tube(400),
-             pb.shock_bubble(64)]
+             pb.shock_bubble(64), pb.random_smooth_state_3d(20, 17, 13, seed=42)]
     for spec in cases:
         s = oracle_setup(spec)
         W = oracle_W(spec, s)
