@@ -121,11 +121,13 @@ typedef struct wcns_ctx wcns_ctx;
 wcns_status wcns_params_default(wcns_params* p);
 
 /* Create a context for one grid.  Validates the fluids against Lemma 1
- * (WCNS_ERR_EOS), the grid (nx, ny >= 1, ndim in {1,2}, bc kinds, reflective
+ * (WCNS_ERR_EOS), the grid (nx, ny >= 1, ndim in {1,2,3}, bc kinds, reflective
  * sides need >= 3 cells) and the parameters (cfl in (0, 0.5], weno_eps in
- * [1e-200, 1e200], scheme, precision; WCNS_ERR_ARG), checks the
+ * [1e-200, 1e200], the six tolerances finite and > 0 with eps_alpha and
+ * hs_alpha < 1/2, scheme, precision; WCNS_ERR_ARG), checks the
  * Dirichlet ghost states (finite, partial densities >= 0 with a positive sum,
- * 0 <= a1 <= 1; else WCNS_ERR_INADMISSIBLE), then allocates all device
+ * 0 <= a1 <= 1, p + pbar_inf > 0, i.e. inside G; else WCNS_ERR_INADMISSIBLE;
+ * all before any device call), then allocates all device
  * scratch once (WCNS_ERR_NOMEM).  stream: hipStream_t or NULL for
  * the default stream.  On success *out owns the scratch until wcns_destroy.
  * 3D grids (ndim = 3): FP64 only, sides periodic, extrapolated or
@@ -137,7 +139,11 @@ wcns_status wcns_create(const wcns_grid* grid, const wcns_eos* eos, const wcns_p
 /* Release the context and its scratch (synchronises its stream). */
 wcns_status wcns_destroy(wcns_ctx* ctx);
 
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on.  Work already enqueued on the
+ * previous stream is not waited for: a caller that switches streams orders
+ * the two itself (e.g. with an event), since both use the context's scratch.
+ * With profiling on, the timings recorded so far are folded first (this
+ * synchronises the previous stream). */
 wcns_status wcns_set_stream(wcns_ctx* ctx, void* stream);
 
 /* Primitive -> conservative on the device (Sec. 2 mixture EOS):
@@ -301,8 +307,11 @@ wcns_status wcns_batch_create(int32_t n, const wcns_grid* grids, const wcns_eos*
                               int64_t capacity_cells, wcns_batch** out);
 
 /* Rebind the batch to another instance set (same ndim) inside its existing
- * scratch; WCNS_ERR_NOMEM if it does not fit.  Synchronises the batch
- * stream; the captured graph is rebuilt on the next step. */
+ * scratch; WCNS_ERR_NOMEM if it does not fit (the bound set stays as it
+ * was).  Synchronises the batch stream; the captured graph is rebuilt on the
+ * next step.  A reset or configure that fails after that check (a HIP error)
+ * leaves no instance set bound: wcns_batch_step and wcns_batch_rhs then
+ * return WCNS_ERR_ARG until a reset succeeds. */
 wcns_status wcns_batch_reset(wcns_batch* b, int32_t n, const wcns_grid* grids, double* const* W);
 
 /* Schedule: ytile in {2, 4, 8, 16} y-face rows per y-sweep block (32
@@ -359,9 +368,10 @@ wcns_status wcns_batch_destroy(wcns_batch* b);
  * validated as by wcns_create and the scratch (node primitives, y-tile edge
  * fluxes, block maxima, step record) lives in a static device array of
  * WCNS_NOALLOC_SCRATCH_BYTES per GPU, held from the library's load until the
- * process ends.  It needs 8 (5 N + 12 nx ceil((ny+1)/16)) bytes plus
- * ~16 KiB for N = nx*ny cells, i.e. up to ~1.45 M cells (1024^2 fits);
- * larger grids return WCNS_ERR_TOO_LARGE.  1D and 2D grids without
+ * process ends.  It needs 8 (5 N + 12 nx ceil((ny+1)/16)) bytes for
+ * N = nx*ny cells (1D: 8 * 5 N) plus at most 33 KiB (block maxima, step
+ * record) and, for the first-order scheme, a 64 KiB sink: up to ~1.45 M
+ * cells in 2D (1024^2 fits); larger grids return WCNS_ERR_TOO_LARGE.  1D and 2D grids without
  * Dirichlet sides (WCNS_ERR_ARG otherwise).  W, dWdt: device [nvar][ny][nx],
  * caller-owned, must not alias; dt as in wcns_rhs.  Calls no allocating
  * routine: the first call on a device looks up the array's address once.

@@ -69,18 +69,21 @@ struct wcns_ctx {
   int64_t prof_cnt[WCNS_NPROF];
 };
 
-// Fold recorded event pairs into the per-class sums (synchronises).
+// Fold recorded event pairs into the per-class sums (synchronises).  The
+// pool is emptied either way: on a HIP error the pairs not yet folded are
+// dropped rather than folded twice later.
 static wcns_status prof_fold(wcns_ctx* c) {
   if (!c->prof_on || c->prof_n == 0) return WCNS_OK;
+  const int n = c->prof_n;
+  c->prof_n = 0;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return WCNS_ERR_HIP;
-  for (int k = 0; k < c->prof_n; ++k) {
+  for (int k = 0; k < n; ++k) {
     if (c->ev_cls[k] < 0) continue;   // a scope that launched nothing
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev[2 * k], c->ev[2 * k + 1]) != hipSuccess) return WCNS_ERR_HIP;
     c->prof_ms[c->ev_cls[k]] += ms;
     c->prof_cnt[c->ev_cls[k]] += 1;
   }
-  c->prof_n = 0;
   return WCNS_OK;
 }
 
@@ -94,6 +97,7 @@ struct ProfScope {
   ProfScope(wcns_ctx* c_, int cls) : c(c_), slot(-1) {
     if (!c->prof_on) return;
     if (c->prof_n == c->prof_cap) (void)prof_fold(c);
+    if (c->prof_n >= c->prof_cap) return;   // (no pool: the launch goes untimed)
     slot = c->prof_n++;
     c->ev_cls[slot] = cls;
     c->prof_pend = slot + 1;
@@ -194,9 +198,11 @@ static int pick_tile_x(int nx) {
   return 1;
 }
 
+// (the pool is zero-filled at allocation, so events never created are null)
 static void prof_release(wcns_ctx* c) {
   if (c->ev) {
-    for (int k = 0; k < 2 * c->prof_cap; ++k) (void)hipEventDestroy(c->ev[k]);
+    for (int k = 0; k < 2 * c->prof_cap; ++k)
+      if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
     free(c->ev);
     free(c->ev_cls);
   }
@@ -247,6 +253,18 @@ static wcns_status alloc_report(wcns_ctx* c) {
 // the operand range on which the kernels' division core is the IEEE divide
 static bool weno_eps_ok(double e) { return e >= 1e-200 && e <= 1e200; }
 
+// Scheme options shared by every form: CFL number in (0, 0.5] (Sec. 3.3,
+// 5.3), the IS-weight epsilon above, a known scheme, and the limiter and
+// hard-switch tolerances of Sec. 5.1 finite and positive (the volume
+// fraction ones below 1/2, so that [eps, 1 - eps] is not empty).
+static bool params_ok(const wcns_params* p) {
+  if (!(p->cfl > 0.0 && p->cfl <= 0.5) || !weno_eps_ok(p->weno_eps)) return false;
+  if (p->scheme != WCNS_SCHEME_PPWCNSIS && p->scheme != WCNS_SCHEME_HLLC1) return false;
+  for (double t : {p->eps_arho, p->eps_alpha, p->eps_rhoc2, p->hs_arho, p->hs_alpha, p->hs_rhoc2})
+    if (!(t > 0.0) || !isfinite(t)) return false;
+  return p->eps_alpha < 0.5 && p->hs_alpha < 0.5;
+}
+
 // A violation seen by earlier work on this context (lazy report): the
 // entry points that enqueue work refuse to run until wcns_violations clears it.
 static bool flagged(const wcns_ctx* c) {
@@ -270,11 +288,34 @@ static wcns_status check_setup(const wcns_grid* g, const wcns_eos* eos, const wc
     if ((lo == WCNS_BC_REFLECT || hi == WCNS_BC_REFLECT) && n < 3) return WCNS_ERR_ARG;
   }
   if (!eos_ok(eos)) return WCNS_ERR_EOS;
-  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5)) return WCNS_ERR_ARG;
-  if (!weno_eps_ok(prm->weno_eps)) return WCNS_ERR_ARG;
-  if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
+  if (!params_ok(prm)) return WCNS_ERR_ARG;
   if (precision != WCNS_FP64 && precision != WCNS_FP32_BULK) return WCNS_ERR_ARG;
   return WCNS_OK;
+}
+
+// Dirichlet ghost states of a 1D/2D grid (primitive, per side or per
+// boundary row): finite and inside the admissible set G of Sec. 2, i.e.
+// partial densities >= 0 with a positive sum, 0 <= a1 <= 1, and
+// rho e - pbar_inf = Gamma (p + pbar_inf) > 0 with Gamma > 0, so
+// p + pbar_inf > 0 (Gamma, Pi and pbar_inf = Pi / (1 + Gamma) of the mixture).
+static bool dirichlet_ok(const wcns_grid* g, const wcns_eos* e) {
+  const int nv = g->ndim == 1 ? 5 : 6;
+  for (int s = 0; s < 2 * g->ndim; ++s) {
+    if (g->bc[s] != WCNS_BC_DIRICHLET) continue;
+    const int n_side = g->dirichlet_rows[s] ? (s < 2 ? g->ny : g->nx) : 1;
+    for (int l = 0; l < n_side; ++l) {
+      const double* V = g->dirichlet_rows[s] ? g->dirichlet_rows[s] + (size_t)l * nv : g->dirichlet[s];
+      for (int k = 0; k < nv; ++k)
+        if (!isfinite(V[k])) return false;
+      const double a1r1 = V[0], a2r2 = V[1], p = V[nv - 2], a1 = V[nv - 1];
+      if (!(a1r1 >= 0.0 && a2r2 >= 0.0 && a1r1 + a2r2 > 0.0 && a1 >= 0.0 && a1 <= 1.0)) return false;
+      const double Gam = a1 / (e->gamma[0] - 1.0) + (1.0 - a1) / (e->gamma[1] - 1.0);
+      const double Pi = a1 * e->gamma[0] * e->pinf[0] / (e->gamma[0] - 1.0) +
+                        (1.0 - a1) * e->gamma[1] * e->pinf[1] / (e->gamma[1] - 1.0);
+      if (!(p + Pi / (1.0 + Gam) > 0.0)) return false;
+    }
+  }
+  return true;
 }
 
 // Everything of a 1D/2D context but its device buffers: sizes, launch
@@ -351,6 +392,7 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
   if (g->ndim == 3) return create3(g, eos, prm, precision, stream, out);
   wcns_status chk = check_setup(g, eos, prm, precision);
   if (chk != WCNS_OK) return chk;
+  if (!dirichlet_ok(g, eos)) return WCNS_ERR_INADMISSIBLE;
 
   wcns_ctx* c = (wcns_ctx*)calloc(1, sizeof(wcns_ctx));
   if (!c) return WCNS_ERR_NOMEM;
@@ -420,12 +462,6 @@ wcns_status wcns_create(const wcns_grid* g, const wcns_eos* eos, const wcns_para
           x = g->dirichlet_rows[s] ? g->dirichlet_rows[s][(size_t)l * nv + k] : g->dirichlet[s][k];
         V[(size_t)k * R + r] = x;
       }
-      if (used) {
-        const double a1r1 = V[r], a2r2 = V[(size_t)R + r], a1 = V[(size_t)(nv - 1) * R + r];
-        bool ok = a1r1 >= 0.0 && a2r2 >= 0.0 && a1r1 + a2r2 > 0.0 && a1 >= 0.0 && a1 <= 1.0;
-        for (int k = 0; k < nv; ++k) ok = ok && isfinite(V[(size_t)k * R + r]);
-        if (!ok) { free(V); wcns_destroy(c); return WCNS_ERR_INADMISSIBLE; }
-      }
     }
   }
   double *dV = nullptr, *dWg = nullptr;
@@ -487,9 +523,7 @@ static wcns_status create3(const wcns_grid* g, const wcns_eos* eos, const wcns_p
     if ((lo == WCNS_BC_REFLECT || hi == WCNS_BC_REFLECT) && len[d] < 3) return WCNS_ERR_ARG;
   }
   if (!eos_ok(eos)) return WCNS_ERR_EOS;
-  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5)) return WCNS_ERR_ARG;
-  if (!weno_eps_ok(prm->weno_eps)) return WCNS_ERR_ARG;
-  if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
+  if (!params_ok(prm)) return WCNS_ERR_ARG;
   if (precision != WCNS_FP64) return WCNS_ERR_ARG;
 
   wcns_ctx* c = (wcns_ctx*)calloc(1, sizeof(wcns_ctx));
@@ -669,8 +703,10 @@ static wcns_status launch_sweeps3(wcns_ctx* c, const double* W, double* out, int
 
 wcns_status wcns_set_stream(wcns_ctx* c, void* stream) {
   if (!c) return WCNS_ERR_ARG;
+  // event pairs recorded on the old stream are folded while it is current
+  const wcns_status st = prof_fold(c);
   c->stream = (hipStream_t)stream;
-  return WCNS_OK;
+  return st;
 }
 
 // dt/lambda from the nblk block-maxima pairs in c->partial
@@ -1187,15 +1223,15 @@ wcns_status wcns_profile(wcns_ctx* c, int32_t enable) {
     const int cap = 4096;
     c->ev = (hipEvent_t*)calloc(2 * cap, sizeof(hipEvent_t));
     c->ev_cls = (int*)calloc(cap, sizeof(int));
+    c->prof_cap = cap;
     if (!c->ev || !c->ev_cls) { prof_release(c); return WCNS_ERR_NOMEM; }
     for (int k = 0; k < 2 * cap; ++k) {
       if (hipEventCreate(&c->ev[k]) != hipSuccess) {
-        c->prof_cap = k / 2;
+        c->ev[k] = nullptr;
         prof_release(c);
         return WCNS_ERR_HIP;
       }
     }
-    c->prof_cap = cap;
     c->prof_n = 0;
     c->prof_on = 1;
     for (int k = 0; k < WCNS_NPROF; ++k) { c->prof_ms[k] = 0.0; c->prof_cnt[k] = 0; }
@@ -1334,8 +1370,19 @@ static void xcd_chunk(std::vector<Task>& t) {
   t.swap(out);
 }
 
+// The batch without an instance set (after a failed rebuild): no graph, no
+// tasks; step and rhs refuse until a reset succeeds.
+static void batch_invalidate(wcns_batch* b) {
+  batch_drop_graph(b);
+  b->n = 0;
+  b->grids.clear();
+  b->W.clear();
+  b->off.clear();
+  b->n_node = b->n_x = b->n_y = b->n_fix = 0;
+}
+
 // (re)build the per-instance arguments and the task lists
-static wcns_status batch_build(wcns_batch* b) {
+static wcns_status batch_build_impl(wcns_batch* b) {
   const int n = b->n;
   std::vector<KArgs> ka(5 * (size_t)n);
   std::vector<int> inst_order(n);
@@ -1372,10 +1419,7 @@ static wcns_status batch_build(wcns_batch* b) {
     a.rdy = checked_recip(a.dy);
     for (int q = 0; q < 4; ++q) a.bc[q] = g.bc[q];
     if (g.ndim == 1) { a.bc[2] = WCNS_BC_PERIODIC; a.bc[3] = WCNS_BC_PERIODIC; }
-    int T = 62;
-    for (T = 62; T >= 1; --T)
-      if (T + (T - 1 + g.nx - 1) / g.nx + 1 <= 64) break;
-    a.tile_x = T;
+    a.tile_x = pick_tile_x(g.nx);
     a.P = P;
     a.Pw = P;
     for (int q = 0; q < 5; ++q) a.Pc[q] = P + q * N;
@@ -1480,12 +1524,14 @@ static wcns_status batch_build(wcns_batch* b) {
   if (all.size() > b->tasks_cap) {
     if (b->d_tasks) (void)hipFree(b->d_tasks);
     b->d_tasks = nullptr;
+    b->tasks_cap = 0;
     if (hipMalloc((void**)&b->d_tasks, all.size() * sizeof(Task)) != hipSuccess) return WCNS_ERR_NOMEM;
     b->tasks_cap = all.size();
   }
   if (ka.size() > b->ka_cap) {
     if (b->d_ka) (void)hipFree(b->d_ka);
     b->d_ka = nullptr;
+    b->ka_cap = 0;
     if (hipMalloc((void**)&b->d_ka, ka.size() * sizeof(KArgs)) != hipSuccess) return WCNS_ERR_NOMEM;
     b->ka_cap = ka.size();
   }
@@ -1494,6 +1540,14 @@ static wcns_status batch_build(wcns_batch* b) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   batch_drop_graph(b);
   return WCNS_OK;
+}
+
+// the rebuild, leaving no instance set bound if it fails part way (the
+// device task list and arguments would no longer match the host's)
+static wcns_status batch_build(wcns_batch* b) {
+  const wcns_status st = batch_build_impl(b);
+  if (st != WCNS_OK) batch_invalidate(b);
+  return st;
 }
 
 // launches of stage s (3: RHS only); cont: stage 1 of a step that follows
@@ -1547,29 +1601,43 @@ static wcns_status batch_layout(wcns_batch* b, int n, const wcns_grid* grids, do
     off[k] = need;
     need += inst_doubles(grids[k], b->nv);
   }
+  // (a set that does not fit, or per-instance arrays that cannot be
+  // allocated, leave the bound set as it was; the caller has synchronised
+  // the batch stream)
   if (need > b->arena_cap) return WCNS_ERR_NOMEM;
+  if (n > b->dt_cap) {
+    double* dt = nullptr;
+    int32_t* live = nullptr;
+    unsigned long long* viol = nullptr;
+    if (hipMalloc((void**)&dt, sizeof(double) * n) != hipSuccess ||
+        hipMalloc((void**)&live, sizeof(int32_t) * n) != hipSuccess ||
+        hipMalloc((void**)&viol, sizeof(unsigned long long) * n) != hipSuccess) {
+      if (dt) (void)hipFree(dt);
+      if (live) (void)hipFree(live);
+      if (viol) (void)hipFree(viol);
+      return WCNS_ERR_NOMEM;
+    }
+    if (b->d_dt) (void)hipFree(b->d_dt);
+    if (b->d_live) (void)hipFree(b->d_live);
+    if (b->d_viol) (void)hipFree(b->d_viol);
+    b->d_dt = dt;
+    b->d_live = live;
+    b->d_viol = viol;
+    b->dt_cap = n;
+  }
   b->n = n;
   b->grids.assign(grids, grids + n);
   b->W.assign(W, W + n);
   b->off = off;
-  if (n > b->dt_cap) {
-    if (b->d_dt) (void)hipFree(b->d_dt);
-    if (b->d_live) (void)hipFree(b->d_live);
-    if (b->d_viol) (void)hipFree(b->d_viol);
-    b->d_dt = nullptr;
-    b->d_live = nullptr;
-    b->d_viol = nullptr;
-    if (hipMalloc((void**)&b->d_dt, sizeof(double) * n) != hipSuccess) return WCNS_ERR_NOMEM;
-    if (hipMalloc((void**)&b->d_live, sizeof(int32_t) * n) != hipSuccess) return WCNS_ERR_NOMEM;
-    if (hipMalloc((void**)&b->d_viol, sizeof(unsigned long long) * n) != hipSuccess)
-      return WCNS_ERR_NOMEM;
-    b->dt_cap = n;
-  }
   // every instance live for ever until told otherwise, no violation yet
   std::vector<int32_t> live(n, 0x7fffffff);
-  HIP_TRY(hipMemcpy(b->d_live, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
   std::vector<unsigned long long> zero(n, 0ull);
-  HIP_TRY(hipMemcpy(b->d_viol, zero.data(), sizeof(unsigned long long) * n, hipMemcpyHostToDevice));
+  if (hipMemcpy(b->d_live, live.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_viol, zero.data(), sizeof(unsigned long long) * n, hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    batch_invalidate(b);
+    return WCNS_ERR_HIP;
+  }
   return batch_build(b);
 }
 
@@ -1603,8 +1671,7 @@ wcns_status wcns_batch_create(int32_t n, const wcns_grid* grids, const wcns_eos*
   wcns_status st = batch_check_grids(n, grids, ndim);
   if (st != WCNS_OK) return st;
   if (!eos_ok(eos)) return WCNS_ERR_EOS;
-  if (!(prm->cfl > 0.0 && prm->cfl <= 0.5) || !weno_eps_ok(prm->weno_eps)) return WCNS_ERR_ARG;
-  if (prm->scheme != WCNS_SCHEME_PPWCNSIS && prm->scheme != WCNS_SCHEME_HLLC1) return WCNS_ERR_ARG;
+  if (!params_ok(prm)) return WCNS_ERR_ARG;
   if (precision != WCNS_FP64 && precision != WCNS_FP32_BULK) return WCNS_ERR_ARG;
   if (capacity_cells < 0) return WCNS_ERR_ARG;
   wcns_batch* b = new wcns_batch();
@@ -1677,11 +1744,11 @@ wcns_status wcns_batch_configure(wcns_batch* b, int32_t ytile, int32_t order) {
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->ytile = ytile;
   b->order = order;
-  return batch_build(b);
+  return b->n > 0 ? batch_build(b) : WCNS_OK;   // (no set bound: the next reset builds)
 }
 
 wcns_status wcns_batch_step(wcns_batch* b, int32_t nsteps) {
-  if (!b || nsteps < 0) return WCNS_ERR_ARG;
+  if (!b || nsteps < 0 || b->n < 1) return WCNS_ERR_ARG;
   if (b->dirty) {
     batch_drop_graph(b);
     for (int cont = 0; cont < 2; ++cont) {
@@ -1702,7 +1769,7 @@ wcns_status wcns_batch_step(wcns_batch* b, int32_t nsteps) {
 }
 
 wcns_status wcns_batch_rhs(wcns_batch* b) {
-  if (!b) return WCNS_ERR_ARG;
+  if (!b || b->n < 1) return WCNS_ERR_ARG;
   batch_stage(b, 3);
   LAUNCH_CHECK();
   return WCNS_OK;
@@ -1722,6 +1789,7 @@ wcns_status wcns_batch_stream(wcns_batch* b, void** stream) {
 
 wcns_status wcns_batch_set_steps(wcns_batch* b, const int32_t* steps) {
   if (!b || !steps) return WCNS_ERR_ARG;
+  if (b->n < 1) return WCNS_OK;
   for (int k = 0; k < b->n; ++k)
     if (steps[k] < 0) return WCNS_ERR_ARG;
   HIP_TRY(hipMemcpyAsync(b->d_live, steps, sizeof(int32_t) * b->n, hipMemcpyHostToDevice, b->stream));
@@ -1731,6 +1799,7 @@ wcns_status wcns_batch_set_steps(wcns_batch* b, const int32_t* steps) {
 
 wcns_status wcns_batch_steps_left(wcns_batch* b, int32_t* steps) {
   if (!b || !steps) return WCNS_ERR_ARG;
+  if (b->n < 1) return WCNS_OK;
   HIP_TRY(hipMemcpyAsync(steps, b->d_live, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   return WCNS_OK;
@@ -1760,6 +1829,7 @@ wcns_status wcns_prim_to_cons_n(const wcns_eos* eos, int32_t ndim, int64_t ncell
 
 wcns_status wcns_batch_violations(wcns_batch* b, int64_t* counts, int32_t clear) {
   if (!b || !counts) return WCNS_ERR_ARG;
+  if (b->n < 1) return WCNS_OK;   // no instance set bound
   std::vector<unsigned long long> h(b->n);
   HIP_TRY(hipMemcpyAsync(h.data(), b->d_viol, sizeof(unsigned long long) * b->n,
                          hipMemcpyDeviceToHost, b->stream));
@@ -1775,6 +1845,7 @@ wcns_status wcns_batch_violations(wcns_batch* b, int64_t* counts, int32_t clear)
 
 wcns_status wcns_batch_dt(wcns_batch* b, double* dt) {
   if (!b || !dt) return WCNS_ERR_ARG;
+  if (b->n < 1) return WCNS_OK;
   HIP_TRY(hipMemcpyAsync(dt, b->d_dt, sizeof(double) * b->n, hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   return WCNS_OK;

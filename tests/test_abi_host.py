@@ -7,6 +7,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from helpers import ROOT
@@ -94,7 +95,8 @@ def _create(**kw):
     e.gamma[0], e.gamma[1] = kw.get("gamma", (6.12, 1.4))
     e.pinf[0], e.pinf[1] = kw.get("pinf", (3.43e8, 0.0))
     p = wcns.default_params()
-    for k in ("cfl", "scheme", "weno_eps"):
+    for k in ("cfl", "scheme", "weno_eps", "eps_arho", "eps_alpha", "eps_rhoc2", "hs_arho",
+              "hs_alpha", "hs_rhoc2"):
         if k in kw:
             setattr(p, k, kw[k])
     ctx = C.c_void_p()
@@ -130,6 +132,14 @@ def _create(**kw):
     (dict(weno_eps=1e201), -1),
     (dict(weno_eps=float("nan")), -1),
     (dict(ndim=3, nz=4, weno_eps=1e-310), -1),
+    (dict(eps_arho=0.0), -1),                   # limiter tolerances (Sec. 5.1): finite, > 0
+    (dict(eps_alpha=-1e-10), -1),
+    (dict(eps_rhoc2=float("nan")), -1),
+    (dict(hs_arho=float("inf")), -1),
+    (dict(hs_rhoc2=0.0), -1),
+    (dict(eps_alpha=0.5), -1),                  # [eps, 1 - eps] empty
+    (dict(hs_alpha=0.75), -1),
+    (dict(ndim=3, nz=4, hs_alpha=-1.0), -1),
     (dict(precision=9), -1),
 ])
 def test_create_rejects_bad_arguments(kw, code):
@@ -228,7 +238,49 @@ def test_batch_create_rejects_bad_arguments():
     assert create(wcns.make_grid(2, 0, 16, 0.0, 1.0, 0.0, 1.0, (1,) * 4)) == -1
     bad = wcns.default_params(cfl=0.7)
     assert create(ok, prm=bad) == -1
+    assert create(ok, prm=wcns.default_params(eps_rhoc2=-1e-8)) == -1
     e2 = wcns._Eos()
     e2.gamma[0], e2.gamma[1] = 1.2, 1.67
     assert create(ok, eos=e2) == -2
     assert out.value is None
+
+
+def _create_grid(g):
+    e = wcns._Eos()
+    e.gamma[0], e.gamma[1] = 6.12, 1.4
+    e.pinf[0], e.pinf[1] = 3.43e8, 0.0
+    p = wcns.default_params()
+    ctx = C.c_void_p()
+    code = wcns.lib().wcns_create(C.byref(g), C.byref(e), C.byref(p), 0, None, C.byref(ctx))
+    if ctx.value:   # (created on a machine with a GPU)
+        wcns.lib().wcns_destroy(ctx)
+    return code
+
+
+@pytest.mark.parametrize("state", [
+    (1000.0, 1e-8, 0.0, 0.0, -4e8, 1.0 - 1e-8),      # water beyond its tension limit: p + pbar_inf < 0
+    (1e-8, 1.0, 0.0, 0.0, -10.0, 1e-8),              # gas below its pbar_inf (1.2 Pa from 1e-8 water)
+    (-1.0, 1.0, 0.0, 0.0, 1e5, 0.5),                  # negative partial density
+    (0.0, 0.0, 0.0, 0.0, 1e5, 0.5),                   # no mass
+    (1.0, 1.0, 0.0, 0.0, 1e5, 1.5),                   # a1 > 1
+    (1.0, 1.0, float("nan"), 0.0, 1e5, 0.5),
+])
+def test_create_rejects_inadmissible_dirichlet_ghosts(state):
+    """Dirichlet ghost states outside the admissible set G are refused with
+    WCNS_ERR_INADMISSIBLE before any device call: one state per side, and a
+    bad row inside a per-row profile."""
+    g = wcns.make_grid(2, 8, 8, 0.0, 1.0, 0.0, 1.0, (3, 1, 1, 1), dirichlet=[state, None, None, None])
+    assert _create_grid(g) == -5
+    rows = np.tile(np.array([1000.0, 1e-8, 10.0, 0.0, 1e5, 1.0 - 1e-8]), (8, 1))
+    rows[5] = state
+    g = wcns.make_grid(2, 8, 8, 0.0, 1.0, 0.0, 1.0, (1, 1, 1, 3), dirichlet=[None, None, None, rows[:8]])
+    assert _create_grid(g) == -5
+
+
+def test_create_accepts_water_below_zero_pressure_inside_g():
+    """Water (pinf = 3.43e8) holds tension down to p > -pbar_inf: a ghost at
+    p = -1e5 lies inside G, so the check passes and creation goes on to the
+    device (without a GPU it fails there, with another status)."""
+    g = wcns.make_grid(2, 8, 8, 0.0, 1.0, 0.0, 1.0, (3, 1, 1, 1),
+                       dirichlet=[(1000.0, 1e-8, 0.0, 0.0, -1e5, 1.0 - 1e-8), None, None, None])
+    assert _create_grid(g) != -5
