@@ -174,11 +174,15 @@ wcns_status wcns_limit(wcns_ctx* ctx, int32_t dir, const double* W, const double
  * in place) from time t0 until t_end or max_steps steps, each step the CFL
  * step of Sec. 3.3 (dt_fixed = 0) or dt_fixed, the last one shortened to land
  * on t_end; every step is the arithmetic of wcns_ssprk3_step, so the result
- * equals stepping with it.  One workgroup runs the whole loop (one launch
- * instead of five per stage).  dts (device, optional): dt of step k at
+ * equals stepping with it.  One workgroup runs the loop (one launch per
+ * 1024 steps instead of five per stage).  dts (device, optional): dt of step k at
  * dts[k] for k < dts_cap.  Synchronous: *steps_out and *t_out (host) receive
- * the steps taken and the final time.  WCNS_ERR_ARG for 2D/3D or larger
- * grids, WCNS_ERR_CFL for non-finite times or a negative dt_fixed. */
+ * the steps taken and the final time.  Cells outside G (the run's input,
+ * every stage result) are counted as by the other entry points.
+ * WCNS_ERR_ARG for 2D/3D or larger grids, WCNS_ERR_CFL for non-finite times
+ * or a negative dt_fixed, and for a run that stopped short of t_end and
+ * max_steps because a step would not advance the time (an infinite wave
+ * speed; *steps_out and *t_out then give where it stopped). */
 wcns_status wcns_run(wcns_ctx* ctx, double* W, double t0, double t_end, double dt_fixed,
                      int64_t max_steps, double* dts, int64_t dts_cap, int64_t* steps_out,
                      double* t_out);
@@ -217,7 +221,9 @@ wcns_status wcns_ssprk3_steps(wcns_ctx* ctx, double* W, int32_t nsteps, double d
  * >= nsteps doubles (may be NULL), the dt of each step slot (0 for a
  * skipped one).  Each step clips its dt to t_end - t when t + dt > t_end; a
  * step that would start at t >= t_end is skipped (its kernels return at
- * once), and so is every later step of the call.  A caller therefore
+ * once), and so is every later step of the call; so is a step that would
+ * not advance t (dt not positive from an infinite wave speed, a NaN, or too
+ * small to change t), which leaves t short of t_end.  A caller therefore
  * enqueues chunks without reading t in between, and stops once a chunk
  * took fewer steps than it enqueued; the chunks can be captured in a HIP
  * graph.  The steps taken are the arithmetic of wcns_ssprk3_steps.

@@ -1068,22 +1068,29 @@ wcns_status wcns_run(wcns_ctx* c, double* W, double t0, double t_end, double dt_
   r.max_steps = max_steps;
   HIP_TRY(hipMemcpyAsync(c->run_dev, &r, sizeof(r), hipMemcpyHostToDevice, c->stream));
   const bool d = diri(c, 0), b32 = c->precision == WCNS_FP32_BULK;
-  {
-    ProfScope ps(c, PROF_OTHER);
-    if (b32) {
-      if (d) KLAUNCH(c, (k_run1d<true, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
-      else KLAUNCH(c, (k_run1d<false, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
-    } else {
-      if (d) KLAUNCH(c, (k_run1d<true, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
-      else KLAUNCH(c, (k_run1d<false, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev);
+  // launches of at most RUN1D_CHUNK steps, each continuing from the record
+  // the last one left, until one takes fewer (t_end, max_steps or a stop)
+  for (;;) {
+    {
+      ProfScope ps(c, PROF_OTHER);
+      const int64_t ch = RUN1D_CHUNK;
+      if (b32) {
+        if (d) KLAUNCH(c, (k_run1d<true, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev, ch);
+        else KLAUNCH(c, (k_run1d<false, true>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev, ch);
+      } else {
+        if (d) KLAUNCH(c, (k_run1d<true, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev, ch);
+        else KLAUNCH(c, (k_run1d<false, false>), dim3(1), dim3(RUN1D_THREADS), 0, c->stream, c->run_dev, ch);
+      }
     }
+    LAUNCH_CHECK();
+    HIP_TRY(hipMemcpyAsync(&r, c->run_dev, sizeof(r), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (r.last < RUN1D_CHUNK || r.stopped || !(r.t < t_end) || r.steps >= max_steps) break;
   }
-  LAUNCH_CHECK();
-  HIP_TRY(hipMemcpyAsync(&r, c->run_dev, sizeof(r), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
   *steps_out = r.steps;
   *t_out = r.t;
-  return WCNS_OK;
+  // stopped short of t_end and of max_steps: a step that would not advance t
+  return r.stopped ? WCNS_ERR_CFL : WCNS_OK;
 }
 
 wcns_status wcns_max_wavespeed(wcns_ctx* c, const double* W, double* d_amax) {

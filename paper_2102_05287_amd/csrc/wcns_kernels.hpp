@@ -653,11 +653,14 @@ struct FinArgs {
 // t_end]: a step that would start at or after t_end is skipped; otherwise
 // dt is clipped to t_end - t and the clock advanced.  Returns false for a
 // skipped step.  (The order of the operations is that of the serial time
-// loop.)
+// loop.)  A step that would not advance the clock (dt not positive from an
+// infinite wave speed, a NaN, or too small to change t) is skipped too, so
+// the loop stops short of t_end instead of running on in place.
 __device__ __forceinline__ bool clock_step(double* clock, int64_t* nsteps, double t_end, double& dt) {
   const double t = *clock;
   if (!(t < t_end)) return false;
   if (t + dt > t_end) dt = t_end - t;
+  if (!(t + dt > t)) return false;
   *clock = t + dt;
   if (nsteps) *nsteps += 1;
   return true;

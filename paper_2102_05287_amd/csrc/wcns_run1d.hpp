@@ -9,8 +9,13 @@
 // then the flux difference and the stage combination, with block barriers
 // between the phases.  The arithmetic of every phase is that of the
 // multi-kernel path (the same device routines), so a run gives the same bits
-// as stepping with wcns_ssprk3_step.  Several instances run side by side, one
-// per block, each with its own arguments and its own number of steps.
+// as stepping with wcns_ssprk3_step, and it counts the same cells outside the
+// admissible set (the run's input and every stage result, Sec. 2).  A step
+// that would not advance the time (an infinite wave speed) ends the run
+// early.  A launch takes at most `chunk` steps and continues from the time
+// and step count in its record, so a long run is a sequence of bounded
+// launches.  Several instances run side by side, one per block, each with
+// its own arguments and its own number of steps.
 #pragma once
 #include "wcns_kernels.hpp"
 
@@ -18,6 +23,7 @@ namespace wcns {
 
 constexpr int RUN1D_THREADS = 512;   // 8 waves, 2 per SIMD (up to 256 VGPRs each)
 constexpr int RUN1D_MAX_CELLS = 4096;
+constexpr int64_t RUN1D_CHUNK = 1024;   // steps per launch (~0.05 s at 400 cells)
 
 struct Run1D {
   KArgs a;             // the instance: W (state, updated in place), Wc/Pc, bc, eos, ...
@@ -28,8 +34,10 @@ struct Run1D {
   const double* damax; // Dirichlet ghost maximum of |u|+c, or null
   double* dts;         // optional: dt of step k at dts[k] for k < dts_cap
   int64_t dts_cap;
-  double t, t_end, dt_fixed, cfl;   // t: start time in, end time out
-  int64_t max_steps, steps;         // steps: taken (out)
+  double t, t_end, dt_fixed, cfl;   // t: the time (in and out)
+  int64_t max_steps, steps;         // steps: taken so far (in and out)
+  int64_t last;                     // steps the last launch took (out)
+  int32_t stopped, pad;             // 1: a step would not advance the time (out)
 };
 
 __device__ __forceinline__ double block_max_run1d(double v, double* red) {
@@ -44,7 +52,7 @@ __device__ __forceinline__ double block_max_run1d(double v, double* red) {
 }
 
 template <bool DIRI, bool B32>
-__global__ __launch_bounds__(RUN1D_THREADS) void k_run1d(Run1D* runs) {
+__global__ __launch_bounds__(RUN1D_THREADS) void k_run1d(Run1D* runs, int64_t chunk) {
   __shared__ double red[RUN1D_THREADS / 64];
   Run1D& r = runs[blockIdx.x];
   const KArgs a0 = r.a;
@@ -59,13 +67,16 @@ __global__ __launch_bounds__(RUN1D_THREADS) void k_run1d(Run1D* runs) {
   double* const Gm = r.G;
   double* const Gp = r.G + 6 * (N + 1);
   double t = r.t;
-  int64_t steps = 0;
+  int64_t steps = r.steps, taken = 0;
   double dt = 0.0;
-  while (t < r.t_end && steps < r.max_steps) {
+  bool stop = false;
+  while (t < r.t_end && steps < r.max_steps && taken < chunk) {
     for (int s = 0; s < 3; ++s) {
       const double* in = stage_in[s];
       double* out = stage_out[s];
-      // node primitives and the wave-speed maximum [Sec. 2, 3.3]
+      // node primitives and the wave-speed maximum [Sec. 2, 3.3]; the
+      // stage's input cells outside G are counted (the run's input, then
+      // every stage result but the last, which is checked after the loop)
       double mx = 0.0;
       for (int i = tid; i < n; i += RUN1D_THREADS) {
         double X[6] = {in[i], in[N + i], in[2 * N + i], 0.0, in[3 * N + i], in[4 * N + i]};
@@ -73,12 +84,18 @@ __global__ __launch_bounds__(RUN1D_THREADS) void k_run1d(Run1D* runs) {
         recover<false>(a0.eos, X, un, ut, p, c, h);
         r.P[i] = un; r.P[N + i] = ut; r.P[2 * N + i] = p; r.P[3 * N + i] = c; r.P[4 * N + i] = h;
         mx = fmax(mx, fabs(un) + c);
+        if (a0.viol) report_bad(a0.viol, a0.vflag, !admissible(X[0], X[1], X[5], h));
       }
       mx = block_max_run1d(mx, red);
       if (r.damax) mx = fmax(mx, r.damax[0]);
       if (s == 0) {
         dt = r.dt_fixed > 0.0 ? r.dt_fixed : r.cfl * a0.dx / mx;
         if (t + dt > r.t_end) dt = r.t_end - t;
+        // (dt is the same on every thread: the block maximum)
+        if (!(t + dt > t)) {
+          stop = true;
+          break;
+        }
       }
       const double lam = dt / a0.dx;
       // faces of the line [Sec. 4.2 steps, Sec. 5 limiters]
@@ -122,13 +139,27 @@ __global__ __launch_bounds__(RUN1D_THREADS) void k_run1d(Run1D* runs) {
       }
       __syncthreads();
     }
+    if (stop) break;
     if (tid == 0 && r.dts && steps < r.dts_cap) r.dts[steps] = dt;
     t += dt;
     ++steps;
+    ++taken;
+  }
+  // the last stage result, where the run ends (on t_end or max_steps: an
+  // early stop has just checked it as the next step's input, and a launch
+  // that ends on its chunk leaves it to the next launch's first stage)
+  const bool more = !stop && taken == chunk && t < r.t_end && steps < r.max_steps;
+  if (a0.viol && taken > 0 && !stop && !more) {
+    for (int i = tid; i < n; i += RUN1D_THREADS) {
+      const double X[6] = {W[i], W[N + i], W[2 * N + i], 0.0, W[3 * N + i], W[4 * N + i]};
+      report_bad(a0.viol, a0.vflag, !admissible(X[0], X[1], X[5], rhoc2_tilde<false>(a0.eos, X)));
+    }
   }
   if (tid == 0) {
     r.t = t;
     r.steps = steps;
+    r.last = taken;
+    r.stopped = stop ? 1 : 0;
   }
 }
 

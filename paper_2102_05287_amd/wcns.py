@@ -330,7 +330,9 @@ class Solver:
         enqueues chunks of `chunk` steps and reads the step count once per
         chunk, stopping when a chunk took fewer steps than it enqueued.
         Raises WcnsError (inadmissible state) if the kernels found a cell
-        outside the admissible set on the way.  Returns (steps, t)."""
+        outside the admissible set on the way, and WcnsError (invalid time
+        step) if the device loop stopped short of t_end because a step was
+        not positive.  Returns (steps, t)."""
         import torch
         clock = torch.full((1,), float(t), dtype=torch.float64, device="cuda")
         taken = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -344,7 +346,11 @@ class Solver:
                 break
             done = now
         self.check_violations()
-        return done, float(clock.item())
+        t_now = float(clock.item())
+        if done < max_steps and not t_now >= t_end:
+            raise WcnsError(-6, f"the device time loop stopped at t = {t_now!r} < t_end "
+                                "(a step would not advance the time)")
+        return done, t_now
 
     def violations(self, clear=False) -> int:
         """Cells the kernels found outside the admissible set since creation

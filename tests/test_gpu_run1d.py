@@ -74,3 +74,46 @@ def test_run_edge_cases():
     sol2 = solver_for(pb.random_smooth_state(16, 16, 1))   # 2D: not available
     with pytest.raises(wcns.WcnsError):
         sol2.run(dev(oracle_W(pb.random_smooth_state(16, 16, 1))), 1e-6)
+
+
+def test_run_counts_inadmissible_cells_like_stepping():
+    """The whole-run kernel counts the cells outside G exactly as the
+    multi-kernel steps do (the run's input, every stage result): Sedov with
+    both limiters off, 3999 fixed steps (three full launches of 1024 steps
+    and a partial one), against wcns_ssprk3_steps on a fresh context.  The
+    final states agree bit for bit (NaNs in the same places)."""
+    spec = pb.sedov_multimaterial(401)
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    sol_r = solver_for(spec, interp_limiter=False, flux_limiter=False)
+    sol_s = solver_for(spec, interp_limiter=False, flux_limiter=False)
+    Wr, Ws = dev(W0), dev(W0)
+    n, t = sol_r.run(Wr, 1.0, dt_fixed=spec.dt_fixed, max_steps=3999)
+    assert n == 3999
+    sol_s.steps(Ws, 3999, spec.dt_fixed)
+    vr, vs = sol_r.violations(clear=True), sol_s.violations(clear=True)
+    print(f"  limiters off, 3999 steps: run counted {vr}, steps counted {vs}", flush=True)
+    assert vr == vs > 0
+    assert np.array_equal(host(Wr), host(Ws), equal_nan=True)
+
+
+def test_run_and_advance_stop_when_a_step_would_not_advance_the_time():
+    """A step too small to change t (here dt = 1e-300 at t = 1; an infinite
+    wave speed gives the same) ends the device time loop instead of leaving
+    it running in place: wcns_run returns WCNS_ERR_CFL and the device loop
+    of Solver.advance skips the step, which raises; the state is untouched."""
+    spec = pb.water_air_shock_tube(64)
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    sol = solver_for(spec)
+    Wd = dev(W0)
+    with pytest.raises(wcns.WcnsError) as e:
+        sol.run(Wd, 2.0, t=1.0, dt_fixed=1e-300)
+    assert e.value.code == -6
+    with pytest.raises(wcns.WcnsError) as e:
+        sol.advance(Wd, 2.0, t=1.0, dt=1e-300, chunk=8)
+    assert e.value.code == -6
+    assert np.array_equal(host(Wd), W0)
+    assert sol.violations() == 0
+    n, t = sol.run(Wd, spec.t_end, dt_fixed=spec.dt_fixed)   # the context still runs
+    assert n > 0 and t == spec.t_end
