@@ -266,7 +266,7 @@ def batched_form(n_inst, steps, seq_steps):
     for name, prec in (("fp64", wcns.FP64), ("fp32_bulk", wcns.FP32_BULK)):
         states = [w.clone() for w in W0]
         b = wcns.Batch(grids, states, precision=prec)
-        best, times = wcns.autotune(b, trials=2)
+        best, times = wcns.autotune(b, trials=3)
         for k in range(n_inst):
             states[k].copy_(W0[k])
         b.step(1)
@@ -280,8 +280,10 @@ def batched_form(n_inst, steps, seq_steps):
         el = time.perf_counter() - t0
         bad = sum(conv[specs[k].nx].count_inadmissible(states[k]) for k in range(n_inst))
         out[f"batched_{name}_mcells_per_s"] = 3 * cells * steps / el / 1e6
-        out[f"batched_{name}_schedule"] = {"ytile": best[0], "order": ["given", "largest_first",
-                                                                          "xcd_chunked"][best[1]]}
+        orders = ["given", "largest_first", "xcd_chunked"]
+        out[f"batched_{name}_schedule"] = {"ytile": best[0], "order": orders[best[1]]}
+        out[f"batched_{name}_autotune_rhs_ms"] = {f"{y}/{orders[o]}": round(t * 1e3, 3)
+                                                  for (y, o), t in times.items()}
         out[f"batched_{name}_inadmissible"] = bad
         b.close()
         del states
