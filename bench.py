@@ -458,7 +458,9 @@ def three_d_form(n=256, steps=10, warmup=2):
 
 def time_to_solution_form():
     """The paper's runs to their final times on the device time loop
-    (Solver.advance): the 1D water-air tube (400 cells, t = 2.4e-4 s), the
+    (Solver.advance), and the 1024^2 shock-bubble over its full 1000 steps
+    (its final state checked against the oracle's whole solve): the 1D
+    water-air tube (400 cells, t = 2.4e-4 s), the
     1D multi-material Sedov blast (401 cells, 4000 fixed steps), and the two
     2D robustness problems, Mach 10 shock-water cylinder (1152 x 768, 16 us)
     and Mach 100 water jet (1024 x 512, 4 us), with PP-WCNS-IS and with the
@@ -526,6 +528,31 @@ def time_to_solution_form():
     out["mach10_cylinder_limiters_off"] = {"refused_after_steps": refused_after,
                                            "chunk_steps": 50, "max_steps": 8000,
                                            "stage_results_outside_G": nviol}
+    sol.close()
+    # the shock-bubble workload over its full 1000 CFL steps in one call; the
+    # final state's SHA-256 against the digest of the oracle's own whole
+    # solve (tests/golden/full_runs.json, written by a script that calls
+    # only the oracle)
+    import hashlib
+    spec = pb.shock_bubble(1024)
+    sol = wcns.Solver.from_spec(spec)
+    W = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+    spec.prim = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol.steps(W, 1000, 0.0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    digest = hashlib.sha256(W.cpu().numpy().astype("<f8").tobytes()).hexdigest()
+    with open(os.path.join(ROOT, "tests", "golden", "full_runs.json")) as f:
+        golden = json.load(f)["runs"]["shock_bubble_1024_1000_steps"]["sha256"]
+    out["shock_bubble_1024_1000_steps"] = {
+        "grid": [spec.nx, spec.ny], "steps": 1000, "wall_s": el, "ms_per_step": el,
+        "mcell_updates_per_s": 3.0 * spec.nx * spec.ny * 1000 / el / 1e6,
+        "inadmissible_at_end": sol.count_inadmissible(W),
+        "final_state_sha256_equals_oracle": digest == golden}
+    print(f"#   shock_bubble_1024_1000_steps: {el:.2f} s, oracle digest "
+          f"{'matched' if digest == golden else 'DIFFERS'}", flush=True)
     sol.close()
     return out
 
