@@ -284,3 +284,58 @@ def test_create_accepts_water_below_zero_pressure_inside_g():
     g = wcns.make_grid(2, 8, 8, 0.0, 1.0, 0.0, 1.0, (3, 1, 1, 1),
                        dirichlet=[(1000.0, 1e-8, 0.0, 0.0, -1e5, 1.0 - 1e-8), None, None, None])
     assert _create_grid(g) != -5
+
+
+C_CLIENT = r"""
+#include <stdio.h>
+#include <string.h>
+#include "wcns.h"
+
+/* A C99 caller of the ABI: only the calls whose argument checks come before
+ * any device work, so it runs on a machine without a GPU. */
+int main(void) {
+  wcns_params p;
+  wcns_grid g;
+  wcns_eos e = {{6.12, 1.4}, {3.43e8, 0.0}};
+  wcns_ctx* ctx = NULL;
+  wcns_batch* b = NULL;
+  int fails = 0;
+  if (wcns_params_default(&p) != WCNS_OK || p.cfl != 0.5 || p.weno_eps != 1e-40) fails |= 1;
+  if (wcns_params_default(NULL) != WCNS_ERR_ARG) fails |= 2;
+  memset(&g, 0, sizeof g);
+  g.ndim = 2; g.nx = 0; g.ny = 8; g.x1 = 1.0; g.y1 = 1.0;
+  if (wcns_create(&g, &e, &p, WCNS_FP64, NULL, &ctx) != WCNS_ERR_ARG || ctx) fails |= 4;
+  g.nx = 8;
+  e.gamma[0] = 1.2; e.gamma[1] = 1.67;
+  if (wcns_create(&g, &e, &p, WCNS_FP64, NULL, &ctx) != WCNS_ERR_EOS || ctx) fails |= 8;
+  e.gamma[0] = 6.12; e.gamma[1] = 1.4;
+  p.eps_rhoc2 = -1.0;
+  if (wcns_create(&g, &e, &p, WCNS_FP64, NULL, &ctx) != WCNS_ERR_ARG || ctx) fails |= 16;
+  if (wcns_batch_create(0, &g, &e, &p, WCNS_FP64, NULL, 0, &b) != WCNS_ERR_ARG || b) fails |= 32;
+  if (wcns_rhs(NULL, NULL, NULL, 0.0) != WCNS_ERR_ARG) fails |= 64;
+  if (strcmp(wcns_status_str(WCNS_ERR_INADMISSIBLE), "state outside the admissible set") != 0) fails |= 128;
+  printf("fails=%d\n", fails);
+  return fails;
+}
+"""
+
+
+def test_header_is_c99_and_the_library_links_from_c(tmp_path):
+    """include/wcns.h compiles as C99 with every warning an error, and a C
+    program linked against libwcns.so calls the ABI (argument checks that
+    come before any device work)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    exe = tmp_path / "client"
+    libdir = os.path.dirname(wcns.LIB_PATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                    "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    "-L", libdir, "-lwcns", f"-Wl,-rpath,{libdir}"], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "fails=0" in r.stdout
