@@ -314,6 +314,49 @@ int main(void) {
   if (wcns_batch_create(0, &g, &e, &p, WCNS_FP64, NULL, 0, &b) != WCNS_ERR_ARG || b) fails |= 32;
   if (wcns_rhs(NULL, NULL, NULL, 0.0) != WCNS_ERR_ARG) fails |= 64;
   if (strcmp(wcns_status_str(WCNS_ERR_INADMISSIBLE), "state outside the admissible set") != 0) fails |= 128;
+  {
+    /* a Dirichlet ghost row outside G (water below its tension limit) */
+    double rows[8][6];
+    int r, k;
+    wcns_params_default(&p);
+    for (r = 0; r < 8; ++r) {
+      double s[6] = {1000.0, 1e-8, 0.0, 0.0, 1e5, 1.0 - 1e-8};
+      for (k = 0; k < 6; ++k) rows[r][k] = s[k];
+    }
+    rows[5][4] = -4e8;
+    g.bc[0] = WCNS_BC_DIRICHLET; g.bc[1] = g.bc[2] = g.bc[3] = WCNS_BC_EXTRAP;
+    g.dirichlet_rows[0] = &rows[0][0];
+    if (wcns_create(&g, &e, &p, WCNS_FP64, NULL, &ctx) != WCNS_ERR_INADMISSIBLE || ctx) fails |= 256;
+    g.dirichlet_rows[0] = NULL;
+    g.bc[0] = WCNS_BC_EXTRAP;
+  }
+  {
+    /* the allocation-free entry: argument checks before any device work */
+    double w[8];
+    if (wcns_rhs_noalloc(NULL, &e, &p, WCNS_FP64, NULL, w, w + 1, 0.0) != WCNS_ERR_ARG) fails |= 512;
+    if (wcns_rhs_noalloc(&g, &e, &p, WCNS_FP64, NULL, w, w, 0.0) != WCNS_ERR_ARG) fails |= 1024;
+    if (wcns_rhs_noalloc(&g, &e, &p, WCNS_FP64, NULL, w, w + 1, -1.0) != WCNS_ERR_CFL) fails |= 2048;
+    p.weno_eps = 1e-310;
+    if (wcns_rhs_noalloc(&g, &e, &p, WCNS_FP64, NULL, w, w + 1, 0.0) != WCNS_ERR_ARG) fails |= 4096;
+    wcns_params_default(&p);
+  }
+  {
+    /* batch: mixed dimensions, a null state */
+    wcns_grid gs[2];
+    double* W[2];
+    double w[2];
+    gs[0] = g;
+    gs[1] = g;
+    gs[1].ndim = 1; gs[1].ny = 1;
+    W[0] = w; W[1] = w + 1;
+    if (wcns_batch_create(2, gs, &e, &p, WCNS_FP64, W, 0, &b) != WCNS_ERR_ARG || b) fails |= 8192;
+    gs[1] = g;
+    W[1] = NULL;
+    if (wcns_batch_create(2, gs, &e, &p, WCNS_FP64, W, 0, &b) != WCNS_ERR_ARG || b) fails |= 16384;
+  }
+  if (wcns_destroy(NULL) != WCNS_ERR_ARG || wcns_profile(NULL, 1) != WCNS_ERR_ARG ||
+      wcns_violations(NULL, NULL, 0) != WCNS_ERR_ARG || wcns_batch_destroy(NULL) != WCNS_ERR_ARG)
+    fails |= 32768;
   printf("fails=%d\n", fails);
   return fails;
 }
@@ -338,4 +381,35 @@ def test_header_is_c99_and_the_library_links_from_c(tmp_path):
                     "-L", libdir, "-lwcns", f"-Wl,-rpath,{libdir}"], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
+    assert "fails=0" in r.stdout
+
+
+def test_host_code_is_clean_under_asan_and_ubsan(tmp_path):
+    """The library's host code (argument checks, validation of the grid,
+    fluids, options and Dirichlet ghosts, batch and allocation-free entry
+    checks) built with AddressSanitizer and UndefinedBehaviorSanitizer on the
+    host side only (the device code is compiled as usual), and driven from the
+    C client above, itself built with both sanitizers; every report is fatal
+    and leaks are reported."""
+    import subprocess
+    from paper_2102_05287_amd import build as B
+    clang = "/opt/rocm/llvm/bin/clang"
+    if not (os.path.exists(B.HIPCC) and os.path.exists(clang)):
+        pytest.skip("no ROCm compilers")
+    libdir = tmp_path / "lib"
+    libdir.mkdir()
+    flags = [f for f in B.FLAGS if f != "-O3"]
+    subprocess.run([B.HIPCC, *flags, "-O1", "-g",
+                    "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                    "-Xarch_host", "-fno-sanitize-recover=all",
+                    B.SRC, "-o", str(libdir / "libwcns.so")], check=True, capture_output=True)
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    exe = tmp_path / "client"
+    subprocess.run([clang, "-std=c99", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                    "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe),
+                    "-L", str(libdir), "-lwcns", f"-Wl,-rpath,{libdir}"], check=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 0, r.stdout + r.stderr[-4000:]
     assert "fails=0" in r.stdout
