@@ -286,3 +286,35 @@ def test_advance_chunks_replayed_as_a_graph():
     g.replay()   # past t_end: every step skipped
     assert int(taken.item()) == steps and float(clock.item()) == t_ref
     assert np.array_equal(host(Wd), W_end)
+
+
+def test_checkpoint_and_resume_are_bit_exact(tmp_path):
+    """Checkpoint and resume: the state of a solve is W, the time and the
+    step count.  Saving W (numpy, raw float64) with the time after 7 steps,
+    loading it into a new context and taking 6 more steps gives the bits of
+    13 steps in one go, with the same time steps (the method is
+    deterministic and every call recovers its first stage's primitives
+    from the state it is given)."""
+    spec = pb.underwater_explosion(160)
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    sol = solver_for(spec)
+    Wa = dev(W0)
+    dts_a = torch.zeros(13, dtype=torch.float64, device="cuda")
+    sol.steps(Wa, 13, 0.0, dts=dts_a)
+    Wb = dev(W0)
+    dts_b = torch.zeros(13, dtype=torch.float64, device="cuda")
+    sol.steps(Wb, 7, 0.0, dts=dts_b[:7])
+    path = tmp_path / "checkpoint.npz"
+    np.savez(path, W=host(Wb), t=float(host(dts_b[:7]).sum()), steps=7)
+    del Wb
+    sol.close()
+    ck = np.load(path)
+    sol2 = solver_for(spec)
+    Wc = dev(ck["W"])
+    sol2.steps(Wc, 6, 0.0, dts=dts_b[7:])
+    assert int(ck["steps"]) + 6 == 13
+    assert torch.equal(dts_a, dts_b)
+    assert np.array_equal(host(Wa), host(Wc))
+    assert float(ck["t"]) + float(host(dts_b[7:]).sum()) == float(host(dts_a).sum()) or \
+        abs(float(ck["t"]) + float(host(dts_b[7:]).sum()) - float(host(dts_a).sum())) < 1e-18
