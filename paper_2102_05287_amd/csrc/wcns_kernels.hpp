@@ -11,8 +11,8 @@
 //               with the full per-face pipeline and the flux difference uses
 //               a cross-lane shuffle (k_sweep_x: the same tiling with global
 //               loads, for rows narrower than 61 cells).
-//   k_sweep_y   one block over 32 columns x 8 y-face rows (4 waves, two face
-//               rows each), stencil rows staged in LDS; every face is
+//   k_sweep_y   one block over 32 columns x 16 y-face rows (8 waves, two
+//               face rows each), stencil rows staged in LDS; every face is
 //               computed once; neighbours exchanged by shuffle and LDS; the
 //               epilogue sums L_x + L_y and (for a step) applies the SSP-RK3
 //               stage combination.
@@ -1096,7 +1096,7 @@ __device__ __forceinline__ void sweep_x_window(const KArgs& a, long tile, bool o
 }
 
 // waves per SIMD the windowed x-sweep is compiled for (VGPR budget 512 / this):
-// 4 (112 VGPRs, no spills; compiled for 5 it spills and runs 2% slower)
+// 4 (110 VGPRs, no spills; compiled for 5 it spills and runs 2% slower)
 constexpr int XL_WPE = 4;
 // (FO: the first-order scheme, memory-bound: six waves per SIMD, the most
 // the LDS windows allow)
@@ -1114,14 +1114,13 @@ __global__ __launch_bounds__(64 * XW) __attribute__((amdgpu_waves_per_eu(FO ? 6 
 // The y-tile on 32 columns: a block of FR/2 waves covers 32 columns x FR
 // face rows; lane (r = lane / 32, col = lane % 32) of wave w computes face
 // row kb + 2w + r.  Stencil rows kb-3 .. kb+FR+1 are staged first (9 values
-// per node, c and rho ctilde^2 of the two centre nodes from global memory,
-// as in the 64-column tile).  Cell row kb + 2w takes G^- of face row
+// per node; c and rho ctilde^2 of the two centre nodes are read from global
+// memory into registers).  Cell row kb + 2w takes G^- of face row
 // kb + 2w + 1 from lane + 32 of its own wave (shuffle); cell row kb + 2w + 1
 // takes it from wave w + 1 through LDS; the tile's first G^- and last G^+
-// go to the edge buffer for the fixup.  Half the columns of the 64-column
-// tile: at 8 face rows a quarter of the LDS per wave pair (four 4-wave
-// blocks per CU); at 16 face rows, two 8-wave blocks per CU with half the
-// fixup rows.
+// go to the edge buffer for the fixup.  The single-grid sweep uses 16 face
+// rows (two 8-wave blocks per CU, half the fixup rows of 8-row tiles); the
+// batched form instantiates 2 to 16.
 // (part: this block's slot for its block maxima when a.Pn is set)
 template <int FR, bool DIRI, bool B32>
 __device__ __forceinline__ void sweep_y_tile32(const KArgs& a, int bx, int by, double* tile, long part) {
