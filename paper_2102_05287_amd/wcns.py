@@ -637,10 +637,11 @@ def autotune(batch, trials=3, candidates=None, margin=0.01):
     """Pick the batch schedule (y-tile height, task order) by the measured
     RHS time on the batch's own instances: each candidate is timed over
     `trials` separate RHS evaluations after one warm-up and scored by their
-    median; the first candidate (by default the library's own schedule,
-    16-row tiles dealt to the XCDs in chunks) is kept unless another is
-    faster by more than `margin`, so schedules within the run-to-run noise
-    of each other do not flip the pick.  Returns (best, {candidate: seconds})."""
+    median; of the candidates within `margin` of the fastest, the first in
+    the candidate order (by default the library's own schedule, 16-row
+    tiles dealt to the XCDs in chunks, then the others in a fixed order) is
+    taken, so schedules within the run-to-run noise of each other do not
+    flip the pick.  Returns (best, {candidate: seconds})."""
     import time
     if candidates is None:
         candidates = [(16, 2)] + [(y, o) for y in (4, 8, 16) for o in (0, 1, 2) if (y, o) != (16, 2)]
@@ -656,9 +657,7 @@ def autotune(batch, trials=3, candidates=None, margin=0.01):
             batch.sync()
             ts.append(time.perf_counter() - t0)
         times[cand] = sorted(ts)[len(ts) // 2]
-    best = candidates[0]
-    for cand in candidates[1:]:
-        if times[cand] < times[best] * (1.0 - margin):
-            best = cand
+    fastest = min(times.values())
+    best = next(c for c in candidates if times[c] <= fastest * (1.0 + margin))
     batch.configure(*best)
     return best, times
