@@ -322,8 +322,8 @@ wcns_status wcns_batch_reset(wcns_batch* b, int32_t n, const wcns_grid* grids, d
 
 /* Schedule: ytile in {2, 4, 8, 16} y-face rows per y-sweep block (32
  * columns, two face rows per wave; default 16); order 0 = instances in the given
- * order, 1 = largest instance first, 2 = tiles of an instance kept on one
- * XCD (blocks are dealt round-robin to the 8 XCDs; default).  Takes effect
+ * order (default), 1 = largest instance first, 2 = tiles of an instance kept
+ * on one XCD (blocks are dealt round-robin to the 8 XCDs).  Takes effect
  * at the next step (the graph is re-captured). */
 wcns_status wcns_batch_configure(wcns_batch* b, int32_t ytile, int32_t order);
 

@@ -1289,7 +1289,7 @@ struct wcns_batch {
   int32_t* d_live = nullptr;   // per-instance steps left (frozen at 0)
   unsigned long long* d_viol = nullptr;   // per-instance cells found outside G
   int dt_cap = 0;
-  int ytile = 16, order = 2;
+  int ytile = 16, order = 0;
   bool x_lds = false;   // x-sweep with LDS windows (every instance has nx >= XLDS_MIN_NX)
   hipGraph_t graph = nullptr;     // first step of a call (node primitives by kb_node)
   hipGraphExec_t exec = nullptr;

@@ -574,7 +574,7 @@ class Batch:
         import torch
         torch.cuda.current_stream().wait_stream(self.stream)
 
-    def configure(self, ytile=16, order=2):
+    def configure(self, ytile=16, order=0):
         _check(lib().wcns_batch_configure(self._b, int(ytile), int(order)), "wcns_batch_configure")
 
     def reset(self, grids, states):
@@ -639,12 +639,12 @@ def autotune(batch, trials=3, candidates=None, margin=0.01):
     `trials` separate RHS evaluations after one warm-up and scored by their
     median; of the candidates within `margin` of the fastest, the first in
     the candidate order (by default the library's own schedule, 16-row
-    tiles dealt to the XCDs in chunks, then the others in a fixed order) is
+    tiles in the given instance order, then the others in a fixed order) is
     taken, so schedules within the run-to-run noise of each other do not
     flip the pick.  Returns (best, {candidate: seconds})."""
     import time
     if candidates is None:
-        candidates = [(16, 2)] + [(y, o) for y in (4, 8, 16) for o in (0, 1, 2) if (y, o) != (16, 2)]
+        candidates = [(16, 0)] + [(y, o) for y in (4, 8, 16) for o in (0, 1, 2) if (y, o) != (16, 0)]
     times = {}
     for cand in candidates:
         batch.configure(*cand)
