@@ -53,3 +53,30 @@ def test_profile_counts_the_launches_of_a_multi_step_call():
     assert prof["node"][1] == 1 and prof["sweep_y"][1] == 1 and prof["finalize"][1] == 1
     sol.profile(False)
     sol.close()
+
+
+def test_profile_survives_a_stream_switch():
+    """Switching the context's stream with profiling on folds the timings
+    recorded on the old stream first: the launch counts of steps taken on
+    two streams add up and every class has a positive time."""
+    import numpy as np
+    from paper_2102_05287_amd import problems as pb
+    spec = pb.random_smooth_state(96, 70, 6)
+    sol = wcns.Solver.from_spec(spec)
+    W = sol.prim_to_cons(torch.from_numpy(np.ascontiguousarray(spec.prim)).cuda())
+    torch.cuda.synchronize()
+    sol.profile(True)
+    sol.steps(W, 2, 0.0)
+    other = torch.cuda.Stream()
+    other.wait_stream(torch.cuda.current_stream())
+    sol.set_stream(other.cuda_stream)
+    sol.steps(W, 3, 0.0)
+    prof = sol.profile_read(reset=True)
+    sol.set_stream(torch.cuda.current_stream().cuda_stream)
+    torch.cuda.current_stream().wait_stream(other)
+    assert prof["node"][1] == 2                      # the first stage of each call
+    for k in ("finalize", "sweep_x", "sweep_y", "fixup_y"):
+        assert prof[k][1] == 3 * 5, (k, prof[k])
+        assert prof[k][0] > 0.0
+    sol.profile(False)
+    sol.close()
