@@ -644,7 +644,7 @@ def autotune(batch, trials=3, candidates=None, margin=0.01):
     flip the pick.  Returns (best, {candidate: seconds})."""
     import time
     if candidates is None:
-        candidates = [(16, 0)] + [(y, o) for y in (4, 8, 16) for o in (0, 1, 2) if (y, o) != (16, 0)]
+        candidates = [(16, 0)] + [(y, o) for y in (2, 4, 8, 16) for o in (0, 1, 2) if (y, o) != (16, 0)]
     times = {}
     for cand in candidates:
         batch.configure(*cand)

@@ -145,7 +145,7 @@ def test_autotune_picks_a_schedule():
     states = [dev(oracle_W(sp, oracle_setup(sp))) for sp in specs]
     b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)
     best, times = wcns.autotune(b, trials=1)
-    assert best in times and len(times) == 9
+    assert best in times and len(times) == 12   # every schedule wcns_batch_configure accepts
     b.close()
 
 
