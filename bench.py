@@ -414,6 +414,46 @@ def first_order_form(n=1024, steps=200, warmup=10):
             "roofline": roof}
 
 
+def sizes_form(sizes=(1024, 1448, 2048), steps=(60, 30, 16)):
+    """Per-launch times of the two 2D sweeps on the shock-bubble at three
+    grid sizes (kernel-stamped events, one multi-step call each after a
+    warm-up), and the least-squares fit time = a + b * cells of each sweep:
+    a is the fixed cost of a launch (its first round of waves staging before
+    any arithmetic, its last round draining), b the cost per cell."""
+    import numpy as np
+    import torch
+    from paper_2102_05287_amd import problems as pb
+    from paper_2102_05287_amd import wcns
+    rows = []
+    for n, k in zip(sizes, steps):
+        spec = pb.shock_bubble(n)
+        sol = wcns.Solver.from_spec(spec)
+        W = sol.prim_to_cons(torch.from_numpy(spec.prim).cuda())
+        spec.prim = None
+        sol.steps(W, 3, 0.0)
+        torch.cuda.synchronize()
+        sol.profile(True)
+        sol.steps(W, k, 0.0)
+        prof = sol.profile_read(reset=True)
+        sol.profile(False)
+        sol.close()
+        rows.append({"grid": [n, n], "cells": n * n, "steps": k,
+                     "sweep_x_us": prof["sweep_x"][0] / prof["sweep_x"][1] * 1e3,
+                     "sweep_y_us": prof["sweep_y"][0] / prof["sweep_y"][1] * 1e3})
+        print(f"#   {n}^2: x {rows[-1]['sweep_x_us']:.1f} us, y {rows[-1]['sweep_y_us']:.1f} us per launch",
+              flush=True)
+    cells = np.array([r["cells"] for r in rows], dtype=float)
+    fit = {}
+    for key in ("sweep_x_us", "sweep_y_us"):
+        t = np.array([r[key] for r in rows])
+        b, a = np.polyfit(cells, t, 1)
+        fit[key.replace("_us", "")] = {"fixed_us_per_launch": a, "ps_per_cell": b * 1e6,
+                                       "fixed_share_at_smallest": a / t[0],
+                                       "fixed_share_at_largest": a / t[-1]}
+    return {"workload": "2D shock-bubble, FP64, sweep launch times at three grid sizes",
+            "sizes": rows, "fit_a_plus_b_cells": fit}
+
+
 def three_d_form(n=256, steps=10, warmup=2):
     """3D underwater explosion near a wall at n^3 (FP64, the direct 3D
     extension): Mcell-updates/s per RHS, per-kernel device time and the
@@ -606,7 +646,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the precision/batched/serving forms")
     ap.add_argument("--form", choices=("precision", "batched", "serving", "solutions", "rates",
-                                       "3d", "first_order"),
+                                       "3d", "first_order", "sizes"),
                     default=None,
                     help="run only this form and print its record")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -633,6 +673,7 @@ def main():
                "solutions": time_to_solution_form,
                "rates": serving_rate_sweep,
                "3d": three_d_form,
+               "sizes": sizes_form,
                "first_order": first_order_form}[args.form]
         print(json.dumps({"form": args.form, **run()}), flush=True)
         return
