@@ -8,7 +8,8 @@ it with ``g++ -O2 -ffp-contract=off`` into ``liboracle.so``.
 
 All arrays are numpy float64, SoA ``[nvar][ny][nx]`` with
 nvar = 5 in 1D (a1r1, a2r2, rho u, E, a1) and 6 in 2D
-(a1r1, a2r2, rho u, rho v, E, a1)  [paper Sec. 2/3, conservative W].
+(a1r1, a2r2, rho u, rho v, E, a1), and ``[7][nz][ny][nx]`` in 3D
+(a1r1, a2r2, rho u, rho v, rho w, E, a1)  [paper Sec. 2/3, conservative W].
 """
 from __future__ import annotations
 
