@@ -77,7 +77,7 @@ class _Group:
 class Server:
     def __init__(self, hbm_budget: int = 32 << 30, max_slots: int = 512, chunk: int = 20,
                  gamma=(6.12, 1.4), pinf=(3.43e8, 0.0), keep_results: bool = False,
-                 ytile: int = 16, order: int = 0):
+                 ytile: int = 16, order: int = 2):
         self.budget = hbm_budget
         self.max_slots = max_slots
         self.chunk = chunk
