@@ -221,3 +221,30 @@ def test_batch_full_size_512_instances_sampled():
     for k in sample:
         assert np.array_equal(host(states[k]), ref[k]), k
     b.close()
+
+
+def test_reset_that_does_not_fit_keeps_the_bound_set():
+    """A reset to an instance set larger than the batch's scratch fails with
+    WCNS_ERR_NOMEM and leaves the bound set as it was: the batch then steps
+    its old instances, bit for bit as the single-solve path does."""
+    specs = instances(4)
+    W0 = [oracle_W(sp, oracle_setup(sp)) for sp in specs]
+    ref = []
+    for sp, w in zip(specs, W0):
+        sol = wcns.Solver.from_spec(sp)
+        Wd = dev(w)
+        for _ in range(2):
+            sol.step(Wd, 0.0)
+        ref.append(host(Wd))
+        sol.close()
+    states = [dev(w) for w in W0]
+    b = wcns.Batch([wcns.grid_of(sp) for sp in specs], states)   # scratch for exactly these
+    big = instances(2, sides=(400, 400))
+    big_states = [dev(oracle_W(sp, oracle_setup(sp))) for sp in big]
+    with pytest.raises(wcns.WcnsError) as e:
+        b.reset([wcns.grid_of(sp) for sp in big], big_states)
+    assert e.value.code == -3
+    b.step(2)
+    for k in range(len(specs)):
+        assert np.array_equal(host(states[k]), ref[k]), k
+    b.close()
