@@ -76,23 +76,25 @@ def test_run_edge_cases():
         sol2.run(dev(oracle_W(pb.random_smooth_state(16, 16, 1))), 1e-6)
 
 
-def test_run_counts_inadmissible_cells_like_stepping():
+@pytest.mark.parametrize("nsteps", [3999, 2048])
+def test_run_counts_inadmissible_cells_like_stepping(nsteps):
     """The whole-run kernel counts the cells outside G exactly as the
     multi-kernel steps do (the run's input, every stage result): Sedov with
     both limiters off, 3999 fixed steps (three full launches of 1024 steps
-    and a partial one), against wcns_ssprk3_steps on a fresh context.  The
-    final states agree bit for bit (NaNs in the same places)."""
+    and a partial one) or 2048 (ending on a launch boundary), against
+    wcns_ssprk3_steps on a fresh context.  The final states agree bit for
+    bit (NaNs in the same places)."""
     spec = pb.sedov_multimaterial(401)
     s = oracle_setup(spec)
     W0 = oracle_W(spec, s)
     sol_r = solver_for(spec, interp_limiter=False, flux_limiter=False)
     sol_s = solver_for(spec, interp_limiter=False, flux_limiter=False)
     Wr, Ws = dev(W0), dev(W0)
-    n, t = sol_r.run(Wr, 1.0, dt_fixed=spec.dt_fixed, max_steps=3999)
-    assert n == 3999
-    sol_s.steps(Ws, 3999, spec.dt_fixed)
+    n, t = sol_r.run(Wr, 1.0, dt_fixed=spec.dt_fixed, max_steps=nsteps)
+    assert n == nsteps
+    sol_s.steps(Ws, nsteps, spec.dt_fixed)
     vr, vs = sol_r.violations(clear=True), sol_s.violations(clear=True)
-    print(f"  limiters off, 3999 steps: run counted {vr}, steps counted {vs}", flush=True)
+    print(f"  limiters off, {nsteps} steps: run counted {vr}, steps counted {vs}", flush=True)
     assert vr == vs > 0
     assert np.array_equal(host(Wr), host(Ws), equal_nan=True)
 
