@@ -1,6 +1,7 @@
 // Device-side arithmetic of the PP-WCNS-IS right-hand side on gfx950.
 //
-// Everything here is per-thread FP64 scalar code: the method is stencil and
+// Everything here is per-thread scalar code, FP64 except the precision
+// form's FP32 routines (marked below): the method is stencil and
 // Riemann-solver arithmetic with no dense contraction, so there is no MFMA
 // use.  Each routine cites the passage of the paper that defines it.
 //
