@@ -185,3 +185,36 @@ def test_first_order_scheme_is_fp64_in_both_precisions():
         print(f"  hllc1 {spec.name}: fp64 == fp32-bulk == oracle", flush=True)
         assert np.array_equal(out[0], out[1]), spec.name
         assert np.array_equal(out[0], ref), spec.name
+
+
+# relative L1 bounds of the 1D FP32-bulk solves against the oracle's FP64
+# solves at their final times, per variable (a1r1, a2r2, rho u, E, a1),
+# about ten times the measured errors:
+#   water-air tube  1.6e-4 1.1e-3 5.3e-4 1.1e-4 3.0e-5
+#   Sedov           3.4e-5 6.0e-5 1.0e-3 1.7e-5 5.4e-7
+# (the largest at the interfaces and the blast front, where the FP64
+# limiters react to the FP32 interpolation, as in 2D)
+ONE_D_BOUND = {"water_air_tube": [2e-3, 1e-2, 5e-3, 1e-3, 3e-4],
+               "sedov": [4e-4, 6e-4, 1e-2, 2e-4, 6e-6]}
+
+
+@pytest.mark.parametrize("name", ["water_air_tube", "sedov"])
+def test_fp32_bulk_1d_runs_to_final_time(name):
+    """The precision form in 1D: the water-air tube (400 cells, CFL steps
+    to 2.4e-4 s) and the multi-material Sedov blast (401 cells, 4000 fixed
+    steps, the limiter stress case) in FP32 bulk through the device time
+    loop, against the oracle's FP64 runs: relative L1 per variable within
+    the bounds above and no stage result outside the admissible set."""
+    spec = pb.water_air_shock_tube(400) if name == "water_air_tube" else pb.sedov_multimaterial(401)
+    s = oracle_setup(spec)
+    W0 = oracle_W(spec, s)
+    ref, steps, _ = orc.run(s, W0, spec.t_end, spec.dt_fixed)
+    sol = wcns.Solver.from_spec(spec, precision=FP32)
+    Wd = dev(W0)
+    n, t = sol.advance(Wd, spec.t_end, chunk=256, dt=spec.dt_fixed)
+    assert t == spec.t_end and sol.violations() == 0
+    got = host(Wd)
+    e = rel_l1(got, ref)
+    print(f"  fp32 1d {name}: {n} steps (oracle {steps}), rel L1 {['%.2e' % x for x in e]}", flush=True)
+    for v, (x, bound) in enumerate(zip(e, ONE_D_BOUND[name])):
+        assert x < bound, (v, x, bound)
